@@ -1,0 +1,692 @@
+/*
+ * CPU oracle for the batched CHIP-8 environment step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, scalar CHIP-8
+ * interpreter and RL wrapper used to check the HIP path.  Only the tests,
+ * the smoke check and the benchmark's CPU-baseline leg may load it.  It
+ * shares no code, header, table or constant with the GPU library: every
+ * constant below is written out here from the paper and the CHIP-8
+ * definition.  The product never calls it.
+ *
+ * Sources followed:
+ *   - Section 3.2 ("How does Octax work?"): memory loaded at 0x200, font at
+ *     0x50, sixteen registers, I, PC, 64x32 display; fetch reads a 16-bit
+ *     instruction and advances PC; decode splits nibbles; execute dispatches
+ *     to one handler per instruction; ALU ops set a carry/borrow flag; the
+ *     wrapper runs several instructions per frame, ticks the 60 Hz timers,
+ *     skips 4 frames per step, stacks 4 frames into a (4, 64, 32) boolean
+ *     observation and maps actions to a key subset plus a no-op.
+ *   - Section 3.3: reward from a score register, termination from a
+ *     register test.
+ *   - Appendix B.2-B.4: 4 KB memory, V0-VF with VF the flag register, XOR
+ *     drawing with collision when a pixel turns off, 16-key keypad, 60 Hz
+ *     delay and sound timers, 4x5 hex font at 0x050-0x09F, BCD (FX33) and
+ *     bulk register store/load (FX55/FX65).
+ * The paper does not print per-opcode semantics.  Where it is silent the
+ * classic COSMAC VIP meaning is used (shift from VY, FX55/FX65 advance I,
+ * BNNN adds V0, 8XY1/2/3 clear VF, flag written after the result), sprites
+ * start at wrapped coordinates and clip at the right and bottom edges, the
+ * stack holds 16 entries with a wrapping pointer, and CXNN draws from a
+ * per-env SplitMix64 stream (Steele, Lea and Flood, OOPSLA 2014).
+ *
+ * Parity notes: the font glyph bytes are the standard CHIP-8 hex font (the
+ * paper fixes only their addresses); the RNG stream is pinned to the
+ * published SplitMix64 definition, not to the paper's JAX keys.
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MEM_BYTES 4096
+#define PROGRAM_ADDR 0x200
+#define FONT_ADDR 0x050
+#define SCREEN_W 64
+#define SCREEN_H 32
+#define STACK_DEPTH 16
+#define MAX_ROM_BYTES (MEM_BYTES - PROGRAM_ADDR)
+
+/* The 4x5 hexadecimal font, glyphs 0..F, five rows each, high nibble = pixels. */
+static const uint8_t oracle_font[80] = {
+    0xF0, 0x90, 0x90, 0x90, 0xF0, /* 0 */
+    0x20, 0x60, 0x20, 0x20, 0x70, /* 1 */
+    0xF0, 0x10, 0xF0, 0x80, 0xF0, /* 2 */
+    0xF0, 0x10, 0xF0, 0x10, 0xF0, /* 3 */
+    0x90, 0x90, 0xF0, 0x10, 0x10, /* 4 */
+    0xF0, 0x80, 0xF0, 0x10, 0xF0, /* 5 */
+    0xF0, 0x80, 0xF0, 0x90, 0xF0, /* 6 */
+    0xF0, 0x10, 0x20, 0x40, 0x40, /* 7 */
+    0xF0, 0x90, 0xF0, 0x90, 0xF0, /* 8 */
+    0xF0, 0x90, 0xF0, 0x10, 0xF0, /* 9 */
+    0xF0, 0x90, 0xF0, 0x90, 0x90, /* A */
+    0xE0, 0x90, 0xE0, 0x90, 0xE0, /* B */
+    0xF0, 0x80, 0x80, 0x80, 0xF0, /* C */
+    0xE0, 0x90, 0x90, 0x90, 0xE0, /* D */
+    0xF0, 0x80, 0xF0, 0x80, 0xF0, /* E */
+    0xF0, 0x80, 0xF0, 0x80, 0x80, /* F */
+};
+
+/* One emulated machine (Appendix B.2). */
+typedef struct {
+    uint8_t v[16];
+    uint16_t i;
+    uint16_t pc;
+    uint8_t sp;
+    uint8_t dt;
+    uint8_t st;
+    uint16_t stack[STACK_DEPTH];
+    uint8_t mem[MEM_BYTES];
+    uint8_t disp[SCREEN_H][SCREEN_W]; /* disp[y][x] is 0 or 1 */
+    uint64_t rng;                     /* SplitMix64 state */
+} oracle_machine;
+
+/* Exported snapshot of one environment.  Field order is part of the
+ * oracle's ctypes interface (oracle.py mirrors it). */
+typedef struct {
+    uint8_t v[16];
+    uint16_t i;
+    uint16_t pc;
+    uint8_t sp;
+    uint8_t dt;
+    uint8_t st;
+    uint8_t pad;
+    uint16_t stack[STACK_DEPTH];
+    uint32_t t;
+    int32_t prev_score;
+    uint64_t rng;
+    uint8_t mem[MEM_BYTES];
+    uint8_t disp[SCREEN_H][SCREEN_W];
+    uint8_t hist[3][SCREEN_H][SCREEN_W];
+} oracle_state;
+
+/* One RL environment around a machine (Section 3.2, "Environment integration"). */
+typedef struct {
+    oracle_machine m;
+    uint8_t hist[3][SCREEN_H][SCREEN_W]; /* the three frames before the current one, oldest first */
+    uint32_t t;                          /* steps since the last reset */
+    int32_t prev_score;
+    uint16_t rom;
+    uint32_t horizon;
+} oracle_env;
+
+typedef struct {
+    int num_envs;
+    int num_roms;
+    uint8_t (*rom)[MAX_ROM_BYTES];
+    uint32_t *rom_len;
+    uint8_t (*action_keys)[16];
+    uint8_t *num_actions;
+    uint8_t *score_reg;
+    uint8_t *term_reg;
+    uint8_t *term_value;
+    int instr_per_frame;
+    int frame_skip;
+    oracle_env *env;
+} oracle_batch;
+
+/* ------------------------------------------------------------------ */
+/* Random bytes for CXNN: SplitMix64.  The state advances by the golden */
+/* gamma, the output is the published 64-bit finaliser of the new      */
+/* state, and CXNN keeps its top byte.                                   */
+/* ------------------------------------------------------------------ */
+uint64_t oracle_splitmix64_next(uint64_t *state)
+{
+    uint64_t z;
+    *state += 0x9E3779B97F4A7C15ULL;
+    z = *state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* ------------------------------------------------------------------ */
+/* Machine                                                              */
+/* ------------------------------------------------------------------ */
+
+/* Power-on state (Section 3.2, "ROM loading and initialization"): memory
+ * cleared, font at 0x50, program at 0x200, registers, I, stack and timers
+ * zero, PC = 0x200, display cleared.  The RNG stream is left as it is. */
+void oracle_machine_load(oracle_machine *m, const uint8_t *rom, uint32_t len)
+{
+    memset(m->v, 0, sizeof m->v);
+    m->i = 0;
+    m->pc = PROGRAM_ADDR;
+    m->sp = 0;
+    m->dt = 0;
+    m->st = 0;
+    memset(m->stack, 0, sizeof m->stack);
+    memset(m->mem, 0, sizeof m->mem);
+    memcpy(m->mem + FONT_ADDR, oracle_font, sizeof oracle_font);
+    memcpy(m->mem + PROGRAM_ADDR, rom, len);
+    memset(m->disp, 0, sizeof m->disp);
+}
+
+static void skip_next(oracle_machine *m) { m->pc = (uint16_t)((m->pc + 2) & 0xFFF); }
+
+/* Draw an n-row sprite from memory at I with its top-left corner at
+ * (VX mod 64, VY mod 32).  Every set sprite bit flips its pixel; pixels past
+ * the right or bottom edge are not drawn.  VF = 1 iff some pixel went from
+ * 1 to 0 (Appendix B.3). */
+static void draw_sprite(oracle_machine *m, int x, int y, int n)
+{
+    int x0 = m->v[x] % SCREEN_W;
+    int y0 = m->v[y] % SCREEN_H;
+    int collided = 0;
+    for (int row = 0; row < n; row++) {
+        int py = y0 + row;
+        if (py >= SCREEN_H)
+            break;
+        uint8_t bits = m->mem[(m->i + row) & 0xFFF];
+        for (int col = 0; col < 8; col++) {
+            int px = x0 + col;
+            if (px >= SCREEN_W)
+                break;
+            int sprite_pixel = (bits >> (7 - col)) & 1;
+            if (sprite_pixel) {
+                if (m->disp[py][px] == 1)
+                    collided = 1;
+                m->disp[py][px] ^= 1;
+            }
+        }
+    }
+    m->v[0xF] = (uint8_t)collided;
+}
+
+/* Fetch, decode and execute one instruction.  key is the held key
+ * (0..15) or -1 when none is held. */
+void oracle_machine_execute(oracle_machine *m, int key)
+{
+    /* fetch: big-endian 16-bit word at PC, then PC += 2 */
+    uint16_t op = (uint16_t)((m->mem[m->pc] << 8) | m->mem[(m->pc + 1) & 0xFFF]);
+    m->pc = (uint16_t)((m->pc + 2) & 0xFFF);
+
+    /* decode */
+    int x = (op >> 8) & 0xF;
+    int y = (op >> 4) & 0xF;
+    int n = op & 0xF;
+    int nn = op & 0xFF;
+    int nnn = op & 0xFFF;
+    uint8_t *V = m->v;
+
+    /* execute */
+    switch (op >> 12) {
+    case 0x0:
+        if (op == 0x00E0) {                       /* CLS */
+            memset(m->disp, 0, sizeof m->disp);
+        } else if (op == 0x00EE) {                /* RET */
+            m->sp = (uint8_t)((m->sp + STACK_DEPTH - 1) % STACK_DEPTH);
+            m->pc = m->stack[m->sp];
+        }                                         /* 0NNN: ignored */
+        break;
+    case 0x1:                                     /* JP NNN */
+        m->pc = (uint16_t)nnn;
+        break;
+    case 0x2:                                     /* CALL NNN */
+        m->stack[m->sp] = m->pc;
+        m->sp = (uint8_t)((m->sp + 1) % STACK_DEPTH);
+        m->pc = (uint16_t)nnn;
+        break;
+    case 0x3:                                     /* SE VX, NN */
+        if (V[x] == nn)
+            skip_next(m);
+        break;
+    case 0x4:                                     /* SNE VX, NN */
+        if (V[x] != nn)
+            skip_next(m);
+        break;
+    case 0x5:                                     /* SE VX, VY */
+        if (n == 0 && V[x] == V[y])
+            skip_next(m);
+        break;
+    case 0x6:                                     /* LD VX, NN */
+        V[x] = (uint8_t)nn;
+        break;
+    case 0x7:                                     /* ADD VX, NN (no flag) */
+        V[x] = (uint8_t)((V[x] + nn) % 256);
+        break;
+    case 0x8: {
+        int vx = V[x], vy = V[y];
+        switch (n) {
+        case 0x0: V[x] = (uint8_t)vy; break;
+        case 0x1: V[x] = (uint8_t)(vx | vy); V[0xF] = 0; break;
+        case 0x2: V[x] = (uint8_t)(vx & vy); V[0xF] = 0; break;
+        case 0x3: V[x] = (uint8_t)(vx ^ vy); V[0xF] = 0; break;
+        case 0x4: {
+            int sum = vx + vy;
+            V[x] = (uint8_t)(sum % 256);
+            V[0xF] = (uint8_t)(sum > 255);
+            break;
+        }
+        case 0x5: {
+            int no_borrow = vx >= vy;
+            V[x] = (uint8_t)((vx - vy + 256) % 256);
+            V[0xF] = (uint8_t)no_borrow;
+            break;
+        }
+        case 0x6: {
+            int out = vy % 2;
+            V[x] = (uint8_t)(vy / 2);
+            V[0xF] = (uint8_t)out;
+            break;
+        }
+        case 0x7: {
+            int no_borrow = vy >= vx;
+            V[x] = (uint8_t)((vy - vx + 256) % 256);
+            V[0xF] = (uint8_t)no_borrow;
+            break;
+        }
+        case 0xE: {
+            int out = vy / 128;
+            V[x] = (uint8_t)((vy * 2) % 256);
+            V[0xF] = (uint8_t)out;
+            break;
+        }
+        default: break;                           /* not an instruction */
+        }
+        break;
+    }
+    case 0x9:                                     /* SNE VX, VY */
+        if (n == 0 && V[x] != V[y])
+            skip_next(m);
+        break;
+    case 0xA:                                     /* LD I, NNN */
+        m->i = (uint16_t)nnn;
+        break;
+    case 0xB:                                     /* JP V0, NNN */
+        m->pc = (uint16_t)((nnn + V[0]) & 0xFFF);
+        break;
+    case 0xC:                                     /* RND VX, NN */
+        V[x] = (uint8_t)((oracle_splitmix64_next(&m->rng) >> 56) & (uint64_t)nn);
+        break;
+    case 0xD:                                     /* DRW VX, VY, N */
+        draw_sprite(m, x, y, n);
+        break;
+    case 0xE:
+        if (nn == 0x9E) {                         /* SKP VX */
+            if (key >= 0 && key == V[x] % 16)
+                skip_next(m);
+        } else if (nn == 0xA1) {                  /* SKNP VX */
+            if (!(key >= 0 && key == V[x] % 16))
+                skip_next(m);
+        }
+        break;
+    case 0xF:
+        switch (nn) {
+        case 0x07: V[x] = m->dt; break;           /* LD VX, DT */
+        case 0x0A:                                /* LD VX, K */
+            if (key >= 0)
+                V[x] = (uint8_t)key;
+            else
+                m->pc = (uint16_t)((m->pc + MEM_BYTES - 2) & 0xFFF);
+            break;
+        case 0x15: m->dt = V[x]; break;           /* LD DT, VX */
+        case 0x18: m->st = V[x]; break;           /* LD ST, VX */
+        case 0x1E: m->i = (uint16_t)((m->i + V[x]) & 0xFFF); break;
+        case 0x29: m->i = (uint16_t)(FONT_ADDR + 5 * (V[x] % 16)); break;
+        case 0x33: {                              /* BCD */
+            int value = V[x];
+            m->mem[m->i] = (uint8_t)(value / 100);
+            m->mem[(m->i + 1) & 0xFFF] = (uint8_t)((value / 10) % 10);
+            m->mem[(m->i + 2) & 0xFFF] = (uint8_t)(value % 10);
+            break;
+        }
+        case 0x55:                                /* LD [I], V0..VX */
+            for (int k = 0; k <= x; k++)
+                m->mem[(m->i + k) & 0xFFF] = V[k];
+            m->i = (uint16_t)((m->i + x + 1) & 0xFFF);
+            break;
+        case 0x65:                                /* LD V0..VX, [I] */
+            for (int k = 0; k <= x; k++)
+                V[k] = m->mem[(m->i + k) & 0xFFF];
+            m->i = (uint16_t)((m->i + x + 1) & 0xFFF);
+            break;
+        default: break;
+        }
+        break;
+    }
+}
+
+/* One 60 Hz timer tick: both timers count down to zero. */
+void oracle_machine_tick(oracle_machine *m)
+{
+    if (m->dt > 0)
+        m->dt--;
+    if (m->st > 0)
+        m->st--;
+}
+
+/* ------------------------------------------------------------------ */
+/* Environment                                                          */
+/* ------------------------------------------------------------------ */
+
+static void env_reset(const oracle_batch *b, oracle_env *e)
+{
+    oracle_machine_load(&e->m, b->rom[e->rom], b->rom_len[e->rom]);
+    for (int k = 0; k < 3; k++)
+        memcpy(e->hist[k], e->m.disp, sizeof e->m.disp);
+    e->t = 0;
+    e->prev_score = e->m.v[b->score_reg[e->rom]];
+}
+
+/* obs[k][x][y] for k = 0..3: the three stored frames then the display. */
+static void env_observe(const oracle_env *e, uint8_t *obs)
+{
+    for (int k = 0; k < 4; k++) {
+        const uint8_t(*frame)[SCREEN_W] = (k < 3) ? e->hist[k] : e->m.disp;
+        for (int x = 0; x < SCREEN_W; x++)
+            for (int y = 0; y < SCREEN_H; y++)
+                obs[(k * SCREEN_W + x) * SCREEN_H + y] = frame[y][x];
+    }
+}
+
+static void env_step(const oracle_batch *b, oracle_env *e, int32_t action, uint8_t *obs,
+                     float *reward, uint8_t *done)
+{
+    int r = e->rom;
+    int key = -1;
+    if (action >= 0 && action < b->num_actions[r])
+        key = b->action_keys[r][action];
+
+    uint8_t before[SCREEN_H][SCREEN_W];
+    memcpy(before, e->m.disp, sizeof before);
+
+    for (int f = 0; f < b->frame_skip; f++) {
+        for (int k = 0; k < b->instr_per_frame; k++)
+            oracle_machine_execute(&e->m, key);
+        oracle_machine_tick(&e->m);
+    }
+
+    memcpy(e->hist[0], e->hist[1], sizeof before);
+    memcpy(e->hist[1], e->hist[2], sizeof before);
+    memcpy(e->hist[2], before, sizeof before);
+
+    int32_t score = e->m.v[b->score_reg[r]];
+    *reward = (float)(score - e->prev_score);
+    e->prev_score = score;
+
+    int terminated = e->m.v[b->term_reg[r]] == b->term_value[r];
+    e->t += 1;
+    int truncated = e->horizon > 0 && e->t >= e->horizon;
+    *done = (uint8_t)(terminated | (truncated << 1));
+    if (terminated || truncated)
+        env_reset(b, e);
+    if (obs)
+        env_observe(e, obs);
+}
+
+/* ------------------------------------------------------------------ */
+/* Exported interface (ctypes)                                          */
+/* ------------------------------------------------------------------ */
+
+oracle_batch *oracle_create(int num_envs, int num_roms, const uint8_t *rom_data,
+                            const uint32_t *rom_offset, const uint32_t *rom_len,
+                            const uint16_t *env_rom, const uint8_t *action_keys,
+                            const uint8_t *num_actions, const uint8_t *score_reg,
+                            const uint8_t *term_reg, const uint8_t *term_value,
+                            const uint32_t *horizon, const uint64_t *env_seed,
+                            int instr_per_frame, int frame_skip)
+{
+    if (num_envs < 0 || num_roms < 1 || instr_per_frame < 0 || frame_skip < 0)
+        return NULL;
+    for (int r = 0; r < num_roms; r++)
+        if (rom_len[r] > MAX_ROM_BYTES || score_reg[r] > 15 || term_reg[r] > 15 ||
+            num_actions[r] > 16)
+            return NULL;
+    for (int e = 0; e < num_envs; e++)
+        if (env_rom[e] >= num_roms)
+            return NULL;
+    oracle_batch *b = calloc(1, sizeof *b);
+    if (!b)
+        return NULL;
+    b->num_envs = num_envs;
+    b->num_roms = num_roms;
+    b->rom = calloc((size_t)num_roms, sizeof *b->rom);
+    b->rom_len = calloc((size_t)num_roms, sizeof *b->rom_len);
+    b->action_keys = calloc((size_t)num_roms, sizeof *b->action_keys);
+    b->num_actions = calloc((size_t)num_roms, 1);
+    b->score_reg = calloc((size_t)num_roms, 1);
+    b->term_reg = calloc((size_t)num_roms, 1);
+    b->term_value = calloc((size_t)num_roms, 1);
+    b->env = calloc((size_t)(num_envs > 0 ? num_envs : 1), sizeof *b->env);
+    if (!b->rom || !b->rom_len || !b->action_keys || !b->num_actions || !b->score_reg ||
+        !b->term_reg || !b->term_value || !b->env) {
+        free(b->rom); free(b->rom_len); free(b->action_keys); free(b->num_actions);
+        free(b->score_reg); free(b->term_reg); free(b->term_value); free(b->env); free(b);
+        return NULL;
+    }
+    for (int r = 0; r < num_roms; r++) {
+        memcpy(b->rom[r], rom_data + rom_offset[r], rom_len[r]);
+        b->rom_len[r] = rom_len[r];
+        memcpy(b->action_keys[r], action_keys + 16 * r, 16);
+        b->num_actions[r] = num_actions[r];
+        b->score_reg[r] = score_reg[r];
+        b->term_reg[r] = term_reg[r];
+        b->term_value[r] = term_value[r];
+    }
+    b->instr_per_frame = instr_per_frame;
+    b->frame_skip = frame_skip;
+    for (int e = 0; e < num_envs; e++) {
+        b->env[e].rom = env_rom[e];
+        b->env[e].horizon = horizon[e];
+        b->env[e].m.rng = env_seed[e];
+        env_reset(b, &b->env[e]);
+    }
+    return b;
+}
+
+void oracle_destroy(oracle_batch *b)
+{
+    if (!b)
+        return;
+    free(b->rom); free(b->rom_len); free(b->action_keys); free(b->num_actions);
+    free(b->score_reg); free(b->term_reg); free(b->term_value); free(b->env);
+    free(b);
+}
+
+/* Reset the envs whose mask byte is non-zero (all when mask is NULL) and
+ * write the observation of every env into obs [E][4][64][32] if given. */
+void oracle_reset(oracle_batch *b, const uint8_t *mask, uint8_t *obs)
+{
+    for (int e = 0; e < b->num_envs; e++) {
+        if (!mask || mask[e])
+            env_reset(b, &b->env[e]);
+        if (obs)
+            env_observe(&b->env[e], obs + (size_t)e * 4 * SCREEN_W * SCREEN_H);
+    }
+}
+
+/* One environment step of every env.  obs may be NULL (not materialised). */
+void oracle_step(oracle_batch *b, const int32_t *action, uint8_t *obs, float *reward,
+                 uint8_t *done)
+{
+    for (int e = 0; e < b->num_envs; e++)
+        env_step(b, &b->env[e], action[e],
+                 obs ? obs + (size_t)e * 4 * SCREEN_W * SCREEN_H : NULL, &reward[e], &done[e]);
+}
+
+typedef struct {
+    oracle_batch *b;
+    int first, last, steps;
+    const int32_t *action; /* [steps][E] */
+    uint8_t *obs;          /* [E][4][64][32], rewritten every step */
+    float *reward;         /* [steps][E] */
+    uint8_t *done;         /* [steps][E] */
+} oracle_shard;
+
+static void *run_shard(void *arg)
+{
+    oracle_shard *s = arg;
+    int E = s->b->num_envs;
+    for (int k = 0; k < s->steps; k++)
+        for (int e = s->first; e < s->last; e++)
+            env_step(s->b, &s->b->env[e], s->action[(size_t)k * E + e],
+                     s->obs + (size_t)e * 4 * SCREEN_W * SCREEN_H,
+                     &s->reward[(size_t)k * E + e], &s->done[(size_t)k * E + e]);
+    return NULL;
+}
+
+/* Run `steps` steps with the envs split into `threads` contiguous shards,
+ * one POSIX thread each; observations are materialised every step into one
+ * reused [E][4][64][32] buffer.  Returns the number of threads used. */
+int oracle_run_threaded(oracle_batch *b, int steps, const int32_t *action, uint8_t *obs,
+                        float *reward, uint8_t *done, int threads)
+{
+    if (threads < 1)
+        threads = 1;
+    if (threads > b->num_envs)
+        threads = b->num_envs > 0 ? b->num_envs : 1;
+    pthread_t *tid = calloc((size_t)threads, sizeof *tid);
+    oracle_shard *sh = calloc((size_t)threads, sizeof *sh);
+    int used = 0;
+    for (int t = 0; t < threads; t++) {
+        sh[t].b = b;
+        sh[t].first = (int)((long)b->num_envs * t / threads);
+        sh[t].last = (int)((long)b->num_envs * (t + 1) / threads);
+        sh[t].steps = steps;
+        sh[t].action = action;
+        sh[t].obs = obs;
+        sh[t].reward = reward;
+        sh[t].done = done;
+    }
+    for (int t = 0; t < threads; t++)
+        if (pthread_create(&tid[t], NULL, run_shard, &sh[t]) == 0)
+            used++;
+        else
+            run_shard(&sh[t]);
+    for (int t = 0; t < threads; t++)
+        pthread_join(tid[t], NULL);
+    free(tid);
+    free(sh);
+    return used > 0 ? threads : 1;
+}
+
+void oracle_get_state(const oracle_batch *b, int first, int count, oracle_state *out)
+{
+    for (int k = 0; k < count; k++) {
+        const oracle_env *e = &b->env[first + k];
+        oracle_state *s = &out[k];
+        memset(s, 0, sizeof *s);
+        memcpy(s->v, e->m.v, 16);
+        s->i = e->m.i;
+        s->pc = e->m.pc;
+        s->sp = e->m.sp;
+        s->dt = e->m.dt;
+        s->st = e->m.st;
+        memcpy(s->stack, e->m.stack, sizeof s->stack);
+        s->t = e->t;
+        s->prev_score = e->prev_score;
+        s->rng = e->m.rng;
+        memcpy(s->mem, e->m.mem, MEM_BYTES);
+        memcpy(s->disp, e->m.disp, sizeof s->disp);
+        memcpy(s->hist, e->hist, sizeof s->hist);
+    }
+}
+
+void oracle_set_state(oracle_batch *b, int first, int count, const oracle_state *in)
+{
+    for (int k = 0; k < count; k++) {
+        oracle_env *e = &b->env[first + k];
+        const oracle_state *s = &in[k];
+        memcpy(e->m.v, s->v, 16);
+        e->m.i = s->i & 0xFFF;
+        e->m.pc = s->pc & 0xFFF;
+        e->m.sp = s->sp % STACK_DEPTH;
+        e->m.dt = s->dt;
+        e->m.st = s->st;
+        for (int j = 0; j < STACK_DEPTH; j++)
+            e->m.stack[j] = s->stack[j] & 0xFFF;
+        e->t = s->t;
+        e->prev_score = s->prev_score;
+        e->m.rng = s->rng;
+        memcpy(e->m.mem, s->mem, MEM_BYTES);
+        for (int y = 0; y < SCREEN_H; y++)
+            for (int x = 0; x < SCREEN_W; x++) {
+                e->m.disp[y][x] = s->disp[y][x] & 1;
+                for (int h = 0; h < 3; h++)
+                    e->hist[h][y][x] = s->hist[h][y][x] & 1;
+            }
+    }
+}
+
+int oracle_state_size(void) { return (int)sizeof(oracle_state); }
+int oracle_machine_size(void) { return (int)sizeof(oracle_machine); }
+
+/* Single-machine access for unit tests of individual instructions. */
+oracle_machine *oracle_machine_new(void) { return calloc(1, sizeof(oracle_machine)); }
+void oracle_machine_free(oracle_machine *m) { free(m); }
+void oracle_machine_to_state(const oracle_machine *m, oracle_state *s)
+{
+    memset(s, 0, sizeof *s);
+    memcpy(s->v, m->v, 16);
+    s->i = m->i;
+    s->pc = m->pc;
+    s->sp = m->sp;
+    s->dt = m->dt;
+    s->st = m->st;
+    memcpy(s->stack, m->stack, sizeof s->stack);
+    s->rng = m->rng;
+    memcpy(s->mem, m->mem, MEM_BYTES);
+    memcpy(s->disp, m->disp, sizeof s->disp);
+}
+void oracle_machine_from_state(oracle_machine *m, const oracle_state *s)
+{
+    memcpy(m->v, s->v, 16);
+    m->i = s->i & 0xFFF;
+    m->pc = s->pc & 0xFFF;
+    m->sp = s->sp % STACK_DEPTH;
+    m->dt = s->dt;
+    m->st = s->st;
+    for (int j = 0; j < STACK_DEPTH; j++)
+        m->stack[j] = s->stack[j] & 0xFFF;
+    m->rng = s->rng;
+    memcpy(m->mem, s->mem, MEM_BYTES);
+    for (int y = 0; y < SCREEN_H; y++)
+        for (int x = 0; x < SCREEN_W; x++)
+            m->disp[y][x] = s->disp[y][x] & 1;
+}
+
+/* Execute one opcode on `count` machines that differ only in V, I and RNG
+ * state (exhaustive operand sweeps in the tests).  The opcode sits at 0x200
+ * of an otherwise freshly loaded machine. */
+void oracle_execute_batch(uint16_t op, int key, int count, const uint8_t *v_in,
+                          const uint16_t *i_in, const uint64_t *rng_in, uint8_t *v_out,
+                          uint16_t *i_out, uint16_t *pc_out, uint8_t *mem_out /* [count][4096] or NULL */)
+{
+    static __thread oracle_machine m;
+    uint8_t rom[2] = {(uint8_t)(op >> 8), (uint8_t)(op & 0xFF)};
+    for (int k = 0; k < count; k++) {
+        oracle_machine_load(&m, rom, 2);
+        memcpy(m.v, v_in + 16 * k, 16);
+        m.i = i_in ? (uint16_t)(i_in[k] & 0xFFF) : 0;
+        m.rng = rng_in ? rng_in[k] : 0;
+        oracle_machine_execute(&m, key);
+        memcpy(v_out + 16 * k, m.v, 16);
+        if (i_out)
+            i_out[k] = m.i;
+        if (pc_out)
+            pc_out[k] = m.pc;
+        if (mem_out)
+            memcpy(mem_out + (size_t)MEM_BYTES * k, m.mem, MEM_BYTES);
+    }
+}
+
+/* Run n_instr instructions (no timer ticks) on each of `count` full
+ * snapshots in place; display, memory and registers all come from the
+ * snapshot.  Used by the tests to start from arbitrary machine states. */
+void oracle_execute_states(oracle_state *states, int count, int key, int n_instr)
+{
+    static __thread oracle_machine m;
+    for (int k = 0; k < count; k++) {
+        oracle_machine_from_state(&m, &states[k]);
+        for (int j = 0; j < n_instr; j++)
+            oracle_machine_execute(&m, key);
+        uint32_t t = states[k].t;
+        int32_t prev = states[k].prev_score;
+        uint8_t hist[3][SCREEN_H][SCREEN_W];
+        memcpy(hist, states[k].hist, sizeof hist);
+        oracle_machine_to_state(&m, &states[k]);
+        states[k].t = t;
+        states[k].prev_score = prev;
+        memcpy(states[k].hist, hist, sizeof hist);
+    }
+}

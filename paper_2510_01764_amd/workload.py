@@ -1,0 +1,424 @@
+"""Seeded synthetic workloads for the batched CHIP-8 environment step.
+
+This module only draws inputs: ROM images, the env -> ROM map, per-ROM action
+sets and reward/termination descriptors, per-env truncation horizons, per-env
+RNG seeds and action streams.  It contains none of the emulator's arithmetic,
+so both the CPU oracle and the HIP path can consume what it produces.
+
+The paper's game ROMs are third-party files that are not available here, so
+seed-generated programs stand in for them.  They keep the paper's shapes: a
+program loaded at 0x200 in a 4 KB memory (Section 3.2, "ROM loading and
+initialization"; Appendix B.2), a 64x32 display drawn with DXYN, a handful of
+keys mapped through an action set (Section 3.3, "Action space optimization"),
+a single score register and an equality termination test (Section 3.3,
+"Score function design" / "Termination logic").
+
+Every generator uses ``numpy.random.Generator(PCG64(seed))`` so a config is a
+pure function of its seed.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+PROGRAM_START = 0x200
+MEMORY_SIZE = 4096
+# 0x200..0xFFF holds at most 3584 bytes = 1792 two-byte instructions.
+MAX_PROGRAM_INSTRUCTIONS = (MEMORY_SIZE - PROGRAM_START) // 2
+FONT_START = 0x050
+# Scratch bytes below the program, used by the generator as a data area for
+# BCD and register saves, like the data areas real games keep.
+SCRATCH_START = 0x0A0
+SCRATCH_END = 0x200
+
+KEYS_5 = (5, 7, 8, 9, 6)  # the five-key set of the paper's Target Shooter wrapper (Appendix C)
+KEYS_8 = (1, 2, 4, 5, 6, 7, 8, 9)
+
+
+@dataclasses.dataclass(frozen=True)
+class OpcodeMix:
+    """Relative weights of the opcode classes the generator draws from."""
+
+    draw: float = 0.15      # DXYN
+    key: float = 0.10       # EX9E / EXA1
+    alu: float = 0.25       # 8XY0..8XY7, 8XYE
+    imm: float = 0.20       # 6XNN / 7XNN
+    index: float = 0.08     # ANNN / FX1E / FX29
+    mem: float = 0.05       # FX33 / FX55 / FX65
+    branch: float = 0.12    # 1NNN 2NNN 00EE 3XNN 4XNN 5XY0 9XY0 BNNN
+    timer: float = 0.03     # FX07 / FX15 / FX18
+    rnd: float = 0.02       # CXNN
+    misc: float = 0.005     # 00E0 / FX0A
+    draw_n_min: int = 1
+    draw_n_max: int = 8
+    # Draw-heavy workloads load VX/VY near the screen edges before DXYN.
+    edge_bias: bool = False
+
+    def weights(self) -> np.ndarray:
+        w = np.array([self.draw, self.key, self.alu, self.imm, self.index,
+                      self.mem, self.branch, self.timer, self.rnd, self.misc],
+                     dtype=np.float64)
+        return w / w.sum()
+
+
+CLASS_NAMES = ("draw", "key", "alu", "imm", "index", "mem", "branch", "timer", "rnd", "misc")
+
+
+def _enc(op: int) -> List[int]:
+    return [(op >> 8) & 0xFF, op & 0xFF]
+
+
+def gen_rom(seed: int, n_instr: int, mix: OpcodeMix = OpcodeMix(),
+            action_keys: Sequence[int] = KEYS_5) -> bytes:
+    """Draw one CHIP-8 program of ``n_instr`` two-byte instructions.
+
+    Slot ``n_instr - 1`` is a jump back to 0x200 so the program is a main
+    loop.  Jump and call targets are even addresses inside the program.  Some
+    classes emit a short prologue in front of the drawn instruction (a key
+    value loaded before a key test, a data-area pointer before a store, edge
+    coordinates before a draw), as game code does.  Prologues count against
+    the instruction budget, so the realised mix is close to, not exactly, the
+    weights.
+    """
+    if not (2 <= n_instr <= MAX_PROGRAM_INSTRUCTIONS):
+        raise ValueError(f"n_instr must be in [2, {MAX_PROGRAM_INSTRUCTIONS}]")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = mix.weights()
+    end = PROGRAM_START + 2 * (n_instr - 1)       # address of the final jump
+    ops: List[int] = []
+
+    def r(n):  # uniform int in [0, n)
+        return int(rng.integers(0, n))
+
+    def target():
+        return PROGRAM_START + 2 * r(n_instr)
+
+    def data_pointer():
+        c = r(3)
+        if c == 0:
+            return FONT_START + 5 * r(16)
+        if c == 1:
+            return PROGRAM_START + r(2 * n_instr)
+        return SCRATCH_START + r(SCRATCH_END - SCRATCH_START - 16)
+
+    budget = n_instr - 1
+    while len(ops) < budget:
+        room = budget - len(ops)
+        cls = CLASS_NAMES[int(rng.choice(len(w), p=w))]
+        x, y, nn = r(16), r(16), r(256)
+        seq: List[int]
+        if cls == "draw":
+            n = int(rng.integers(mix.draw_n_min, mix.draw_n_max + 1))
+            seq = []
+            if mix.edge_bias and room >= 3:
+                seq.append(0x6000 | (x << 8) | int(rng.integers(56, 71)))
+                seq.append(0x6000 | (y << 8) | int(rng.integers(24, 37)))
+            seq.append(0xD000 | (x << 8) | (y << 4) | n)
+        elif cls == "key":
+            seq = []
+            if room >= 2 and r(2):
+                seq.append(0x6000 | (x << 8) | int(action_keys[r(len(action_keys))]))
+            seq.append(0xE000 | (x << 8) | (0x9E if r(2) else 0xA1))
+        elif cls == "alu":
+            n = (0, 1, 2, 3, 4, 5, 6, 7, 0xE)[r(9)]
+            seq = [0x8000 | (x << 8) | (y << 4) | n]
+        elif cls == "imm":
+            seq = [(0x6000 if r(2) else 0x7000) | (x << 8) | nn]
+        elif cls == "index":
+            c = r(3)
+            if c == 0:
+                seq = [0xA000 | data_pointer()]
+            elif c == 1:
+                seq = [0xF01E | (x << 8)]
+            else:
+                seq = [0xF029 | (x << 8)]
+        elif cls == "mem":
+            low = (0x33, 0x55, 0x65)[r(3)]
+            seq = []
+            if low != 0x65 and room >= 2 and r(4) != 0:
+                seq.append(0xA000 | (SCRATCH_START + r(SCRATCH_END - SCRATCH_START - 16)))
+            seq.append(0xF000 | (x << 8) | low)
+        elif cls == "branch":
+            c = r(8)
+            if c == 0:
+                seq = [0x1000 | target()]
+            elif c == 1:
+                seq = [0x2000 | target()]
+            elif c == 2:
+                seq = [0x00EE]
+            elif c == 3:
+                seq = [0x3000 | (x << 8) | nn]
+            elif c == 4:
+                seq = [0x4000 | (x << 8) | nn]
+            elif c == 5:
+                seq = [0x5000 | (x << 8) | (y << 4)]
+            elif c == 6:
+                seq = [0x9000 | (x << 8) | (y << 4)]
+            else:
+                seq = [0xB000 | (target() & 0xFFF)]
+        elif cls == "timer":
+            seq = [0xF000 | (x << 8) | (0x07, 0x15, 0x18)[r(3)]]
+        elif cls == "rnd":
+            seq = [0xC000 | (x << 8) | nn]
+        else:
+            seq = [0x00E0] if r(2) else [0xF00A | (x << 8)]
+        ops.extend(seq[:room])
+    ops.append(0x1000 | PROGRAM_START)
+    assert len(ops) == n_instr
+    out = bytearray()
+    for op in ops:
+        out += bytes(_enc(op))
+    assert PROGRAM_START + len(out) <= MEMORY_SIZE and end == PROGRAM_START + len(out) - 2
+    return bytes(out)
+
+
+def opcode_class(op: int) -> str:
+    """Classify one opcode into the generator's classes (for mix checks)."""
+    hi = op >> 12
+    low = op & 0xFF
+    if hi == 0xD:
+        return "draw"
+    if hi == 0xE:
+        return "key"
+    if hi == 0x8:
+        return "alu"
+    if hi in (0x6, 0x7):
+        return "imm"
+    if hi == 0xA or (hi == 0xF and low in (0x1E, 0x29)):
+        return "index"
+    if hi == 0xF and low in (0x33, 0x55, 0x65):
+        return "mem"
+    if hi in (0x1, 0x2, 0x3, 0x4, 0x5, 0x9, 0xB) or op == 0x00EE:
+        return "branch"
+    if hi == 0xF and low in (0x07, 0x15, 0x18):
+        return "timer"
+    if hi == 0xC:
+        return "rnd"
+    return "misc"
+
+
+@dataclasses.dataclass
+class EnvSpec:
+    """Everything an engine needs to be created, as plain numpy arrays."""
+
+    name: str
+    roms: List[bytes]
+    env_rom: np.ndarray          # uint16 [E]
+    action_keys: np.ndarray      # uint8  [R, 16]
+    num_actions: np.ndarray      # uint8  [R]
+    score_reg: np.ndarray        # uint8  [R]
+    term_reg: np.ndarray         # uint8  [R]
+    term_value: np.ndarray       # uint8  [R]
+    horizon: np.ndarray          # uint32 [E], 0 = no truncation
+    env_seed: np.ndarray         # uint64 [E]
+    instr_per_frame: int
+    frame_skip: int
+    steps: int                   # length of the workload's run
+    action_seed: int
+
+    @property
+    def num_envs(self) -> int:
+        return int(self.env_rom.shape[0])
+
+    @property
+    def num_roms(self) -> int:
+        return len(self.roms)
+
+    def actions(self, step0: int, count: int) -> np.ndarray:
+        """Actions for steps [step0, step0+count) as int32 [count, E].
+
+        Each env draws uniformly over its ROM's key actions (0..K-1; the
+        no-op index K is never drawn).  Step s is generated from its own
+        seeded stream so any window can be produced without the ones before.
+        """
+        k = self.num_actions[self.env_rom].astype(np.int64)
+        out = np.empty((count, self.num_envs), dtype=np.int32)
+        for i in range(count):
+            g = np.random.Generator(np.random.PCG64([self.action_seed, step0 + i]))
+            out[i] = (g.integers(0, 1 << 30, size=self.num_envs) % k).astype(np.int32)
+        return out
+
+    def subset(self, envs: np.ndarray, name: Optional[str] = None) -> "EnvSpec":
+        """The same workload restricted to the listed env indices."""
+        envs = np.asarray(envs, dtype=np.int64)
+        return dataclasses.replace(
+            self, name=name or f"{self.name}[subset {len(envs)}]",
+            env_rom=self.env_rom[envs].copy(), horizon=self.horizon[envs].copy(),
+            env_seed=self.env_seed[envs].copy())
+
+
+def _descriptors(n_roms: int, keys: Sequence[Sequence[int]]):
+    action_keys = np.zeros((n_roms, 16), dtype=np.uint8)
+    num_actions = np.zeros(n_roms, dtype=np.uint8)
+    for r_, ks in enumerate(keys):
+        action_keys[r_, :len(ks)] = ks
+        num_actions[r_] = len(ks)
+    score_reg = np.full(n_roms, 5, dtype=np.uint8)     # reward = delta of V5
+    term_reg = np.full(n_roms, 6, dtype=np.uint8)      # done when V6 == 0xFF
+    term_value = np.full(n_roms, 0xFF, dtype=np.uint8)
+    return action_keys, num_actions, score_reg, term_reg, term_value
+
+
+def geometric_horizons(rng: np.random.Generator, n: int, mean: float) -> np.ndarray:
+    return rng.geometric(1.0 / mean, size=n).astype(np.uint32)
+
+
+def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] = None) -> EnvSpec:
+    """Named workloads.
+
+    ``c1``  16 envs, one 256-instruction ROM, 5 keys, ipf 10, horizon 1000.
+    ``c2``  4,096 envs, one 1,024-instruction ROM, 8 keys, ipf 10, horizon 1000.
+    ``c3``  65,536 envs over 16 ROMs of 256..1792 instructions with varying
+            draw and branch shares, geometric horizons (mean 500), ipf 10.
+    ``c4``  the 32-ROM pool used by the serving loop (groups are drawn by the
+            serving module); here E is a placeholder of one env per ROM.
+    ``c5``  1,048,576 envs over 64 draw-heavy ROMs (40% DXYN, N up to 15,
+            edge-biased coordinates), ipf 20, geometric horizons.
+    ``num_envs`` and ``steps`` override the sizes (for tests at small scale).
+    """
+    name = name.lower()
+    if name == "c1":
+        seed, E, R, L, keys, ipf, steps_ = 0, 16, 1, (256,), KEYS_5, 10, 1000
+    elif name == "c2":
+        seed, E, R, L, keys, ipf, steps_ = 1, 4096, 1, (1024,), KEYS_8, 10, 10000
+    elif name == "c3":
+        seed, E, R, L, keys, ipf, steps_ = 2, 65536, 16, None, KEYS_8, 10, 64
+    elif name == "c4":
+        seed, E, R, L, keys, ipf, steps_ = 3, 32, 32, None, KEYS_8, 10, 200
+    elif name == "c5":
+        seed, E, R, L, keys, ipf, steps_ = 4, 1 << 20, 64, None, KEYS_8, 20, 1000
+    else:
+        raise KeyError(name)
+    if num_envs is not None:
+        E = int(num_envs)
+    if steps is not None:
+        steps_ = int(steps)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    roms: List[bytes] = []
+    for r_ in range(R):
+        if L is not None:
+            n, mix = L[r_], OpcodeMix()
+        elif name == "c5":
+            n = int(rng.integers(256, MAX_PROGRAM_INSTRUCTIONS + 1))
+            mix = OpcodeMix(draw=0.40, key=0.06, alu=0.15, imm=0.12, index=0.10, mem=0.04,
+                            branch=0.08, timer=0.03, rnd=0.02, draw_n_max=15, edge_bias=True)
+        else:
+            n = int(rng.integers(256, MAX_PROGRAM_INSTRUCTIONS + 1))
+            draw = float(rng.uniform(0.05, 0.40))
+            branch = float(rng.uniform(0.10, 0.30))
+            rest = 1.0 - draw - branch
+            base = OpcodeMix()
+            others = np.array([base.key, base.alu, base.imm, base.index, base.mem,
+                               base.timer, base.rnd, base.misc])
+            others = others / others.sum() * rest
+            mix = OpcodeMix(draw, *others[:5], branch, *others[5:])
+        roms.append(gen_rom(seed * 1000 + r_, n, mix, keys))
+    if R == 1:
+        env_rom = np.zeros(E, dtype=np.uint16)
+    else:
+        # Every ROM gets E/R envs (rounded), in a random order so ROMs mix
+        # within every wavefront of consecutive envs.
+        env_rom = (np.arange(E) % R).astype(np.uint16)
+        env_rom = env_rom[rng.permutation(E)]
+    akeys, nact, sreg, treg, tval = _descriptors(R, [keys] * R)
+    if name in ("c1", "c2"):
+        horizon = np.full(E, 1000, dtype=np.uint32)
+    else:
+        horizon = geometric_horizons(rng, E, 500.0)
+    env_seed = rng.integers(0, np.iinfo(np.uint64).max, size=E, dtype=np.uint64, endpoint=True)
+    return EnvSpec(name=name, roms=roms, env_rom=env_rom, action_keys=akeys, num_actions=nact,
+                   score_reg=sreg, term_reg=treg, term_value=tval, horizon=horizon,
+                   env_seed=env_seed, instr_per_frame=ipf, frame_skip=4, steps=steps_,
+                   action_seed=seed + 7919)
+
+
+def custom_spec(roms: Sequence[bytes], num_envs: int = 1, *, keys: Sequence[int] = KEYS_5,
+                instr_per_frame: int = 10, frame_skip: int = 4, horizon: int = 0,
+                seed: int = 0, env_rom: Optional[np.ndarray] = None,
+                score_reg: int = 5, term_reg: int = 6, term_value: int = 0xFF,
+                name: str = "custom") -> EnvSpec:
+    """A spec around explicit ROM bytes (hand-assembled test programs)."""
+    R = len(roms)
+    if env_rom is None:
+        env_rom = (np.arange(num_envs) % R).astype(np.uint16)
+    akeys, nact, sreg, treg, tval = _descriptors(R, [keys] * R)
+    sreg[:] = score_reg
+    treg[:] = term_reg
+    tval[:] = term_value
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return EnvSpec(name=name, roms=list(roms), env_rom=np.asarray(env_rom, dtype=np.uint16),
+                   action_keys=akeys, num_actions=nact, score_reg=sreg, term_reg=treg,
+                   term_value=tval, horizon=np.full(num_envs, horizon, dtype=np.uint32),
+                   env_seed=rng.integers(0, np.iinfo(np.uint64).max, size=num_envs,
+                                         dtype=np.uint64, endpoint=True),
+                   instr_per_frame=instr_per_frame, frame_skip=frame_skip, steps=0,
+                   action_seed=seed + 7919)
+
+
+def assemble(words: Sequence[int]) -> bytes:
+    """Big-endian bytes of a list of 16-bit opcodes (hand-assembled programs)."""
+    out = bytearray()
+    for wd in words:
+        if not 0 <= wd <= 0xFFFF:
+            raise ValueError(hex(wd))
+        out += bytes(_enc(wd))
+    return bytes(out)
+
+
+@dataclasses.dataclass
+class Group:
+    """One serving request: a group of envs of one ROM run for ``steps`` steps."""
+
+    gid: int
+    arrival: float
+    rom: int
+    size: int
+    steps: int
+    seed: int
+
+
+def serving_groups(n_groups: int, rate: float, seed: int = 3, n_roms: int = 32,
+                   max_size: int = 4096, min_steps: int = 200, max_steps: int = 2000) -> List[Group]:
+    """Poisson arrivals (``rate`` groups/s) of groups with log-uniform sizes in 1..max_size."""
+    rng = np.random.Generator(np.random.PCG64([seed, 1]))
+    t = 0.0
+    out = []
+    for g in range(n_groups):
+        t += float(rng.exponential(1.0 / rate)) if rate > 0 else 0.0
+        size = int(math.floor(math.exp(rng.uniform(0.0, math.log(max_size + 1)))))
+        size = max(1, min(max_size, size))
+        steps = int(rng.integers(min_steps, max_steps + 1))
+        out.append(Group(gid=g, arrival=t, rom=int(rng.integers(0, n_roms)), size=size,
+                         steps=steps, seed=int(rng.integers(0, 1 << 62))))
+    return out
+
+
+def group_env_seeds(group: Group) -> np.ndarray:
+    """Per-env RNG seeds of a serving group: a function of the group only, never of its slots."""
+    g = np.random.Generator(np.random.PCG64([group.seed, 2]))
+    return g.integers(0, np.iinfo(np.uint64).max, size=group.size, dtype=np.uint64, endpoint=True)
+
+
+def group_actions(group: Group, step0: int, count: int, num_actions: int) -> np.ndarray:
+    out = np.empty((count, group.size), dtype=np.int32)
+    for i in range(count):
+        g = np.random.Generator(np.random.PCG64([group.seed, 3, step0 + i]))
+        out[i] = (g.integers(0, 1 << 30, size=group.size) % num_actions).astype(np.int32)
+    return out
+
+
+def group_horizons(group: Group, mean: float = 500.0) -> np.ndarray:
+    g = np.random.Generator(np.random.PCG64([group.seed, 4]))
+    return geometric_horizons(g, group.size, mean)
+
+
+def mix_summary(rom: bytes) -> Dict[str, float]:
+    """Fraction of each generator class among the ROM's instructions."""
+    ops = [(rom[i] << 8) | rom[i + 1] for i in range(0, len(rom), 2)]
+    counts = {c: 0 for c in CLASS_NAMES}
+    for op in ops:
+        counts[opcode_class(op)] += 1
+    return {c: v / len(ops) for c, v in counts.items()}

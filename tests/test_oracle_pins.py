@@ -1,0 +1,429 @@
+"""Pins of the CPU oracle against facts fixed outside the oracle itself.
+
+Each test checks the oracle against something it cannot supply: hand-worked
+programs (tests/golden/programs.ini), the digit pictures of the font, the
+published SplitMix64 outputs, closed forms over every operand pair, and an
+independent numpy rasteriser for sprite drawing.  A slip anywhere in the
+interpreter (a dropped flag, a wrong nibble, a swapped operand, an off-by-one
+in clipping) fails at least one of them.
+"""
+import numpy as np
+import pytest
+
+from tests import golden_util as G
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+# --------------------------------------------------------------------------
+# Hand-assembled programs
+# --------------------------------------------------------------------------
+
+def _run_machine_program(oracle_mod, sec):
+    m = oracle_mod.Machine(G.program_bytes(sec))
+    init = G.parse_assignments(sec.get("init", ""))
+    s = m.state()
+    for k, v in init.items():
+        if k == "PC":
+            s["pc"] = v
+        elif k == "I":
+            s["i"] = v
+        elif k.startswith("V"):
+            s["v"][int(k[1:], 16)] = v
+        elif k.startswith("M"):
+            s["mem"][int(k[1:], 16)] = v
+        else:
+            raise KeyError(k)
+    m.set_state(s)
+    key = int(sec.get("key", "-1"))
+    for tok in sec.get("seq", "r1").split():
+        n = int(tok[1:])
+        if tok[0] == "r":
+            m.execute(n, key)
+        else:
+            m.tick(n)
+    return m.state()
+
+
+@pytest.mark.parametrize("name,sec", G.machine_programs(), ids=[n for n, _ in G.machine_programs()])
+def test_hand_assembled_program(oracle_mod, name, sec):
+    s = _run_machine_program(oracle_mod, sec)
+    for k, v in G.parse_assignments(sec.get("expect", "")).items():
+        if k == "PC":
+            got = int(s["pc"])
+        elif k == "I":
+            got = int(s["i"])
+        elif k == "SP":
+            got = int(s["sp"])
+        elif k == "DT":
+            got = int(s["dt"])
+        elif k == "ST":
+            got = int(s["st"])
+        elif k.startswith("V"):
+            got = int(s["v"][int(k[1:], 16)])
+        elif k.startswith("S"):
+            got = int(s["stack"][int(k[1:])])
+        elif k.startswith("M"):
+            got = int(s["mem"][int(k[1:], 16)])
+        else:
+            raise KeyError(k)
+        assert got == v, f"{name}: {k} = {got:#x}, expected {v:#x} ({sec['cite']})"
+    if "pixels" in sec:
+        assert G.lit_pixels(s["disp"]) == G.parse_pixels(sec["pixels"]), name
+
+
+# --------------------------------------------------------------------------
+# Font and RNG
+# --------------------------------------------------------------------------
+
+def test_font_bytes_match_digit_pictures(oracle_mod):
+    glyphs = G.font_glyphs()
+    mem = oracle_mod.blank_state()["mem"]
+    for d in range(16):
+        assert list(mem[0x50 + 5 * d: 0x55 + 5 * d]) == glyphs[d], f"glyph {d:X}"
+    # nothing else below 0x200 is set at power-on
+    assert not mem[:0x50].any() and not mem[0xA0:0x200].any()
+
+
+def test_font_glyphs_render_as_pictures(oracle_mod):
+    """FX29 then DXY5 at (0,0) lights exactly the pixels of the digit's picture."""
+    glyphs = G.font_glyphs()
+    for d in range(16):
+        rom = bytes([0x60, d, 0xF0, 0x29, 0x61, 0x00, 0xD1, 0x15])   # V0=d; I=glyph; V1=0; DRW V1,V1,5
+        m = oracle_mod.Machine(rom)
+        m.execute(4)
+        want = {(c, r) for r in range(5) for c in range(4) if glyphs[d][r] & (0x80 >> c)}
+        assert G.lit_pixels(m.state()["disp"]) == want, f"glyph {d:X}"
+
+
+def test_splitmix64_published_vectors(oracle_mod):
+    for seed, outs in G.splitmix_vectors().items():
+        assert oracle_mod.splitmix64(seed, len(outs)) == outs
+
+
+def test_rnd_takes_top_byte_and_masks(oracle_mod):
+    seeds = np.array([0, 1234567, 0xDEADBEEF, 2 ** 63 + 5], dtype=np.uint64)
+    vec = G.splitmix_vectors()
+    tops = {0: vec[0][0] >> 56, 1234567: vec[1234567][0] >> 56}
+    for nn in (0xFF, 0x0F, 0xA5, 0x00):
+        v, _, _, _ = oracle_mod.execute_batch(0xC300 | nn, np.zeros((4, 16), np.uint8), rng=seeds)
+        assert v[0, 3] == tops[0] & nn
+        assert v[1, 3] == tops[1234567] & nn
+
+
+# --------------------------------------------------------------------------
+# Closed forms over every operand pair
+# --------------------------------------------------------------------------
+
+def _all_pairs(x, y):
+    a = np.repeat(np.arange(256, dtype=np.int64), 256)
+    b = np.tile(np.arange(256, dtype=np.int64), 256)
+    v = np.zeros((65536, 16), dtype=np.uint8)
+    v[:, 7] = 0x5A                      # a bystander register
+    v[:, x] = a
+    v[:, y] = b
+    if x == y:
+        a = b          # one register holds both operands
+    return v, a, b
+
+
+ALU_CASES = [
+    # (n, result(vx, vy), flag(vx, vy) or None = cleared, or "keep")
+    (0x0, lambda a, b: b, "keep"),
+    (0x1, lambda a, b: a | b, 0),
+    (0x2, lambda a, b: a & b, 0),
+    (0x3, lambda a, b: a ^ b, 0),
+    (0x4, lambda a, b: (a + b) % 256, lambda a, b: (a + b >= 256).astype(np.int64)),
+    (0x5, lambda a, b: (a - b) % 256, lambda a, b: (a >= b).astype(np.int64)),
+    (0x6, lambda a, b: b // 2, lambda a, b: b % 2),
+    (0x7, lambda a, b: (b - a) % 256, lambda a, b: (b >= a).astype(np.int64)),
+    (0xE, lambda a, b: (b * 2) % 256, lambda a, b: b // 128),
+]
+
+
+@pytest.mark.parametrize("n,res,flag", ALU_CASES, ids=[f"8XY{c[0]:X}" for c in ALU_CASES])
+@pytest.mark.parametrize("x,y", [(0, 1), (3, 3), (0xE, 0x2)])
+def test_alu_all_pairs(oracle_mod, n, res, flag, x, y):
+    v, a, b = _all_pairs(x, y)
+    out, i, pc, _ = oracle_mod.execute_batch(0x8000 | (x << 8) | (y << 4) | n, v)
+    assert (out[:, x] == res(a, b)).all()
+    if flag == "keep":
+        assert (out[:, 0xF] == 0).all()
+    elif isinstance(flag, int):
+        assert (out[:, 0xF] == flag).all()
+    else:
+        assert (out[:, 0xF] == flag(a, b)).all()
+    assert (out[:, 7] == 0x5A).all() and (pc == 0x202).all() and (i == 0).all()
+
+
+@pytest.mark.parametrize("n,res,flag", [c for c in ALU_CASES if c[2] not in ("keep", 0)],
+                         ids=[f"8FY{c[0]:X}" for c in ALU_CASES if c[2] not in ("keep", 0)])
+def test_alu_flag_overrides_result_when_x_is_f(oracle_mod, n, res, flag):
+    """With VF as the destination the flag is written after the result."""
+    v, a, b = _all_pairs(0xF, 0x1)
+    out, _, _, _ = oracle_mod.execute_batch(0x8F10 | n, v)
+    assert (out[:, 0xF] == flag(a, b)).all()
+
+
+def test_alu_named_cases(oracle_mod):
+    cases = [(0x8014, 200, 100, 44, 1), (0x8015, 20, 10, 10, 1), (0x8015, 10, 20, 246, 0),
+             (0x8015, 7, 7, 0, 1), (0x8017, 10, 20, 10, 1)]
+    for op, a, b, r, f in cases:
+        v = np.zeros((1, 16), np.uint8)
+        v[0, 0], v[0, 1] = a, b
+        out, _, _, _ = oracle_mod.execute_batch(op, v)
+        assert (out[0, 0], out[0, 15]) == (r, f), hex(op)
+
+
+def test_immediates_all_values(oracle_mod):
+    base = np.arange(256, dtype=np.int64)
+    for nn in (0, 1, 0x7F, 0x80, 0xFF):
+        v = np.zeros((256, 16), np.uint8)
+        v[:, 4] = base
+        v[:, 0xF] = 9
+        out6, _, _, _ = oracle_mod.execute_batch(0x6400 | nn, v)
+        out7, _, _, _ = oracle_mod.execute_batch(0x7400 | nn, v)
+        assert (out6[:, 4] == nn).all()
+        assert (out7[:, 4] == (base + nn) % 256).all() and (out7[:, 0xF] == 9).all()
+
+
+def test_bcd_all_values(oracle_mod):
+    v = np.zeros((256, 16), np.uint8)
+    v[:, 5] = np.arange(256)
+    i = np.full(256, 0x300, np.uint16)
+    out, iout, _, mem = oracle_mod.execute_batch(0xF533, v, i=i, want_mem=True)
+    vals = np.arange(256)
+    assert (mem[:, 0x300] == vals // 100).all()
+    assert (mem[:, 0x301] == (vals // 10) % 10).all()
+    assert (mem[:, 0x302] == vals % 10).all()
+    assert (iout == 0x300).all()
+    assert list(mem[255, 0x300:0x303]) == [2, 5, 5]
+
+
+def test_skips_truth_tables(oracle_mod):
+    vals = np.arange(256)
+    v = np.zeros((256, 16), np.uint8)
+    v[:, 2] = vals
+    v[:, 3] = 0x40
+    for op, want in [(0x3240, vals == 0x40), (0x4240, vals != 0x40),
+                     (0x5230, vals == 0x40), (0x9230, vals != 0x40)]:
+        _, _, pc, _ = oracle_mod.execute_batch(op, v)
+        assert (pc == np.where(want, 0x204, 0x202)).all(), hex(op)
+    # key skips: every (VX, held key) combination, plus no key
+    v = np.zeros((256, 16), np.uint8)
+    v[:, 2] = vals
+    for key in list(range(16)) + [-1]:
+        held = (vals % 16 == key) if key >= 0 else np.zeros(256, bool)
+        _, _, pc9e, _ = oracle_mod.execute_batch(0xE29E, v, key=key)
+        _, _, pca1, _ = oracle_mod.execute_batch(0xE2A1, v, key=key)
+        assert (pc9e == np.where(held, 0x204, 0x202)).all()
+        assert (pca1 == np.where(held, 0x202, 0x204)).all()
+
+
+def test_store_load_every_x(oracle_mod):
+    rng = np.random.default_rng(5)
+    for x in range(16):
+        v = rng.integers(0, 256, size=(64, 16)).astype(np.uint8)
+        i = rng.integers(0, 4096, size=64).astype(np.uint16)
+        i[:32] = rng.integers(0x300, 0xFF0, size=32)      # away from the opcode at 0x200
+        out, iout, _, mem = oracle_mod.execute_batch(0xF055 | (x << 8), v, i=i, want_mem=True)
+        assert (iout == (i.astype(np.int64) + x + 1) % 4096).all()
+        assert (out == v).all()
+        for k in range(64):
+            addrs = (int(i[k]) + np.arange(x + 1)) % 4096
+            assert (mem[k, addrs] == v[k, :x + 1]).all()
+        # load the stored bytes back into cleared registers (FX65)
+        states = np.zeros(32, dtype=oracle_mod.STATE_DTYPE)
+        for k in range(32):
+            states[k]["mem"] = mem[k]
+            states[k]["mem"][0x200:0x202] = [0xF0 | x, 0x65]
+            states[k]["i"] = i[k]
+            states[k]["pc"] = 0x200
+        s2 = oracle_mod.execute_states(states, 1)
+        for k in range(32):
+            assert (s2[k]["v"][:x + 1] == v[k, :x + 1]).all()
+            assert (s2[k]["v"][x + 1:] == 0).all()
+            assert s2[k]["i"] == (int(i[k]) + x + 1) % 4096
+
+
+# --------------------------------------------------------------------------
+# Sprite drawing against an independent numpy rasteriser
+# --------------------------------------------------------------------------
+
+def _numpy_draw(disp, sprite, x0, y0):
+    """Reference XOR blit with clipping: returns (new display, collision)."""
+    n = len(sprite)
+    bits = np.unpackbits(np.asarray(sprite, dtype=np.uint8)[:, None], axis=1)  # [n, 8], MSB first
+    canvas = np.zeros((32 + 16, 64 + 8), dtype=np.uint8)
+    canvas[y0:y0 + n, x0:x0 + 8] = bits
+    mask = canvas[:32, :64]
+    collision = bool((disp & mask).any())
+    return disp ^ mask, collision
+
+
+def test_draw_matches_numpy_rasteriser_everywhere(oracle_mod):
+    rng = np.random.default_rng(11)
+    base = oracle_mod.blank_state(bytes([0xD0, 0x10]))
+    for n in range(1, 16):
+        states = np.zeros(64 * 32, dtype=oracle_mod.STATE_DTYPE)
+        sprites, disps = [], []
+        for k in range(64 * 32):
+            x0, y0 = k % 64, k // 64
+            s = base.copy()
+            sprite = rng.integers(0, 256, size=n).astype(np.uint8)
+            disp = (rng.random((32, 64)) < 0.3).astype(np.uint8)
+            addr = int(rng.integers(0x300, 0x1000 - 16))
+            s["mem"][addr:addr + n] = sprite
+            s["i"] = addr
+            s["mem"][0x200:0x202] = [0xD0, 0x10 | n]
+            # VX = x0 (+64 on odd rows to exercise start wrap), VY = y0 (+32 on odd columns)
+            s["v"][0] = x0 + (64 if y0 % 2 else 0)
+            s["v"][1] = y0 + (32 if x0 % 2 else 0)
+            s["disp"] = disp
+            states[k] = s
+            sprites.append(sprite)
+            disps.append(disp)
+        out = oracle_mod.execute_states(states, 1)
+        for k in range(64 * 32):
+            want, coll = _numpy_draw(disps[k], sprites[k], k % 64, k // 64)
+            assert (out[k]["disp"] == want).all(), (n, k % 64, k // 64)
+            assert out[k]["v"][0xF] == coll, (n, k % 64, k // 64)
+
+
+def test_draw_popcount_identity(oracle_mod):
+    """pop(after) = pop(before) + pop(drawn) - 2 * overlap; VF = overlap > 0."""
+    rng = np.random.default_rng(3)
+    base = oracle_mod.blank_state(bytes([0xD0, 0x1F]))
+    states = np.zeros(512, dtype=oracle_mod.STATE_DTYPE)
+    for k in range(512):
+        s = base.copy()
+        s["mem"][0x300:0x30F] = rng.integers(0, 256, size=15)
+        s["i"] = 0x300
+        s["v"][0], s["v"][1] = rng.integers(0, 256), rng.integers(0, 256)
+        s["disp"] = (rng.random((32, 64)) < 0.5).astype(np.uint8)
+        states[k] = s
+    out = oracle_mod.execute_states(states, 1)
+    for k in range(512):
+        before, after = states[k]["disp"].astype(int), out[k]["disp"].astype(int)
+        drawn = before ^ after                  # pixels the sprite touched
+        overlap = int((before & drawn).sum())   # touched pixels that were lit
+        assert after.sum() == before.sum() + drawn.sum() - 2 * overlap
+        assert out[k]["v"][0xF] == (overlap > 0)
+        # drawing again restores the display; it collides wherever the first draw lit a pixel
+        s3 = out[k].copy()
+        s3["pc"] = 0x200
+        back = oracle_mod.execute_states(np.array([s3]), 1)[0]
+        assert (back["disp"] == states[k]["disp"]).all()
+        assert back["v"][0xF] == ((after & drawn).sum() > 0)
+
+
+# --------------------------------------------------------------------------
+# Environment semantics on seed-generated programs
+# --------------------------------------------------------------------------
+
+def test_env_invariants_on_generated_roms(oracle_mod):
+    from paper_2510_01764_amd import workload as W
+    spec = W.make_config("c1", steps=300)
+    b = oracle_mod.OracleBatch(spec)
+    obs0 = b.reset()
+    assert not obs0.any()                           # reset obs: four blank frames
+    prev_obs = obs0
+    st_prev = b.get_state()
+    score_at_reset = st_prev["v"][:, 5].astype(np.int64)
+    ep_reward = np.zeros(spec.num_envs)
+    acts = spec.actions(0, 300)
+    for t in range(300):
+        obs, rew, done = b.step(acts[t])
+        st = b.get_state()
+        for e in range(spec.num_envs):
+            if done[e]:
+                # telescoping: the episode's rewards sum to V5(end) - V5(reset); the end value is gone
+                # after the auto-reset, so check the reset state and the reset observation instead.
+                assert st["t"][e] == 0 and st["pc"][e] == 0x200 and not obs[e].any()
+                assert st["prev_score"][e] == 0 and (st["v"][e] == 0).all()
+                ep_reward[e] = 0
+                continue
+            ep_reward[e] += rew[e]
+            assert ep_reward[e] == int(st["v"][e, 5]) - score_at_reset[e]
+            # rolling stack: the three older frames are the previous obs shifted by one
+            assert (obs[e, :3] == prev_obs[e, 1:]).all()
+            # frame 3 is the display, x-major
+            assert (obs[e, 3] == st["disp"][e].T).all()
+            assert st["t"][e] == st_prev["t"][e] + 1
+            assert (st["v"][e, 6] != 0xFF)
+        prev_obs = obs
+        st_prev = st
+    b.close()
+
+
+def test_env_determinism_and_independence(oracle_mod):
+    from paper_2510_01764_amd import workload as W
+    spec = W.make_config("c1", steps=50)
+    acts = spec.actions(0, 50)
+    a = oracle_mod.OracleBatch(spec)
+    perm = np.random.default_rng(0).permutation(spec.num_envs)
+    b = oracle_mod.OracleBatch(spec.subset(perm))
+    for t in range(50):
+        oa, ra, da = a.step(acts[t])
+        ob, rb, db = b.step(acts[t][perm])
+        assert (oa[perm] == ob).all() and (ra[perm] == rb).all() and (da[perm] == db).all()
+    sa, sb = a.get_state(), b.get_state()
+    assert (sa[perm] == sb).all()
+
+
+@pytest.mark.parametrize("name,sec", G.env_programs(), ids=[n for n, _ in G.env_programs()])
+def test_env_golden_program(oracle_mod, name, sec):
+    from paper_2510_01764_amd import workload as W
+    keys = [int(k) for k in sec.get("keys", "5 7 8 9 6").split()]
+    spec = W.custom_spec([G.program_bytes(sec)], 1, keys=keys, instr_per_frame=int(sec["ipf"]),
+                         frame_skip=int(sec["frame_skip"]), horizon=int(sec.get("horizon", "0")))
+    b = oracle_mod.OracleBatch(spec)
+    actions = G.expand(sec["actions"])
+    rewards, dones, dts, pops = [], [], [], []
+    obs_hist = []
+    for a in actions:
+        obs, r, d = b.step(np.array([a], np.int32))
+        rewards.append(float(r[0]))
+        dones.append(int(d[0]))
+        dts.append(int(b.get_state()["dt"][0]))
+        pops.append("/".join(str(int(obs[0, k].sum())) for k in range(4)))
+        obs_hist.append(obs[0])
+    if "rewards" in sec:
+        assert rewards == [float(v) for v in G.expand(sec["rewards"])], name
+    if "dones" in sec:
+        assert dones == G.expand(sec["dones"]), name
+    if "dt_after" in sec:
+        assert dts == G.expand(sec["dt_after"]), name
+    if "popcounts" in sec:
+        assert pops == sec["popcounts"].split(), name
+    for tok in sec.get("pixel", "").split():
+        where, val = tok.split("=")
+        step, frame, x, y = (int(c) for c in where.split(":"))
+        assert obs_hist[step - 1][frame, x, y] == int(val), (name, tok)
+    b.close()
+
+
+def test_generator_is_deterministic_and_in_range():
+    from paper_2510_01764_amd import workload as W
+    a = W.make_config("c3", num_envs=256)
+    b = W.make_config("c3", num_envs=256)
+    assert a.roms == b.roms and (a.env_rom == b.env_rom).all() and (a.env_seed == b.env_seed).all()
+    for rom in a.roms:
+        n = len(rom) // 2
+        assert 256 <= n <= W.MAX_PROGRAM_INSTRUCTIONS
+        assert rom[-2:] == bytes([0x12, 0x00])
+        for k in range(n):
+            op = (rom[2 * k] << 8) | rom[2 * k + 1]
+            if op >> 12 in (1, 2):
+                assert 0x200 <= (op & 0xFFF) < 0x200 + 2 * n and (op & 1) == 0
+
+
+def test_generator_mix_close_to_weights():
+    from paper_2510_01764_amd import workload as W
+    mix = W.OpcodeMix()
+    rom = W.gen_rom(123, 1792, mix)
+    got = W.mix_summary(rom)
+    w = dict(zip(W.CLASS_NAMES, mix.weights()))
+    # prologue instructions (6XNN before key tests, ANNN before stores) move a few percent to imm/index
+    for c in ("draw", "alu", "branch", "key", "mem"):
+        assert abs(got[c] - w[c]) < 0.03, (c, got[c], w[c])
