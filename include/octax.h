@@ -1,0 +1,265 @@
+/*
+ * octax.h - C ABI of the MI355X batched CHIP-8 environment library (liboctax.so).
+ *
+ * The library runs many independent CHIP-8 machines, each wrapped as a
+ * reinforcement-learning environment, on one AMD Instinct MI355X (gfx950).
+ * What one environment step computes follows the paper "Octax: Accelerated
+ * CHIP-8 Arcade Environments for Reinforcement Learning in JAX":
+ *   - Section 3.2 ("How does Octax work?"): programs loaded at 0x200 in a 4 KB
+ *     memory with the font at 0x50; a fetch-decode-execute cycle over the
+ *     35-instruction set; several instructions per 60 Hz frame; delay and
+ *     sound timers ticked once per frame; frame skip 4; a (4, 64, 32)
+ *     observation of the last four frames; actions mapped to a key subset
+ *     plus a no-op; functional state updates (state in, new state out).
+ *   - Section 3.3: reward from a score register, termination from a
+ *     register test.
+ *   - Section 3.4: Gymnax-compatible environments, i.e. automatic reset when
+ *     an episode ends, returning the observation of the reset state.
+ *   - Appendix B: memory map, registers, 64x32 XOR display with collision
+ *     flag, 16-key keypad, timers, 4x5 hex font at 0x050-0x09F.
+ * The paper does not print per-instruction semantics; the library fixes one
+ * documented profile, OCTAX_QUIRKS_V1:
+ *   8XY6/8XYE shift VY into VX (VF = bit shifted out); FX55/FX65 leave
+ *   I = I + X + 1; BNNN jumps to NNN + V0; 8XY1/8XY2/8XY3 clear VF; every
+ *   flag is written after the result; 8XY5/8XY7 set VF = 1 when there is
+ *   no borrow (equal operands included); DXYN starts at (VX mod 64,
+ *   VY mod 32), clips at the right and bottom edges and sets VF = 1 iff a
+ *   lit pixel was turned off (N = 0 draws nothing); the stack has 16
+ *   entries and its pointer wraps; I and PC are 12-bit; instruction words
+ *   not in the set do nothing; EX9E/EXA1 test key VX & 15; FX0A with no key
+ *   held repeats itself; CXNN = (top byte of the env's next SplitMix64
+ *   output) & NN.
+ *
+ * Environment step (per env): the action selects the held key for the whole
+ * step (0 <= a < num_actions: action_keys[rom][a]; any other value: no key);
+ * frame_skip frames of instr_per_frame instructions, each frame followed by a
+ * timer tick; the new frame joins the observation stack (oldest first, the
+ * current display last); reward = V[score_reg] - previous V[score_reg] as a
+ * float; terminated = (V[term_reg] == term_value); truncated = (steps since
+ * reset >= horizon, when horizon > 0); done = terminated | truncated << 1;
+ * on done the env is reset (its RNG stream is not reseeded) and the
+ * observation returned is that of the reset state.
+ *
+ * Conventions for every entry point:
+ *   - Return value: OCTAX_OK (0) or a negative OCTAX_E_* code; the message
+ *     of the last failure on the calling thread is octax_last_error().  An
+ *     argument error enqueues no GPU work.
+ *   - Pointers named d_* are device pointers on the engine's GPU, owned by
+ *     the caller, contiguous, with the layout given; h_* pointers are host
+ *     memory owned by the caller.  The engine owns its own device state.
+ *   - reset, step, step_many and graph launches are asynchronous on the
+ *     engine's stream; create, destroy, get_state and set_state synchronize.
+ *   - Every output is a pure function of the config and the call sequence;
+ *     it does not depend on the kernel, the tuning or the env placement.
+ *   - Observation layout: uint8 [E][4][64][32] = [env][frame][x][y], values
+ *     0/1, frame 3 the newest.
+ */
+#ifndef OCTAX_H
+#define OCTAX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OCTAX_ABI_VERSION 1u
+#define OCTAX_QUIRKS_V1 1u
+
+#define OCTAX_MAX_ROM_BYTES 3584u   /* 0x200..0xFFF */
+#define OCTAX_OBS_BYTES 8192u       /* 4 * 64 * 32 */
+
+enum octax_status {
+    OCTAX_OK = 0,
+    OCTAX_E_INVALID = -1, /* bad argument or config */
+    OCTAX_E_NOMEM = -2,   /* device or host allocation failed; pool full */
+    OCTAX_E_HIP = -3,     /* a HIP runtime call failed */
+    OCTAX_E_STATE = -4    /* call not valid in the engine's current state */
+};
+
+/* Step kernels. */
+enum octax_kernel {
+    OCTAX_KERNEL_PLAIN = 0, /* one env per lane, state through HBM every step */
+    OCTAX_KERNEL_FUSED = 1  /* K steps per launch, LDS-staged ROM and display, coalesced obs */
+};
+
+/* Placement of envs in the engine's state slots. */
+enum octax_placement {
+    OCTAX_PLACE_IDENTITY = 0, /* slot = env index */
+    OCTAX_PLACE_BY_ROM = 1    /* slots sorted by ROM id (stable), so workgroups share ROMs */
+};
+
+typedef struct octax_config {
+    uint32_t abi_version;      /* must be OCTAX_ABI_VERSION */
+    uint32_t num_envs;         /* E >= 1 */
+    uint32_t num_roms;         /* R >= 1 */
+    uint32_t instr_per_frame;  /* instructions per 60 Hz frame, 1..1000 */
+    uint32_t frame_skip;       /* frames per step, 1..64 (paper default 4) */
+    uint32_t quirks;           /* must be OCTAX_QUIRKS_V1 */
+    uint32_t kernel;           /* enum octax_kernel */
+    uint32_t placement;        /* enum octax_placement */
+    uint32_t envs_per_block;   /* fused kernel: envs per workgroup (0 = default) */
+    uint32_t lanes_per_env;    /* fused kernel: lanes per env; only 1 is implemented (0 = 1) */
+    uint32_t rom_in_lds;       /* fused kernel: 1 = stage ROM images in LDS, 0 = read through L2 */
+    uint32_t reserved;
+    /* host arrays, copied at create */
+    const uint8_t *h_rom_data;     /* concatenated ROM bytes */
+    const uint32_t *h_rom_offset;  /* [R] offset of ROM r in h_rom_data */
+    const uint32_t *h_rom_len;     /* [R] 0..OCTAX_MAX_ROM_BYTES */
+    const uint16_t *h_env_rom;     /* [E] ROM of each env, < R */
+    const uint8_t *h_action_keys;  /* [R][16] key of each action */
+    const uint8_t *h_num_actions;  /* [R] 0..16; action == num_actions is the no-op */
+    const uint8_t *h_score_reg;    /* [R] 0..15 */
+    const uint8_t *h_term_reg;     /* [R] 0..15 */
+    const uint8_t *h_term_value;   /* [R] */
+    const uint32_t *h_horizon;     /* [E] truncation horizon, 0 = none */
+    const uint64_t *h_env_seed;    /* [E] initial SplitMix64 state of each env */
+    void *stream;                  /* hipStream_t for all work; NULL = null stream */
+} octax_config;
+
+/* Architectural state of one env (get_state / set_state). */
+typedef struct octax_env_state {
+    uint8_t v[16];          /* V0..VF */
+    uint16_t i;             /* index register, 12-bit */
+    uint16_t pc;            /* program counter, 12-bit */
+    uint8_t sp;             /* stack pointer 0..15 */
+    uint8_t dt;             /* delay timer */
+    uint8_t st;             /* sound timer */
+    uint8_t reserved;
+    uint16_t stack[16];     /* return addresses */
+    uint32_t t;             /* steps since the last reset */
+    int32_t prev_score;     /* V[score_reg] after the previous step */
+    uint64_t rng;           /* SplitMix64 state */
+    uint8_t ram[4096];      /* memory */
+    uint64_t fb[32];        /* display row y: bit (63 - x) is pixel (x, y) */
+    uint64_t hist[3][32];   /* the three frames before fb, oldest first, same packing */
+} octax_env_state;
+
+typedef struct octax_engine octax_engine;
+typedef struct octax_graph octax_graph;
+
+/*
+ * Create an engine: validates cfg, allocates the state of E envs in device
+ * memory (about 5.6 KB per env), copies the ROM images and descriptors and
+ * resets every env (Section 3.2, ROM loading and initialization).  On
+ * success *out owns the engine; on failure *out is NULL and nothing leaks.
+ * Errors: OCTAX_E_INVALID (any field out of range, ROM too long, env_rom
+ * >= R, wrong abi_version or quirks), OCTAX_E_NOMEM, OCTAX_E_HIP.
+ */
+int32_t octax_create(const octax_config *cfg, octax_engine **out);
+
+/*
+ * Reset the envs whose d_mask byte is non-zero (all envs when d_mask is
+ * NULL) to the power-on state of their ROM (Section 3.2, ROM loading and
+ * initialization): memory = font + program, registers, I, stack and timers
+ * zero, PC = 0x200, display and frame stack blank, step count zero.  Each
+ * env's RNG stream continues.  If d_obs is not NULL the observation of every
+ * env (reset or not) is written to d_obs [E][4][64][32].
+ * d_mask: device uint8 [E] or NULL.  Errors: OCTAX_E_INVALID (NULL engine),
+ * OCTAX_E_HIP.
+ */
+int32_t octax_reset(octax_engine *eng, const uint8_t *d_mask, uint8_t *d_obs);
+
+/*
+ * One environment step of every env (Section 3.2, Environment integration;
+ * Section 3.3 reward and termination; Section 3.4 automatic reset).
+ * d_action: device int32 [E]; out-of-range values are the no-op.
+ * d_obs: device uint8 [E][4][64][32] (may be NULL: not written).
+ * d_reward: device float [E]; d_done: device uint8 [E], bit 0 terminated,
+ * bit 1 truncated.  Errors: OCTAX_E_INVALID (NULL engine/action/reward/done),
+ * OCTAX_E_HIP.
+ */
+int32_t octax_step(octax_engine *eng, const int32_t *d_action, uint8_t *d_obs,
+                   float *d_reward, uint8_t *d_done);
+
+/*
+ * K consecutive environment steps in one launch (the same semantics as K
+ * octax_step calls).  d_action: device int32 [K][E]; d_reward: float [K][E];
+ * d_done: uint8 [K][E]; d_obs: uint8 [obs_slots][E][4][64][32] where step k
+ * writes slot k % obs_slots (obs_slots = K keeps the whole rollout,
+ * obs_slots = 1 keeps the last), or NULL.
+ * Errors: OCTAX_E_INVALID (K == 0, obs_slots == 0 with d_obs, NULL
+ * arguments), OCTAX_E_HIP.
+ */
+int32_t octax_step_many(octax_engine *eng, uint32_t K, const int32_t *d_action,
+                        uint8_t *d_obs, uint32_t obs_slots, float *d_reward, uint8_t *d_done);
+
+/*
+ * Capture octax_step_many(eng, K, d_action, d_obs, obs_slots, d_reward,
+ * d_done) into a HIP graph with these fixed buffers.  Each
+ * octax_graph_launch replays it on the engine's stream: the caller rewrites
+ * d_action between replays and reads the outputs after them.  The graph
+ * holds the engine; destroy graphs before their engine.
+ * Errors: as octax_step_many, plus OCTAX_E_HIP if capture fails.
+ */
+int32_t octax_graph_create(octax_engine *eng, uint32_t K, const int32_t *d_action,
+                           uint8_t *d_obs, uint32_t obs_slots, float *d_reward,
+                           uint8_t *d_done, octax_graph **out);
+int32_t octax_graph_launch(octax_graph *g);
+int32_t octax_graph_destroy(octax_graph *g);
+
+/*
+ * Copy the architectural state of envs [first, first+count) to h_out
+ * (count entries).  Synchronizes the engine's stream first.
+ * Errors: OCTAX_E_INVALID (range outside 0..E, NULL), OCTAX_E_HIP.
+ */
+int32_t octax_get_state(octax_engine *eng, uint32_t first, uint32_t count,
+                        octax_env_state *h_out);
+
+/*
+ * Overwrite the state of envs [first, first+count) from h_in (I, PC, stack
+ * entries masked to 12 bits, SP to 4 bits, display bits as given).  The
+ * next step continues from it exactly as from the state it was saved from.
+ * Errors: OCTAX_E_INVALID, OCTAX_E_HIP.
+ */
+int32_t octax_set_state(octax_engine *eng, uint32_t first, uint32_t count,
+                        const octax_env_state *h_in);
+
+/*
+ * Select the step kernel (enum octax_kernel) for subsequent calls; the
+ * state layout is the same for both, so results do not change.
+ * Errors: OCTAX_E_INVALID.
+ */
+int32_t octax_set_kernel(octax_engine *eng, uint32_t kernel);
+
+/*
+ * Fused-kernel tuning for subsequent calls: envs_per_block in {64, 128, 256},
+ * rom_in_lds 0/1 (stage the block's two most frequent ROM images in LDS).
+ * Results do not change.  Errors: OCTAX_E_INVALID.
+ */
+int32_t octax_set_tuning(octax_engine *eng, uint32_t envs_per_block, uint32_t rom_in_lds);
+
+/*
+ * Bind the engine to another stream (hipStream_t, NULL = null stream).
+ */
+int32_t octax_set_stream(octax_engine *eng, void *stream);
+
+/* Number of envs, and device bytes held by the engine. */
+int32_t octax_info(const octax_engine *eng, uint32_t *num_envs, uint64_t *device_bytes);
+
+/*
+ * Destroy an engine (synchronizes its stream, frees its device memory).
+ * NULL is accepted.  Errors: OCTAX_E_HIP.
+ */
+int32_t octax_destroy(octax_engine *eng);
+
+/*
+ * Roofline calibration (no part of the environment step): stream `bytes`
+ * (a multiple of 16) of the 32-bit value v into d_dst, or copy `bytes` from
+ * d_src to d_dst, asynchronously on `stream` (hipStream_t, NULL = null
+ * stream).  The measured rate of these kernels on the same device is the
+ * attainable HBM bandwidth the step kernels are compared with, and the copy
+ * kernel's hardware counters calibrate byte counters.  Returns 0, -1 for a
+ * bad argument, -3 if the launch failed.
+ */
+int32_t octax_calib_write(void *d_dst, uint64_t bytes, uint32_t v, void *stream);
+int32_t octax_calib_copy(const void *d_src, void *d_dst, uint64_t bytes, void *stream);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char *octax_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCTAX_H */

@@ -1,0 +1,39 @@
+// Roofline calibration kernels: a streaming HBM write of a known byte count
+// and a plain device copy, timed on the same device as the step kernels.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+extern "C" {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void octax_calib_write_kernel(u32x4 *dst, uint64_t n16, uint32_t v) {
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    const u32x4 val = {v, v, v, v};
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride)
+        __builtin_nontemporal_store(val, dst + i);
+}
+
+__global__ __launch_bounds__(256) void octax_calib_copy_kernel(const uint4 *src, uint4 *dst, uint64_t n16) {
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride)
+        dst[i] = src[i];
+}
+
+// Stream `bytes` (a multiple of 16) of the value v into d_dst.
+int32_t octax_calib_write(void *d_dst, uint64_t bytes, uint32_t v, void *stream) {
+    if (!d_dst || bytes % 16) return -1;
+    hipLaunchKernelGGL(octax_calib_write_kernel, dim3(256 * 8), dim3(256), 0, (hipStream_t)stream,
+                       (u32x4 *)d_dst, bytes / 16, v);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// Copy `bytes` (a multiple of 16) from d_src to d_dst.
+int32_t octax_calib_copy(const void *d_src, void *d_dst, uint64_t bytes, void *stream) {
+    if (!d_src || !d_dst || bytes % 16) return -1;
+    hipLaunchKernelGGL(octax_calib_copy_kernel, dim3(256 * 8), dim3(256), 0, (hipStream_t)stream,
+                       (const uint4 *)d_src, (uint4 *)d_dst, bytes / 16);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}

@@ -1,0 +1,198 @@
+// The CHIP-8 instruction cycle (Section 3.2: fetch a 16-bit word at PC and
+// advance PC, decode its nibbles, execute one of the 35 instructions) for one
+// machine held in registers.  Memory, display and stack live wherever the
+// kernel keeps them; a kernel supplies that through the `Mem` policy:
+//   uint32_t read(a)            byte at 12-bit address a
+//   void     write(a, v)        store byte (also marks its 64-byte page dirty)
+//   uint32_t draw(x0, y0, I, n) XOR an n-row sprite from memory at I onto the
+//                               display at (x0, y0), clipped; 1 on collision
+//   void     clear()            blank display
+//   uint32_t stack_get(i), void stack_set(i, v)
+// Semantics are those of the OCTAX_QUIRKS_V1 profile documented in octax.h.
+#pragma once
+
+#include "octax_device.h"
+
+namespace octax {
+
+struct Core {
+    Regs r;
+    uint32_t pc;   // 12-bit
+    uint32_t I;    // 12-bit
+    uint32_t sp;   // 0..15
+    uint32_t dt;
+    uint32_t st;
+    uint64_t rng;
+};
+
+__device__ __forceinline__ void skip(Core &c) { c.pc = (c.pc + 2) & 0xFFF; }
+
+template <class Mem>
+__device__ __forceinline__ void exec_one(Core &c, Mem &mem, uint32_t key) {
+    const uint32_t op = (mem.read(c.pc) << 8) | mem.read((c.pc + 1) & 0xFFF);
+    c.pc = (c.pc + 2) & 0xFFF;
+    const uint32_t x = (op >> 8) & 0xF;
+    const uint32_t y = (op >> 4) & 0xF;
+    const uint32_t n = op & 0xF;
+    const uint32_t nn = op & 0xFF;
+    const uint32_t nnn = op & 0xFFF;
+    const uint32_t vx = vget(c.r, x);
+    const uint32_t vy = vget(c.r, y);
+    switch (op >> 12) {
+    case 0x0:
+        if (op == 0x00E0) {
+            mem.clear();
+        } else if (op == 0x00EE) {
+            c.sp = (c.sp - 1) & 15;
+            c.pc = mem.stack_get(c.sp);
+        }
+        break;
+    case 0x1:
+        c.pc = nnn;
+        break;
+    case 0x2:
+        mem.stack_set(c.sp, c.pc);
+        c.sp = (c.sp + 1) & 15;
+        c.pc = nnn;
+        break;
+    case 0x3:
+        if (vx == nn) skip(c);
+        break;
+    case 0x4:
+        if (vx != nn) skip(c);
+        break;
+    case 0x5:
+        if (n == 0 && vx == vy) skip(c);
+        break;
+    case 0x6:
+        vset(c.r, x, nn);
+        break;
+    case 0x7:
+        vset(c.r, x, vx + nn);
+        break;
+    case 0x8: {
+        uint32_t res = 0, flag = 0;
+        bool write = true, has_flag = true;
+        switch (n) {
+        case 0x0: res = vy; has_flag = false; break;
+        case 0x1: res = vx | vy; flag = 0; break;
+        case 0x2: res = vx & vy; flag = 0; break;
+        case 0x3: res = vx ^ vy; flag = 0; break;
+        case 0x4: res = vx + vy; flag = res >> 8; break;
+        case 0x5: res = vx - vy; flag = vx >= vy; break;
+        case 0x6: res = vy >> 1; flag = vy & 1; break;
+        case 0x7: res = vy - vx; flag = vy >= vx; break;
+        case 0xE: res = vy << 1; flag = vy >> 7; break;
+        default: write = false; break;
+        }
+        if (write) {
+            vset(c.r, x, res);
+            if (has_flag) set_vf(c.r, flag);
+        }
+        break;
+    }
+    case 0x9:
+        if (n == 0 && vx != vy) skip(c);
+        break;
+    case 0xA:
+        c.I = nnn;
+        break;
+    case 0xB:
+        c.pc = (nnn + (c.r.w0 & 0xFF)) & 0xFFF;
+        break;
+    case 0xC:
+        vset(c.r, x, rnd_byte(c.rng) & nn);
+        break;
+    case 0xD:
+        set_vf(c.r, mem.draw(vx & 63, vy & 31, c.I, n));
+        break;
+    case 0xE:
+        if (nn == 0x9E) {
+            if (key == (vx & 15)) skip(c);
+        } else if (nn == 0xA1) {
+            if (key != (vx & 15)) skip(c);
+        }
+        break;
+    default:  // 0xF
+        switch (nn) {
+        case 0x07: vset(c.r, x, c.dt); break;
+        case 0x0A:
+            if (key < 16) vset(c.r, x, key);
+            else c.pc = (c.pc - 2) & 0xFFF;
+            break;
+        case 0x15: c.dt = vx; break;
+        case 0x18: c.st = vx; break;
+        case 0x1E: c.I = (c.I + vx) & 0xFFF; break;
+        case 0x29: c.I = kFont + 5 * (vx & 15); break;
+        case 0x33:
+            mem.write(c.I, vx / 100);
+            mem.write((c.I + 1) & 0xFFF, (vx / 10) % 10);
+            mem.write((c.I + 2) & 0xFFF, vx % 10);
+            break;
+        case 0x55:
+            for (uint32_t k = 0; k <= x; k++) mem.write((c.I + k) & 0xFFF, vget(c.r, k));
+            c.I = (c.I + x + 1) & 0xFFF;
+            break;
+        case 0x65:
+            for (uint32_t k = 0; k <= x; k++) vset(c.r, k, mem.read((c.I + k) & 0xFFF));
+            c.I = (c.I + x + 1) & 0xFFF;
+            break;
+        default: break;
+        }
+        break;
+    }
+}
+
+// One 60 Hz tick of the delay and sound timers.
+__device__ __forceinline__ void tick(Core &c) {
+    c.dt -= (c.dt > 0);
+    c.st -= (c.st > 0);
+}
+
+// Load / store the register part of an env's state from the SoA arrays.
+__device__ __forceinline__ void load_core(const State &s, uint32_t slot, Core &c, uint32_t &head) {
+    const uint32_t E = s.num;
+    c.r.w0 = s.regs[0 * E + slot];
+    c.r.w1 = s.regs[1 * E + slot];
+    c.r.w2 = s.regs[2 * E + slot];
+    c.r.w3 = s.regs[3 * E + slot];
+    const uint32_t pi = s.pc_i[slot];
+    c.pc = pi & 0xFFF;
+    c.I = (pi >> 16) & 0xFFF;
+    const uint32_t m = s.misc[slot];
+    c.sp = m & 15;
+    c.dt = (m >> 8) & 0xFF;
+    c.st = (m >> 16) & 0xFF;
+    head = (m >> 24) & 3;
+    c.rng = s.rng[slot];
+}
+
+__device__ __forceinline__ void store_core(const State &s, uint32_t slot, const Core &c, uint32_t head) {
+    const uint32_t E = s.num;
+    s.regs[0 * E + slot] = c.r.w0;
+    s.regs[1 * E + slot] = c.r.w1;
+    s.regs[2 * E + slot] = c.r.w2;
+    s.regs[3 * E + slot] = c.r.w3;
+    s.pc_i[slot] = c.pc | (c.I << 16);
+    s.misc[slot] = c.sp | (c.dt << 8) | (c.st << 16) | (head << 24);
+    s.rng[slot] = c.rng;
+}
+
+// Power-on registers (Section 3.2, ROM loading and initialization).
+__device__ __forceinline__ void reset_core(Core &c) {
+    c.r.w0 = c.r.w1 = c.r.w2 = c.r.w3 = 0;
+    c.pc = kProgram;
+    c.I = 0;
+    c.sp = 0;
+    c.dt = 0;
+    c.st = 0;
+}
+
+// The held key of a step: the action's key, or none for the no-op and for
+// out-of-range actions.
+__device__ __forceinline__ uint32_t action_key(const Roms &roms, uint32_t rom, uint32_t desc, int32_t a) {
+    const int32_t nact = (int32_t)(desc >> 24);
+    return (a >= 0 && a < nact) ? roms.keys[rom * 16 + a] & 15 : kKeyNone;
+}
+
+}  // namespace octax

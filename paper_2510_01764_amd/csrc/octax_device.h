@@ -1,0 +1,145 @@
+// Device-side definitions shared by the step kernels of liboctax: the
+// structure-of-arrays layout of the env state in HBM, packed register access,
+// the CXNN random stream and the built-in font.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace octax {
+
+constexpr uint32_t kMem = 4096;
+constexpr uint32_t kProgram = 0x200;
+constexpr uint32_t kFont = 0x050;
+constexpr uint32_t kKeyNone = 16;      // "no key held"
+constexpr uint32_t kObsBytes = 8192;   // [4][64][32]
+
+// Env state in device memory, one entry per slot (see octax_host.cpp for the
+// byte budget).  Small per-env fields are stored field-major ([field][slot])
+// so that a lane-per-env kernel reads them coalesced; big per-env blocks
+// (memory, display, frame ring) are slot-major.
+struct State {
+    uint32_t *regs;      // [4][E]  V0..V15, register 4w+b in byte b of regs[w][slot]
+    uint32_t *pc_i;      // [E]     PC | I << 16
+    uint32_t *misc;      // [E]     SP | DT << 8 | ST << 16 | ring head << 24
+    uint32_t *stack;     // [E][8]  16 return addresses, two per word (entry 2k in the low half)
+    uint32_t *t;         // [E]     steps since reset
+    int32_t *prev;       // [E]     V[score_reg] after the previous step
+    uint64_t *rng;       // [E]     SplitMix64 state
+    uint64_t *dirty;     // [E]     bit p: 64-byte page p written since reset
+    uint64_t *fb;        // [E][32] display rows, bit 63 - x = pixel (x, y)
+    uint32_t *cols;      // [E][4][64] frame ring, column x: bit y = pixel (x, y)
+    uint8_t *ram;        // [E][4096]
+    const uint32_t *rom_of;   // [E] ROM id
+    const uint32_t *horizon;  // [E]
+    const uint32_t *env_of;   // [E] env index (output position) of each slot
+    uint32_t num;             // E
+};
+
+// Per-ROM tables.
+struct Roms {
+    const uint8_t *image;    // [R][4096] power-on memory: font at 0x50, program at 0x200
+    const uint8_t *keys;     // [R][16]
+    const uint32_t *desc;    // [R] score_reg | term_reg << 8 | term_value << 16 | num_actions << 24
+};
+
+// ---------------------------------------------------------------------------
+// V registers packed four to a 32-bit word (byte b of word w is V[4w+b]).
+// ---------------------------------------------------------------------------
+struct Regs {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ uint32_t vget(const Regs &r, uint32_t x) {
+    uint32_t lo = (x & 4) ? r.w1 : r.w0;
+    uint32_t hi = (x & 4) ? r.w3 : r.w2;
+    uint32_t w = (x & 8) ? hi : lo;
+    return __builtin_amdgcn_ubfe(w, (x & 3) * 8, 8);
+}
+
+__device__ __forceinline__ void vset(Regs &r, uint32_t x, uint32_t val) {
+    uint32_t sh = (x & 3) * 8;
+    uint32_t m = 0xFFu << sh;
+    uint32_t s = (val & 0xFFu) << sh;
+    uint32_t q = x >> 2;
+    r.w0 = (q == 0) ? ((r.w0 & ~m) | s) : r.w0;
+    r.w1 = (q == 1) ? ((r.w1 & ~m) | s) : r.w1;
+    r.w2 = (q == 2) ? ((r.w2 & ~m) | s) : r.w2;
+    r.w3 = (q == 3) ? ((r.w3 & ~m) | s) : r.w3;
+}
+
+__device__ __forceinline__ uint32_t vf(const Regs &r) { return r.w3 >> 24; }
+__device__ __forceinline__ void set_vf(Regs &r, uint32_t f) { r.w3 = (r.w3 & 0x00FFFFFFu) | (f << 24); }
+
+// Byte k (0..3) of word w, for V0..V15 bulk access.
+__device__ __forceinline__ uint32_t regs_word(const Regs &r, uint32_t w) {
+    return w == 0 ? r.w0 : w == 1 ? r.w1 : w == 2 ? r.w2 : r.w3;
+}
+
+// ---------------------------------------------------------------------------
+// CXNN randomness: SplitMix64 (Steele, Lea and Flood, OOPSLA 2014).  The
+// state advances by the golden-ratio increment and the output is the
+// 64-bit finaliser (xor-shift 30, multiply, xor-shift 27, multiply,
+// xor-shift 31) of the new state.  CXNN keeps the top byte.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t rnd_byte(uint64_t &s) {
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (uint32_t)(z >> 56);
+}
+
+// 16-byte store that bypasses cache retention (observations are written once
+// and read by the consumer later).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_stream(void *dst, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    u32x4 v = {a, b, c, d};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(dst));
+}
+
+// ---------------------------------------------------------------------------
+// Observation expansion: four column bits -> four 0/1 bytes.
+// n * 0x00204081 places bit j of n at bit 8j (j = 0..3) with no carries
+// between the copies; the mask keeps those bits.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t spread4(uint32_t col, uint32_t shift) {
+    return (__builtin_amdgcn_ubfe(col, shift, 4) * 0x00204081u) & 0x01010101u;
+}
+
+// 32 pixels of one column (bit y = pixel y) -> 32 bytes at dst (16-byte aligned).
+__device__ __forceinline__ void store_column(uint8_t *dst, uint32_t col) {
+    store_stream(dst, spread4(col, 0), spread4(col, 4), spread4(col, 8), spread4(col, 12));
+    store_stream(dst + 16, spread4(col, 16), spread4(col, 20), spread4(col, 24), spread4(col, 28));
+}
+
+// ---------------------------------------------------------------------------
+// 32 x 64 bit-matrix transpose of one frame held in registers.
+// rows[y] (bit 63 - x = pixel (x, y)) -> cols[x] (bit y = pixel (x, y)).
+// Recursive block swap on 32-bit words (Warren, Hacker's Delight, 2nd ed.,
+// section 7-3): five rounds swap the off-diagonal j x j blocks for
+// j = 16, 8, 4, 2, 1.  It is applied to the high and low halves of the rows
+// with the row order reversed, which yields bit y = row y.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void transpose32(uint32_t a[32]) {
+    uint32_t m = 0x0000FFFFu;
+#pragma unroll
+    for (int j = 16; j != 0; j >>= 1, m ^= (m << j)) {
+#pragma unroll
+        for (int k = 0; k < 32; k = (k + j + 1) & ~j) {
+            uint32_t t = (a[k] ^ (a[k + j] >> j)) & m;
+            a[k] ^= t;
+            a[k + j] ^= (t << j);
+        }
+    }
+}
+
+// Frame rows -> columns 0..63.  hi[r] must hold the high words of rows in
+// reverse order (hi[r] = row[31 - r] >> 32) and lo[r] the low words.
+__device__ __forceinline__ void rows_to_cols(uint32_t hi[32], uint32_t lo[32]) {
+    transpose32(hi);   // hi[x] = column x (x = 0..31)
+    transpose32(lo);   // lo[x] = column 32 + x
+}
+
+}  // namespace octax

@@ -1,0 +1,485 @@
+// Host side of the liboctax C ABI (declared in include/octax.h).
+//
+// Device memory per env (E envs):
+//   regs 16 B, pc_i 4, misc 4, t 4, prev 4, rng 8, dirty 8, stack 32,
+//   display 256, frame ring 1024, memory 4096, rom/horizon/env maps 12
+//   = 5,468 B per env, plus the power-on images (4 KB per ROM).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/octax.h"
+#include "octax_kernels.h"
+
+using namespace octax;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int32_t fail(int32_t code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int32_t hip_fail(hipError_t e, const char *what) {
+    return fail(OCTAX_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// The 4x5 hexadecimal font of the machine, glyphs 0..F (Appendix B.4 places
+// it at 0x050-0x09F).
+const uint8_t kFontBytes[80] = {
+    0xF0, 0x90, 0x90, 0x90, 0xF0, 0x20, 0x60, 0x20, 0x20, 0x70, 0xF0, 0x10, 0xF0, 0x80, 0xF0,
+    0xF0, 0x10, 0xF0, 0x10, 0xF0, 0x90, 0x90, 0xF0, 0x10, 0x10, 0xF0, 0x80, 0xF0, 0x10, 0xF0,
+    0xF0, 0x80, 0xF0, 0x90, 0xF0, 0xF0, 0x10, 0x20, 0x40, 0x40, 0xF0, 0x90, 0xF0, 0x90, 0xF0,
+    0xF0, 0x90, 0xF0, 0x10, 0xF0, 0xF0, 0x90, 0xF0, 0x90, 0x90, 0xE0, 0x90, 0xE0, 0x90, 0xE0,
+    0xF0, 0x80, 0x80, 0x80, 0xF0, 0xE0, 0x90, 0x90, 0x90, 0xE0, 0xF0, 0x80, 0xF0, 0x80, 0xF0,
+    0xF0, 0x80, 0xF0, 0x80, 0x80,
+};
+
+}  // namespace
+
+struct octax_engine {
+    uint32_t E = 0, R = 0, ipf = 0, frame_skip = 0;
+    uint32_t kernel = OCTAX_KERNEL_PLAIN;
+    uint32_t placement = OCTAX_PLACE_IDENTITY;
+    uint32_t envs_per_block = 256, rom_in_lds = 1;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    uint64_t device_bytes = 0;
+    std::vector<void *> allocations;
+    std::vector<uint32_t> env_of, slot_of, rom_of;   // host copies of the placement
+    State s{};
+    Roms roms{};
+    uint32_t *d_block_roms = nullptr;                 // [blocks][2] for the current tuning
+    uint32_t *d_slot_scratch = nullptr;               // slot lists for get/set_state
+    RawState *d_raw = nullptr;
+    uint32_t raw_capacity = 0;
+    int graphs = 0;
+
+    template <class T>
+    hipError_t alloc(T **p, size_t count) {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, std::max<size_t>(count * sizeof(T), 16));
+        if (e != hipSuccess) return e;
+        allocations.push_back(q);
+        device_bytes += count * sizeof(T);
+        *p = static_cast<T *>(q);
+        return hipSuccess;
+    }
+    void free_all() {
+        for (void *p : allocations) (void)hipFree(p);
+        allocations.clear();
+    }
+};
+
+struct octax_graph {
+    octax_engine *eng = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+hipError_t upload_block_roms(octax_engine *g) {
+    const uint32_t ipw = g->envs_per_block;
+    const uint32_t blocks = (g->E + ipw - 1) / ipw;
+    std::vector<uint32_t> table(2 * (size_t)blocks, 0xFFFFFFFFu);
+    std::vector<uint32_t> count(g->R, 0);
+    for (uint32_t b = 0; b < blocks; b++) {
+        const uint32_t lo = b * ipw, hi = std::min(g->E, lo + ipw);
+        std::vector<uint32_t> seen;
+        for (uint32_t sl = lo; sl < hi; sl++) {
+            const uint32_t r = g->rom_of[sl];
+            if (count[r]++ == 0) seen.push_back(r);
+        }
+        uint32_t best0 = 0xFFFFFFFFu, best1 = 0xFFFFFFFFu, c0 = 0, c1 = 0;
+        for (uint32_t r : seen) {
+            if (count[r] > c0 || (count[r] == c0 && r < best0)) {
+                best1 = best0; c1 = c0; best0 = r; c0 = count[r];
+            } else if (count[r] > c1 || (count[r] == c1 && r < best1)) {
+                best1 = r; c1 = count[r];
+            }
+        }
+        for (uint32_t r : seen) count[r] = 0;
+        table[2 * (size_t)b] = best0;
+        table[2 * (size_t)b + 1] = best1;
+    }
+    if (g->d_block_roms) {
+        (void)hipFree(g->d_block_roms);
+        g->allocations.erase(std::find(g->allocations.begin(), g->allocations.end(),
+                                       static_cast<void *>(g->d_block_roms)));
+        g->d_block_roms = nullptr;
+    }
+    hipError_t e = g->alloc(&g->d_block_roms, table.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpy(g->d_block_roms, table.data(), table.size() * sizeof(uint32_t),
+                     hipMemcpyHostToDevice);
+}
+
+hipError_t launch_steps(octax_engine *g, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
+                        uint32_t obs_slots, float *d_reward, uint8_t *d_done, hipStream_t st) {
+    StepIO io{d_action, d_obs, d_reward, d_done, K, obs_slots ? obs_slots : 1, g->ipf, g->frame_skip};
+    if (g->kernel == OCTAX_KERNEL_FUSED) {
+        FusedCfg f{g->envs_per_block, g->rom_in_lds, g->d_block_roms};
+        return launch_step_fused(g->s, g->roms, io, f, st);
+    }
+    return launch_step_plain(g->s, g->roms, io, st);
+}
+
+hipError_t ensure_raw(octax_engine *g, uint32_t count) {
+    if (count <= g->raw_capacity) return hipSuccess;
+    for (void *p : {static_cast<void *>(g->d_raw), static_cast<void *>(g->d_slot_scratch)}) {
+        if (p) {
+            (void)hipFree(p);
+            g->allocations.erase(std::find(g->allocations.begin(), g->allocations.end(), p));
+        }
+    }
+    g->d_raw = nullptr;
+    g->d_slot_scratch = nullptr;
+    g->raw_capacity = 0;
+    hipError_t e = g->alloc(&g->d_raw, count);
+    if (e != hipSuccess) return e;
+    e = g->alloc(&g->d_slot_scratch, count);
+    if (e != hipSuccess) return e;
+    g->raw_capacity = count;
+    return hipSuccess;
+}
+
+void raw_to_canonical(const RawState &r, octax_env_state &o) {
+    std::memset(&o, 0, sizeof o);
+    for (int k = 0; k < 16; k++) o.v[k] = (uint8_t)(r.regs[k >> 2] >> (8 * (k & 3)));
+    o.pc = (uint16_t)(r.pc_i & 0xFFF);
+    o.i = (uint16_t)((r.pc_i >> 16) & 0xFFF);
+    o.sp = (uint8_t)(r.misc & 15);
+    o.dt = (uint8_t)(r.misc >> 8);
+    o.st = (uint8_t)(r.misc >> 16);
+    const uint32_t head = (r.misc >> 24) & 3;
+    for (int k = 0; k < 16; k++) o.stack[k] = (uint16_t)((r.stack[k >> 1] >> (16 * (k & 1))) & 0xFFFF);
+    o.t = r.t;
+    o.prev_score = r.prev;
+    o.rng = r.rng;
+    std::memcpy(o.ram, r.ram, 4096);
+    std::memcpy(o.fb, r.fb, sizeof o.fb);
+    for (int h = 0; h < 3; h++) {
+        const uint32_t *col = r.cols + ((head + 1 + h) & 3) * 64;
+        for (int y = 0; y < 32; y++) {
+            uint64_t row = 0;
+            for (int x = 0; x < 64; x++) row |= (uint64_t)((col[x] >> y) & 1) << (63 - x);
+            o.hist[h][y] = row;
+        }
+    }
+}
+
+void canonical_to_raw(const octax_env_state &o, RawState &r) {
+    std::memset(&r, 0, sizeof r);
+    for (int k = 0; k < 16; k++) r.regs[k >> 2] |= (uint32_t)o.v[k] << (8 * (k & 3));
+    r.pc_i = (o.pc & 0xFFFu) | ((uint32_t)(o.i & 0xFFFu) << 16);
+    const uint32_t head = 3;
+    r.misc = (o.sp & 15u) | ((uint32_t)o.dt << 8) | ((uint32_t)o.st << 16) | (head << 24);
+    for (int k = 0; k < 16; k++) r.stack[k >> 1] |= (uint32_t)(o.stack[k] & 0xFFFu) << (16 * (k & 1));
+    r.t = o.t;
+    r.prev = o.prev_score;
+    r.rng = o.rng;
+    r.dirty = ~0ull;   // every page is taken from ram; a later reset restores all of them
+    std::memcpy(r.ram, o.ram, 4096);
+    std::memcpy(r.fb, o.fb, sizeof r.fb);
+    const uint64_t *frames[4] = {o.hist[0], o.hist[1], o.hist[2], o.fb};
+    for (int h = 0; h < 4; h++) {
+        uint32_t *col = r.cols + h * 64;   // ring slots 0..3 with head = 3
+        for (int x = 0; x < 64; x++) {
+            uint32_t c = 0;
+            for (int y = 0; y < 32; y++) c |= (uint32_t)((frames[h][y] >> (63 - x)) & 1) << y;
+            col[x] = c;
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *octax_last_error(void) { return g_last_error.c_str(); }
+
+int32_t octax_create(const octax_config *cfg, octax_engine **out) {
+    if (!out) return fail(OCTAX_E_INVALID, "octax_create: out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(OCTAX_E_INVALID, "octax_create: cfg is NULL");
+    if (cfg->abi_version != OCTAX_ABI_VERSION) return fail(OCTAX_E_INVALID, "octax_create: abi_version mismatch");
+    if (cfg->quirks != OCTAX_QUIRKS_V1) return fail(OCTAX_E_INVALID, "octax_create: quirks must be OCTAX_QUIRKS_V1");
+    const uint32_t E = cfg->num_envs, R = cfg->num_roms;
+    if (E == 0 || E > (1u << 26)) return fail(OCTAX_E_INVALID, "octax_create: num_envs out of range");
+    if (R == 0 || R > 65535) return fail(OCTAX_E_INVALID, "octax_create: num_roms out of range");
+    if (cfg->instr_per_frame == 0 || cfg->instr_per_frame > 1000)
+        return fail(OCTAX_E_INVALID, "octax_create: instr_per_frame out of range");
+    if (cfg->frame_skip == 0 || cfg->frame_skip > 64) return fail(OCTAX_E_INVALID, "octax_create: frame_skip out of range");
+    if (cfg->kernel > OCTAX_KERNEL_FUSED) return fail(OCTAX_E_INVALID, "octax_create: unknown kernel");
+    if (cfg->placement > OCTAX_PLACE_BY_ROM) return fail(OCTAX_E_INVALID, "octax_create: unknown placement");
+    if (cfg->lanes_per_env > 1) return fail(OCTAX_E_INVALID, "octax_create: lanes_per_env must be 0 or 1");
+    const uint32_t ipw = cfg->envs_per_block ? cfg->envs_per_block : 256;
+    if (ipw != 64 && ipw != 128 && ipw != 256) return fail(OCTAX_E_INVALID, "octax_create: envs_per_block must be 64, 128 or 256");
+    if (!cfg->h_rom_data || !cfg->h_rom_offset || !cfg->h_rom_len || !cfg->h_env_rom ||
+        !cfg->h_action_keys || !cfg->h_num_actions || !cfg->h_score_reg || !cfg->h_term_reg ||
+        !cfg->h_term_value || !cfg->h_horizon || !cfg->h_env_seed)
+        return fail(OCTAX_E_INVALID, "octax_create: a host array is NULL");
+    for (uint32_t r = 0; r < R; r++) {
+        if (cfg->h_rom_len[r] > OCTAX_MAX_ROM_BYTES) return fail(OCTAX_E_INVALID, "octax_create: ROM longer than 3584 bytes");
+        if (cfg->h_num_actions[r] > 16) return fail(OCTAX_E_INVALID, "octax_create: num_actions > 16");
+        if (cfg->h_score_reg[r] > 15 || cfg->h_term_reg[r] > 15) return fail(OCTAX_E_INVALID, "octax_create: register index > 15");
+        for (uint32_t a = 0; a < cfg->h_num_actions[r]; a++)
+            if (cfg->h_action_keys[16 * r + a] > 15) return fail(OCTAX_E_INVALID, "octax_create: key > 15");
+    }
+    for (uint32_t e = 0; e < E; e++)
+        if (cfg->h_env_rom[e] >= R) return fail(OCTAX_E_INVALID, "octax_create: env_rom >= num_roms");
+
+    octax_engine *g = new (std::nothrow) octax_engine;
+    if (!g) return fail(OCTAX_E_NOMEM, "octax_create: out of host memory");
+    g->E = E;
+    g->R = R;
+    g->ipf = cfg->instr_per_frame;
+    g->frame_skip = cfg->frame_skip;
+    g->kernel = cfg->kernel;
+    g->placement = cfg->placement;
+    g->envs_per_block = ipw;
+    g->rom_in_lds = cfg->rom_in_lds ? 1 : 0;
+    g->stream = static_cast<hipStream_t>(cfg->stream);
+    (void)hipGetDevice(&g->device);
+
+    // Placement: slot -> env.
+    g->env_of.resize(E);
+    for (uint32_t e = 0; e < E; e++) g->env_of[e] = e;
+    if (g->placement == OCTAX_PLACE_BY_ROM)
+        std::stable_sort(g->env_of.begin(), g->env_of.end(),
+                         [&](uint32_t a, uint32_t b) { return cfg->h_env_rom[a] < cfg->h_env_rom[b]; });
+    g->slot_of.resize(E);
+    g->rom_of.resize(E);
+    std::vector<uint32_t> horizon(E);
+    std::vector<uint64_t> seed(E);
+    for (uint32_t sl = 0; sl < E; sl++) {
+        const uint32_t e = g->env_of[sl];
+        g->slot_of[e] = sl;
+        g->rom_of[sl] = cfg->h_env_rom[e];
+        horizon[sl] = cfg->h_horizon[e];
+        seed[sl] = cfg->h_env_seed[e];
+    }
+
+    // Power-on images and descriptors.
+    std::vector<uint8_t> image((size_t)R * kMem, 0);
+    std::vector<uint32_t> desc(R);
+    for (uint32_t r = 0; r < R; r++) {
+        uint8_t *m = image.data() + (size_t)r * kMem;
+        std::memcpy(m + kFont, kFontBytes, sizeof kFontBytes);
+        std::memcpy(m + kProgram, cfg->h_rom_data + cfg->h_rom_offset[r], cfg->h_rom_len[r]);
+        desc[r] = cfg->h_score_reg[r] | ((uint32_t)cfg->h_term_reg[r] << 8) |
+                  ((uint32_t)cfg->h_term_value[r] << 16) | ((uint32_t)cfg->h_num_actions[r] << 24);
+    }
+
+    hipError_t e = hipSuccess;
+    uint32_t *rom_of = nullptr, *hor = nullptr, *env_of = nullptr, *d_desc = nullptr;
+    uint8_t *d_img = nullptr, *d_keys = nullptr;
+#define TRY(x)                                                    \
+    do {                                                          \
+        e = (x);                                                  \
+        if (e != hipSuccess) {                                    \
+            g->free_all();                                        \
+            delete g;                                             \
+            return e == hipErrorOutOfMemory                       \
+                       ? fail(OCTAX_E_NOMEM, "octax_create: device allocation failed") \
+                       : hip_fail(e, "octax_create");             \
+        }                                                         \
+    } while (0)
+    TRY(g->alloc(&g->s.regs, 4 * (size_t)E));
+    TRY(g->alloc(&g->s.pc_i, E));
+    TRY(g->alloc(&g->s.misc, E));
+    TRY(g->alloc(&g->s.stack, 8 * (size_t)E));
+    TRY(g->alloc(&g->s.t, E));
+    TRY(g->alloc(&g->s.prev, E));
+    TRY(g->alloc(&g->s.rng, E));
+    TRY(g->alloc(&g->s.dirty, E));
+    TRY(g->alloc(&g->s.fb, 32 * (size_t)E));
+    TRY(g->alloc(&g->s.cols, 256 * (size_t)E));
+    TRY(g->alloc(&g->s.ram, (size_t)kMem * E));
+    TRY(g->alloc(&rom_of, E));
+    TRY(g->alloc(&hor, E));
+    TRY(g->alloc(&env_of, E));
+    TRY(g->alloc(&d_img, (size_t)R * kMem));
+    TRY(g->alloc(&d_keys, 16 * (size_t)R));
+    TRY(g->alloc(&d_desc, R));
+    TRY(hipMemcpy(rom_of, g->rom_of.data(), 4 * (size_t)E, hipMemcpyHostToDevice));
+    TRY(hipMemcpy(hor, horizon.data(), 4 * (size_t)E, hipMemcpyHostToDevice));
+    TRY(hipMemcpy(env_of, g->env_of.data(), 4 * (size_t)E, hipMemcpyHostToDevice));
+    TRY(hipMemcpy(g->s.rng, seed.data(), 8 * (size_t)E, hipMemcpyHostToDevice));
+    TRY(hipMemcpy(d_img, image.data(), image.size(), hipMemcpyHostToDevice));
+    TRY(hipMemcpy(d_keys, cfg->h_action_keys, 16 * (size_t)R, hipMemcpyHostToDevice));
+    TRY(hipMemcpy(d_desc, desc.data(), 4 * (size_t)R, hipMemcpyHostToDevice));
+    g->s.rom_of = rom_of;
+    g->s.horizon = hor;
+    g->s.env_of = env_of;
+    g->s.num = E;
+    g->roms.image = d_img;
+    g->roms.keys = d_keys;
+    g->roms.desc = d_desc;
+    TRY(upload_block_roms(g));
+    TRY(launch_reset(g->s, g->roms, nullptr, true, g->stream));
+    TRY(hipStreamSynchronize(g->stream));
+#undef TRY
+    *out = g;
+    return OCTAX_OK;
+}
+
+int32_t octax_destroy(octax_engine *g) {
+    if (!g) return OCTAX_OK;
+    hipError_t e = hipStreamSynchronize(g->stream);
+    g->free_all();
+    delete g;
+    if (e != hipSuccess) return hip_fail(e, "octax_destroy");
+    return OCTAX_OK;
+}
+
+int32_t octax_reset(octax_engine *g, const uint8_t *d_mask, uint8_t *d_obs) {
+    if (!g) return fail(OCTAX_E_INVALID, "octax_reset: engine is NULL");
+    hipError_t e = launch_reset(g->s, g->roms, d_mask, false, g->stream);
+    if (e == hipSuccess && d_obs) e = launch_observe(g->s, d_obs, g->stream);
+    return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_reset");
+}
+
+int32_t octax_step(octax_engine *g, const int32_t *d_action, uint8_t *d_obs, float *d_reward,
+                   uint8_t *d_done) {
+    if (!g || !d_action || !d_reward || !d_done)
+        return fail(OCTAX_E_INVALID, "octax_step: NULL engine, action, reward or done");
+    hipError_t e = launch_steps(g, 1, d_action, d_obs, 1, d_reward, d_done, g->stream);
+    return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_step");
+}
+
+int32_t octax_step_many(octax_engine *g, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
+                        uint32_t obs_slots, float *d_reward, uint8_t *d_done) {
+    if (!g || !d_action || !d_reward || !d_done)
+        return fail(OCTAX_E_INVALID, "octax_step_many: NULL engine, action, reward or done");
+    if (K == 0) return fail(OCTAX_E_INVALID, "octax_step_many: K == 0");
+    if (d_obs && obs_slots == 0) return fail(OCTAX_E_INVALID, "octax_step_many: obs_slots == 0");
+    hipError_t e = launch_steps(g, K, d_action, d_obs, obs_slots, d_reward, d_done, g->stream);
+    return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_step_many");
+}
+
+int32_t octax_graph_create(octax_engine *g, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
+                           uint32_t obs_slots, float *d_reward, uint8_t *d_done, octax_graph **out) {
+    if (!out) return fail(OCTAX_E_INVALID, "octax_graph_create: out is NULL");
+    *out = nullptr;
+    if (!g || !d_action || !d_reward || !d_done)
+        return fail(OCTAX_E_INVALID, "octax_graph_create: NULL engine, action, reward or done");
+    if (K == 0) return fail(OCTAX_E_INVALID, "octax_graph_create: K == 0");
+    if (d_obs && obs_slots == 0) return fail(OCTAX_E_INVALID, "octax_graph_create: obs_slots == 0");
+    octax_graph *gr = new (std::nothrow) octax_graph;
+    if (!gr) return fail(OCTAX_E_NOMEM, "octax_graph_create: out of host memory");
+    gr->eng = g;
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = launch_steps(g, K, d_action, d_obs, obs_slots, d_reward, d_done, cap);
+        e = hipStreamEndCapture(cap, &gr->graph);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        delete gr;
+        return hip_fail(e, "octax_graph_create");
+    }
+    g->graphs++;
+    *out = gr;
+    return OCTAX_OK;
+}
+
+int32_t octax_graph_launch(octax_graph *gr) {
+    if (!gr) return fail(OCTAX_E_INVALID, "octax_graph_launch: graph is NULL");
+    hipError_t e = hipGraphLaunch(gr->exec, gr->eng->stream);
+    return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_graph_launch");
+}
+
+int32_t octax_graph_destroy(octax_graph *gr) {
+    if (!gr) return OCTAX_OK;
+    hipError_t e = hipStreamSynchronize(gr->eng->stream);
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    gr->eng->graphs--;
+    delete gr;
+    return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_graph_destroy");
+}
+
+int32_t octax_get_state(octax_engine *g, uint32_t first, uint32_t count, octax_env_state *h_out) {
+    if (!g || (!h_out && count)) return fail(OCTAX_E_INVALID, "octax_get_state: NULL argument");
+    if ((uint64_t)first + count > g->E) return fail(OCTAX_E_INVALID, "octax_get_state: range outside 0..E");
+    if (count == 0) return OCTAX_OK;
+    hipError_t e = ensure_raw(g, count);
+    std::vector<uint32_t> slots(count);
+    for (uint32_t k = 0; k < count; k++) slots[k] = g->slot_of[first + k];
+    std::vector<RawState> raw(count);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess) e = hipMemcpy(g->d_slot_scratch, slots.data(), 4 * (size_t)count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_pack(g->s, g->d_slot_scratch, count, g->d_raw, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess) e = hipMemcpy(raw.data(), g->d_raw, sizeof(RawState) * (size_t)count, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "octax_get_state");
+    for (uint32_t k = 0; k < count; k++) raw_to_canonical(raw[k], h_out[k]);
+    return OCTAX_OK;
+}
+
+int32_t octax_set_state(octax_engine *g, uint32_t first, uint32_t count, const octax_env_state *h_in) {
+    if (!g || (!h_in && count)) return fail(OCTAX_E_INVALID, "octax_set_state: NULL argument");
+    if ((uint64_t)first + count > g->E) return fail(OCTAX_E_INVALID, "octax_set_state: range outside 0..E");
+    if (count == 0) return OCTAX_OK;
+    hipError_t e = ensure_raw(g, count);
+    std::vector<uint32_t> slots(count);
+    std::vector<RawState> raw(count);
+    for (uint32_t k = 0; k < count; k++) {
+        slots[k] = g->slot_of[first + k];
+        canonical_to_raw(h_in[k], raw[k]);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess) e = hipMemcpy(g->d_slot_scratch, slots.data(), 4 * (size_t)count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g->d_raw, raw.data(), sizeof(RawState) * (size_t)count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_unpack(g->s, g->d_slot_scratch, count, g->d_raw, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_set_state");
+}
+
+int32_t octax_set_kernel(octax_engine *g, uint32_t kernel) {
+    if (!g || kernel > OCTAX_KERNEL_FUSED) return fail(OCTAX_E_INVALID, "octax_set_kernel: bad argument");
+    g->kernel = kernel;
+    return OCTAX_OK;
+}
+
+int32_t octax_set_tuning(octax_engine *g, uint32_t envs_per_block, uint32_t rom_in_lds) {
+    if (!g || (envs_per_block != 64 && envs_per_block != 128 && envs_per_block != 256))
+        return fail(OCTAX_E_INVALID, "octax_set_tuning: envs_per_block must be 64, 128 or 256");
+    if (g->graphs > 0) return fail(OCTAX_E_STATE, "octax_set_tuning: destroy the engine's graphs first");
+    hipError_t e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "octax_set_tuning");
+    g->envs_per_block = envs_per_block;
+    g->rom_in_lds = rom_in_lds ? 1 : 0;
+    e = upload_block_roms(g);
+    return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_set_tuning");
+}
+
+int32_t octax_set_stream(octax_engine *g, void *stream) {
+    if (!g) return fail(OCTAX_E_INVALID, "octax_set_stream: engine is NULL");
+    g->stream = static_cast<hipStream_t>(stream);
+    return OCTAX_OK;
+}
+
+int32_t octax_info(const octax_engine *g, uint32_t *num_envs, uint64_t *device_bytes) {
+    if (!g) return fail(OCTAX_E_INVALID, "octax_info: engine is NULL");
+    if (num_envs) *num_envs = g->E;
+    if (device_bytes) *device_bytes = g->device_bytes;
+    return OCTAX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// Host-visible launch interface of the liboctax kernels (implemented in the
+// .hip files, called from octax_host.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "octax_device.h"
+
+namespace octax {
+
+struct StepIO {
+    const int32_t *action;  // [K][E]
+    uint8_t *obs;           // [obs_slots][E][8192] or nullptr
+    float *reward;          // [K][E]
+    uint8_t *done;          // [K][E]
+    uint32_t K;
+    uint32_t obs_slots;
+    uint32_t ipf;
+    uint32_t frame_skip;
+};
+
+// Fused-kernel tuning.
+struct FusedCfg {
+    uint32_t envs_per_block;      // 64, 128 or 256
+    uint32_t rom_in_lds;          // stage up to two ROM images per block in LDS
+    const uint32_t *block_roms;   // [blocks][2] ROM ids to stage (0xFFFFFFFF = none)
+};
+
+hipError_t launch_step_plain(const State &s, const Roms &r, const StepIO &io, hipStream_t st);
+hipError_t launch_step_fused(const State &s, const Roms &r, const StepIO &io, const FusedCfg &f,
+                             hipStream_t st);
+// Power-on state for the slots whose env has mask[env] != 0 (all if mask is
+// null).  full_ram: copy every page of the image (first reset after
+// allocation), else only pages marked dirty.
+hipError_t launch_reset(const State &s, const Roms &r, const uint8_t *mask, bool full_ram,
+                        hipStream_t st);
+// Write the observation of every env from its frame ring.
+hipError_t launch_observe(const State &s, uint8_t *obs, hipStream_t st);
+
+}  // namespace octax
+
+namespace octax {
+
+// Flat per-env state used to move envs between the SoA arrays and the host.
+struct RawState {
+    uint32_t regs[4];
+    uint32_t pc_i;
+    uint32_t misc;
+    uint32_t t;
+    int32_t prev;
+    uint64_t rng;
+    uint64_t dirty;
+    uint32_t stack[8];
+    uint64_t fb[32];
+    uint32_t cols[256];
+    uint8_t ram[4096];
+};
+
+// Gather slots slot_list[0..count) into raw[0..count), or scatter back.
+hipError_t launch_pack(const State &s, const uint32_t *slot_list, uint32_t count, RawState *raw,
+                       hipStream_t st);
+hipError_t launch_unpack(const State &s, const uint32_t *slot_list, uint32_t count,
+                         const RawState *raw, hipStream_t st);
+
+}  // namespace octax

@@ -1,0 +1,148 @@
+// Reset and observation kernels (Section 3.2, ROM loading and initialization;
+// Section 3.2, Environment integration: the (4, 64, 32) frame stack).
+#include "octax_core.h"
+#include "octax_kernels.h"
+
+namespace octax {
+namespace {
+
+// One thread per slot: registers, display, stack, frame ring, counters.
+__global__ __launch_bounds__(256) void reset_regs_kernel(State s, const uint8_t *mask) {
+    const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
+    if (slot >= s.num) return;
+    const uint32_t env = s.env_of[slot];
+    if (mask && !mask[env]) return;
+    const uint32_t E = s.num;
+    s.regs[0 * E + slot] = 0;
+    s.regs[1 * E + slot] = 0;
+    s.regs[2 * E + slot] = 0;
+    s.regs[3 * E + slot] = 0;
+    s.pc_i[slot] = kProgram;
+    s.misc[slot] = 0;
+    s.t[slot] = 0;
+    s.prev[slot] = 0;   // V[score_reg] of the power-on state
+    uint4 z = make_uint4(0, 0, 0, 0);
+    uint4 *fb = reinterpret_cast<uint4 *>(s.fb + (size_t)slot * 32);
+    for (int q = 0; q < 16; q++) fb[q] = z;
+    uint4 *stk = reinterpret_cast<uint4 *>(s.stack + (size_t)slot * 8);
+    stk[0] = z;
+    stk[1] = z;
+    uint4 *ring = reinterpret_cast<uint4 *>(s.cols + (size_t)slot * 256);
+    for (int q = 0; q < 64; q++) ring[q] = z;
+}
+
+// 256 threads per slot, 16 bytes each: memory back to the ROM's power-on
+// image (all pages, or only those written since the last reset), then the
+// dirty mask is cleared by the last wave to read it.
+__global__ __launch_bounds__(256) void reset_ram_kernel(State s, Roms roms, const uint8_t *mask,
+                                                        uint32_t full) {
+    const uint32_t slot = blockIdx.x;
+    if (slot >= s.num) return;
+    const uint32_t env = s.env_of[slot];
+    if (mask && !mask[env]) return;
+    const uint32_t q = threadIdx.x;          // 16-byte chunk, page q / 4
+    const uint64_t dirty = s.dirty[slot];
+    if (full || ((dirty >> (q >> 2)) & 1)) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(roms.image + (size_t)s.rom_of[slot] * kMem);
+        uint4 *dst = reinterpret_cast<uint4 *>(s.ram + (size_t)slot * kMem);
+        dst[q] = src[q];
+    }
+    __syncthreads();
+    if (q == 0) s.dirty[slot] = 0;
+}
+
+// One thread per 16 bytes of observation: frame fr, column x, rows 16h..16h+15.
+__global__ __launch_bounds__(256) void observe_kernel(State s, uint8_t *obs) {
+    const uint64_t gid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint32_t slot = (uint32_t)(gid >> 9);
+    if (slot >= s.num) return;
+    const uint32_t q = (uint32_t)(gid & 511);
+    const uint32_t fr = q >> 7, x = (q >> 1) & 63, h = q & 1;
+    const uint32_t head = s.misc[slot] >> 24 & 3;
+    const uint32_t col = s.cols[(size_t)slot * 256 + ((head + 1 + fr) & 3) * 64 + x] >> (16 * h);
+    uint4 v = make_uint4(spread4(col, 0), spread4(col, 4), spread4(col, 8), spread4(col, 12));
+    uint4 *dst = reinterpret_cast<uint4 *>(obs + (size_t)s.env_of[slot] * kObsBytes) + q;
+    *dst = v;
+}
+
+}  // namespace
+
+hipError_t launch_reset(const State &s, const Roms &r, const uint8_t *mask, bool full_ram,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(reset_ram_kernel, dim3(s.num), dim3(256), 0, st, s, r, mask, full_ram ? 1u : 0u);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reset_regs_kernel, dim3((s.num + 255) / 256), dim3(256), 0, st, s, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_observe(const State &s, uint8_t *obs, hipStream_t st) {
+    const uint64_t threads = (uint64_t)s.num * 512;
+    hipLaunchKernelGGL(observe_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, st, s, obs);
+    return hipGetLastError();
+}
+
+}  // namespace octax
+
+namespace octax {
+namespace {
+
+// One block per env: copy every field between the SoA arrays and RawState.
+__global__ __launch_bounds__(256) void pack_kernel(State s, const uint32_t *slots, uint32_t count,
+                                                   RawState *raw, uint32_t to_raw) {
+    const uint32_t k = blockIdx.x;
+    if (k >= count) return;
+    const uint32_t slot = slots[k];
+    const uint32_t E = s.num;
+    const uint32_t q = threadIdx.x;
+    RawState &r = raw[k];
+    uint4 *ram = reinterpret_cast<uint4 *>(s.ram + (size_t)slot * kMem);
+    uint4 *rram = reinterpret_cast<uint4 *>(r.ram);
+    uint32_t *cols = s.cols + (size_t)slot * 256;
+    if (to_raw) {
+        rram[q] = ram[q];
+        r.cols[q] = cols[q];
+        if (q < 32) r.fb[q] = s.fb[(size_t)slot * 32 + q];
+        if (q < 8) r.stack[q] = s.stack[(size_t)slot * 8 + q];
+        if (q < 4) r.regs[q] = s.regs[q * E + slot];
+        if (q == 0) {
+            r.pc_i = s.pc_i[slot];
+            r.misc = s.misc[slot];
+            r.t = s.t[slot];
+            r.prev = s.prev[slot];
+            r.rng = s.rng[slot];
+            r.dirty = s.dirty[slot];
+        }
+    } else {
+        ram[q] = rram[q];
+        cols[q] = r.cols[q];
+        if (q < 32) s.fb[(size_t)slot * 32 + q] = r.fb[q];
+        if (q < 8) s.stack[(size_t)slot * 8 + q] = r.stack[q];
+        if (q < 4) s.regs[q * E + slot] = r.regs[q];
+        if (q == 0) {
+            s.pc_i[slot] = r.pc_i;
+            s.misc[slot] = r.misc;
+            s.t[slot] = r.t;
+            s.prev[slot] = r.prev;
+            s.rng[slot] = r.rng;
+            s.dirty[slot] = r.dirty;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_pack(const State &s, const uint32_t *slot_list, uint32_t count, RawState *raw,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(pack_kernel, dim3(count), dim3(256), 0, st, s, slot_list, count, raw, 1u);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const State &s, const uint32_t *slot_list, uint32_t count,
+                         const RawState *raw, hipStream_t st) {
+    hipLaunchKernelGGL(pack_kernel, dim3(count), dim3(256), 0, st, s, slot_list, count,
+                       const_cast<RawState *>(raw), 0u);
+    return hipGetLastError();
+}
+
+}  // namespace octax

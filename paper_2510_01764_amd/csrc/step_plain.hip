@@ -1,0 +1,157 @@
+// Plain step kernel: one env per lane, every field of the env's state read
+// from and written back to HBM on every step, memory and display accessed in
+// HBM/L2, observations stored by each lane for its own env.  This is the
+// direct lane-per-instance mapping of a vectorised environment step and the
+// baseline the fused kernel is measured against.
+#include "octax_core.h"
+#include "octax_kernels.h"
+
+namespace octax {
+namespace {
+
+struct PlainMem {
+    uint8_t *ram;
+    uint64_t *fb;
+    uint32_t *stack;
+    uint64_t dirty;
+
+    __device__ __forceinline__ uint32_t read(uint32_t a) const { return ram[a]; }
+    __device__ __forceinline__ void write(uint32_t a, uint32_t v) {
+        ram[a] = (uint8_t)v;
+        dirty |= 1ull << (a >> 6);
+    }
+    // XOR rows of the sprite onto the display; bits past x = 63 fall off the
+    // right of the shifted mask, rows past y = 31 are skipped.
+    __device__ __forceinline__ uint32_t draw(uint32_t x0, uint32_t y0, uint32_t I, uint32_t n) {
+        uint64_t hit = 0;
+        for (uint32_t r = 0; r < n; r++) {
+            const uint32_t yy = y0 + r;
+            if (yy >= 32) break;
+            const uint64_t m = ((uint64_t)ram[(I + r) & 0xFFF] << 56) >> x0;
+            const uint64_t row = fb[yy];
+            hit |= row & m;
+            fb[yy] = row ^ m;
+        }
+        return hit != 0;
+    }
+    __device__ __forceinline__ void clear() {
+        for (int y = 0; y < 32; y++) fb[y] = 0;
+    }
+    __device__ __forceinline__ uint32_t stack_get(uint32_t i) const {
+        const uint32_t w = stack[i >> 1];
+        return (i & 1) ? (w >> 16) : (w & 0xFFFF);
+    }
+    __device__ __forceinline__ void stack_set(uint32_t i, uint32_t v) {
+        const uint32_t w = stack[i >> 1];
+        stack[i >> 1] = (i & 1) ? ((w & 0xFFFFu) | (v << 16)) : ((w & 0xFFFF0000u) | v);
+    }
+};
+
+__global__ __launch_bounds__(256) void step_plain_kernel(State s, Roms roms, StepIO io, uint32_t k) {
+    const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
+    if (slot >= s.num) return;
+    const uint32_t E = s.num;
+    const uint32_t env = s.env_of[slot];
+    const uint32_t rom = s.rom_of[slot];
+    const uint32_t desc = roms.desc[rom];
+
+    Core c;
+    uint32_t head;
+    load_core(s, slot, c, head);
+    const uint32_t key = action_key(roms, rom, desc, io.action[(size_t)k * E + env]);
+    PlainMem mem{s.ram + (size_t)slot * kMem, s.fb + (size_t)slot * 32, s.stack + (size_t)slot * 8,
+                 s.dirty[slot]};
+
+    for (uint32_t f = 0; f < io.frame_skip; f++) {
+        for (uint32_t i = 0; i < io.ipf; i++) exec_one(c, mem, key);
+        tick(c);
+    }
+
+    const int32_t score = (int32_t)vget(c.r, desc & 15);
+    int32_t prev = s.prev[slot];
+    const float reward = (float)(score - prev);
+    const uint32_t term = vget(c.r, (desc >> 8) & 15) == ((desc >> 16) & 0xFF);
+    uint32_t t = s.t[slot] + 1;
+    const uint32_t hor = s.horizon[slot];
+    const uint32_t trunc = (hor != 0) && (t >= hor);
+    const uint32_t done = term | (trunc << 1);
+    io.reward[(size_t)k * E + env] = reward;
+    io.done[(size_t)k * E + env] = (uint8_t)done;
+
+    uint32_t *ring = s.cols + (size_t)slot * 256;
+    uint8_t *obs = io.obs ? io.obs + ((size_t)(k % io.obs_slots) * E + env) * kObsBytes : nullptr;
+    if (done) {
+        // Automatic reset (Section 3.4): restore the pages written since the
+        // last reset, clear everything else; the RNG stream continues.
+        const uint8_t *img = roms.image + (size_t)rom * kMem;
+        uint64_t d = mem.dirty;
+        while (d) {
+            const uint32_t p = __builtin_ctzll(d);
+            d &= d - 1;
+            const uint4 *src = reinterpret_cast<const uint4 *>(img + p * 64);
+            uint4 *dst = reinterpret_cast<uint4 *>(mem.ram + p * 64);
+            for (int q = 0; q < 4; q++) dst[q] = src[q];
+        }
+        mem.dirty = 0;
+        reset_core(c);
+        mem.clear();
+        for (int q = 0; q < 8; q++) mem.stack[q] = 0;
+        uint4 *r4 = reinterpret_cast<uint4 *>(ring);
+        for (int q = 0; q < 64; q++) r4[q] = make_uint4(0, 0, 0, 0);
+        head = 0;
+        t = 0;
+        prev = 0;
+        if (obs) {
+            for (int q = 0; q < 512; q++) store_stream(obs + 16 * q, 0, 0, 0, 0);
+        }
+    } else {
+        prev = score;
+        uint32_t hi[32], lo[32];
+#pragma unroll
+        for (int r = 0; r < 32; r++) {
+            const uint64_t row = mem.fb[31 - r];
+            hi[r] = (uint32_t)(row >> 32);
+            lo[r] = (uint32_t)row;
+        }
+        rows_to_cols(hi, lo);
+        head = (head + 1) & 3;
+        uint32_t *dst = ring + head * 64;
+#pragma unroll
+        for (int x = 0; x < 32; x += 4) {
+            reinterpret_cast<uint4 *>(dst)[x / 4] = make_uint4(hi[x], hi[x + 1], hi[x + 2], hi[x + 3]);
+            reinterpret_cast<uint4 *>(dst + 32)[x / 4] = make_uint4(lo[x], lo[x + 1], lo[x + 2], lo[x + 3]);
+        }
+        if (obs) {
+            // frames 0..2: the three older ring entries, oldest first
+            for (uint32_t fr = 0; fr < 3; fr++) {
+                const uint32_t *src = ring + ((head + 1 + fr) & 3) * 64;
+                uint8_t *o = obs + fr * 2048;
+                for (int x = 0; x < 64; x++) store_column(o + x * 32, src[x]);
+            }
+            uint8_t *o = obs + 3 * 2048;
+#pragma unroll
+            for (int x = 0; x < 32; x++) {
+                store_column(o + x * 32, hi[x]);
+                store_column(o + (32 + x) * 32, lo[x]);
+            }
+        }
+    }
+    store_core(s, slot, c, head);
+    s.t[slot] = t;
+    s.prev[slot] = prev;
+    s.dirty[slot] = mem.dirty;
+}
+
+}  // namespace
+
+hipError_t launch_step_plain(const State &s, const Roms &r, const StepIO &io, hipStream_t st) {
+    const uint32_t blocks = (s.num + 255) / 256;
+    for (uint32_t k = 0; k < io.K; k++) {
+        hipLaunchKernelGGL(step_plain_kernel, dim3(blocks), dim3(256), 0, st, s, r, io, k);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace octax

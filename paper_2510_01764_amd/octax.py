@@ -1,0 +1,339 @@
+"""Python binding of liboctax (the C ABI in include/octax.h).
+
+Argument marshalling only: every step of the environment runs in the HIP
+kernels of liboctax.so.  torch supplies device memory and streams.  The
+library must be built (``python -m paper_2510_01764_amd.build``); importing
+this module on a machine without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liboctax.so")
+
+OCTAX_ABI_VERSION = 1
+OCTAX_QUIRKS_V1 = 1
+OCTAX_OK = 0
+OCTAX_E_INVALID = -1
+OCTAX_E_NOMEM = -2
+OCTAX_E_HIP = -3
+OCTAX_E_STATE = -4
+OCTAX_KERNEL_PLAIN = 0
+OCTAX_KERNEL_FUSED = 1
+OCTAX_PLACE_IDENTITY = 0
+OCTAX_PLACE_BY_ROM = 1
+OBS_BYTES = 8192
+
+EXPORTED = (
+    "octax_create", "octax_reset", "octax_step", "octax_step_many", "octax_graph_create",
+    "octax_graph_launch", "octax_graph_destroy", "octax_get_state", "octax_set_state",
+    "octax_set_kernel", "octax_set_tuning", "octax_set_stream", "octax_info", "octax_destroy",
+    "octax_last_error", "octax_calib_write", "octax_calib_copy",
+)
+
+
+class OctaxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"octax error {code}: {msg}")
+        self.code = code
+
+
+class octax_config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_uint32), ("num_envs", ctypes.c_uint32),
+        ("num_roms", ctypes.c_uint32), ("instr_per_frame", ctypes.c_uint32),
+        ("frame_skip", ctypes.c_uint32), ("quirks", ctypes.c_uint32),
+        ("kernel", ctypes.c_uint32), ("placement", ctypes.c_uint32),
+        ("envs_per_block", ctypes.c_uint32), ("lanes_per_env", ctypes.c_uint32),
+        ("rom_in_lds", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("h_rom_data", ctypes.c_void_p), ("h_rom_offset", ctypes.c_void_p),
+        ("h_rom_len", ctypes.c_void_p), ("h_env_rom", ctypes.c_void_p),
+        ("h_action_keys", ctypes.c_void_p), ("h_num_actions", ctypes.c_void_p),
+        ("h_score_reg", ctypes.c_void_p), ("h_term_reg", ctypes.c_void_p),
+        ("h_term_value", ctypes.c_void_p), ("h_horizon", ctypes.c_void_p),
+        ("h_env_seed", ctypes.c_void_p), ("stream", ctypes.c_void_p),
+    ]
+
+
+# octax_env_state as a numpy structured dtype (C layout, natural alignment).
+ENV_STATE_DTYPE = np.dtype([
+    ("v", np.uint8, (16,)), ("i", np.uint16), ("pc", np.uint16), ("sp", np.uint8),
+    ("dt", np.uint8), ("st", np.uint8), ("reserved", np.uint8), ("stack", np.uint16, (16,)),
+    ("t", np.uint32), ("prev_score", np.int32), ("rng", np.uint64), ("ram", np.uint8, (4096,)),
+    ("fb", np.uint64, (32,)), ("hist", np.uint64, (3, 32)),
+], align=True)
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Load liboctax.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2510_01764_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P, u32, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32
+    sig = {
+        "octax_create": ([ctypes.POINTER(octax_config), ctypes.POINTER(P)], i32),
+        "octax_reset": ([P, P, P], i32),
+        "octax_step": ([P, P, P, P, P], i32),
+        "octax_step_many": ([P, u32, P, P, u32, P, P], i32),
+        "octax_graph_create": ([P, u32, P, P, u32, P, P, ctypes.POINTER(P)], i32),
+        "octax_graph_launch": ([P], i32),
+        "octax_graph_destroy": ([P], i32),
+        "octax_get_state": ([P, u32, u32, P], i32),
+        "octax_set_state": ([P, u32, u32, P], i32),
+        "octax_set_kernel": ([P, u32], i32),
+        "octax_set_tuning": ([P, u32, u32], i32),
+        "octax_set_stream": ([P, P], i32),
+        "octax_info": ([P, ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_uint64)], i32),
+        "octax_destroy": ([P], i32),
+        "octax_last_error": ([], ctypes.c_char_p),
+        "octax_calib_write": ([P, ctypes.c_uint64, u32, P], i32),
+        "octax_calib_copy": ([P, P, ctypes.c_uint64, P], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != OCTAX_OK:
+        raise OctaxError(code, library().octax_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a contiguous torch tensor (None passes NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    return int(getattr(stream, "cuda_stream", stream)) or None
+
+
+# ---------------------------------------------------------------------------
+# Thin functions with the C names (arguments are torch tensors or None)
+# ---------------------------------------------------------------------------
+
+def octax_reset(eng, d_mask=None, d_obs=None):
+    _check(library().octax_reset(eng, _ptr(d_mask), _ptr(d_obs)))
+
+
+def octax_step(eng, d_action, d_obs, d_reward, d_done):
+    _check(library().octax_step(eng, _ptr(d_action), _ptr(d_obs), _ptr(d_reward), _ptr(d_done)))
+
+
+def octax_step_many(eng, K, d_action, d_obs, obs_slots, d_reward, d_done):
+    _check(library().octax_step_many(eng, K, _ptr(d_action), _ptr(d_obs), obs_slots,
+                                     _ptr(d_reward), _ptr(d_done)))
+
+
+def octax_destroy(eng):
+    _check(library().octax_destroy(eng))
+
+
+class Engine:
+    """One liboctax engine built from a ``workload.EnvSpec``.
+
+    Output buffers are torch tensors on the engine's device: obs uint8
+    [E, 4, 64, 32] (or [slots, E, 4, 64, 32]), reward float32 [E] ([K, E]),
+    done uint8 [E] ([K, E]); actions int32 [E] ([K, E]).
+    """
+
+    def __init__(self, spec, kernel: str = "fused", placement: Optional[str] = None,
+                 envs_per_block: int = 256, rom_in_lds: bool = True, stream=None):
+        import torch  # noqa: F401  (device memory for the caller's buffers)
+        L = library()
+        self.spec = spec
+        self.E = int(spec.num_envs)
+        roms = spec.roms
+        data = np.frombuffer(b"".join(roms) or b"\0", dtype=np.uint8).copy()
+        lens = np.array([len(r) for r in roms], dtype=np.uint32)
+        offs = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint32)
+        keep = dict(
+            data=data, lens=lens, offs=offs,
+            env_rom=np.ascontiguousarray(spec.env_rom, dtype=np.uint16),
+            akeys=np.ascontiguousarray(spec.action_keys, dtype=np.uint8),
+            nact=np.ascontiguousarray(spec.num_actions, dtype=np.uint8),
+            sreg=np.ascontiguousarray(spec.score_reg, dtype=np.uint8),
+            treg=np.ascontiguousarray(spec.term_reg, dtype=np.uint8),
+            tval=np.ascontiguousarray(spec.term_value, dtype=np.uint8),
+            hor=np.ascontiguousarray(spec.horizon, dtype=np.uint32),
+            seed=np.ascontiguousarray(spec.env_seed, dtype=np.uint64))
+        if placement is None:
+            placement = "by_rom" if kernel == "fused" else "identity"
+        cfg = octax_config()
+        cfg.abi_version = OCTAX_ABI_VERSION
+        cfg.num_envs = self.E
+        cfg.num_roms = len(roms)
+        cfg.instr_per_frame = int(spec.instr_per_frame)
+        cfg.frame_skip = int(spec.frame_skip)
+        cfg.quirks = OCTAX_QUIRKS_V1
+        cfg.kernel = {"plain": OCTAX_KERNEL_PLAIN, "fused": OCTAX_KERNEL_FUSED}[kernel]
+        cfg.placement = {"identity": OCTAX_PLACE_IDENTITY, "by_rom": OCTAX_PLACE_BY_ROM}[placement]
+        cfg.envs_per_block = int(envs_per_block)
+        cfg.lanes_per_env = 1
+        cfg.rom_in_lds = 1 if rom_in_lds else 0
+        cfg.h_rom_data = keep["data"].ctypes.data
+        cfg.h_rom_offset = keep["offs"].ctypes.data
+        cfg.h_rom_len = keep["lens"].ctypes.data
+        cfg.h_env_rom = keep["env_rom"].ctypes.data
+        cfg.h_action_keys = keep["akeys"].ctypes.data
+        cfg.h_num_actions = keep["nact"].ctypes.data
+        cfg.h_score_reg = keep["sreg"].ctypes.data
+        cfg.h_term_reg = keep["treg"].ctypes.data
+        cfg.h_term_value = keep["tval"].ctypes.data
+        cfg.h_horizon = keep["hor"].ctypes.data
+        cfg.h_env_seed = keep["seed"].ctypes.data
+        cfg.stream = _stream_handle(stream)
+        h = ctypes.c_void_p()
+        _check(L.octax_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.kernel = kernel
+        self.placement = placement
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(library().octax_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _need(self, t, dtype, shape, name):
+        import torch
+        if t is None:
+            return
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must be a device tensor")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        del torch
+
+    def reset(self, mask=None, obs=None):
+        import torch
+        self._need(mask, torch.uint8, (self.E,), "mask")
+        self._need(obs, torch.uint8, (self.E, 4, 64, 32), "obs")
+        _check(library().octax_reset(self._h, _ptr(mask), _ptr(obs)))
+
+    def step(self, action, obs, reward, done):
+        import torch
+        self._need(action, torch.int32, (self.E,), "action")
+        self._need(obs, torch.uint8, (self.E, 4, 64, 32), "obs")
+        self._need(reward, torch.float32, (self.E,), "reward")
+        self._need(done, torch.uint8, (self.E,), "done")
+        _check(library().octax_step(self._h, _ptr(action), _ptr(obs), _ptr(reward), _ptr(done)))
+
+    def step_many(self, action, obs, reward, done):
+        import torch
+        K = int(action.shape[0])
+        self._need(action, torch.int32, (K, self.E), "action")
+        slots = 0 if obs is None else int(obs.shape[0])
+        self._need(obs, torch.uint8, (slots, self.E, 4, 64, 32), "obs")
+        self._need(reward, torch.float32, (K, self.E), "reward")
+        self._need(done, torch.uint8, (K, self.E), "done")
+        _check(library().octax_step_many(self._h, K, _ptr(action), _ptr(obs), slots,
+                                         _ptr(reward), _ptr(done)))
+
+    def graph(self, action, obs, reward, done) -> "Graph":
+        import torch
+        K = int(action.shape[0])
+        self._need(action, torch.int32, (K, self.E), "action")
+        slots = 0 if obs is None else int(obs.shape[0])
+        self._need(obs, torch.uint8, (slots, self.E, 4, 64, 32), "obs")
+        self._need(reward, torch.float32, (K, self.E), "reward")
+        self._need(done, torch.uint8, (K, self.E), "done")
+        g = ctypes.c_void_p()
+        _check(library().octax_graph_create(self._h, K, _ptr(action), _ptr(obs), slots,
+                                            _ptr(reward), _ptr(done), ctypes.byref(g)))
+        return Graph(g, (action, obs, reward, done))
+
+    def get_state(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        count = self.E - first if count is None else int(count)
+        out = np.zeros(count, dtype=ENV_STATE_DTYPE)
+        _check(library().octax_get_state(self._h, first, count, out.ctypes.data))
+        return out
+
+    def set_state(self, first: int, states: np.ndarray):
+        s = np.ascontiguousarray(states, dtype=ENV_STATE_DTYPE)
+        _check(library().octax_set_state(self._h, first, len(s), s.ctypes.data))
+
+    def set_kernel(self, kernel: str):
+        _check(library().octax_set_kernel(self._h, {"plain": 0, "fused": 1}[kernel]))
+        self.kernel = kernel
+
+    def set_tuning(self, envs_per_block: int, rom_in_lds: bool):
+        _check(library().octax_set_tuning(self._h, int(envs_per_block), 1 if rom_in_lds else 0))
+
+    def set_stream(self, stream):
+        _check(library().octax_set_stream(self._h, _stream_handle(stream)))
+
+    def info(self):
+        n = ctypes.c_uint32()
+        b = ctypes.c_uint64()
+        _check(library().octax_info(self._h, ctypes.byref(n), ctypes.byref(b)))
+        return int(n.value), int(b.value)
+
+
+class Graph:
+    """A captured K-step launch over fixed buffers (octax_graph_*)."""
+
+    def __init__(self, handle, buffers):
+        self._h = handle
+        self._buffers = buffers   # keep the captured buffers alive
+
+    def launch(self):
+        _check(library().octax_graph_launch(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(library().octax_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def canonical(states: np.ndarray) -> dict:
+    """Architectural state in the oracle's comparison format (pixels unpacked)."""
+    def unpack_rows(rows):
+        bits = ((rows[..., None] >> np.arange(63, -1, -1, dtype=np.uint64)) & np.uint64(1))
+        return bits.astype(np.uint8)  # [..., 32, 64] = [y][x]
+    return {
+        "v": states["v"].copy(), "i": states["i"].astype(np.uint16), "pc": states["pc"].astype(np.uint16),
+        "sp": states["sp"].astype(np.uint8), "dt": states["dt"].copy(), "st": states["st"].copy(),
+        "stack": states["stack"].copy(), "t": states["t"].copy(),
+        "prev_score": states["prev_score"].copy(), "rng": states["rng"].copy(),
+        "mem": states["ram"].copy(), "disp": unpack_rows(states["fb"]),
+        "hist": unpack_rows(states["hist"]),
+    }

@@ -1,0 +1,59 @@
+"""Side-by-side runs of the HIP engine and the CPU oracle on the same inputs."""
+import numpy as np
+
+FIELDS = ("v", "i", "pc", "sp", "dt", "st", "stack", "t", "prev_score", "rng", "mem", "disp", "hist")
+
+
+def compare_states(gpu_states, oracle_states, where=""):
+    from oracle import oracle as O
+    from paper_2510_01764_amd import octax as X
+    g = X.canonical(gpu_states)
+    o = O.canonical(oracle_states)
+    for f in FIELDS:
+        a, b = np.asarray(g[f]), np.asarray(o[f])
+        if a.shape != b.shape or not np.array_equal(a, b):
+            bad = np.argwhere(a != b) if a.shape == b.shape else "shape"
+            raise AssertionError(f"{where}: field {f} differs (first mismatches {bad[:5] if not isinstance(bad, str) else bad})")
+
+
+class Pair:
+    """An engine and an oracle batch stepped in lockstep."""
+
+    def __init__(self, spec, kernel="fused", placement=None, envs_per_block=256, rom_in_lds=True):
+        import torch
+        from oracle import oracle as O
+        from paper_2510_01764_amd import octax as X
+        self.torch = torch
+        self.spec = spec
+        self.E = spec.num_envs
+        self.eng = X.Engine(spec, kernel=kernel, placement=placement, envs_per_block=envs_per_block,
+                            rom_in_lds=rom_in_lds)
+        self.orc = O.OracleBatch(spec)
+        dev = torch.device("cuda")
+        self.obs = torch.zeros((self.E, 4, 64, 32), dtype=torch.uint8, device=dev)
+        self.rew = torch.zeros(self.E, dtype=torch.float32, device=dev)
+        self.done = torch.zeros(self.E, dtype=torch.uint8, device=dev)
+        self.act = torch.zeros(self.E, dtype=torch.int32, device=dev)
+
+    def step(self, actions_np, check_obs=True):
+        torch = self.torch
+        self.act.copy_(torch.from_numpy(np.ascontiguousarray(actions_np, dtype=np.int32)))
+        self.eng.step(self.act, self.obs if check_obs else None, self.rew, self.done)
+        oo, orw, od = self.orc.step(actions_np, want_obs=check_obs)
+        torch.cuda.synchronize()
+        gr, gd = self.rew.cpu().numpy(), self.done.cpu().numpy()
+        assert np.array_equal(gr, orw), f"reward differs at envs {np.nonzero(gr != orw)[0][:8]}"
+        assert np.array_equal(gd, od), f"done differs at envs {np.nonzero(gd != od)[0][:8]}"
+        if check_obs:
+            go = self.obs.cpu().numpy()
+            if not np.array_equal(go, oo):
+                bad = np.unique(np.nonzero(go != oo)[0])
+                raise AssertionError(f"obs differs at envs {bad[:8]}")
+        return gr, gd
+
+    def check_state(self, where=""):
+        compare_states(self.eng.get_state(), self.orc.get_state(), where)
+
+    def close(self):
+        self.eng.close()
+        self.orc.close()

@@ -1,0 +1,113 @@
+"""CPU checks of the C ABI library: it loads, exports every declared symbol,
+and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2510_01764_amd import octax as X
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(octax_\w+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = X.library()
+    declared = _declared()
+    assert {"octax_create", "octax_reset", "octax_step", "octax_destroy"} <= declared
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    for name in X.EXPORTED:
+        assert name in declared, f"{name} is bound but not declared in include/"
+
+
+def test_struct_layouts_match_header():
+    # sizes computed by a C compiler from the header itself
+    import subprocess
+    import tempfile
+    src = ('#include <stdio.h>\n#include <stddef.h>\n#include "octax.h"\n'
+           'int main(){printf("%zu %zu %zu %zu\\n", sizeof(octax_config), sizeof(octax_env_state),'
+           ' offsetof(octax_env_state, ram), offsetof(octax_config, h_rom_data));}\n')
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "s")
+        subprocess.check_call(["gcc", "-I" + os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe]).decode().split()
+    assert int(out[0]) == ctypes.sizeof(X.octax_config)
+    assert int(out[1]) == X.ENV_STATE_DTYPE.itemsize
+    assert int(out[2]) == X.ENV_STATE_DTYPE.fields["ram"][1]
+    assert int(out[3]) == X.octax_config.h_rom_data.offset
+
+
+def _cfg(**over):
+    import numpy as np
+    keep = dict(rom=np.frombuffer(bytes([0x12, 0x00]), dtype=np.uint8).copy(),
+                off=np.zeros(1, np.uint32), ln=np.array([2], np.uint32),
+                env_rom=np.zeros(4, np.uint16), keys=np.zeros(16, np.uint8),
+                nact=np.array([5], np.uint8), reg=np.array([5], np.uint8),
+                hor=np.zeros(4, np.uint32), seed=np.zeros(4, np.uint64))
+    c = X.octax_config()
+    c.abi_version = X.OCTAX_ABI_VERSION
+    c.num_envs, c.num_roms, c.instr_per_frame, c.frame_skip = 4, 1, 10, 4
+    c.quirks = X.OCTAX_QUIRKS_V1
+    c.h_rom_data, c.h_rom_offset, c.h_rom_len = keep["rom"].ctypes.data, keep["off"].ctypes.data, keep["ln"].ctypes.data
+    c.h_env_rom, c.h_action_keys, c.h_num_actions = keep["env_rom"].ctypes.data, keep["keys"].ctypes.data, keep["nact"].ctypes.data
+    c.h_score_reg = c.h_term_reg = c.h_term_value = keep["reg"].ctypes.data
+    c.h_horizon, c.h_env_seed = keep["hor"].ctypes.data, keep["seed"].ctypes.data
+    for k, v in over.items():
+        setattr(c, k, v)
+    return c, keep
+
+
+@pytest.mark.parametrize("field,value", [
+    ("abi_version", 99), ("quirks", 2), ("num_envs", 0), ("num_roms", 0), ("instr_per_frame", 0),
+    ("frame_skip", 0), ("frame_skip", 65), ("kernel", 7), ("placement", 9), ("envs_per_block", 96),
+    ("lanes_per_env", 4), ("h_env_seed", None),
+])
+def test_create_rejects_bad_config_without_gpu(field, value):
+    L = X.library()
+    c, keep = _cfg(**{field: value})
+    h = ctypes.c_void_p()
+    rc = L.octax_create(ctypes.byref(c), ctypes.byref(h))
+    assert rc == X.OCTAX_E_INVALID and not h.value
+    assert L.octax_last_error().decode()
+
+
+def test_create_rejects_long_rom_and_bad_rom_index():
+    import numpy as np
+    L = X.library()
+    c, keep = _cfg()
+    keep["ln"][0] = 3585
+    h = ctypes.c_void_p()
+    assert L.octax_create(ctypes.byref(c), ctypes.byref(h)) == X.OCTAX_E_INVALID
+    c, keep = _cfg()
+    keep["env_rom"][2] = 1
+    assert L.octax_create(ctypes.byref(c), ctypes.byref(h)) == X.OCTAX_E_INVALID
+    c, keep = _cfg()
+    keep["keys"][0] = 16
+    assert L.octax_create(ctypes.byref(c), ctypes.byref(h)) == X.OCTAX_E_INVALID
+    del np
+
+
+def test_null_engine_calls_fail_cleanly():
+    L = X.library()
+    assert L.octax_step(None, None, None, None, None) == X.OCTAX_E_INVALID
+    assert L.octax_step_many(None, 1, None, None, 1, None, None) == X.OCTAX_E_INVALID
+    assert L.octax_reset(None, None, None) == X.OCTAX_E_INVALID
+    assert L.octax_get_state(None, 0, 1, None) == X.OCTAX_E_INVALID
+    assert L.octax_set_kernel(None, 0) == X.OCTAX_E_INVALID
+    assert L.octax_set_tuning(None, 256, 1) == X.OCTAX_E_INVALID
+    assert L.octax_graph_launch(None) == X.OCTAX_E_INVALID
+    assert L.octax_destroy(None) == X.OCTAX_OK
+    assert L.octax_create(None, None) == X.OCTAX_E_INVALID
