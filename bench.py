@@ -1,0 +1,257 @@
+"""Benchmark: batched CHIP-8 environment step on one MI355X.
+
+Workload: 65,536 envs over 16 seed-generated ROMs mixed within every
+wavefront (256-1792 instructions, draw share 5-40%, branch share 10-30%),
+10 instructions per frame, frame skip 4, (4, 64, 32) uint8 observations,
+geometric truncation horizons (mean 500), auto-reset.  One benchmark step is
+one replay of a captured HIP graph holding one fused launch of 64
+environment steps over all envs (64 x 65,536 env steps); actions for each
+replay are copied into the graph's action buffer from a pool already in HBM.
+The same inputs are then run through the plain one-env-per-lane kernel.
+
+Prints one JSON line on stdout.  Everything else goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+ALGO_BYTES_PER_ENV_STEP = 8192 + 4 + 1 + 4   # obs + reward + done + action
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_fused_c3_traffic.json")
+KERNEL_SOURCES = ["step_fused.hip", "octax_grouped.h", "octax_core.h", "octax_device.h", "octax_kernels.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_01764_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the kernel source as it is now; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(spec, sample_envs: int, sample_steps: int):
+    """The CPU oracle on a bounded sample of the same workload."""
+    from oracle import oracle as O
+    cores = min(16, len(os.sched_getaffinity(0)))
+    sub = spec.subset(list(range(sample_envs)), name="cpu-sample")
+    orc = O.OracleBatch(sub)
+    acts = spec.actions(0, sample_steps)[:, :sample_envs]
+    t0 = time.perf_counter()
+    _, _, used = orc.run_threaded(acts, cores)
+    dt = time.perf_counter() - t0
+    orc.close()
+    return {"value": sample_envs * sample_steps / dt, "unit": "env steps/s", "cores": int(used),
+            "kind": "oracle",
+            "sample": f"first {sample_envs} envs of the workload x {sample_steps} steps, observations "
+                      f"materialised every step, {used} POSIX threads, {dt:.2f} s wall"}
+
+
+def time_replays(torch, stream, graph, act_buf, act_pool, n, start):
+    """Launch n replays; per-replay durations (ms) from events on the engine's stream."""
+    evs = []
+    for i in range(n):
+        with torch.cuda.stream(stream):
+            act_buf.copy_(act_pool[(start + i) % act_pool.shape[0]], non_blocking=True)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            graph.launch()
+            e1.record(stream)
+        evs.append((e0, e1))
+    return evs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed graph replays (64 env steps each)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--envs", type=int, default=65536)
+    ap.add_argument("--k", type=int, default=64, help="env steps per replay")
+    ap.add_argument("--latency-steps", type=int, default=50)
+    ap.add_argument("--cpu-envs", type=int, default=16384)
+    ap.add_argument("--cpu-steps", type=int, default=96)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--tune", choices=["auto", "default"], default="auto")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only; launch it without torch.distributed", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2510_01764_amd import octax as X
+    from paper_2510_01764_amd import workload as W
+    from paper_2510_01764_amd import autotune as T
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    spec = W.make_config("c3", num_envs=args.envs)
+    E, K = spec.num_envs, args.k
+    stream = torch.cuda.Stream(device=dev)
+
+    n_pool = max(1, min(args.warmup + args.steps, 8))
+    act_pool = torch.from_numpy(spec.actions(0, n_pool * K).reshape(n_pool, K, E)).to(dev)
+    act = torch.empty((K, E), dtype=torch.int32, device=dev)
+    obs = torch.empty((K, E, 4, 64, 32), dtype=torch.uint8, device=dev)
+    rew = torch.empty((K, E), dtype=torch.float32, device=dev)
+    done = torch.empty((K, E), dtype=torch.uint8, device=dev)
+
+    # calibration: attainable write bandwidth and a copy of known size (its
+    # counters scale the HBM byte counters of the step kernel)
+    calib_bytes = 1 << 30
+    cbuf = torch.empty(2 * calib_bytes, dtype=torch.uint8, device=dev)
+    L = X.library()
+    with torch.cuda.stream(stream):
+        for _ in range(2):
+            L.octax_calib_write(cbuf.data_ptr(), 2 * calib_bytes, 7, 0, stream.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            L.octax_calib_write(cbuf.data_ptr(), 2 * calib_bytes, 7, 0, stream.cuda_stream)
+        e1.record(stream)
+        L.octax_calib_copy(cbuf.data_ptr(), cbuf.data_ptr() + calib_bytes, calib_bytes, stream.cuda_stream)
+    stream.synchronize()
+    write_gbs = 5 * 2 * calib_bytes / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del cbuf
+    log(f"calibration: streaming write {write_gbs:.0f} GB/s")
+
+    # fused engine, tuned for this workload
+    act.copy_(act_pool[0])
+    tuning = (T.default_tuning() if args.tune == "default" else
+              T.tune(spec, K=K, stream=stream, log=log, buffers=(act, obs, rew, done), use_cache=False))
+    eng = X.Engine(spec, kernel="fused", envs_per_block=tuning["envs_per_block"],
+                   rom_in_lds=tuning["rom_in_lds"], stream=stream)
+    graph = eng.graph(act, obs, rew, done)
+    for ev in time_replays(torch, stream, graph, act, act_pool, args.warmup, 0):
+        pass
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = time_replays(torch, stream, graph, act, act_pool, args.steps, args.warmup)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    replay_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    value = E * K * args.steps / wall
+    kernel_ms = float(replay_ms.mean())
+
+    # single-step latency: octax_step (one fused launch of K = 1) over all envs
+    a1 = act_pool[0, 0].contiguous()
+    obs1, rew1, done1 = obs[0], rew[0], done[0]
+    lat = []
+    for i in range(5 + args.latency_steps):
+        with torch.cuda.stream(stream):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            eng.step(a1, obs1, rew1, done1)
+            e1.record(stream)
+        stream.synchronize()
+        if i >= 5:
+            lat.append(e0.elapsed_time(e1))
+    lat = np.array(lat if lat else [float("nan")])
+    graph.close()
+    eng.close()
+
+    # plain kernel on identical inputs (fresh engine, same seeds and actions)
+    plain = None
+    if not args.no_plain:
+        engp = X.Engine(spec, kernel="plain", stream=stream)
+        gp = engp.graph(act, obs, rew, done)
+        time_replays(torch, stream, gp, act, act_pool, 1, 0)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        pevs = time_replays(torch, stream, gp, act, act_pool, max(2, args.steps // 4), args.warmup)
+        stream.synchronize()
+        pwall = time.perf_counter() - t0
+        n_p = max(2, args.steps // 4)
+        plain = {"value": E * K * n_p / pwall, "ms_per_step": pwall * 1e3 / n_p,
+                 "replays": n_p}
+        gp.close()
+        engp.close()
+
+    algo_per_launch = E * K * ALGO_BYTES_PER_ENV_STEP
+    achieved = algo_per_launch / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": "env steps/s @65,536 envs mixed-ROM (fused vs plain), p99 step latency",
+        "value": value,
+        "unit": "env steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic: seed-generated CHIP-8 ROMs and uniform random actions",
+        "config": {
+            "workload": "mixed-ROM batching: 65,536 envs over 16 seed-generated ROMs, 64 env steps "
+                        "per graph replay, ipf 10, frame skip 4, 4x64x32 uint8 obs, geometric "
+                        "horizons mean 500, auto-reset",
+            "envs": E, "roms": spec.num_roms, "env_steps_per_bench_step": E * K,
+            "instr_per_frame": spec.instr_per_frame, "frame_skip": spec.frame_skip,
+            "kernel": "fused", "envs_per_block": tuning["envs_per_block"],
+            "lanes_per_env": 1, "rom_in_lds": bool(tuning["rom_in_lds"]), "placement": "by_rom",
+        },
+        "frames_per_s": 4 * value,
+        "chip8_instr_per_s": value * spec.instr_per_frame * spec.frame_skip,
+        "p50_step_latency_ms": float(np.percentile(lat, 50)),
+        "p99_step_latency_ms": float(np.percentile(lat, 99)),
+        "step_latency_def": "octax_step on all 65,536 envs (one fused launch, K = 1), HIP events on the engine's stream",
+        "replay_ms_p50": float(np.percentile(replay_ms, 50)),
+        "replay_ms_p99": float(np.percentile(replay_ms, 99)),
+        "plain": plain,
+        "fused_over_plain": (value / plain["value"]) if plain else None,
+        "calib_write_GBs": write_gbs,
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": f"step_fused_kernel<{tuning['envs_per_block']}>",
+            "algorithmic_bytes_per_launch": algo_per_launch,
+            "kernel_ms": kernel_ms,
+        },
+        "context": "paper: 350,000 env steps/s (Pong, constant action, RTX 3090) - other hardware and workload",
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(spec, min(args.cpu_envs, E), args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -245,14 +245,14 @@ int32_t octax_destroy(octax_engine *eng);
 
 /*
  * Roofline calibration (no part of the environment step): stream `bytes`
- * (a multiple of 16) of the 32-bit value v into d_dst, or copy `bytes` from
- * d_src to d_dst, asynchronously on `stream` (hipStream_t, NULL = null
- * stream).  The measured rate of these kernels on the same device is the
+ * (a multiple of 16) of the 32-bit value v into d_dst (nontemporal != 0: with
+ * the nontemporal store hint), or copy `bytes` from d_src to d_dst,
+ * asynchronously on `stream` (hipStream_t, NULL = null stream).  The measured rate of these kernels on the same device is the
  * attainable HBM bandwidth the step kernels are compared with, and the copy
  * kernel's hardware counters calibrate byte counters.  Returns 0, -1 for a
  * bad argument, -3 if the launch failed.
  */
-int32_t octax_calib_write(void *d_dst, uint64_t bytes, uint32_t v, void *stream);
+int32_t octax_calib_write(void *d_dst, uint64_t bytes, uint32_t v, uint32_t nontemporal, void *stream);
 int32_t octax_calib_copy(const void *d_src, void *d_dst, uint64_t bytes, void *stream);
 
 /* Message describing the last failure on this thread ("" if none). */

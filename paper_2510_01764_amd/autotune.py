@@ -1,0 +1,96 @@
+"""Autotuner for the fused step kernel.
+
+Searches envs-per-workgroup (64, 128, 256 envs, one lane each) and whether
+the workgroup's ROM images are staged in LDS, by timing graph replays of the
+real workload on the device, and caches the winner per (workload, device)
+in a JSON file.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from typing import Callable, Dict, Optional
+
+CANDIDATES = [(256, True), (256, False), (128, True), (128, False), (64, True)]
+CACHE = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")),
+                     "octax", "autotune.json")
+
+
+def default_tuning() -> Dict:
+    return {"envs_per_block": 256, "rom_in_lds": True}
+
+
+def workload_key(spec, K: int, device_name: str) -> str:
+    h = hashlib.sha256()
+    for r in spec.roms:
+        h.update(r)
+    h.update(spec.env_rom.tobytes())
+    return f"{device_name}|E={spec.num_envs}|R={spec.num_roms}|ipf={spec.instr_per_frame}|" \
+           f"fs={spec.frame_skip}|K={K}|{h.hexdigest()[:16]}"
+
+
+def _load_cache() -> Dict:
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(d: Dict):
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        tmp = CACHE + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1)
+        os.replace(tmp, CACHE)
+    except OSError:
+        pass
+
+
+def tune(spec, K: int = 64, stream=None, log: Callable = print, replays: int = 3,
+         buffers: Optional[tuple] = None, use_cache: bool = True) -> Dict:
+    """Time each candidate on `spec` (K env steps per graph replay) and return the fastest."""
+    import torch
+    from . import octax as X
+    dev = torch.device("cuda")
+    key = workload_key(spec, K, torch.cuda.get_device_name(dev))
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        log(f"autotune: cached {cache[key]}")
+        return cache[key]
+    E = spec.num_envs
+    Kt = K   # the launch shape that will run (same kernel instantiation and work per launch)
+    if buffers is None:
+        act = torch.from_numpy(spec.actions(0, Kt)).to(dev)
+        obs = torch.empty((Kt, E, 4, 64, 32), dtype=torch.uint8, device=dev)
+        rew = torch.empty((Kt, E), dtype=torch.float32, device=dev)
+        done = torch.empty((Kt, E), dtype=torch.uint8, device=dev)
+    else:
+        act, obs, rew, done = (b[:Kt] for b in buffers)
+    stream = stream or torch.cuda.current_stream(dev)
+    eng = X.Engine(spec, kernel="fused", stream=stream)
+    results = []
+    for ipw, lds in CANDIDATES:
+        eng.set_tuning(ipw, lds)
+        g = eng.graph(act, obs, rew, done)
+        with torch.cuda.stream(stream):
+            g.launch()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(replays):
+                g.launch()
+            e1.record(stream)
+        stream.synchronize()
+        ms = e0.elapsed_time(e1) / replays
+        g.close()
+        results.append((ms, ipw, lds))
+        log(f"autotune: envs_per_block={ipw} rom_in_lds={lds}: {ms / Kt * 1e3:.1f} us/step")
+    eng.close()
+    ms, ipw, lds = min(results)
+    best = {"envs_per_block": ipw, "rom_in_lds": lds, "us_per_step": ms / Kt * 1e3}
+    if use_cache:
+        cache[key] = best
+        _save_cache(cache)
+    return best

@@ -3,11 +3,19 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 extern "C" {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void octax_calib_write_kernel(u32x4 *dst, uint64_t n16, uint32_t v) {
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    const u32x4 val = {v, v, v, v};
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) dst[i] = val;
+}
+
+__global__ __launch_bounds__(256) void octax_calib_write_nt_kernel(u32x4 *dst, uint64_t n16, uint32_t v) {
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     const u32x4 val = {v, v, v, v};
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride)
@@ -20,19 +28,28 @@ __global__ __launch_bounds__(256) void octax_calib_copy_kernel(const uint4 *src,
         dst[i] = src[i];
 }
 
-// Stream `bytes` (a multiple of 16) of the value v into d_dst.
-int32_t octax_calib_write(void *d_dst, uint64_t bytes, uint32_t v, void *stream) {
+// Stream `bytes` (a multiple of 16) of the value v into d_dst; nontemporal
+// != 0 uses stores with the nontemporal hint.
+int32_t octax_calib_write(void *d_dst, uint64_t bytes, uint32_t v, uint32_t nontemporal, void *stream) {
     if (!d_dst || bytes % 16) return -1;
-    hipLaunchKernelGGL(octax_calib_write_kernel, dim3(256 * 8), dim3(256), 0, (hipStream_t)stream,
-                       (u32x4 *)d_dst, bytes / 16, v);
+    const uint64_t n16 = bytes / 16;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(256 * 32, (n16 + 255) / 256);
+    if (nontemporal)
+        hipLaunchKernelGGL(octax_calib_write_nt_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                           (u32x4 *)d_dst, n16, v);
+    else
+        hipLaunchKernelGGL(octax_calib_write_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                           (u32x4 *)d_dst, n16, v);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 // Copy `bytes` (a multiple of 16) from d_src to d_dst.
 int32_t octax_calib_copy(const void *d_src, void *d_dst, uint64_t bytes, void *stream) {
     if (!d_src || !d_dst || bytes % 16) return -1;
-    hipLaunchKernelGGL(octax_calib_copy_kernel, dim3(256 * 8), dim3(256), 0, (hipStream_t)stream,
-                       (const uint4 *)d_src, (uint4 *)d_dst, bytes / 16);
+    const uint64_t n16 = bytes / 16;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(256 * 32, (n16 + 255) / 256);
+    hipLaunchKernelGGL(octax_calib_copy_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const uint4 *)d_src, (uint4 *)d_dst, n16);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -2,11 +2,14 @@
 // advance PC, decode its nibbles, execute one of the 35 instructions) for one
 // machine held in registers.  Memory, display and stack live wherever the
 // kernel keeps them; a kernel supplies that through the `Mem` policy:
-//   uint32_t read(a)            byte at 12-bit address a
-//   void     write(a, v)        store byte (also marks its 64-byte page dirty)
-//   uint32_t draw(x0, y0, I, n) XOR an n-row sprite from memory at I onto the
-//                               display at (x0, y0), clipped; 1 on collision
-//   void     clear()            blank display
+//   uint32_t fetch(pc)              big-endian word at pc, pc+1 (12-bit wrap)
+//   u32x4    load_bytes(a, count)   bytes a .. a+count-1 (count 1..16), byte k
+//                                   of the result = memory[a + k], rest zero
+//   void     store_bytes(a, count, bytes)  the inverse (marks pages dirty)
+//   uint32_t draw(x0, y0, I, n)     XOR an n-row sprite from memory at I onto
+//                                   the display at (x0, y0), clipped;
+//                                   returns 1 on collision
+//   void     clear()                blank display
 //   uint32_t stack_get(i), void stack_set(i, v)
 // Semantics are those of the OCTAX_QUIRKS_V1 profile documented in octax.h.
 #pragma once
@@ -27,9 +30,35 @@ struct Core {
 
 __device__ __forceinline__ void skip(Core &c) { c.pc = (c.pc + 2) & 0xFFF; }
 
+// Mask of the first `count` bytes (0..16) of a 16-byte vector.
+__device__ __forceinline__ u32x4 byte_mask(uint32_t count) {
+    u32x4 m;
+    m.x = count >= 4 ? 0xFFFFFFFFu : (1u << (8 * count)) - 1;
+    m.y = count >= 8 ? 0xFFFFFFFFu : count <= 4 ? 0u : (1u << (8 * (count - 4))) - 1;
+    m.z = count >= 12 ? 0xFFFFFFFFu : count <= 8 ? 0u : (1u << (8 * (count - 8))) - 1;
+    m.w = count >= 16 ? 0xFFFFFFFFu : count <= 12 ? 0u : (1u << (8 * (count - 12))) - 1;
+    return m;
+}
+
+// Byte k (0..15) of a 16-byte vector; used with k a constant of an unrolled
+// loop, so the selection folds away.
+__device__ __forceinline__ uint32_t byte_of(const u32x4 &v, int k) {
+    const uint32_t w = k < 4 ? v.x : k < 8 ? v.y : k < 12 ? v.z : v.w;
+    return (w >> (8 * (k & 3))) & 0xFF;
+}
+
+// v with byte k (0..15, a constant of an unrolled loop) or-ed with b.
+__device__ __forceinline__ void or_byte(u32x4 &v, int k, uint32_t b) {
+    const uint32_t s = b << (8 * (k & 3));
+    if (k < 4) v.x |= s;
+    else if (k < 8) v.y |= s;
+    else if (k < 12) v.z |= s;
+    else v.w |= s;
+}
+
 template <class Mem>
 __device__ __forceinline__ void exec_one(Core &c, Mem &mem, uint32_t key) {
-    const uint32_t op = (mem.read(c.pc) << 8) | mem.read((c.pc + 1) & 0xFFF);
+    const uint32_t op = mem.fetch(c.pc);
     c.pc = (c.pc + 2) & 0xFFF;
     const uint32_t x = (op >> 8) & 0xF;
     const uint32_t y = (op >> 4) & 0xF;
@@ -98,7 +127,7 @@ __device__ __forceinline__ void exec_one(Core &c, Mem &mem, uint32_t key) {
         c.I = nnn;
         break;
     case 0xB:
-        c.pc = (nnn + (c.r.w0 & 0xFF)) & 0xFFF;
+        c.pc = (nnn + (c.r.w.x & 0xFF)) & 0xFFF;
         break;
     case 0xC:
         vset(c.r, x, rnd_byte(c.rng) & nn);
@@ -124,19 +153,23 @@ __device__ __forceinline__ void exec_one(Core &c, Mem &mem, uint32_t key) {
         case 0x18: c.st = vx; break;
         case 0x1E: c.I = (c.I + vx) & 0xFFF; break;
         case 0x29: c.I = kFont + 5 * (vx & 15); break;
-        case 0x33:
-            mem.write(c.I, vx / 100);
-            mem.write((c.I + 1) & 0xFFF, (vx / 10) % 10);
-            mem.write((c.I + 2) & 0xFFF, vx % 10);
+        case 0x33: {
+            const uint32_t bcd = (vx / 100) | (((vx / 10) % 10) << 8) | ((vx % 10) << 16);
+            mem.store_bytes(c.I, 3, u32x4{bcd, 0, 0, 0});
             break;
+        }
         case 0x55:
-            for (uint32_t k = 0; k <= x; k++) mem.write((c.I + k) & 0xFFF, vget(c.r, k));
+            // V0..VX are packed in memory order in the register vector
+            mem.store_bytes(c.I, x + 1, c.r.w);
             c.I = (c.I + x + 1) & 0xFFF;
             break;
-        case 0x65:
-            for (uint32_t k = 0; k <= x; k++) vset(c.r, k, mem.read((c.I + k) & 0xFFF));
+        case 0x65: {
+            const u32x4 b = mem.load_bytes(c.I, x + 1);
+            const u32x4 m = byte_mask(x + 1);
+            c.r.w = (c.r.w & ~m) | (b & m);
             c.I = (c.I + x + 1) & 0xFFF;
             break;
+        }
         default: break;
         }
         break;
@@ -152,10 +185,10 @@ __device__ __forceinline__ void tick(Core &c) {
 // Load / store the register part of an env's state from the SoA arrays.
 __device__ __forceinline__ void load_core(const State &s, uint32_t slot, Core &c, uint32_t &head) {
     const uint32_t E = s.num;
-    c.r.w0 = s.regs[0 * E + slot];
-    c.r.w1 = s.regs[1 * E + slot];
-    c.r.w2 = s.regs[2 * E + slot];
-    c.r.w3 = s.regs[3 * E + slot];
+    c.r.w.x = s.regs[0 * E + slot];
+    c.r.w.y = s.regs[1 * E + slot];
+    c.r.w.z = s.regs[2 * E + slot];
+    c.r.w.w = s.regs[3 * E + slot];
     const uint32_t pi = s.pc_i[slot];
     c.pc = pi & 0xFFF;
     c.I = (pi >> 16) & 0xFFF;
@@ -169,10 +202,10 @@ __device__ __forceinline__ void load_core(const State &s, uint32_t slot, Core &c
 
 __device__ __forceinline__ void store_core(const State &s, uint32_t slot, const Core &c, uint32_t head) {
     const uint32_t E = s.num;
-    s.regs[0 * E + slot] = c.r.w0;
-    s.regs[1 * E + slot] = c.r.w1;
-    s.regs[2 * E + slot] = c.r.w2;
-    s.regs[3 * E + slot] = c.r.w3;
+    s.regs[0 * E + slot] = c.r.w.x;
+    s.regs[1 * E + slot] = c.r.w.y;
+    s.regs[2 * E + slot] = c.r.w.z;
+    s.regs[3 * E + slot] = c.r.w.w;
     s.pc_i[slot] = c.pc | (c.I << 16);
     s.misc[slot] = c.sp | (c.dt << 8) | (c.st << 16) | (head << 24);
     s.rng[slot] = c.rng;
@@ -180,7 +213,7 @@ __device__ __forceinline__ void store_core(const State &s, uint32_t slot, const 
 
 // Power-on registers (Section 3.2, ROM loading and initialization).
 __device__ __forceinline__ void reset_core(Core &c) {
-    c.r.w0 = c.r.w1 = c.r.w2 = c.r.w3 = 0;
+    c.r.w = u32x4{0, 0, 0, 0};
     c.pc = kProgram;
     c.I = 0;
     c.sp = 0;

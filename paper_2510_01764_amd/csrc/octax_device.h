@@ -28,7 +28,7 @@ struct State {
     uint64_t *rng;       // [E]     SplitMix64 state
     uint64_t *dirty;     // [E]     bit p: 64-byte page p written since reset
     uint64_t *fb;        // [E][32] display rows, bit 63 - x = pixel (x, y)
-    uint32_t *cols;      // [E][4][64] frame ring, column x: bit y = pixel (x, y)
+    uint32_t *cols;      // [E][4][64] frame ring of packed frames (see pack_frame), slot = misc head
     uint8_t *ram;        // [E][4096]
     const uint32_t *rom_of;   // [E] ROM id
     const uint32_t *horizon;  // [E]
@@ -44,37 +44,35 @@ struct Roms {
 };
 
 // ---------------------------------------------------------------------------
-// V registers packed four to a 32-bit word (byte b of word w is V[4w+b]).
+// V registers packed four to a 32-bit word (byte b of word w is V[4w+b]),
+// held as one 4-word vector value.  Indexing it with a per-lane register
+// number lowers to compare/select on the four VGPRs (never to memory).
 // ---------------------------------------------------------------------------
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 struct Regs {
-    uint32_t w0, w1, w2, w3;
+    u32x4 w;
 };
 
 __device__ __forceinline__ uint32_t vget(const Regs &r, uint32_t x) {
-    uint32_t lo = (x & 4) ? r.w1 : r.w0;
-    uint32_t hi = (x & 4) ? r.w3 : r.w2;
-    uint32_t w = (x & 8) ? hi : lo;
-    return __builtin_amdgcn_ubfe(w, (x & 3) * 8, 8);
+    const uint32_t q = x >> 2;
+    const uint32_t lo = (q & 1) ? r.w.y : r.w.x;
+    const uint32_t hi = (q & 1) ? r.w.w : r.w.z;
+    return __builtin_amdgcn_ubfe((q & 2) ? hi : lo, (x & 3) * 8, 8);
 }
 
 __device__ __forceinline__ void vset(Regs &r, uint32_t x, uint32_t val) {
-    uint32_t sh = (x & 3) * 8;
-    uint32_t m = 0xFFu << sh;
-    uint32_t s = (val & 0xFFu) << sh;
-    uint32_t q = x >> 2;
-    r.w0 = (q == 0) ? ((r.w0 & ~m) | s) : r.w0;
-    r.w1 = (q == 1) ? ((r.w1 & ~m) | s) : r.w1;
-    r.w2 = (q == 2) ? ((r.w2 & ~m) | s) : r.w2;
-    r.w3 = (q == 3) ? ((r.w3 & ~m) | s) : r.w3;
+    const uint32_t sh = (x & 3) * 8;
+    const uint32_t m = 0xFFu << sh;
+    const uint32_t s = (val & 0xFFu) << sh;
+    const uint32_t q = x >> 2;
+    r.w.x = (q == 0) ? ((r.w.x & ~m) | s) : r.w.x;
+    r.w.y = (q == 1) ? ((r.w.y & ~m) | s) : r.w.y;
+    r.w.z = (q == 2) ? ((r.w.z & ~m) | s) : r.w.z;
+    r.w.w = (q == 3) ? ((r.w.w & ~m) | s) : r.w.w;
 }
 
-__device__ __forceinline__ uint32_t vf(const Regs &r) { return r.w3 >> 24; }
-__device__ __forceinline__ void set_vf(Regs &r, uint32_t f) { r.w3 = (r.w3 & 0x00FFFFFFu) | (f << 24); }
-
-// Byte k (0..3) of word w, for V0..V15 bulk access.
-__device__ __forceinline__ uint32_t regs_word(const Regs &r, uint32_t w) {
-    return w == 0 ? r.w0 : w == 1 ? r.w1 : w == 2 ? r.w2 : r.w3;
-}
+__device__ __forceinline__ void set_vf(Regs &r, uint32_t f) { r.w.w = (r.w.w & 0x00FFFFFFu) | (f << 24); }
 
 // ---------------------------------------------------------------------------
 // CXNN randomness: SplitMix64 (Steele, Lea and Flood, OOPSLA 2014).  The
@@ -91,12 +89,16 @@ __device__ __forceinline__ uint32_t rnd_byte(uint64_t &s) {
     return (uint32_t)(z >> 56);
 }
 
-// 16-byte store that bypasses cache retention (observations are written once
-// and read by the consumer later).
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// 16-byte observation store.  Plain stores: on MI355X they stream to HBM
+// faster than stores with the nontemporal hint (measured with the
+// calibration kernels); OCTAX_OBS_NONTEMPORAL selects the hinted form.
 __device__ __forceinline__ void store_stream(void *dst, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
     u32x4 v = {a, b, c, d};
+#ifdef OCTAX_OBS_NONTEMPORAL
     __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(dst));
+#else
+    *reinterpret_cast<u32x4 *>(dst) = v;
+#endif
 }
 
 // ---------------------------------------------------------------------------
@@ -140,6 +142,25 @@ __device__ __forceinline__ void transpose32(uint32_t a[32]) {
 __device__ __forceinline__ void rows_to_cols(uint32_t hi[32], uint32_t lo[32]) {
     transpose32(hi);   // hi[x] = column x (x = 0..31)
     transpose32(lo);   // lo[x] = column 32 + x
+}
+
+// Packed frame: 64 words in observation store order.  The observation of a
+// frame is 2048 bytes, [x][y]; word l holds in its low half the 16 pixels of
+// bytes [16l, 16l + 16) (column l / 2, rows 16 (l % 2) ..) and in its high
+// half those of bytes [1024 + 16l, ...) (column 32 + l / 2, same rows).
+// Lane l of a wave therefore stores the two 16-byte pieces of word l and a
+// wave's store instruction covers 1 KB of contiguous observation.
+__device__ __forceinline__ void pack_frame(const uint32_t hi[32], const uint32_t lo[32], uint32_t w[64]) {
+#pragma unroll
+    for (int m = 0; m < 32; m++) {
+        w[2 * m] = __builtin_amdgcn_perm(lo[m], hi[m], 0x05040100u);      // hi.lo16 | lo.lo16 << 16
+        w[2 * m + 1] = __builtin_amdgcn_perm(lo[m], hi[m], 0x07060302u);  // hi.hi16 | lo.hi16 << 16
+    }
+}
+
+// 16 pixel bits -> 16 bytes at dst.
+__device__ __forceinline__ void store16(uint8_t *dst, uint32_t bits) {
+    store_stream(dst, spread4(bits, 0), spread4(bits, 4), spread4(bits, 8), spread4(bits, 12));
 }
 
 }  // namespace octax

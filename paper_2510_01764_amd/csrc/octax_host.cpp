@@ -150,6 +150,15 @@ hipError_t ensure_raw(octax_engine *g, uint32_t count) {
     return hipSuccess;
 }
 
+// Packed frame layout of the frame ring (observation store order): pixel
+// (x, y) is byte 32x + y of the frame's observation; word l covers bytes
+// [16l, 16l + 16) in its low half and [1024 + 16l, ...) in its high half.
+int packed_word(int x, int y) { return 2 * (x & 31) + (y >> 4); }
+int packed_bit(int x, int y) { return (x >= 32 ? 16 : 0) + (y & 15); }
+uint32_t packed_pixel(const uint32_t *frame, int x, int y) {
+    return (frame[packed_word(x, y)] >> packed_bit(x, y)) & 1;
+}
+
 void raw_to_canonical(const RawState &r, octax_env_state &o) {
     std::memset(&o, 0, sizeof o);
     for (int k = 0; k < 16; k++) o.v[k] = (uint8_t)(r.regs[k >> 2] >> (8 * (k & 3)));
@@ -166,10 +175,10 @@ void raw_to_canonical(const RawState &r, octax_env_state &o) {
     std::memcpy(o.ram, r.ram, 4096);
     std::memcpy(o.fb, r.fb, sizeof o.fb);
     for (int h = 0; h < 3; h++) {
-        const uint32_t *col = r.cols + ((head + 1 + h) & 3) * 64;
+        const uint32_t *frame = r.cols + ((head + 1 + h) & 3) * 64;
         for (int y = 0; y < 32; y++) {
             uint64_t row = 0;
-            for (int x = 0; x < 64; x++) row |= (uint64_t)((col[x] >> y) & 1) << (63 - x);
+            for (int x = 0; x < 64; x++) row |= (uint64_t)packed_pixel(frame, x, y) << (63 - x);
             o.hist[h][y] = row;
         }
     }
@@ -190,12 +199,10 @@ void canonical_to_raw(const octax_env_state &o, RawState &r) {
     std::memcpy(r.fb, o.fb, sizeof r.fb);
     const uint64_t *frames[4] = {o.hist[0], o.hist[1], o.hist[2], o.fb};
     for (int h = 0; h < 4; h++) {
-        uint32_t *col = r.cols + h * 64;   // ring slots 0..3 with head = 3
-        for (int x = 0; x < 64; x++) {
-            uint32_t c = 0;
-            for (int y = 0; y < 32; y++) c |= (uint32_t)((frames[h][y] >> (63 - x)) & 1) << y;
-            col[x] = c;
-        }
+        uint32_t *frame = r.cols + h * 64;   // ring slots 0..3 with head = 3
+        for (int y = 0; y < 32; y++)
+            for (int x = 0; x < 64; x++)
+                if ((frames[h][y] >> (63 - x)) & 1) frame[packed_word(x, y)] |= 1u << packed_bit(x, y);
     }
 }
 

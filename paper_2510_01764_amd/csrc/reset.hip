@@ -51,18 +51,17 @@ __global__ __launch_bounds__(256) void reset_ram_kernel(State s, Roms roms, cons
     if (q == 0) s.dirty[slot] = 0;
 }
 
-// One thread per 16 bytes of observation: frame fr, column x, rows 16h..16h+15.
+// One thread per 16 bytes of observation: frame fr, piece q of the packed
+// frame (q < 64: low half of word q; else high half of word q - 64).
 __global__ __launch_bounds__(256) void observe_kernel(State s, uint8_t *obs) {
     const uint64_t gid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     const uint32_t slot = (uint32_t)(gid >> 9);
     if (slot >= s.num) return;
-    const uint32_t q = (uint32_t)(gid & 511);
-    const uint32_t fr = q >> 7, x = (q >> 1) & 63, h = q & 1;
+    const uint32_t piece = (uint32_t)(gid & 511);
+    const uint32_t fr = piece >> 7, q = piece & 127;
     const uint32_t head = s.misc[slot] >> 24 & 3;
-    const uint32_t col = s.cols[(size_t)slot * 256 + ((head + 1 + fr) & 3) * 64 + x] >> (16 * h);
-    uint4 v = make_uint4(spread4(col, 0), spread4(col, 4), spread4(col, 8), spread4(col, 12));
-    uint4 *dst = reinterpret_cast<uint4 *>(obs + (size_t)s.env_of[slot] * kObsBytes) + q;
-    *dst = v;
+    const uint32_t word = s.cols[(size_t)slot * 256 + ((head + 1 + fr) & 3) * 64 + (q & 63)];
+    store16(obs + (size_t)s.env_of[slot] * kObsBytes + fr * 2048 + 16 * q, q < 64 ? (word & 0xFFFF) : (word >> 16));
 }
 
 }  // namespace

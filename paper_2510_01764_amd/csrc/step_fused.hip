@@ -8,69 +8,256 @@
 //     reads of memory pages not written since the reset are served from the
 //     staged image, written pages from the env's memory in HBM;
 //   * each step ends with a per-lane 32x64 bit transpose of the display into
-//     64 column words (the observation is x-major), staged in LDS, and a
-//     wave-cooperative pass that expands the four frames of each env into
-//     bytes with fully coalesced 1 KB stores per instruction;
+//     a packed frame (64 words in observation store order) and a
+//     wave-cooperative pass that expands each env's frame into bytes with
+//     1 KB contiguous stores per instruction;
+//   * a frame is written, when it is computed, into the four observations it
+//     belongs to (step k as frame 3, step k+1 as frame 2, ...), so the step
+//     loop issues no global loads between its observation stores: on CDNA a
+//     load waits for every earlier store of the wave to complete;
 //   * the state goes back to HBM once per launch.
-#include "octax_core.h"
+#include "octax_grouped.h"
 #include "octax_kernels.h"
 
 namespace octax {
 namespace {
 
-constexpr uint32_t kNoRom = 0xFFFFFFFFu;
-constexpr int kFbStride = 33;      // u64 per env row block: odd stride spreads lanes over banks
-constexpr int kStageStride = 68;   // u32 per env column block (64 + 4 pad, 16-byte aligned)
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+typedef __attribute__((address_space(1))) uint8_t glb_u8;
 
+constexpr uint32_t kNoRom = 0xFFFFFFFFu;
+constexpr int kStageEnvs = 16;     // envs staged per round of the cooperative pass
+constexpr int kStageStride = 68;   // u32 per staged env (64 + 4 pad, 16-byte aligned)
+constexpr int kCacheStride = 136;  // bytes per env: two 64-byte pages + pad (spreads lanes over banks)
+
+// LDS of one block.  Display row y of lane l is fb[l][y ^ (l & 31)]: lanes
+// reading the same row index hit different banks.
 template <int IPW>
 struct Shared {
-    uint64_t fb[IPW][kFbStride];
-    uint32_t stage[IPW][kStageStride];
+    uint64_t fb[IPW][32];
+    uint8_t cache[IPW][kCacheStride];
+    uint32_t stage[IPW / 64][kStageEnvs][kStageStride];
     uint32_t stack[IPW][9];
     uint8_t img[2][kMem];
 };
 
+// Memory of one env in the fused kernel.
+//   * pages not written since the reset read from the power-on image: the
+//     LDS copy when the block staged this ROM, else HBM;
+//   * written pages live in the env's memory in HBM (every write goes
+//     there) and up to two of them are cached in LDS: a write fills a slot
+//     (from the image for a clean page, from HBM for a written one), a read
+//     of an uncached written page fills one from HBM; slots are replaced
+//     least recently filled first;
+//   * multi-byte accesses (fetch, FX33/FX55/FX65, DXYN rows) touch at most
+//     two pages; when both are readable from LDS all their LDS accesses are
+//     issued back to back (one round trip per instruction, not one per byte).
 template <int IPW>
 struct FusedMem {
     Shared<IPW> &sh;
     uint32_t lane;
-    int32_t lidx;          // staged image index or -1
-    const uint8_t *gimg;   // power-on image in HBM
-    uint8_t *ram;          // env memory in HBM
+    int32_t lidx;            // staged image index or -1
+    const glb_u8 *gimg;      // power-on image in HBM
+    glb_u8 *ram;             // env memory in HBM
     uint64_t dirty;
+    uint32_t tags;           // slot 0 page | valid << 6, slot 1 at bit 8, next victim at bit 16
 
-    __device__ __forceinline__ uint32_t read(uint32_t a) const {
-        if ((dirty >> (a >> 6)) & 1) return ram[a];
-        if (lidx >= 0) return sh.img[lidx][a];
+    __device__ __forceinline__ lds_u8 *slot_ptr(uint32_t s) const {
+        return (lds_u8 *)&sh.cache[lane][0] + 64 * s;
+    }
+    __device__ __forceinline__ bool is_dirty(uint32_t p) const { return (dirty >> p) & 1; }
+    __device__ __forceinline__ int32_t find(uint32_t p) const {
+        if ((tags & 0x7F) == (p | 0x40)) return 0;
+        if (((tags >> 8) & 0x7F) == (p | 0x40)) return 1;
+        return -1;
+    }
+    // Take a slot for page p, never slot `keep` (-1: none).
+    __device__ __forceinline__ uint32_t claim(uint32_t p, int32_t keep) {
+        uint32_t s = (tags >> 16) & 1;
+        if ((int32_t)s == keep) s ^= 1;
+        tags = (tags & ~(0x7Fu << (8 * s))) | ((p | 0x40) << (8 * s));
+        tags = (tags & ~(1u << 16)) | ((s ^ 1) << 16);
+        return s;
+    }
+    __device__ __forceinline__ uint32_t fill_from_ram(uint32_t p, int32_t keep) {
+        const uint32_t s = claim(p, keep);
+        const uint4 *src = reinterpret_cast<const uint4 *>((const uint8_t *)ram + p * 64);
+        uint4 *dst = reinterpret_cast<uint4 *>(&sh.cache[lane][64 * s]);
+#pragma unroll
+        for (int q = 0; q < 4; q++) dst[q] = src[q];
+        return s;
+    }
+    __device__ __forceinline__ uint32_t fill_from_image(uint32_t p, int32_t keep) {
+        const uint32_t s = claim(p, keep);
+        uint4 *dst = reinterpret_cast<uint4 *>(&sh.cache[lane][64 * s]);
+        if (lidx >= 0) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(&sh.img[lidx][p * 64]);
+#pragma unroll
+            for (int q = 0; q < 4; q++) dst[q] = src[q];
+        } else {
+            const uint4 *src = reinterpret_cast<const uint4 *>((const uint8_t *)gimg + p * 64);
+#pragma unroll
+            for (int q = 0; q < 4; q++) dst[q] = src[q];
+        }
+        return s;
+    }
+    // LDS base of page p (byte a at base[a & 63]) when p is readable from LDS
+    // without a fill.
+    __device__ __forceinline__ bool lds_page(uint32_t p, lds_u8 *&base) const {
+        if (!is_dirty(p)) {
+            base = (lds_u8 *)&sh.img[lidx & 1][0] + 64 * p;
+            return lidx >= 0;
+        }
+        const int32_t s = find(p);
+        base = slot_ptr(s & 1);
+        return s >= 0;
+    }
+    // One byte, any page (fills a slot for an uncached written page).
+    __device__ __forceinline__ uint32_t read(uint32_t a) {
+        const uint32_t p = a >> 6;
+        if (is_dirty(p)) {
+            int32_t s = find(p);
+            if (s < 0) s = (int32_t)fill_from_ram(p, -1);
+            return slot_ptr((uint32_t)s)[a & 63];
+        }
+        if (lidx >= 0) return ((const lds_u8 *)&sh.img[lidx][0])[a];
         return gimg[a];
     }
-    __device__ __forceinline__ void write(uint32_t a, uint32_t v) {
-        ram[a] = (uint8_t)v;
-        dirty |= 1ull << (a >> 6);
+    __device__ __forceinline__ uint32_t fetch(uint32_t pc) {
+        const uint32_t a1 = (pc + 1) & 0xFFF;
+        lds_u8 *b0, *b1;
+        const bool ok0 = lds_page(pc >> 6, b0);
+        const bool ok1 = lds_page(a1 >> 6, b1);
+        if (ok0 && ok1) return ((uint32_t)b0[pc & 63] << 8) | b1[a1 & 63];
+        return (read(pc) << 8) | read(a1);
+    }
+    __device__ __forceinline__ u32x4 load_bytes(uint32_t a, uint32_t count) {
+        const uint32_t p0 = a >> 6, p1 = ((a + count - 1) & 0xFFF) >> 6;
+        lds_u8 *b0, *b1;
+        const bool ok0 = lds_page(p0, b0);
+        const bool ok1 = lds_page(p1, b1);
+        u32x4 v = {0, 0, 0, 0};
+        if (ok0 && ok1) {
+            uint32_t b[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                const uint32_t ak = (a + k) & 0xFFF;
+                b[k] = (((ak >> 6) == p0) ? b0 : b1)[ak & 63];
+            }
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+                if ((uint32_t)k < count) or_byte(v, k, b[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+                if ((uint32_t)k < count) or_byte(v, k, read((a + k) & 0xFFF));
+        }
+        return v;
+    }
+    __device__ __forceinline__ void store_bytes(uint32_t a, uint32_t count, u32x4 bytes) {
+        const uint32_t p0 = a >> 6, p1 = ((a + count - 1) & 0xFFF) >> 6;
+        int32_t s0 = find(p0);
+        if (s0 < 0) s0 = (int32_t)(is_dirty(p0) ? fill_from_ram(p0, -1) : fill_from_image(p0, -1));
+        int32_t s1 = s0;
+        if (p1 != p0) {
+            s1 = find(p1);
+            if (s1 < 0) s1 = (int32_t)(is_dirty(p1) ? fill_from_ram(p1, s0) : fill_from_image(p1, s0));
+        }
+        lds_u8 *c0 = slot_ptr((uint32_t)s0), *c1 = slot_ptr((uint32_t)s1);
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if ((uint32_t)k < count) {
+                const uint32_t ak = (a + k) & 0xFFF;
+                const uint32_t v = byte_of(bytes, k);
+                ram[ak] = (uint8_t)v;
+                (((ak >> 6) == p0) ? c0 : c1)[ak & 63] = (uint8_t)v;
+            }
+        }
+        dirty |= (1ull << p0) | (1ull << p1);
+    }
+    // Rows r < cnt of the sprite: one batch of LDS reads (sprite bytes and
+    // display rows), then the XOR and the row writes.
+    template <int R0, int NR>
+    __device__ __forceinline__ uint64_t draw_rows(lds_u64 *fb, uint32_t sw, uint32_t x0, uint32_t y0,
+                                                  uint32_t cnt, uint32_t I, uint32_t p0,
+                                                  lds_u8 *b0, lds_u8 *b1) {
+        uint32_t spr[NR];
+        uint64_t row[NR];
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const uint32_t ar = (I + R0 + r) & 0xFFF;
+            spr[r] = (((ar >> 6) == p0) ? b0 : b1)[ar & 63];
+            row[r] = fb[(y0 + min((uint32_t)(R0 + r), cnt - 1)) ^ sw];
+        }
+        uint64_t hit = 0;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if ((uint32_t)(R0 + r) < cnt) {
+                const uint64_t m = ((uint64_t)spr[r] << 56) >> x0;
+                hit |= row[r] & m;
+                fb[(y0 + R0 + r) ^ sw] = row[r] ^ m;
+            }
+        }
+        return hit;
     }
     __device__ __forceinline__ uint32_t draw(uint32_t x0, uint32_t y0, uint32_t I, uint32_t n) {
+        lds_u64 *fb = (lds_u64 *)&sh.fb[lane][0];
+        const uint32_t sw = lane & 31;
+        const uint32_t cnt = min(n, 32 - y0);   // rows below the screen are clipped
+        if (cnt == 0) return 0;
+        const uint32_t p0 = I >> 6, p1 = ((I + cnt - 1) & 0xFFF) >> 6;
+        lds_u8 *b0, *b1;
+        const bool ok0 = lds_page(p0, b0);
+        const bool ok1 = lds_page(p1, b1);
         uint64_t hit = 0;
-        for (uint32_t r = 0; r < n; r++) {
-            const uint32_t yy = y0 + r;
-            if (yy >= 32) break;
-            const uint64_t m = ((uint64_t)read((I + r) & 0xFFF) << 56) >> x0;
-            const uint64_t row = sh.fb[lane][yy];
-            hit |= row & m;
-            sh.fb[lane][yy] = row ^ m;
+        if (ok0 && ok1) {
+            hit = draw_rows<0, 8>(fb, sw, x0, y0, cnt, I, p0, b0, b1);
+            if (cnt > 8) hit |= draw_rows<8, 7>(fb, sw, x0, y0, cnt, I, p0, b0, b1);
+        } else {
+            for (uint32_t r = 0; r < cnt; r++) {
+                const uint64_t m = ((uint64_t)read((I + r) & 0xFFF) << 56) >> x0;
+                const uint64_t row = fb[(y0 + r) ^ sw];
+                hit |= row & m;
+                fb[(y0 + r) ^ sw] = row ^ m;
+            }
         }
         return hit != 0;
     }
     __device__ __forceinline__ void clear() {
+        lds_u64 *fb = (lds_u64 *)&sh.fb[lane][0];
 #pragma unroll
-        for (int y = 0; y < 32; y++) sh.fb[lane][y] = 0;
+        for (int y = 0; y < 32; y++) fb[y] = 0;
     }
     __device__ __forceinline__ uint32_t stack_get(uint32_t i) const {
-        const uint32_t w = sh.stack[lane][i >> 1];
+        const uint32_t w = ((const lds_u32 *)&sh.stack[lane][0])[i >> 1];
         return (i & 1) ? (w >> 16) : (w & 0xFFFF);
     }
     __device__ __forceinline__ void stack_set(uint32_t i, uint32_t v) {
-        const uint32_t w = sh.stack[lane][i >> 1];
-        sh.stack[lane][i >> 1] = (i & 1) ? ((w & 0xFFFFu) | (v << 16)) : ((w & 0xFFFF0000u) | v);
+        lds_u32 *st = (lds_u32 *)&sh.stack[lane][0];
+        const uint32_t w = st[i >> 1];
+        st[i >> 1] = (i & 1) ? ((w & 0xFFFFu) | (v << 16)) : ((w & 0xFFFF0000u) | v);
+    }
+    // Restore the written pages from the image (automatic reset).
+    __device__ __forceinline__ void restore_pages() {
+        uint64_t d = dirty;
+        while (d) {
+            const uint32_t p = __builtin_ctzll(d);
+            d &= d - 1;
+            uint4 *dst = reinterpret_cast<uint4 *>((uint8_t *)ram + p * 64);
+            if (lidx >= 0) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(&sh.img[lidx][p * 64]);
+#pragma unroll
+                for (int q = 0; q < 4; q++) dst[q] = src[q];
+            } else {
+                const uint4 *src = reinterpret_cast<const uint4 *>((const uint8_t *)gimg + p * 64);
+#pragma unroll
+                for (int q = 0; q < 4; q++) dst[q] = src[q];
+            }
+        }
+        dirty = 0;
+        tags = 0;
     }
 };
 
@@ -81,20 +268,29 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// 16 column bits -> 16 bytes at dst.
-__device__ __forceinline__ void store16(uint8_t *dst, uint32_t bits) {
-    store_stream(dst, spread4(bits, 0), spread4(bits, 4), spread4(bits, 8), spread4(bits, 12));
+// Lane l's share of one packed frame: bytes [16l, 16l+16) and [1024+16l, ...).
+__device__ __forceinline__ void store_frame(uint8_t *frame, uint32_t lane64, uint32_t w) {
+    store16(frame + 16 * lane64, w & 0xFFFF);
+    store16(frame + 1024 + 16 * lane64, w >> 16);
 }
 
-template <int IPW>
+// kRollout separates the K-step launches (graph-captured rollouts) from the
+// K = 1 launches of octax_step into two instantiations of the same code, so
+// profiles report them apart.
+template <int IPW, bool kRollout>
 __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, StepIO io, FusedCfg cfg) {
     __shared__ Shared<IPW> sh;
     const uint32_t l = threadIdx.x;
     const uint32_t lane64 = l & 63;
+    const uint32_t wave = l >> 6;
     const uint32_t wave_base = l & ~63u;
     const uint32_t slot = blockIdx.x * IPW + l;
     const uint32_t E = s.num;
+    const uint32_t K = io.K;
     const bool active = slot < E;
+    const uint32_t wave_slot0 = blockIdx.x * IPW + wave_base;
+    const uint32_t nj = (E > wave_slot0) ? min(64u, E - wave_slot0) : 0u;   // envs of this wave
+    const uint32_t sw = l & 31;                                              // display row swizzle
 
     // Stage the block's ROM images.
     uint32_t brom0 = kNoRom, brom1 = kNoRom;
@@ -112,9 +308,10 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
     }
 
     Core c;
-    uint32_t head = 0, env = 0, rom = 0, desc = 0, t = 0, hor = 0;
+    uint32_t head = 0, env = 0, rom = 0, desc = 0, t = 0, hor = 0, tags = 0;
     int32_t prev = 0;
     uint64_t dirty = 0;
+    u32x4 keys = {0, 0, 0, 0};   // the ROM's 16 action keys, one byte each
     if (active) {
         load_core(s, slot, c, head);
         env = s.env_of[slot];
@@ -124,12 +321,13 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
         hor = s.horizon[slot];
         prev = s.prev[slot];
         dirty = s.dirty[slot];
+        keys = *reinterpret_cast<const u32x4 *>(roms.keys + (size_t)rom * 16);
         const uint4 *fb4 = reinterpret_cast<const uint4 *>(s.fb + (size_t)slot * 32);
 #pragma unroll
         for (int q = 0; q < 16; q++) {
             const uint4 v = fb4[q];
-            sh.fb[l][2 * q] = (uint64_t)v.x | ((uint64_t)v.y << 32);
-            sh.fb[l][2 * q + 1] = (uint64_t)v.z | ((uint64_t)v.w << 32);
+            sh.fb[l][(2 * q) ^ sw] = (uint64_t)v.x | ((uint64_t)v.y << 32);
+            sh.fb[l][(2 * q + 1) ^ sw] = (uint64_t)v.z | ((uint64_t)v.w << 32);
         }
         const uint4 *st4 = reinterpret_cast<const uint4 *>(s.stack + (size_t)slot * 8);
         const uint4 a0 = st4[0], a1 = st4[1];
@@ -140,17 +338,73 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
         c.rng = 0;
     }
     const int32_t lidx = (rom == brom0) ? 0 : (rom == brom1) ? 1 : -1;
-    const uint8_t *gimg = roms.image + (size_t)rom * kMem;
-    uint8_t *ram = s.ram + (size_t)slot * kMem;
+    const glb_u8 *gimg = (const glb_u8 *)(roms.image + (size_t)rom * kMem);
+    glb_u8 *ram = (glb_u8 *)(s.ram + (size_t)slot * kMem);
+    const uint32_t nact = desc >> 24;
+    const size_t obs_step = (size_t)E * kObsBytes;
+    auto obs_of = [&](uint32_t kk, uint32_t e) -> uint8_t * {
+        return io.obs + (size_t)(kk % io.obs_slots) * obs_step + (size_t)e * kObsBytes;
+    };
+
+    // Prologue: the three frames before this launch go into the observations
+    // of steps 0..2 (frame f of step k is the frame of step k - 3 + f).  All
+    // loads of a chunk of envs are issued before its stores.
+    if (io.obs) {
+        for (uint32_t j0 = 0; j0 < nj; j0 += kStageEnvs) {
+            uint32_t w[kStageEnvs][3];
+#pragma unroll
+            for (int jj = 0; jj < kStageEnvs; jj++) {
+                const uint32_t j = min(j0 + jj, nj - 1);
+                const uint32_t jh = __builtin_amdgcn_readlane(head, j);
+                const uint32_t *ring = s.cols + (size_t)(wave_slot0 + j) * 256 + lane64;
+                w[jj][0] = ring[jh * 64];                 // step -1
+                w[jj][1] = ring[((jh + 3) & 3) * 64];     // step -2
+                w[jj][2] = ring[((jh + 2) & 3) * 64];     // step -3
+            }
+#pragma unroll
+            for (int jj = 0; jj < kStageEnvs; jj++) {
+                const uint32_t j = j0 + jj;
+                if (j >= nj) break;
+                const uint32_t je = __builtin_amdgcn_readlane(env, j);
+#pragma unroll
+                for (int back = 0; back < 3; back++) {          // frame of step -1 - back
+#pragma unroll
+                    for (int kk = 0; kk < 3 - back; kk++) {      // lands in step kk as frame 2 - back - kk
+                        if ((uint32_t)kk < K)
+                            store_frame(obs_of(kk, je) + (2 - back - kk) * 2048, lane64, w[jj][back]);
+                    }
+                }
+            }
+        }
+    }
     __syncthreads();
 
-    for (uint32_t k = 0; k < io.K; k++) {
+    u32x4 kchunk = {0, 0, 0, 0};   // held keys of 16 consecutive steps, one byte each
+    FusedMem<IPW> mem{sh, l, lidx, gimg, ram, dirty, tags};
+    for (uint32_t k = 0; k < K; k++) {
         uint32_t done = 0;
+        uint32_t pw[64];
+        if ((k & 15) == 0 && active) {
+            // actions of the next 16 steps -> held keys (16 = none)
+            uint32_t kb[16];
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const int32_t a = (k + q < K) ? io.action[(size_t)(k + q) * E + env] : -1;
+                const uint32_t ua = (uint32_t)a;
+                const uint32_t word = (ua & 8) ? ((ua & 4) ? keys.w : keys.z) : ((ua & 4) ? keys.y : keys.x);
+                kb[q] = (ua < nact) ? (__builtin_amdgcn_ubfe(word, (ua & 3) * 8, 8) & 15) : kKeyNone;
+            }
+            kchunk.x = kb[0] | (kb[1] << 8) | (kb[2] << 16) | (kb[3] << 24);
+            kchunk.y = kb[4] | (kb[5] << 8) | (kb[6] << 16) | (kb[7] << 24);
+            kchunk.z = kb[8] | (kb[9] << 8) | (kb[10] << 16) | (kb[11] << 24);
+            kchunk.w = kb[12] | (kb[13] << 8) | (kb[14] << 16) | (kb[15] << 24);
+        }
         if (active) {
-            const uint32_t key = action_key(roms, rom, desc, io.action[(size_t)k * E + env]);
-            FusedMem<IPW> mem{sh, l, lidx, gimg, ram, dirty};
+            const uint32_t kq = (k >> 2) & 3;
+            const uint32_t kword = kq == 0 ? kchunk.x : kq == 1 ? kchunk.y : kq == 2 ? kchunk.z : kchunk.w;
+            const uint32_t key = __builtin_amdgcn_ubfe(kword, (k & 3) * 8, 8);
             for (uint32_t f = 0; f < io.frame_skip; f++) {
-                for (uint32_t i = 0; i < io.ipf; i++) exec_one(c, mem, key);
+                for (uint32_t i = 0; i < io.ipf; i++) exec_grouped(c, mem, key);
                 tick(c);
             }
             const int32_t score = (int32_t)vget(c.r, desc & 15);
@@ -163,15 +417,7 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
             io.done[(size_t)k * E + env] = (uint8_t)done;
             if (done) {
                 // Automatic reset (Section 3.4); the RNG stream continues.
-                uint64_t d = mem.dirty;
-                while (d) {
-                    const uint32_t p = __builtin_ctzll(d);
-                    d &= d - 1;
-                    const uint4 *src = reinterpret_cast<const uint4 *>(gimg + p * 64);
-                    uint4 *dst = reinterpret_cast<uint4 *>(ram + p * 64);
-                    for (int q = 0; q < 4; q++) dst[q] = src[q];
-                }
-                mem.dirty = 0;
+                mem.restore_pages();
                 reset_core(c);
                 mem.clear();
                 for (int q = 0; q < 8; q++) sh.stack[l][q] = 0;
@@ -182,66 +428,65 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
                 prev = score;
                 head = (head + 1) & 3;
             }
-            dirty = mem.dirty;
-            // display rows -> 64 column words, staged for the cooperative pass
             uint32_t hi[32], lo[32];
 #pragma unroll
             for (int r = 0; r < 32; r++) {
-                const uint64_t row = sh.fb[l][31 - r];
+                const uint64_t row = sh.fb[l][(31 - r) ^ sw];
                 hi[r] = (uint32_t)(row >> 32);
                 lo[r] = (uint32_t)row;
             }
             rows_to_cols(hi, lo);
-            uint4 *stg = reinterpret_cast<uint4 *>(sh.stage[l]);
-#pragma unroll
-            for (int q = 0; q < 8; q++) {
-                stg[q] = make_uint4(hi[4 * q], hi[4 * q + 1], hi[4 * q + 2], hi[4 * q + 3]);
-                stg[8 + q] = make_uint4(lo[4 * q], lo[4 * q + 1], lo[4 * q + 2], lo[4 * q + 3]);
-            }
+            pack_frame(hi, lo, pw);
         }
-        wave_sync();
 
-        // Cooperative pass over the wave's envs: frame ring update and the
-        // observation, one env at a time.  Lane x owns column x of every
-        // frame: it is the only lane that writes or reads ring word x, so
-        // ring traffic is ordered by program order alone, and it stores the
-        // 32 bytes of column x of each frame (a wave covers 2 KB per frame).
-        const uint32_t nj = (E > blockIdx.x * IPW + wave_base)
-                                ? min(64u, E - (blockIdx.x * IPW + wave_base)) : 0u;
-        uint8_t *obs_k = io.obs ? io.obs + (size_t)(k % io.obs_slots) * E * kObsBytes : nullptr;
-        for (uint32_t j = 0; j < nj; j++) {
-            const uint32_t jl = wave_base + j;
-            const uint32_t jslot = blockIdx.x * IPW + jl;
-            const uint32_t jhead = __builtin_amdgcn_readlane(head, j);
-            const uint32_t jdone = __builtin_amdgcn_readlane(done, j);
-            uint32_t *ring = s.cols + (size_t)jslot * 256 + lane64;
-            const uint32_t c3 = sh.stage[jl][lane64];
-            uint32_t c0 = 0, c1 = 0, c2 = 0;
-            if (jdone) {
-                ring[64] = 0;
-                ring[128] = 0;
-                ring[192] = 0;
-            } else if (obs_k) {
-                c0 = ring[((jhead + 1) & 3) * 64];
-                c1 = ring[((jhead + 2) & 3) * 64];
-                c2 = ring[((jhead + 3) & 3) * 64];
+        // Cooperative pass, 16 envs per round: stage their packed frames, then
+        // for each env store its frame into every observation it belongs to
+        // and keep the last four frames of the launch in the env's ring.
+        const bool ring_step = k + 4 >= K;
+        for (uint32_t r0 = 0; r0 < nj; r0 += kStageEnvs) {
+            if (active && lane64 - r0 < (uint32_t)kStageEnvs) {
+                uint4 *stg = reinterpret_cast<uint4 *>(sh.stage[wave][lane64 - r0]);
+#pragma unroll
+                for (int q = 0; q < 16; q++)
+                    stg[q] = make_uint4(pw[4 * q], pw[4 * q + 1], pw[4 * q + 2], pw[4 * q + 3]);
             }
-            ring[jhead * 64] = c3;
-            if (obs_k) {
-                const uint32_t jenv = __builtin_amdgcn_readlane(env, j);
-                uint8_t *o = obs_k + (size_t)jenv * kObsBytes + 32 * lane64;
-                store16(o, c0);
-                store16(o + 16, c0 >> 16);
-                store16(o + 2048, c1);
-                store16(o + 2048 + 16, c1 >> 16);
-                store16(o + 4096, c2);
-                store16(o + 4096 + 16, c2 >> 16);
-                store16(o + 6144, c3);
-                store16(o + 6144 + 16, c3 >> 16);
+            wave_sync();
+            const uint32_t r1 = min(r0 + (uint32_t)kStageEnvs, nj);
+            for (uint32_t j = r0; j < r1; j++) {
+                const uint32_t w = sh.stage[wave][j - r0][lane64];
+                const uint32_t jdone = __builtin_amdgcn_readlane(done, j);
+                if (io.obs) {
+                    const uint32_t je = __builtin_amdgcn_readlane(env, j);
+#pragma unroll
+                    for (uint32_t d = 0; d < 4; d++)
+                        if (k + d < K) store_frame(obs_of(k + d, je) + (3 - d) * 2048, lane64, w);
+                    if (jdone) {
+                        // the frames before the reset belong to the old episode
+#pragma unroll
+                        for (uint32_t d = 0; d < 3; d++)
+#pragma unroll
+                            for (uint32_t f = 0; f < 3 - d; f++)
+                                if (k + d < K) store_frame(obs_of(k + d, je) + f * 2048, lane64, 0);
+                    }
+                }
+                // the last four frames of the launch stay in the ring; a reset
+                // blanks the three slots before the new head
+                if (ring_step) {
+                    const uint32_t jh = __builtin_amdgcn_readlane(head, j);
+                    uint32_t *ring = s.cols + (size_t)(wave_slot0 + j) * 256 + lane64;
+                    ring[jh * 64] = w;
+                    if (jdone) {
+                        ring[((jh + 1) & 3) * 64] = 0;
+                        ring[((jh + 2) & 3) * 64] = 0;
+                        ring[((jh + 3) & 3) * 64] = 0;
+                    }
+                }
             }
+            wave_sync();
         }
-        wave_sync();
     }
+    dirty = mem.dirty;
+    tags = mem.tags;
 
     if (active) {
         store_core(s, slot, c, head);
@@ -251,7 +496,7 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
         uint4 *fb4 = reinterpret_cast<uint4 *>(s.fb + (size_t)slot * 32);
 #pragma unroll
         for (int q = 0; q < 16; q++) {
-            const uint64_t a = sh.fb[l][2 * q], b = sh.fb[l][2 * q + 1];
+            const uint64_t a = sh.fb[l][(2 * q) ^ sw], b = sh.fb[l][(2 * q + 1) ^ sw];
             fb4[q] = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
         }
         uint4 *st4 = reinterpret_cast<uint4 *>(s.stack + (size_t)slot * 8);
@@ -263,7 +508,10 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
 template <int IPW>
 hipError_t launch_ipw(const State &s, const Roms &r, const StepIO &io, const FusedCfg &f, hipStream_t st) {
     const uint32_t blocks = (s.num + IPW - 1) / IPW;
-    hipLaunchKernelGGL(step_fused_kernel<IPW>, dim3(blocks), dim3(IPW), 0, st, s, r, io, f);
+    if (io.K == 1)
+        hipLaunchKernelGGL((step_fused_kernel<IPW, false>), dim3(blocks), dim3(IPW), 0, st, s, r, io, f);
+    else
+        hipLaunchKernelGGL((step_fused_kernel<IPW, true>), dim3(blocks), dim3(IPW), 0, st, s, r, io, f);
     return hipGetLastError();
 }
 

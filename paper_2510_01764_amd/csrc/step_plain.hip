@@ -15,10 +15,25 @@ struct PlainMem {
     uint32_t *stack;
     uint64_t dirty;
 
-    __device__ __forceinline__ uint32_t read(uint32_t a) const { return ram[a]; }
-    __device__ __forceinline__ void write(uint32_t a, uint32_t v) {
-        ram[a] = (uint8_t)v;
-        dirty |= 1ull << (a >> 6);
+    __device__ __forceinline__ uint32_t fetch(uint32_t pc) const {
+        return ((uint32_t)ram[pc] << 8) | ram[(pc + 1) & 0xFFF];
+    }
+    __device__ __forceinline__ u32x4 load_bytes(uint32_t a, uint32_t count) const {
+        u32x4 v = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            if ((uint32_t)k < count) or_byte(v, k, ram[(a + k) & 0xFFF]);
+        return v;
+    }
+    __device__ __forceinline__ void store_bytes(uint32_t a, uint32_t count, u32x4 bytes) {
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if ((uint32_t)k < count) {
+                const uint32_t ak = (a + k) & 0xFFF;
+                ram[ak] = (uint8_t)byte_of(bytes, k);
+                dirty |= 1ull << (ak >> 6);
+            }
+        }
     }
     // XOR rows of the sprite onto the display; bits past x = 63 fall off the
     // right of the shifted mask, rows past y = 31 are skipped.
@@ -114,25 +129,28 @@ __global__ __launch_bounds__(256) void step_plain_kernel(State s, Roms roms, Ste
             lo[r] = (uint32_t)row;
         }
         rows_to_cols(hi, lo);
+        uint32_t pw[64];
+        pack_frame(hi, lo, pw);
         head = (head + 1) & 3;
-        uint32_t *dst = ring + head * 64;
+        uint4 *dst = reinterpret_cast<uint4 *>(ring + head * 64);
 #pragma unroll
-        for (int x = 0; x < 32; x += 4) {
-            reinterpret_cast<uint4 *>(dst)[x / 4] = make_uint4(hi[x], hi[x + 1], hi[x + 2], hi[x + 3]);
-            reinterpret_cast<uint4 *>(dst + 32)[x / 4] = make_uint4(lo[x], lo[x + 1], lo[x + 2], lo[x + 3]);
-        }
+        for (int q = 0; q < 16; q++) dst[q] = make_uint4(pw[4 * q], pw[4 * q + 1], pw[4 * q + 2], pw[4 * q + 3]);
         if (obs) {
             // frames 0..2: the three older ring entries, oldest first
             for (uint32_t fr = 0; fr < 3; fr++) {
                 const uint32_t *src = ring + ((head + 1 + fr) & 3) * 64;
                 uint8_t *o = obs + fr * 2048;
-                for (int x = 0; x < 64; x++) store_column(o + x * 32, src[x]);
+                for (int w = 0; w < 64; w++) {
+                    const uint32_t word = src[w];
+                    store16(o + 16 * w, word & 0xFFFF);
+                    store16(o + 1024 + 16 * w, word >> 16);
+                }
             }
             uint8_t *o = obs + 3 * 2048;
 #pragma unroll
-            for (int x = 0; x < 32; x++) {
-                store_column(o + x * 32, hi[x]);
-                store_column(o + (32 + x) * 32, lo[x]);
+            for (int w = 0; w < 64; w++) {
+                store16(o + 16 * w, pw[w] & 0xFFFF);
+                store16(o + 1024 + 16 * w, pw[w] >> 16);
             }
         }
     }

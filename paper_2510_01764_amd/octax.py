@@ -96,7 +96,7 @@ def library() -> ctypes.CDLL:
         "octax_info": ([P, ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_uint64)], i32),
         "octax_destroy": ([P], i32),
         "octax_last_error": ([], ctypes.c_char_p),
-        "octax_calib_write": ([P, ctypes.c_uint64, u32, P], i32),
+        "octax_calib_write": ([P, ctypes.c_uint64, u32, u32, P], i32),
         "octax_calib_copy": ([P, P, ctypes.c_uint64, P], i32),
     }
     for name, (args, res) in sig.items():

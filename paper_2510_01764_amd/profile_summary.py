@@ -1,0 +1,118 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+  python -m paper_2510_01764_amd.profile_summary stats <rocprof dir> <out.txt> --command "..."
+      per-kernel call count and duration statistics (from --kernel-trace --stats)
+  python -m paper_2510_01764_amd.profile_summary traffic <fetch dir> <write dir> <out.json>
+      --calib-bytes N --kernel step_fused_kernel<256, true> --command-fetch "..." --command-write "..."
+      HBM bytes per launch of one kernel from FETCH_SIZE and WRITE_SIZE counter runs, each
+      scaled by what the same counter reads for the calibration copy kernel of known size.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import json
+import os
+import sys
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _find(d, pattern):
+    hits = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+    if not hits:
+        raise SystemExit(f"no {pattern} under {d}")
+    return hits
+
+
+def stats(d, out, command):
+    rows = []
+    for f in _find(d, "*kernel_stats.csv"):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
+             f"{'kernel':<70} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_ms':>10} {'pct':>6}"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"{r['Name'][:70]:<70} {int(r['Calls']):>6} {float(r['AverageNs'])/1e3:>10.1f} "
+                     f"{float(r['MinNs'])/1e3:>10.1f} {float(r['MaxNs'])/1e3:>10.1f} "
+                     f"{float(r['TotalDurationNs'])/1e6:>10.2f} {float(r['Percentage']):>6.2f}")
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as fh:
+        fh.write(text)
+    print(text)
+
+
+def _counter_means(d, counter):
+    per = defaultdict(list)
+    for f in _find(d, "*counter_collection.csv"):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in per.items()}
+
+
+def _pick(means, needle):
+    hits = [k for k in means if needle in k]
+    if len(hits) != 1:
+        raise SystemExit(f"kernel '{needle}' matches {hits}")
+    return means[hits[0]]
+
+
+def traffic(fetch_dir, write_dir, out, calib_bytes, kernel, cmd_f, cmd_w):
+    sys.path.insert(0, ROOT)
+    import bench
+    f = _counter_means(fetch_dir, "FETCH_SIZE")
+    w = _counter_means(write_dir, "WRITE_SIZE")
+    cf, _ = _pick(f, "octax_calib_copy_kernel")
+    cw, _ = _pick(w, "octax_calib_copy_kernel")
+    kf, nf = _pick(f, kernel)
+    kw, nw = _pick(w, kernel)
+    scale_f = calib_bytes / (cf * 1024.0)
+    scale_w = calib_bytes / (cw * 1024.0)
+    fetch_b = kf * 1024.0 * scale_f
+    write_b = kw * 1024.0 * scale_w
+    d = {
+        "kernel": kernel,
+        "kernel_source_hash": bench.kernel_source_hash(),
+        "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw,
+        "dispatches": [nf, nw],
+        "calib_copy_bytes": calib_bytes,
+        "calib_fetch_kib": cf, "calib_write_kib": cw,
+        "scale_fetch": scale_f, "scale_write": scale_w,
+        "hbm_fetch_bytes_per_launch": fetch_b,
+        "hbm_write_bytes_per_launch": write_b,
+        "hbm_bytes_per_launch": fetch_b + write_b,
+        "command_fetch": cmd_f, "command_write": cmd_w,
+    }
+    with open(out, "w") as fh:
+        json.dump(d, fh, indent=1)
+    print(json.dumps(d, indent=1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("out")
+    s.add_argument("--command", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_dir")
+    t.add_argument("write_dir")
+    t.add_argument("out")
+    t.add_argument("--calib-bytes", type=int, required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--command-fetch", required=True)
+    t.add_argument("--command-write", required=True)
+    a = ap.parse_args()
+    if a.cmd == "stats":
+        stats(a.dir, a.out, a.command)
+    else:
+        traffic(a.fetch_dir, a.write_dir, a.out, a.calib_bytes, a.kernel, a.command_fetch, a.command_write)
+
+
+if __name__ == "__main__":
+    main()
