@@ -87,6 +87,41 @@ def time_replays(torch, stream, graph, act_buf, act_pool, n, start):
     return evs
 
 
+def serving_run(args, step_lat_ms, log):
+    """Continuous batching of Poisson-arriving groups (32 ROMs, sizes log-uniform
+    in 1..4096, 200-2000 steps each) on a pool of args.serving_slots slots; the
+    arrival rate offers args.serving_load of the pool's step capacity, taken
+    from the single-step latency over 65,536 envs measured above."""
+    import numpy as np
+    from paper_2510_01764_amd import serving as S
+    from paper_2510_01764_amd import workload as W
+    from paper_2510_01764_amd import octax as X
+    spec = W.make_config("c4")
+    capacity = args.serving_slots / (float(np.percentile(step_lat_ms, 50)) * 1e-3)   # env steps/s, full pool
+    probe = W.serving_groups(args.serving_groups, 1.0, seed=3)
+    mean_work = float(np.mean([g.size * g.steps for g in probe]))
+    rate = args.serving_load * capacity / mean_work
+    groups = W.serving_groups(args.serving_groups, rate, seed=3)
+    be = S.PoolBackend(spec, args.serving_slots * X.Pool.slot_bytes(), depth=2)
+    out = S.serve(spec, groups, be, log=log)
+    be.close()
+    return {
+        "workload": f"{args.serving_groups} groups over 32 ROMs, sizes log-uniform 1..4096, 200-2000 steps, "
+                    f"Poisson arrivals at {rate:.1f} groups/s ({args.serving_load:.0%} of pool capacity)",
+        "pool_slots": args.serving_slots,
+        "env_steps_per_s": out["env_steps_per_s"],
+        "busy_env_steps_per_s": out["busy_env_steps_per_s"],
+        "p50_step_latency_ms": out["p50_step_latency_ms"],
+        "p99_step_latency_ms": out["p99_step_latency_ms"],
+        "p50_queue_ms": out["p50_queue_ms"],
+        "p99_queue_ms": out["p99_queue_ms"],
+        "ticks": out["ticks"],
+        "tick_ms_mean": out["tick_ms_mean"],
+        "wall_s": out["wall_s"],
+        "step_latency_def": "per group step: host time from enqueueing the tick to its rewards and done flags on the host",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +135,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--tune", choices=["auto", "default"], default="auto")
+    ap.add_argument("--serving-groups", type=int, default=2000,
+                    help="groups of the serving run (0 = skip it)")
+    ap.add_argument("--serving-load", type=float, default=0.7,
+                    help="offered load as a fraction of the pool's measured step capacity")
+    ap.add_argument("--serving-slots", type=int, default=65536)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -203,6 +243,10 @@ def main():
         gp.close()
         engp.close()
 
+    serving = None
+    if args.serving_groups > 0:
+        serving = serving_run(args, lat, log)
+
     algo_per_launch = E * K * ALGO_BYTES_PER_ENV_STEP
     achieved = algo_per_launch / (kernel_ms * 1e-3) / 1e9
     traffic = measured_traffic()
@@ -248,6 +292,8 @@ def main():
         },
         "context": "paper: 350,000 env steps/s (Pong, constant action, RTX 3090) - other hardware and workload",
     }
+    if serving is not None:
+        out["serving"] = serving
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, min(args.cpu_envs, E), args.cpu_steps)
     print(json.dumps(out), flush=True)

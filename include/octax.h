@@ -244,6 +244,95 @@ int32_t octax_info(const octax_engine *eng, uint32_t *num_envs, uint64_t *device
 int32_t octax_destroy(octax_engine *eng);
 
 /*
+ * Serving pool: continuous batching of environment groups (requests) that
+ * arrive and finish at different times, all stepped by one fused launch per
+ * tick while their state stays resident in device memory.
+ *
+ * A pool holds `capacity` env slots, fixed at creation from a device-memory
+ * budget (pool_bytes / octax_pool_slot_bytes()).  octax_pool_admit places a
+ * group of `count` envs of one ROM in a free contiguous range of slots
+ * (first fit) and resets them to the power-on state of that ROM (Section 3.2,
+ * ROM loading and initialization); with no free range large enough it
+ * returns OCTAX_E_NOMEM and changes nothing, so the caller keeps the request
+ * queued.  octax_pool_step runs K environment steps (the semantics of
+ * octax_step_many) of every occupied slot; free slots are neither read nor
+ * written.  octax_pool_retire frees a group's slots.  A group's results do
+ * not depend on its slots or on the other groups in the pool: each env's
+ * RNG stream starts from the seed given at admission.
+ *
+ * Buffers of octax_pool_step are indexed by slot: d_action int32 [K][capacity],
+ * d_obs uint8 [obs_slots][capacity][4][64][32] (or NULL), d_reward float
+ * [K][capacity], d_done uint8 [K][capacity]; only occupied slots are used.
+ * Admission, retirement and steps are ordered on the pool's stream; admit
+ * and retire return without waiting for the device.  Host arrays passed to
+ * admit are copied before it returns.
+ */
+typedef struct octax_pool_config {
+    uint32_t abi_version;      /* must be OCTAX_ABI_VERSION */
+    uint32_t num_roms;         /* R >= 1 */
+    uint32_t instr_per_frame;  /* 1..1000 */
+    uint32_t frame_skip;       /* 1..64 */
+    uint32_t quirks;           /* must be OCTAX_QUIRKS_V1 */
+    uint32_t envs_per_block;   /* fused kernel tuning: 64, 128 or 256 (0 = 256) */
+    uint64_t pool_bytes;       /* device-memory budget of the env slots */
+    const uint8_t *h_rom_data;     /* as in octax_config */
+    const uint32_t *h_rom_offset;  /* [R] */
+    const uint32_t *h_rom_len;     /* [R] */
+    const uint8_t *h_action_keys;  /* [R][16] */
+    const uint8_t *h_num_actions;  /* [R] */
+    const uint8_t *h_score_reg;    /* [R] */
+    const uint8_t *h_term_reg;     /* [R] */
+    const uint8_t *h_term_value;   /* [R] */
+    void *stream;                  /* hipStream_t; NULL = null stream */
+} octax_pool_config;
+
+typedef struct octax_pool octax_pool;
+
+/* Device bytes of one env slot of a pool. */
+uint64_t octax_pool_slot_bytes(void);
+
+/*
+ * Create a pool (allocates capacity slots and the ROM images, synchronizes).
+ * Errors: OCTAX_E_INVALID (bad field, budget below one slot), OCTAX_E_NOMEM,
+ * OCTAX_E_HIP.
+ */
+int32_t octax_pool_create(const octax_pool_config *cfg, octax_pool **out);
+
+/*
+ * Admit a group: count envs of ROM `rom`, env k with RNG seed h_env_seed[k]
+ * and truncation horizon h_horizon[k] (0 = none).  On success *first_slot is
+ * the first of its count contiguous slots.  Errors: OCTAX_E_INVALID (rom >= R,
+ * count == 0 or > capacity, NULL), OCTAX_E_NOMEM (no free range of count
+ * slots: nothing changed), OCTAX_E_HIP.
+ */
+int32_t octax_pool_admit(octax_pool *p, uint32_t rom, uint32_t count, const uint64_t *h_env_seed,
+                         const uint32_t *h_horizon, uint32_t *first_slot);
+
+/*
+ * Free the group that starts at first_slot.  Steps already enqueued still
+ * see it.  Errors: OCTAX_E_INVALID (no group starts there).
+ */
+int32_t octax_pool_retire(octax_pool *p, uint32_t first_slot);
+
+/* K environment steps of every occupied slot (buffers as described above).
+ * Errors: OCTAX_E_INVALID (K == 0, NULL action/reward/done, obs_slots == 0
+ * with d_obs), OCTAX_E_HIP. */
+int32_t octax_pool_step(octax_pool *p, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
+                        uint32_t obs_slots, float *d_reward, uint8_t *d_done);
+
+/* Capacity, free slots, largest free range and number of groups. */
+int32_t octax_pool_info(const octax_pool *p, uint32_t *capacity, uint32_t *free_slots,
+                        uint32_t *largest_free, uint32_t *groups);
+
+/* Architectural state of slots [first, first + count) (synchronizes).  The
+ * observation history is that of the env in the slot.  Errors as
+ * octax_get_state. */
+int32_t octax_pool_get_state(octax_pool *p, uint32_t first, uint32_t count, octax_env_state *h_out);
+
+/* Destroy a pool (synchronizes its stream).  NULL is accepted. */
+int32_t octax_pool_destroy(octax_pool *p);
+
+/*
  * Roofline calibration (no part of the environment step): stream `bytes`
  * (a multiple of 16) of the 32-bit value v into d_dst (nontemporal != 0: with
  * the nontemporal store hint), or copy `bytes` from d_src to d_dst,

@@ -33,8 +33,14 @@ struct State {
     const uint32_t *rom_of;   // [E] ROM id
     const uint32_t *horizon;  // [E]
     const uint32_t *env_of;   // [E] env index (output position) of each slot
+    const uint8_t *occupied;  // [E] slot holds an env (serving pool); null: every slot does
     uint32_t num;             // E
 };
+
+// Slot holds an env that steps.
+__device__ __forceinline__ bool slot_live(const State &s, uint32_t slot) {
+    return slot < s.num && (s.occupied == nullptr || s.occupied[slot] != 0);
+}
 
 // Per-ROM tables.
 struct Roms {
@@ -54,11 +60,13 @@ struct Regs {
     u32x4 w;
 };
 
+// V[x]: v_perm picks byte x & 7 out of a register pair (selector 0x0C gives a
+// zero byte), the pair chosen by bit 3 of x.
 __device__ __forceinline__ uint32_t vget(const Regs &r, uint32_t x) {
-    const uint32_t q = x >> 2;
-    const uint32_t lo = (q & 1) ? r.w.y : r.w.x;
-    const uint32_t hi = (q & 1) ? r.w.w : r.w.z;
-    return __builtin_amdgcn_ubfe((q & 2) ? hi : lo, (x & 3) * 8, 8);
+    const uint32_t sel = 0x0C0C0C00u | (x & 7);
+    const uint32_t lo = __builtin_amdgcn_perm(r.w.y, r.w.x, sel);
+    const uint32_t hi = __builtin_amdgcn_perm(r.w.w, r.w.z, sel);
+    return (x & 8) ? hi : lo;
 }
 
 __device__ __forceinline__ void vset(Regs &r, uint32_t x, uint32_t val) {

@@ -1,0 +1,70 @@
+// Engine and graph objects of liboctax, shared by the host files of the
+// library (octax_host.cpp: the environment API; octax_pool.cpp: the serving
+// pool).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/octax.h"
+#include "octax_kernels.h"
+
+struct octax_engine {
+    uint32_t E = 0, R = 0, ipf = 0, frame_skip = 0;
+    uint32_t kernel = OCTAX_KERNEL_PLAIN;
+    uint32_t placement = OCTAX_PLACE_IDENTITY;
+    uint32_t envs_per_block = 256, rom_in_lds = 1;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    uint64_t device_bytes = 0;
+    std::vector<void *> allocations;
+    std::vector<uint32_t> env_of, slot_of, rom_of;   // host copies of the placement
+    std::vector<uint8_t> occupied;                    // serving pool: host copy of State::occupied (empty: all)
+    octax::State s{};
+    octax::Roms roms{};
+    uint32_t *d_block_roms = nullptr;                 // [blocks][2] for the current tuning
+    uint32_t *d_slot_scratch = nullptr;               // slot lists for get/set_state
+    octax::RawState *d_raw = nullptr;
+    uint32_t raw_capacity = 0;
+    int graphs = 0;
+
+    template <class T>
+    hipError_t alloc(T **p, size_t count) {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, std::max<size_t>(count * sizeof(T), 16));
+        if (e != hipSuccess) return e;
+        allocations.push_back(q);
+        device_bytes += count * sizeof(T);
+        *p = static_cast<T *>(q);
+        return hipSuccess;
+    }
+    void free_all() {
+        for (void *p : allocations) (void)hipFree(p);
+        allocations.clear();
+    }
+};
+
+struct octax_graph {
+    octax_engine *eng = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace octax {
+
+// Record the message of a failure for octax_last_error and return code.
+int32_t fail(int32_t code, const std::string &msg);
+int32_t hip_fail(hipError_t e, const char *what);
+
+// Fill table[2b], table[2b+1] with the two most frequent ROMs among the
+// (occupied) slots of block b (0xFFFFFFFF = none); blocks of envs_per_block.
+void block_rom_table(const octax_engine *g, std::vector<uint32_t> &table);
+
+// K fused or plain steps of every env of g on stream st.
+hipError_t launch_steps(octax_engine *g, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
+                        uint32_t obs_slots, float *d_reward, uint8_t *d_done, hipStream_t st);
+
+}  // namespace octax

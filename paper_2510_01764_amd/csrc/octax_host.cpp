@@ -12,23 +12,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/octax.h"
-#include "octax_kernels.h"
+#include "octax_engine.h"
 
 using namespace octax;
 
 namespace {
 
 thread_local std::string g_last_error;
-
-int32_t fail(int32_t code, const std::string &msg) {
-    g_last_error = msg;
-    return code;
-}
-
-int32_t hip_fail(hipError_t e, const char *what) {
-    return fail(OCTAX_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
 
 // The 4x5 hexadecimal font of the machine, glyphs 0..F (Appendix B.4 places
 // it at 0x050-0x09F).
@@ -43,57 +33,26 @@ const uint8_t kFontBytes[80] = {
 
 }  // namespace
 
-struct octax_engine {
-    uint32_t E = 0, R = 0, ipf = 0, frame_skip = 0;
-    uint32_t kernel = OCTAX_KERNEL_PLAIN;
-    uint32_t placement = OCTAX_PLACE_IDENTITY;
-    uint32_t envs_per_block = 256, rom_in_lds = 1;
-    hipStream_t stream = nullptr;
-    int device = 0;
-    uint64_t device_bytes = 0;
-    std::vector<void *> allocations;
-    std::vector<uint32_t> env_of, slot_of, rom_of;   // host copies of the placement
-    State s{};
-    Roms roms{};
-    uint32_t *d_block_roms = nullptr;                 // [blocks][2] for the current tuning
-    uint32_t *d_slot_scratch = nullptr;               // slot lists for get/set_state
-    RawState *d_raw = nullptr;
-    uint32_t raw_capacity = 0;
-    int graphs = 0;
+int32_t octax::fail(int32_t code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
 
-    template <class T>
-    hipError_t alloc(T **p, size_t count) {
-        void *q = nullptr;
-        hipError_t e = hipMalloc(&q, std::max<size_t>(count * sizeof(T), 16));
-        if (e != hipSuccess) return e;
-        allocations.push_back(q);
-        device_bytes += count * sizeof(T);
-        *p = static_cast<T *>(q);
-        return hipSuccess;
-    }
-    void free_all() {
-        for (void *p : allocations) (void)hipFree(p);
-        allocations.clear();
-    }
-};
+int32_t octax::hip_fail(hipError_t e, const char *what) {
+    return fail(OCTAX_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
 
-struct octax_graph {
-    octax_engine *eng = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-};
-
-namespace {
-
-hipError_t upload_block_roms(octax_engine *g) {
+void octax::block_rom_table(const octax_engine *g, std::vector<uint32_t> &table) {
     const uint32_t ipw = g->envs_per_block;
     const uint32_t blocks = (g->E + ipw - 1) / ipw;
-    std::vector<uint32_t> table(2 * (size_t)blocks, 0xFFFFFFFFu);
+    table.assign(2 * (size_t)blocks, 0xFFFFFFFFu);
     std::vector<uint32_t> count(g->R, 0);
+    std::vector<uint32_t> seen;
     for (uint32_t b = 0; b < blocks; b++) {
         const uint32_t lo = b * ipw, hi = std::min(g->E, lo + ipw);
-        std::vector<uint32_t> seen;
+        seen.clear();
         for (uint32_t sl = lo; sl < hi; sl++) {
+            if (!g->occupied.empty() && !g->occupied[sl]) continue;
             const uint32_t r = g->rom_of[sl];
             if (count[r]++ == 0) seen.push_back(r);
         }
@@ -109,6 +68,13 @@ hipError_t upload_block_roms(octax_engine *g) {
         table[2 * (size_t)b] = best0;
         table[2 * (size_t)b + 1] = best1;
     }
+}
+
+namespace {
+
+hipError_t upload_block_roms(octax_engine *g) {
+    std::vector<uint32_t> table;
+    block_rom_table(g, table);
     if (g->d_block_roms) {
         (void)hipFree(g->d_block_roms);
         g->allocations.erase(std::find(g->allocations.begin(), g->allocations.end(),
@@ -121,8 +87,10 @@ hipError_t upload_block_roms(octax_engine *g) {
                      hipMemcpyHostToDevice);
 }
 
-hipError_t launch_steps(octax_engine *g, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
-                        uint32_t obs_slots, float *d_reward, uint8_t *d_done, hipStream_t st) {
+}  // namespace
+
+hipError_t octax::launch_steps(octax_engine *g, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
+                               uint32_t obs_slots, float *d_reward, uint8_t *d_done, hipStream_t st) {
     StepIO io{d_action, d_obs, d_reward, d_done, K, obs_slots ? obs_slots : 1, g->ipf, g->frame_skip};
     if (g->kernel == OCTAX_KERNEL_FUSED) {
         FusedCfg f{g->envs_per_block, g->rom_in_lds, g->d_block_roms};
@@ -130,6 +98,8 @@ hipError_t launch_steps(octax_engine *g, uint32_t K, const int32_t *d_action, ui
     }
     return launch_step_plain(g->s, g->roms, io, st);
 }
+
+namespace {
 
 hipError_t ensure_raw(octax_engine *g, uint32_t count) {
     if (count <= g->raw_capacity) return hipSuccess;

@@ -35,6 +35,9 @@ hipError_t launch_step_fused(const State &s, const Roms &r, const StepIO &io, co
 // allocation), else only pages marked dirty.
 hipError_t launch_reset(const State &s, const Roms &r, const uint8_t *mask, bool full_ram,
                         hipStream_t st);
+// The same for slots [first, first + count) only.
+hipError_t launch_reset_range(const State &s, const Roms &r, const uint8_t *mask, bool full_ram,
+                              uint32_t first, uint32_t count, hipStream_t st);
 // Write the observation of every env from its frame ring.
 hipError_t launch_observe(const State &s, uint8_t *obs, hipStream_t st);
 

@@ -7,8 +7,11 @@ namespace octax {
 namespace {
 
 // One thread per slot: registers, display, stack, frame ring, counters.
-__global__ __launch_bounds__(256) void reset_regs_kernel(State s, const uint8_t *mask) {
-    const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void reset_regs_kernel(State s, const uint8_t *mask, uint32_t first,
+                                                         uint32_t count) {
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= count) return;
+    const uint32_t slot = first + k;
     if (slot >= s.num) return;
     const uint32_t env = s.env_of[slot];
     if (mask && !mask[env]) return;
@@ -35,8 +38,8 @@ __global__ __launch_bounds__(256) void reset_regs_kernel(State s, const uint8_t 
 // image (all pages, or only those written since the last reset), then the
 // dirty mask is cleared by the last wave to read it.
 __global__ __launch_bounds__(256) void reset_ram_kernel(State s, Roms roms, const uint8_t *mask,
-                                                        uint32_t full) {
-    const uint32_t slot = blockIdx.x;
+                                                        uint32_t full, uint32_t first) {
+    const uint32_t slot = first + blockIdx.x;
     if (slot >= s.num) return;
     const uint32_t env = s.env_of[slot];
     if (mask && !mask[env]) return;
@@ -56,7 +59,7 @@ __global__ __launch_bounds__(256) void reset_ram_kernel(State s, Roms roms, cons
 __global__ __launch_bounds__(256) void observe_kernel(State s, uint8_t *obs) {
     const uint64_t gid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     const uint32_t slot = (uint32_t)(gid >> 9);
-    if (slot >= s.num) return;
+    if (!slot_live(s, slot)) return;
     const uint32_t piece = (uint32_t)(gid & 511);
     const uint32_t fr = piece >> 7, q = piece & 127;
     const uint32_t head = s.misc[slot] >> 24 & 3;
@@ -68,10 +71,16 @@ __global__ __launch_bounds__(256) void observe_kernel(State s, uint8_t *obs) {
 
 hipError_t launch_reset(const State &s, const Roms &r, const uint8_t *mask, bool full_ram,
                         hipStream_t st) {
-    hipLaunchKernelGGL(reset_ram_kernel, dim3(s.num), dim3(256), 0, st, s, r, mask, full_ram ? 1u : 0u);
+    return launch_reset_range(s, r, mask, full_ram, 0, s.num, st);
+}
+
+hipError_t launch_reset_range(const State &s, const Roms &r, const uint8_t *mask, bool full_ram,
+                              uint32_t first, uint32_t count, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(reset_ram_kernel, dim3(count), dim3(256), 0, st, s, r, mask, full_ram ? 1u : 0u, first);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reset_regs_kernel, dim3((s.num + 255) / 256), dim3(256), 0, st, s, mask);
+    hipLaunchKernelGGL(reset_regs_kernel, dim3((count + 255) / 256), dim3(256), 0, st, s, mask, first, count);
     return hipGetLastError();
 }
 

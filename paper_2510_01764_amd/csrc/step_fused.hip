@@ -2,19 +2,23 @@
 // stays resident for the whole launch.
 //
 //   * registers, PC, I, timers and the RNG state of each env live in VGPRs for
-//     all K steps (one env per lane);
+//     all K steps (one env per lane of an emulator wave);
 //   * the display (32 rows of 64 bits), the call stack and the power-on
 //     images of up to two ROMs are staged in LDS; code fetches and sprite
 //     reads of memory pages not written since the reset are served from the
-//     staged image, written pages from the env's memory in HBM;
-//   * each step ends with a per-lane 32x64 bit transpose of the display into
-//     a packed frame (64 words in observation store order) and a
-//     wave-cooperative pass that expands each env's frame into bytes with
-//     1 KB contiguous stores per instruction;
+//     staged image, written pages from two LDS cache slots per env or from
+//     the env's memory in HBM;
+//   * observations are written by a second set of waves of the same block:
+//     after each step they copy the displays out of LDS, transpose each one
+//     (32x64 bits) into a packed frame (64 words in observation store order)
+//     and expand it into bytes with 1 KB contiguous stores per instruction,
+//     while the emulator waves already run the next step;
 //   * a frame is written, when it is computed, into the four observations it
-//     belongs to (step k as frame 3, step k+1 as frame 2, ...), so the step
-//     loop issues no global loads between its observation stores: on CDNA a
-//     load waits for every earlier store of the wave to complete;
+//     belongs to (step k as frame 3, step k+1 as frame 2, ...), so the writer
+//     waves issue no global loads between their observation stores: on CDNA
+//     a load waits for every earlier store of the wave to complete;
+//   * free slots of a serving pool are skipped, and blocks without an env
+//     exit at once;
 //   * the state goes back to HBM once per launch.
 #include "octax_grouped.h"
 #include "octax_kernels.h"
@@ -23,6 +27,7 @@ namespace octax {
 namespace {
 
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
 typedef __attribute__((address_space(1))) uint8_t glb_u8;
@@ -32,15 +37,22 @@ constexpr int kStageEnvs = 16;     // envs staged per round of the cooperative p
 constexpr int kStageStride = 68;   // u32 per staged env (64 + 4 pad, 16-byte aligned)
 constexpr int kCacheStride = 136;  // bytes per env: two 64-byte pages + pad (spreads lanes over banks)
 
-// LDS of one block.  Display row y of lane l is fb[l][y ^ (l & 31)]: lanes
-// reading the same row index hit different banks.
+// LDS of one block.  The display of lane l is fb[l][0..31], one padded
+// 33-row stride per lane, so a lane's rows are contiguous (sprite rows are
+// addressed with immediate offsets) and lanes reading the same row index
+// spread over the banks.  The tail pad keeps reads a few bytes past the last
+// image page inside the allocation.
+constexpr int kFbStride = 33;
+
 template <int IPW>
 struct Shared {
-    uint64_t fb[IPW][32];
+    uint64_t fb[IPW][kFbStride];
     uint8_t cache[IPW][kCacheStride];
     uint32_t stage[IPW / 64][kStageEnvs][kStageStride];
     uint32_t stack[IPW][9];
+    uint8_t done[IPW];        // done bits of the step just emulated, for the writer waves
     uint8_t img[2][kMem];
+    uint8_t tail_pad[64];
 };
 
 // Memory of one env in the fused kernel.
@@ -103,17 +115,6 @@ struct FusedMem {
         }
         return s;
     }
-    // LDS base of page p (byte a at base[a & 63]) when p is readable from LDS
-    // without a fill.
-    __device__ __forceinline__ bool lds_page(uint32_t p, lds_u8 *&base) const {
-        if (!is_dirty(p)) {
-            base = (lds_u8 *)&sh.img[lidx & 1][0] + 64 * p;
-            return lidx >= 0;
-        }
-        const int32_t s = find(p);
-        base = slot_ptr(s & 1);
-        return s >= 0;
-    }
     // One byte, any page (fills a slot for an uncached written page).
     __device__ __forceinline__ uint32_t read(uint32_t a) {
         const uint32_t p = a >> 6;
@@ -125,27 +126,37 @@ struct FusedMem {
         if (lidx >= 0) return ((const lds_u8 *)&sh.img[lidx][0])[a];
         return gimg[a];
     }
-    __device__ __forceinline__ uint32_t fetch(uint32_t pc) {
+    // LDS address of byte a, computed with selects only: a clean page of the
+    // staged image or a cached written page.  `slow` is raised when neither
+    // holds (the address is then some other byte of the block's LDS).
+    __device__ __forceinline__ const lds_u8 *lds_byte(uint32_t a, bool &slow) const {
+        return lds_page_sel(a >> 6, slow) + (a & 63);
+    }
+    // Instruction word at pc and, in the same LDS round trip, the return
+    // address stack[(sp - 1) & 15]; lanes whose code bytes are not in LDS
+    // take the fill path afterwards.
+    __device__ __forceinline__ uint32_t fetch(uint32_t pc, uint32_t sp, uint32_t &ret) {
         const uint32_t a1 = (pc + 1) & 0xFFF;
-        lds_u8 *b0, *b1;
-        const bool ok0 = lds_page(pc >> 6, b0);
-        const bool ok1 = lds_page(a1 >> 6, b1);
-        if (ok0 && ok1) return ((uint32_t)b0[pc & 63] << 8) | b1[a1 & 63];
-        return (read(pc) << 8) | read(a1);
+        bool slow = false;
+        const lds_u8 *b0 = lds_byte(pc, slow);
+        const lds_u8 *b1 = lds_byte(a1, slow);
+        uint32_t op = ((uint32_t)*b0 << 8) | *b1;
+        ret = stack_get((sp - 1) & 15);
+        if (slow) op = (read(pc) << 8) | read(a1);
+        return op;
     }
     __device__ __forceinline__ u32x4 load_bytes(uint32_t a, uint32_t count) {
-        const uint32_t p0 = a >> 6, p1 = ((a + count - 1) & 0xFFF) >> 6;
-        lds_u8 *b0, *b1;
-        const bool ok0 = lds_page(p0, b0);
-        const bool ok1 = lds_page(p1, b1);
+        const uint32_t off = a & 63;
+        const uint32_t a_last = (a + count - 1) & 0xFFF;
+        bool slow = false;
+        const lds_u8 *s0 = lds_page_sel(a >> 6, slow) + off;
+        const lds_u8 *s1 = lds_page_sel(a_last >> 6, slow) + off - 64;
+        const uint32_t rb = 64 - off;   // bytes k < rb are on the first page
         u32x4 v = {0, 0, 0, 0};
-        if (ok0 && ok1) {
+        if (!slow) {
             uint32_t b[16];
 #pragma unroll
-            for (int k = 0; k < 16; k++) {
-                const uint32_t ak = (a + k) & 0xFFF;
-                b[k] = (((ak >> 6) == p0) ? b0 : b1)[ak & 63];
-            }
+            for (int k = 0; k < 16; k++) b[k] = ((uint32_t)k < rb ? s0 : s1)[k];
 #pragma unroll
             for (int k = 0; k < 16; k++)
                 if ((uint32_t)k < count) or_byte(v, k, b[k]);
@@ -177,19 +188,27 @@ struct FusedMem {
         }
         dirty |= (1ull << p0) | (1ull << p1);
     }
-    // Rows r < cnt of the sprite: one batch of LDS reads (sprite bytes and
-    // display rows), then the XOR and the row writes.
+    // LDS base of page p, computed with selects only (see lds_byte).
+    __device__ __forceinline__ lds_u8 *lds_page_sel(uint32_t p, bool &slow) const {
+        const bool d = (dirty >> p) & 1;
+        const uint32_t tp = p | 0x40;
+        const bool h0 = (tags & 0x7F) == tp, h1 = ((tags >> 8) & 0x7F) == tp;
+        slow = slow || (d ? !(h0 || h1) : lidx < 0);
+        return d ? slot_ptr(h1 ? 1u : 0u) : (lds_u8 *)&sh.img[lidx & 1][0] + 64 * p;
+    }
+    // Rows [R0, R0 + NR) of the sprite that lie above cnt: one batch of LDS
+    // reads (sprite row r at s0[r] while r < rb, else at s1[r]; display row
+    // y0 + r at fbr[r]), then the XOR and the row writes.  Rows at or past
+    // cnt are read (inside the block's LDS) but neither used nor written.
     template <int R0, int NR>
-    __device__ __forceinline__ uint64_t draw_rows(lds_u64 *fb, uint32_t sw, uint32_t x0, uint32_t y0,
-                                                  uint32_t cnt, uint32_t I, uint32_t p0,
-                                                  lds_u8 *b0, lds_u8 *b1) {
+    __device__ __forceinline__ uint64_t draw_rows(lds_u64 *fbr, uint32_t x0, uint32_t cnt,
+                                                  const lds_u8 *s0, const lds_u8 *s1, uint32_t rb) {
         uint32_t spr[NR];
         uint64_t row[NR];
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            const uint32_t ar = (I + R0 + r) & 0xFFF;
-            spr[r] = (((ar >> 6) == p0) ? b0 : b1)[ar & 63];
-            row[r] = fb[(y0 + min((uint32_t)(R0 + r), cnt - 1)) ^ sw];
+            spr[r] = ((uint32_t)(R0 + r) < rb ? s0 : s1)[R0 + r];
+            row[r] = fbr[R0 + r];
         }
         uint64_t hit = 0;
 #pragma unroll
@@ -197,30 +216,34 @@ struct FusedMem {
             if ((uint32_t)(R0 + r) < cnt) {
                 const uint64_t m = ((uint64_t)spr[r] << 56) >> x0;
                 hit |= row[r] & m;
-                fb[(y0 + R0 + r) ^ sw] = row[r] ^ m;
+                fbr[R0 + r] = row[r] ^ m;
             }
         }
         return hit;
     }
+    // DXYN at (x0, y0) = (VX & 63, VY & 31): rows below the screen are
+    // clipped, pixels past x = 63 fall off the shifted mask.  Sprite bytes
+    // are at I + r (12-bit wrap), on at most two pages.
     __device__ __forceinline__ uint32_t draw(uint32_t x0, uint32_t y0, uint32_t I, uint32_t n) {
-        lds_u64 *fb = (lds_u64 *)&sh.fb[lane][0];
-        const uint32_t sw = lane & 31;
-        const uint32_t cnt = min(n, 32 - y0);   // rows below the screen are clipped
-        if (cnt == 0) return 0;
-        const uint32_t p0 = I >> 6, p1 = ((I + cnt - 1) & 0xFFF) >> 6;
-        lds_u8 *b0, *b1;
-        const bool ok0 = lds_page(p0, b0);
-        const bool ok1 = lds_page(p1, b1);
+        lds_u64 *fbr = (lds_u64 *)&sh.fb[lane][0] + y0;
+        const uint32_t cnt = min(n, 32 - y0);
+        const uint32_t off = I & 63;
+        const uint32_t a_last = (I + max(cnt, 1u) - 1) & 0xFFF;
+        bool slow = false;
+        const lds_u8 *s0 = lds_page_sel(I >> 6, slow) + off;
+        const lds_u8 *s1 = lds_page_sel(a_last >> 6, slow) + off - 64;
+        const uint32_t rb = 64 - off;   // rows r < rb are on the first page
         uint64_t hit = 0;
-        if (ok0 && ok1) {
-            hit = draw_rows<0, 8>(fb, sw, x0, y0, cnt, I, p0, b0, b1);
-            if (cnt > 8) hit |= draw_rows<8, 7>(fb, sw, x0, y0, cnt, I, p0, b0, b1);
+        if (!slow) {
+            hit = draw_rows<0, 4>(fbr, x0, cnt, s0, s1, rb);
+            if (cnt > 4) hit |= draw_rows<4, 4>(fbr, x0, cnt, s0, s1, rb);
+            if (cnt > 8) hit |= draw_rows<8, 7>(fbr, x0, cnt, s0, s1, rb);
         } else {
             for (uint32_t r = 0; r < cnt; r++) {
                 const uint64_t m = ((uint64_t)read((I + r) & 0xFFF) << 56) >> x0;
-                const uint64_t row = fb[(y0 + r) ^ sw];
+                const uint64_t row = fbr[r];
                 hit |= row & m;
-                fb[(y0 + r) ^ sw] = row ^ m;
+                fbr[r] = row ^ m;
             }
         }
         return hit != 0;
@@ -230,14 +253,12 @@ struct FusedMem {
 #pragma unroll
         for (int y = 0; y < 32; y++) fb[y] = 0;
     }
+    // Stack entry i is the i-th 16-bit half of the env's stack words.
     __device__ __forceinline__ uint32_t stack_get(uint32_t i) const {
-        const uint32_t w = ((const lds_u32 *)&sh.stack[lane][0])[i >> 1];
-        return (i & 1) ? (w >> 16) : (w & 0xFFFF);
+        return ((const lds_u16 *)&sh.stack[lane][0])[i];
     }
     __device__ __forceinline__ void stack_set(uint32_t i, uint32_t v) {
-        lds_u32 *st = (lds_u32 *)&sh.stack[lane][0];
-        const uint32_t w = st[i >> 1];
-        st[i >> 1] = (i & 1) ? ((w & 0xFFFFu) | (v << 16)) : ((w & 0xFFFF0000u) | v);
+        ((lds_u16 *)&sh.stack[lane][0])[i] = (uint16_t)v;
     }
     // Restore the written pages from the image (automatic reset).
     __device__ __forceinline__ void restore_pages() {
@@ -274,30 +295,44 @@ __device__ __forceinline__ void store_frame(uint8_t *frame, uint32_t lane64, uin
     store16(frame + 1024 + 16 * lane64, w >> 16);
 }
 
+// Wave roles.  A block runs IPW envs with 2 * IPW threads: waves
+// 0 .. IPW/64 - 1 emulate (one env per lane, thread l is env l) and waves
+// IPW/64 .. 2 * IPW/64 - 1 write observations (thread IPW + l serves env l).
+// Each step ends with two block barriers: after the first the display of
+// every env is final (auto-reset included), between the two the writer waves
+// copy it into registers, after the second the emulators start the next step
+// while the writers transpose, expand and store the frame just taken.  The
+// observation stores and the emulation of the next step thus share each
+// SIMD as two waves instead of running back to back in one.
+//
 // kRollout separates the K-step launches (graph-captured rollouts) from the
 // K = 1 launches of octax_step into two instantiations of the same code, so
 // profiles report them apart.
 template <int IPW, bool kRollout>
-__global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, StepIO io, FusedCfg cfg) {
+__global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms, StepIO io, FusedCfg cfg) {
     __shared__ Shared<IPW> sh;
-    const uint32_t l = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
+    const bool emu = __builtin_amdgcn_readfirstlane(tid) < (uint32_t)IPW;   // wave-uniform role
+    const uint32_t l = emu ? tid : tid - IPW;                                 // env of this thread
     const uint32_t lane64 = l & 63;
     const uint32_t wave = l >> 6;
     const uint32_t wave_base = l & ~63u;
     const uint32_t slot = blockIdx.x * IPW + l;
     const uint32_t E = s.num;
     const uint32_t K = io.K;
-    const bool active = slot < E;
+    const bool active = slot_live(s, slot);
+    // a block with no env (free range of a serving pool) has nothing to do
+    if (!__syncthreads_or(active)) return;
+    const uint32_t live = active ? 1u : 0u;
     const uint32_t wave_slot0 = blockIdx.x * IPW + wave_base;
-    const uint32_t nj = (E > wave_slot0) ? min(64u, E - wave_slot0) : 0u;   // envs of this wave
-    const uint32_t sw = l & 31;                                              // display row swizzle
+    const uint32_t nj = (E > wave_slot0) ? min(64u, E - wave_slot0) : 0u;   // slots of this wave
 
-    // Stage the block's ROM images.
+    // Stage the block's ROM images (all threads).
     uint32_t brom0 = kNoRom, brom1 = kNoRom;
     if (cfg.rom_in_lds) {
         brom0 = cfg.block_roms[blockIdx.x * 2 + 0];
         brom1 = cfg.block_roms[blockIdx.x * 2 + 1];
-        for (uint32_t q = l; q < 2 * kMem / 16; q += IPW) {
+        for (uint32_t q = tid; q < 2 * kMem / 16; q += 2 * IPW) {
             const uint32_t which = q / (kMem / 16);
             const uint32_t rid = which ? brom1 : brom0;
             if (rid != kNoRom) {
@@ -312,9 +347,14 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
     int32_t prev = 0;
     uint64_t dirty = 0;
     u32x4 keys = {0, 0, 0, 0};   // the ROM's 16 action keys, one byte each
+    reset_core(c);
+    c.rng = 0;
     if (active) {
-        load_core(s, slot, c, head);
+        head = (s.misc[slot] >> 24) & 3;
         env = s.env_of[slot];
+    }
+    if (emu && active) {
+        load_core(s, slot, c, head);
         rom = s.rom_of[slot];
         desc = roms.desc[rom];
         t = s.t[slot];
@@ -326,16 +366,13 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
 #pragma unroll
         for (int q = 0; q < 16; q++) {
             const uint4 v = fb4[q];
-            sh.fb[l][(2 * q) ^ sw] = (uint64_t)v.x | ((uint64_t)v.y << 32);
-            sh.fb[l][(2 * q + 1) ^ sw] = (uint64_t)v.z | ((uint64_t)v.w << 32);
+            sh.fb[l][2 * q] = (uint64_t)v.x | ((uint64_t)v.y << 32);
+            sh.fb[l][2 * q + 1] = (uint64_t)v.z | ((uint64_t)v.w << 32);
         }
         const uint4 *st4 = reinterpret_cast<const uint4 *>(s.stack + (size_t)slot * 8);
         const uint4 a0 = st4[0], a1 = st4[1];
         sh.stack[l][0] = a0.x; sh.stack[l][1] = a0.y; sh.stack[l][2] = a0.z; sh.stack[l][3] = a0.w;
         sh.stack[l][4] = a1.x; sh.stack[l][5] = a1.y; sh.stack[l][6] = a1.z; sh.stack[l][7] = a1.w;
-    } else {
-        reset_core(c);
-        c.rng = 0;
     }
     const int32_t lidx = (rom == brom0) ? 0 : (rom == brom1) ? 1 : -1;
     const glb_u8 *gimg = (const glb_u8 *)(roms.image + (size_t)rom * kMem);
@@ -346,10 +383,10 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
         return io.obs + (size_t)(kk % io.obs_slots) * obs_step + (size_t)e * kObsBytes;
     };
 
-    // Prologue: the three frames before this launch go into the observations
-    // of steps 0..2 (frame f of step k is the frame of step k - 3 + f).  All
-    // loads of a chunk of envs are issued before its stores.
-    if (io.obs) {
+    // Writers, prologue: the three frames before this launch go into the
+    // observations of steps 0..2 (frame f of step k is the frame of step
+    // k - 3 + f).  All loads of a chunk of envs are issued before its stores.
+    if (!emu && io.obs) {
         for (uint32_t j0 = 0; j0 < nj; j0 += kStageEnvs) {
             uint32_t w[kStageEnvs][3];
 #pragma unroll
@@ -365,6 +402,7 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
             for (int jj = 0; jj < kStageEnvs; jj++) {
                 const uint32_t j = j0 + jj;
                 if (j >= nj) break;
+                if (!__builtin_amdgcn_readlane(live, j)) continue;
                 const uint32_t je = __builtin_amdgcn_readlane(env, j);
 #pragma unroll
                 for (int back = 0; back < 3; back++) {          // frame of step -1 - back
@@ -382,24 +420,23 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
     u32x4 kchunk = {0, 0, 0, 0};   // held keys of 16 consecutive steps, one byte each
     FusedMem<IPW> mem{sh, l, lidx, gimg, ram, dirty, tags};
     for (uint32_t k = 0; k < K; k++) {
-        uint32_t done = 0;
-        uint32_t pw[64];
-        if ((k & 15) == 0 && active) {
-            // actions of the next 16 steps -> held keys (16 = none)
-            uint32_t kb[16];
+        // ---- emulators: step k ----
+        if (emu && active) {
+            if ((k & 15) == 0) {
+                // actions of the next 16 steps -> held keys (16 = none)
+                uint32_t kb[16];
 #pragma unroll
-            for (int q = 0; q < 16; q++) {
-                const int32_t a = (k + q < K) ? io.action[(size_t)(k + q) * E + env] : -1;
-                const uint32_t ua = (uint32_t)a;
-                const uint32_t word = (ua & 8) ? ((ua & 4) ? keys.w : keys.z) : ((ua & 4) ? keys.y : keys.x);
-                kb[q] = (ua < nact) ? (__builtin_amdgcn_ubfe(word, (ua & 3) * 8, 8) & 15) : kKeyNone;
+                for (int q = 0; q < 16; q++) {
+                    const int32_t a = (k + q < K) ? io.action[(size_t)(k + q) * E + env] : -1;
+                    const uint32_t ua = (uint32_t)a;
+                    const uint32_t word = (ua & 8) ? ((ua & 4) ? keys.w : keys.z) : ((ua & 4) ? keys.y : keys.x);
+                    kb[q] = (ua < nact) ? (__builtin_amdgcn_ubfe(word, (ua & 3) * 8, 8) & 15) : kKeyNone;
+                }
+                kchunk.x = kb[0] | (kb[1] << 8) | (kb[2] << 16) | (kb[3] << 24);
+                kchunk.y = kb[4] | (kb[5] << 8) | (kb[6] << 16) | (kb[7] << 24);
+                kchunk.z = kb[8] | (kb[9] << 8) | (kb[10] << 16) | (kb[11] << 24);
+                kchunk.w = kb[12] | (kb[13] << 8) | (kb[14] << 16) | (kb[15] << 24);
             }
-            kchunk.x = kb[0] | (kb[1] << 8) | (kb[2] << 16) | (kb[3] << 24);
-            kchunk.y = kb[4] | (kb[5] << 8) | (kb[6] << 16) | (kb[7] << 24);
-            kchunk.z = kb[8] | (kb[9] << 8) | (kb[10] << 16) | (kb[11] << 24);
-            kchunk.w = kb[12] | (kb[13] << 8) | (kb[14] << 16) | (kb[15] << 24);
-        }
-        if (active) {
             const uint32_t kq = (k >> 2) & 3;
             const uint32_t kword = kq == 0 ? kchunk.x : kq == 1 ? kchunk.y : kq == 2 ? kchunk.z : kchunk.w;
             const uint32_t key = __builtin_amdgcn_ubfe(kword, (k & 3) * 8, 8);
@@ -412,7 +449,7 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
             const uint32_t term = vget(c.r, (desc >> 8) & 15) == ((desc >> 16) & 0xFF);
             t += 1;
             const uint32_t trunc = (hor != 0) && (t >= hor);
-            done = term | (trunc << 1);
+            const uint32_t done = term | (trunc << 1);
             io.reward[(size_t)k * E + env] = reward;
             io.done[(size_t)k * E + env] = (uint8_t)done;
             if (done) {
@@ -428,67 +465,83 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
                 prev = score;
                 head = (head + 1) & 3;
             }
-            uint32_t hi[32], lo[32];
+            sh.done[l] = (uint8_t)done;
+        }
+        __syncthreads();   // the displays of step k are final
+
+        // ---- writers: take the frames of step k, then store them ----
+        uint32_t hi[32], lo[32];
+        uint32_t done = 0;
+        if (!emu) {
 #pragma unroll
             for (int r = 0; r < 32; r++) {
-                const uint64_t row = sh.fb[l][(31 - r) ^ sw];
+                const uint64_t row = sh.fb[l][31 - r];
                 hi[r] = (uint32_t)(row >> 32);
                 lo[r] = (uint32_t)row;
             }
+            done = active ? sh.done[l] : 0u;
+        }
+        __syncthreads();   // the displays may change again
+        const bool ring_step = k + 4 >= K;
+        if (!emu && (io.obs || ring_step)) {
+            head = done ? 0u : (head + 1) & 3;
+            uint32_t pw[64];
             rows_to_cols(hi, lo);
             pack_frame(hi, lo, pw);
-        }
-
-        // Cooperative pass, 16 envs per round: stage their packed frames, then
-        // for each env store its frame into every observation it belongs to
-        // and keep the last four frames of the launch in the env's ring.
-        const bool ring_step = k + 4 >= K;
-        for (uint32_t r0 = 0; r0 < nj; r0 += kStageEnvs) {
-            if (active && lane64 - r0 < (uint32_t)kStageEnvs) {
-                uint4 *stg = reinterpret_cast<uint4 *>(sh.stage[wave][lane64 - r0]);
+            // Cooperative pass, 16 envs per round: stage their packed frames,
+            // then for each env store its frame into every observation it
+            // belongs to and keep the last four frames of the launch in the
+            // env's ring.
+            for (uint32_t r0 = 0; r0 < nj; r0 += kStageEnvs) {
+                if (active && lane64 - r0 < (uint32_t)kStageEnvs) {
+                    uint4 *stg = reinterpret_cast<uint4 *>(sh.stage[wave][lane64 - r0]);
 #pragma unroll
-                for (int q = 0; q < 16; q++)
-                    stg[q] = make_uint4(pw[4 * q], pw[4 * q + 1], pw[4 * q + 2], pw[4 * q + 3]);
-            }
-            wave_sync();
-            const uint32_t r1 = min(r0 + (uint32_t)kStageEnvs, nj);
-            for (uint32_t j = r0; j < r1; j++) {
-                const uint32_t w = sh.stage[wave][j - r0][lane64];
-                const uint32_t jdone = __builtin_amdgcn_readlane(done, j);
-                if (io.obs) {
-                    const uint32_t je = __builtin_amdgcn_readlane(env, j);
+                    for (int q = 0; q < 16; q++)
+                        stg[q] = make_uint4(pw[4 * q], pw[4 * q + 1], pw[4 * q + 2], pw[4 * q + 3]);
+                }
+                wave_sync();
+                const uint32_t r1 = min(r0 + (uint32_t)kStageEnvs, nj);
+                for (uint32_t j = r0; j < r1; j++) {
+                    if (!__builtin_amdgcn_readlane(live, j)) continue;
+                    const uint32_t w = sh.stage[wave][j - r0][lane64];
+                    const uint32_t jdone = __builtin_amdgcn_readlane(done, j);
+                    if (io.obs) {
+                        const uint32_t je = __builtin_amdgcn_readlane(env, j);
 #pragma unroll
-                    for (uint32_t d = 0; d < 4; d++)
-                        if (k + d < K) store_frame(obs_of(k + d, je) + (3 - d) * 2048, lane64, w);
-                    if (jdone) {
-                        // the frames before the reset belong to the old episode
+                        for (uint32_t d = 0; d < 4; d++)
+                            if (k + d < K) store_frame(obs_of(k + d, je) + (3 - d) * 2048, lane64, w);
+                        if (jdone) {
+                            // the frames before the reset belong to the old episode
 #pragma unroll
-                        for (uint32_t d = 0; d < 3; d++)
+                            for (uint32_t d = 0; d < 3; d++)
 #pragma unroll
-                            for (uint32_t f = 0; f < 3 - d; f++)
-                                if (k + d < K) store_frame(obs_of(k + d, je) + f * 2048, lane64, 0);
+                                for (uint32_t f = 0; f < 3 - d; f++)
+                                    if (k + d < K) store_frame(obs_of(k + d, je) + f * 2048, lane64, 0);
+                        }
+                    }
+                    // the last four frames of the launch stay in the ring; a
+                    // reset blanks the three slots before the new head
+                    if (ring_step) {
+                        const uint32_t jh = __builtin_amdgcn_readlane(head, j);
+                        uint32_t *ring = s.cols + (size_t)(wave_slot0 + j) * 256 + lane64;
+                        ring[jh * 64] = w;
+                        if (jdone) {
+                            ring[((jh + 1) & 3) * 64] = 0;
+                            ring[((jh + 2) & 3) * 64] = 0;
+                            ring[((jh + 3) & 3) * 64] = 0;
+                        }
                     }
                 }
-                // the last four frames of the launch stay in the ring; a reset
-                // blanks the three slots before the new head
-                if (ring_step) {
-                    const uint32_t jh = __builtin_amdgcn_readlane(head, j);
-                    uint32_t *ring = s.cols + (size_t)(wave_slot0 + j) * 256 + lane64;
-                    ring[jh * 64] = w;
-                    if (jdone) {
-                        ring[((jh + 1) & 3) * 64] = 0;
-                        ring[((jh + 2) & 3) * 64] = 0;
-                        ring[((jh + 3) & 3) * 64] = 0;
-                    }
-                }
+                wave_sync();
             }
-            wave_sync();
+        } else if (!emu) {
+            head = done ? 0u : (head + 1) & 3;
         }
     }
     dirty = mem.dirty;
     tags = mem.tags;
 
-    if (active) {
+    if (emu && active) {
         store_core(s, slot, c, head);
         s.t[slot] = t;
         s.prev[slot] = prev;
@@ -496,7 +549,7 @@ __global__ __launch_bounds__(IPW) void step_fused_kernel(State s, Roms roms, Ste
         uint4 *fb4 = reinterpret_cast<uint4 *>(s.fb + (size_t)slot * 32);
 #pragma unroll
         for (int q = 0; q < 16; q++) {
-            const uint64_t a = sh.fb[l][(2 * q) ^ sw], b = sh.fb[l][(2 * q + 1) ^ sw];
+            const uint64_t a = sh.fb[l][2 * q], b = sh.fb[l][2 * q + 1];
             fb4[q] = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
         }
         uint4 *st4 = reinterpret_cast<uint4 *>(s.stack + (size_t)slot * 8);
@@ -509,9 +562,9 @@ template <int IPW>
 hipError_t launch_ipw(const State &s, const Roms &r, const StepIO &io, const FusedCfg &f, hipStream_t st) {
     const uint32_t blocks = (s.num + IPW - 1) / IPW;
     if (io.K == 1)
-        hipLaunchKernelGGL((step_fused_kernel<IPW, false>), dim3(blocks), dim3(IPW), 0, st, s, r, io, f);
+        hipLaunchKernelGGL((step_fused_kernel<IPW, false>), dim3(blocks), dim3(2 * IPW), 0, st, s, r, io, f);
     else
-        hipLaunchKernelGGL((step_fused_kernel<IPW, true>), dim3(blocks), dim3(IPW), 0, st, s, r, io, f);
+        hipLaunchKernelGGL((step_fused_kernel<IPW, true>), dim3(blocks), dim3(2 * IPW), 0, st, s, r, io, f);
     return hipGetLastError();
 }
 

@@ -64,7 +64,7 @@ struct PlainMem {
 
 __global__ __launch_bounds__(256) void step_plain_kernel(State s, Roms roms, StepIO io, uint32_t k) {
     const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
-    if (slot >= s.num) return;
+    if (!slot_live(s, slot)) return;
     const uint32_t E = s.num;
     const uint32_t env = s.env_of[slot];
     const uint32_t rom = s.rom_of[slot];

@@ -34,6 +34,8 @@ EXPORTED = (
     "octax_graph_launch", "octax_graph_destroy", "octax_get_state", "octax_set_state",
     "octax_set_kernel", "octax_set_tuning", "octax_set_stream", "octax_info", "octax_destroy",
     "octax_last_error", "octax_calib_write", "octax_calib_copy",
+    "octax_pool_slot_bytes", "octax_pool_create", "octax_pool_admit", "octax_pool_retire",
+    "octax_pool_step", "octax_pool_info", "octax_pool_get_state", "octax_pool_destroy",
 )
 
 
@@ -57,6 +59,20 @@ class octax_config(ctypes.Structure):
         ("h_score_reg", ctypes.c_void_p), ("h_term_reg", ctypes.c_void_p),
         ("h_term_value", ctypes.c_void_p), ("h_horizon", ctypes.c_void_p),
         ("h_env_seed", ctypes.c_void_p), ("stream", ctypes.c_void_p),
+    ]
+
+
+class octax_pool_config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_uint32), ("num_roms", ctypes.c_uint32),
+        ("instr_per_frame", ctypes.c_uint32), ("frame_skip", ctypes.c_uint32),
+        ("quirks", ctypes.c_uint32), ("envs_per_block", ctypes.c_uint32),
+        ("pool_bytes", ctypes.c_uint64),
+        ("h_rom_data", ctypes.c_void_p), ("h_rom_offset", ctypes.c_void_p),
+        ("h_rom_len", ctypes.c_void_p), ("h_action_keys", ctypes.c_void_p),
+        ("h_num_actions", ctypes.c_void_p), ("h_score_reg", ctypes.c_void_p),
+        ("h_term_reg", ctypes.c_void_p), ("h_term_value", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
     ]
 
 
@@ -98,6 +114,14 @@ def library() -> ctypes.CDLL:
         "octax_last_error": ([], ctypes.c_char_p),
         "octax_calib_write": ([P, ctypes.c_uint64, u32, u32, P], i32),
         "octax_calib_copy": ([P, P, ctypes.c_uint64, P], i32),
+        "octax_pool_slot_bytes": ([], ctypes.c_uint64),
+        "octax_pool_create": ([ctypes.POINTER(octax_pool_config), ctypes.POINTER(P)], i32),
+        "octax_pool_admit": ([P, u32, u32, P, P, ctypes.POINTER(u32)], i32),
+        "octax_pool_retire": ([P, u32], i32),
+        "octax_pool_step": ([P, u32, P, P, u32, P, P], i32),
+        "octax_pool_info": ([P] + [ctypes.POINTER(u32)] * 4, i32),
+        "octax_pool_get_state": ([P, u32, u32, P], i32),
+        "octax_pool_destroy": ([P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -315,6 +339,99 @@ class Graph:
     def close(self):
         if getattr(self, "_h", None):
             _check(library().octax_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pool:
+    """A liboctax serving pool (octax_pool_*) over a set of ROMs.
+
+    ``roms`` and the per-ROM descriptors come from a ``workload.EnvSpec``
+    (its env fields are not used).  Step buffers are indexed by slot:
+    action int32 [K, capacity], obs uint8 [slots, capacity, 4, 64, 32] or
+    None, reward float32 [K, capacity], done uint8 [K, capacity].
+    """
+
+    def __init__(self, spec, pool_bytes: int, envs_per_block: int = 256, stream=None):
+        L = library()
+        roms = spec.roms
+        data = np.frombuffer(b"".join(roms) or b"\0", dtype=np.uint8).copy()
+        lens = np.array([len(r) for r in roms], dtype=np.uint32)
+        offs = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint32)
+        keep = dict(data=data, lens=lens, offs=offs,
+                    akeys=np.ascontiguousarray(spec.action_keys, dtype=np.uint8),
+                    nact=np.ascontiguousarray(spec.num_actions, dtype=np.uint8),
+                    sreg=np.ascontiguousarray(spec.score_reg, dtype=np.uint8),
+                    treg=np.ascontiguousarray(spec.term_reg, dtype=np.uint8),
+                    tval=np.ascontiguousarray(spec.term_value, dtype=np.uint8))
+        cfg = octax_pool_config()
+        cfg.abi_version = OCTAX_ABI_VERSION
+        cfg.num_roms = len(roms)
+        cfg.instr_per_frame = int(spec.instr_per_frame)
+        cfg.frame_skip = int(spec.frame_skip)
+        cfg.quirks = OCTAX_QUIRKS_V1
+        cfg.envs_per_block = int(envs_per_block)
+        cfg.pool_bytes = int(pool_bytes)
+        cfg.h_rom_data = keep["data"].ctypes.data
+        cfg.h_rom_offset = keep["offs"].ctypes.data
+        cfg.h_rom_len = keep["lens"].ctypes.data
+        cfg.h_action_keys = keep["akeys"].ctypes.data
+        cfg.h_num_actions = keep["nact"].ctypes.data
+        cfg.h_score_reg = keep["sreg"].ctypes.data
+        cfg.h_term_reg = keep["treg"].ctypes.data
+        cfg.h_term_value = keep["tval"].ctypes.data
+        cfg.stream = _stream_handle(stream)
+        h = ctypes.c_void_p()
+        _check(L.octax_pool_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.spec = spec
+        self.capacity = self.info()["capacity"]
+
+    @staticmethod
+    def slot_bytes() -> int:
+        return int(library().octax_pool_slot_bytes())
+
+    def admit(self, rom: int, env_seed: np.ndarray, horizon: np.ndarray) -> Optional[int]:
+        """First slot of the admitted group, or None when no free range fits it."""
+        seeds = np.ascontiguousarray(env_seed, dtype=np.uint64)
+        hor = np.ascontiguousarray(horizon, dtype=np.uint32)
+        if seeds.shape != hor.shape or seeds.ndim != 1:
+            raise ValueError("env_seed and horizon must be 1-D of the same length")
+        first = ctypes.c_uint32()
+        code = library().octax_pool_admit(self._h, int(rom), len(seeds), seeds.ctypes.data,
+                                          hor.ctypes.data, ctypes.byref(first))
+        if code == OCTAX_E_NOMEM:
+            return None
+        _check(code)
+        return int(first.value)
+
+    def retire(self, first_slot: int):
+        _check(library().octax_pool_retire(self._h, int(first_slot)))
+
+    def step(self, action, obs, reward, done):
+        K = int(action.shape[0])
+        slots = 0 if obs is None else int(obs.shape[0])
+        _check(library().octax_pool_step(self._h, K, _ptr(action), _ptr(obs), slots,
+                                         _ptr(reward), _ptr(done)))
+
+    def info(self) -> dict:
+        v = [ctypes.c_uint32() for _ in range(4)]
+        _check(library().octax_pool_info(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("capacity", "free", "largest_free", "groups"), (int(x.value) for x in v)))
+
+    def get_state(self, first: int, count: int) -> np.ndarray:
+        out = np.zeros(int(count), dtype=ENV_STATE_DTYPE)
+        _check(library().octax_pool_get_state(self._h, int(first), int(count), out.ctypes.data))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(library().octax_pool_destroy(self._h))
             self._h = None
 
     def __del__(self):

@@ -402,11 +402,24 @@ def group_env_seeds(group: Group) -> np.ndarray:
     return g.integers(0, np.iinfo(np.uint64).max, size=group.size, dtype=np.uint64, endpoint=True)
 
 
+ACTION_CHUNK = 64
+
+
 def group_actions(group: Group, step0: int, count: int, num_actions: int) -> np.ndarray:
+    """Actions of a serving group for steps [step0, step0+count) as int32 [count, size].
+
+    Steps are drawn in chunks of ``ACTION_CHUNK`` from one stream per chunk,
+    uniform over the ROM's key actions, so any window is cheap to produce.
+    """
     out = np.empty((count, group.size), dtype=np.int32)
-    for i in range(count):
-        g = np.random.Generator(np.random.PCG64([group.seed, 3, step0 + i]))
-        out[i] = (g.integers(0, 1 << 30, size=group.size) % num_actions).astype(np.int32)
+    s = step0
+    while s < step0 + count:
+        c = s // ACTION_CHUNK
+        g = np.random.Generator(np.random.PCG64([group.seed, 3, c]))
+        chunk = (g.integers(0, 1 << 30, size=(ACTION_CHUNK, group.size)) % num_actions).astype(np.int32)
+        lo, hi = s - c * ACTION_CHUNK, min(step0 + count - c * ACTION_CHUNK, ACTION_CHUNK)
+        out[s - step0:s - step0 + hi - lo] = chunk[lo:hi]
+        s += hi - lo
     return out
 
 

@@ -16,6 +16,15 @@ def compare_states(gpu_states, oracle_states, where=""):
             raise AssertionError(f"{where}: field {f} differs (first mismatches {bad[:5] if not isinstance(bad, str) else bad})")
 
 
+def compare_gpu_states(a, b, where=""):
+    """Two architectural-state snapshots taken from the GPU library."""
+    from paper_2510_01764_amd import octax as X
+    g, h = X.canonical(a), X.canonical(b)
+    for f in FIELDS:
+        if not np.array_equal(g[f], h[f]):
+            raise AssertionError(f"{where}: field {f} differs")
+
+
 class Pair:
     """An engine and an oracle batch stepped in lockstep."""
 

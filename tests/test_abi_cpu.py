@@ -111,3 +111,63 @@ def test_null_engine_calls_fail_cleanly():
     assert L.octax_graph_launch(None) == X.OCTAX_E_INVALID
     assert L.octax_destroy(None) == X.OCTAX_OK
     assert L.octax_create(None, None) == X.OCTAX_E_INVALID
+
+
+def test_pool_config_layout_matches_header():
+    import subprocess
+    import tempfile
+    src = ('#include <stdio.h>\n#include <stddef.h>\n#include "octax.h"\n'
+           'int main(){printf("%zu %zu %zu\\n", sizeof(octax_pool_config),'
+           ' offsetof(octax_pool_config, pool_bytes), offsetof(octax_pool_config, stream));}\n')
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "p.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "p")
+        subprocess.check_call(["gcc", "-I" + os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe]).decode().split()
+    assert int(out[0]) == ctypes.sizeof(X.octax_pool_config)
+    assert int(out[1]) == X.octax_pool_config.pool_bytes.offset
+    assert int(out[2]) == X.octax_pool_config.stream.offset
+
+
+def _pool_cfg(**over):
+    import numpy as np
+    keep = dict(rom=np.frombuffer(bytes([0x12, 0x00]), dtype=np.uint8).copy(),
+                off=np.zeros(1, np.uint32), ln=np.array([2], np.uint32),
+                keys=np.zeros(16, np.uint8), nact=np.array([5], np.uint8), reg=np.array([5], np.uint8))
+    c = X.octax_pool_config()
+    c.abi_version = X.OCTAX_ABI_VERSION
+    c.num_roms, c.instr_per_frame, c.frame_skip, c.quirks = 1, 10, 4, X.OCTAX_QUIRKS_V1
+    c.pool_bytes = 64 * X.library().octax_pool_slot_bytes()
+    c.h_rom_data, c.h_rom_offset, c.h_rom_len = keep["rom"].ctypes.data, keep["off"].ctypes.data, keep["ln"].ctypes.data
+    c.h_action_keys, c.h_num_actions = keep["keys"].ctypes.data, keep["nact"].ctypes.data
+    c.h_score_reg = c.h_term_reg = c.h_term_value = keep["reg"].ctypes.data
+    for k, v in over.items():
+        setattr(c, k, v)
+    return c, keep
+
+
+@pytest.mark.parametrize("field,value", [
+    ("abi_version", 3), ("num_roms", 0), ("pool_bytes", 100), ("instr_per_frame", 0),
+    ("quirks", 0), ("envs_per_block", 100), ("h_num_actions", None),
+])
+def test_pool_create_rejects_bad_config_without_gpu(field, value):
+    L = X.library()
+    c, keep = _pool_cfg(**{field: value})
+    h = ctypes.c_void_p()
+    assert L.octax_pool_create(ctypes.byref(c), ctypes.byref(h)) == X.OCTAX_E_INVALID
+    assert not h.value
+    assert L.octax_last_error().decode()
+
+
+def test_null_pool_calls_fail_cleanly():
+    L = X.library()
+    first = ctypes.c_uint32()
+    assert L.octax_pool_admit(None, 0, 1, None, None, ctypes.byref(first)) == X.OCTAX_E_INVALID
+    assert L.octax_pool_retire(None, 0) == X.OCTAX_E_INVALID
+    assert L.octax_pool_step(None, 1, None, None, 1, None, None) == X.OCTAX_E_INVALID
+    assert L.octax_pool_info(None, None, None, None, None) == X.OCTAX_E_INVALID
+    assert L.octax_pool_get_state(None, 0, 1, None) == X.OCTAX_E_INVALID
+    assert L.octax_pool_destroy(None) == X.OCTAX_OK
+    assert L.octax_pool_create(None, None) == X.OCTAX_E_INVALID
+    assert L.octax_pool_slot_bytes() == 5470

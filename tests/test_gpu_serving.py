@@ -1,0 +1,111 @@
+"""Serving pool on the GPU: each group's results in the mix equal its results alone.
+
+Groups of different ROMs and sizes arrive while others run, wait for memory,
+share fused ticks and leave; every step's rewards and done flags, the last
+observation and the final architectural state of each group must equal a
+standalone engine run of that group, and for some groups the CPU oracle.
+Integer emulation: all comparisons are exact.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from tests.parity_util import compare_gpu_states, compare_states
+
+pytestmark = pytest.mark.gpu
+
+
+def _group_spec(spec, g):
+    from paper_2510_01764_amd import workload as W
+    return dataclasses.replace(spec, name=f"group {g.gid}",
+                               env_rom=np.full(g.size, g.rom, dtype=np.uint16),
+                               horizon=W.group_horizons(g), env_seed=W.group_env_seeds(g))
+
+
+def _alone(spec, g):
+    import torch
+    from paper_2510_01764_amd import octax as X
+    from paper_2510_01764_amd import workload as W
+    gs = _group_spec(spec, g)
+    dev = torch.device("cuda")
+    eng = X.Engine(gs, kernel="fused")
+    acts = torch.from_numpy(W.group_actions(g, 0, g.steps, int(spec.num_actions[g.rom]))).to(dev)
+    obs = torch.zeros((1, g.size, 4, 64, 32), dtype=torch.uint8, device=dev)
+    rew = torch.zeros((g.steps, g.size), dtype=torch.float32, device=dev)
+    done = torch.zeros((g.steps, g.size), dtype=torch.uint8, device=dev)
+    eng.step_many(acts, obs, rew, done)
+    torch.cuda.synchronize()
+    out = rew.cpu().numpy(), done.cpu().numpy(), obs[0].cpu().numpy(), eng.get_state()
+    eng.close()
+    return out
+
+
+def test_pool_admit_retire_and_info():
+    import torch
+    from paper_2510_01764_amd import octax as X
+    from paper_2510_01764_amd import workload as W
+    spec = W.make_config("c4")
+    pool = X.Pool(spec, pool_bytes=300 * X.Pool.slot_bytes() + 7)
+    assert pool.capacity == 300
+    z = np.zeros(100, dtype=np.uint64)
+    h = np.zeros(100, dtype=np.uint32)
+    a = pool.admit(0, z, h)
+    b = pool.admit(1, z, h)
+    c = pool.admit(2, z, h)
+    assert (a, b, c) == (0, 100, 200)
+    assert pool.admit(3, z[:1], h[:1]) is None          # full: nothing changes
+    pool.retire(100)
+    assert pool.info() == {"capacity": 300, "free": 100, "largest_free": 100, "groups": 2}
+    assert pool.admit(4, z[:60], h[:60]) == 100
+    pool.retire(0)
+    pool.retire(100)
+    assert pool.info()["largest_free"] == 200           # freed ranges coalesce
+    with pytest.raises(X.OctaxError):
+        pool.retire(5)                                   # no group starts there
+    with pytest.raises(X.OctaxError):
+        pool.admit(32, z[:1], h[:1])                     # no such ROM
+    # a step with one resident group touches only its slots
+    act = torch.zeros((1, 300), dtype=torch.int32, device="cuda")
+    rew = torch.full((1, 300), 7.0, dtype=torch.float32, device="cuda")
+    done = torch.full((1, 300), 9, dtype=torch.uint8, device="cuda")
+    pool.step(act, None, rew, done)
+    torch.cuda.synchronize()
+    r = rew.cpu().numpy()[0]
+    d = done.cpu().numpy()[0]
+    assert (r[:200] == 7.0).all() and (d[:200] == 9).all()
+    assert (d[200:] != 9).all()
+    pool.close()
+
+
+@pytest.mark.parametrize("depth", [1, 2])
+def test_groups_in_the_mix_match_groups_alone(depth):
+    from oracle import oracle as O
+    from paper_2510_01764_amd import serving as S
+    from paper_2510_01764_amd import workload as W
+    spec = W.make_config("c4")
+    groups = W.serving_groups(18, rate=3000.0, seed=21, n_roms=32, max_size=400,
+                              min_steps=20, max_steps=70)
+    be = S.PoolBackend(spec, pool_bytes=700 * 5470, depth=depth)
+    out = S.serve(spec, groups, be, record=True)
+    be.close()
+    runs = out["runs"]
+    assert any(r.t_admit > r.t_arrival + 1e-4 for r in runs), "some group waited for memory"
+    for r in runs:
+        g = r.group
+        rew, done, obs, state = _alone(spec, g)
+        assert np.array_equal(r.rewards, rew), f"group {g.gid}: rewards differ"
+        assert np.array_equal(r.dones, done), f"group {g.gid}: done flags differ"
+        assert np.array_equal(r.final_obs, obs), f"group {g.gid}: last observation differs"
+        compare_gpu_states(r.final_state, state, f"group {g.gid} in the pool vs alone")
+    # and the oracle for three of them
+    for r in runs[:3]:
+        g = r.group
+        orc = O.OracleBatch(_group_spec(spec, g))
+        acts = W.group_actions(g, 0, g.steps, int(spec.num_actions[g.rom]))
+        for k in range(g.steps):
+            oo, orw, od = orc.step(acts[k], want_obs=(k == g.steps - 1))
+            assert np.array_equal(r.rewards[k], orw) and np.array_equal(r.dones[k], od), (g.gid, k)
+        assert np.array_equal(r.final_obs, oo)
+        compare_states(r.final_state, orc.get_state(), f"group {g.gid} vs oracle")
+        orc.close()

@@ -1,0 +1,167 @@
+"""Host logic of the serving loop, on the CPU with a stand-in backend.
+
+The stand-in keeps the pool's contract (first-fit contiguous slot ranges of a
+fixed capacity, admission refused when no range fits, one result vector per
+tick indexed by slot) and reports, as each slot's reward, the tick number and
+the slot, so the tests can check which group stepped where and when.
+"""
+import numpy as np
+import pytest
+
+from paper_2510_01764_amd import serving as S
+from paper_2510_01764_amd import workload as W
+
+
+class FakeBackend:
+    def __init__(self, capacity, depth=2, rows=128):
+        self.capacity = capacity
+        self.depth = depth
+        self.rows = rows
+        self.sched = np.zeros((rows, capacity), dtype=np.int32)
+        self.free = [(0, capacity)]        # sorted (first, length)
+        self.groups = {}
+        self.occupied = np.zeros(capacity, dtype=np.int32)
+        self.ticks = []                     # per tick: copy of the occupied map
+        self.n = 0
+        self.acts = []
+        self.max_used = 0
+
+    def admit(self, rom, seeds, horizons):
+        count = len(seeds)
+        for i, (f, ln) in enumerate(self.free):
+            if ln >= count:
+                self.free[i] = (f + count, ln - count)
+                if self.free[i][1] == 0:
+                    del self.free[i]
+                self.groups[f] = count
+                assert not self.occupied[f:f + count].any()
+                self.occupied[f:f + count] = 1
+                self.max_used = max(self.max_used, int(self.occupied.sum()))
+                return f
+        return None
+
+    def retire(self, first):
+        count = self.groups.pop(first)
+        self.occupied[first:first + count] = 0
+        self.free.append((first, count))
+        self.free.sort()
+        merged = []
+        for f, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == f:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((f, ln))
+        self.free = merged
+
+    def schedule(self):
+        return self.sched
+
+    def launch(self, row):
+        self.ticks.append(self.occupied.copy())
+        self.acts.append(self.sched[row].copy())
+        self.n += 1
+        return self.n - 1
+
+    def wait(self, ticket):
+        rew = (ticket * 1000 + np.arange(self.capacity)).astype(np.float32)   # exact below 2^24
+        done = (self.ticks[ticket] != 0).astype(np.uint8)
+        return rew, done, 0.1
+
+    def finish(self):
+        pass
+
+    def obs_of(self, first, count):
+        return np.zeros((count, 4, 64, 32), dtype=np.uint8)
+
+    def state_of(self, first, count):
+        return np.zeros(count)
+
+
+class FakeClock:
+    """Time advances 1 ms per clock read, and sleep jumps ahead."""
+
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        self.t += 1e-3
+        return self.t
+
+    def sleep(self, dt):
+        self.t += dt
+
+
+def _groups(n, rate, max_size=300, steps=(5, 30), seed=11):
+    gs = W.serving_groups(n, rate, seed=seed, n_roms=32, max_size=max_size,
+                          min_steps=steps[0], max_steps=steps[1])
+    return gs
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_every_group_runs_exactly_its_steps_in_its_own_slots(depth):
+    spec = W.make_config("c4")
+    groups = _groups(40, rate=400.0, steps=(5, 150))
+    be = FakeBackend(capacity=700, depth=depth)
+    clk = FakeClock()
+    out = S.serve(spec, groups, be, record=True, clock=clk, sleep=clk.sleep)
+    runs = out["runs"]
+    assert len(runs) == len(groups)
+    for r in runs:
+        g = r.group
+        assert r.t_admit >= r.t_arrival and r.t_done > r.t_admit
+        # recorded rewards identify (tick, slot): consecutive ticks, the group's own slots
+        ticks = (r.rewards[:, 0] // 1000).astype(int)
+        slots = (r.rewards % 1000).astype(int)
+        assert np.all(np.diff(ticks) == 1), "a resident group steps in every tick"
+        assert np.all(slots == r.first + np.arange(g.size)[None, :])
+        # the actions sent in those ticks are the group's own stream
+        for k in sorted({0, 63, 64, 65, g.steps // 2, g.steps - 1}):
+            if k >= g.steps:
+                continue
+            sent = be.acts[ticks[k]][r.first:r.first + g.size]
+            assert np.array_equal(sent, W.group_actions(g, k, 1, int(spec.num_actions[g.rom]))[0])
+    assert be.max_used <= be.capacity
+    assert not be.groups, "every group was retired"
+    assert out["env_steps"] == sum(g.size * g.steps for g in groups)
+
+
+def test_group_waits_for_memory_and_later_groups_backfill():
+    spec = W.make_config("c4")
+    # two big groups that cannot be resident together, then a small one
+    gs = [W.Group(0, 0.0, 1, 600, 20, 5), W.Group(1, 0.0005, 2, 600, 20, 6),
+          W.Group(2, 0.0006, 3, 50, 10, 7)]
+    be = FakeBackend(capacity=700, depth=2)
+    clk = FakeClock()
+    out = S.serve(spec, gs, be, clock=clk, sleep=clk.sleep)
+    r0, r1, r2 = out["runs"]
+    assert r1.t_admit >= r0.t_done, "the second big group waits until the first leaves"
+    assert r2.t_admit < r0.t_done, "the small group fills the free range meanwhile"
+    assert be.max_used <= 700
+
+
+def test_group_larger_than_pool_is_an_error():
+    spec = W.make_config("c4")
+    be = FakeBackend(capacity=100)
+    clk = FakeClock()
+    with pytest.raises(RuntimeError):
+        S.serve(spec, [W.Group(0, 0.0, 0, 101, 5, 1)], be, clock=clk, sleep=clk.sleep)
+
+
+def test_idle_pool_sleeps_until_next_arrival():
+    spec = W.make_config("c4")
+    gs = [W.Group(0, 0.0, 0, 10, 3, 1), W.Group(1, 5.0, 1, 10, 3, 2)]
+    be = FakeBackend(capacity=64)
+    clk = FakeClock()
+    out = S.serve(spec, gs, be, clock=clk, sleep=clk.sleep)
+    assert out["runs"][1].t_admit >= 5.0
+    assert be.n == 6
+
+
+def test_group_generators_are_slot_independent_and_windowed():
+    g = W.serving_groups(5, 10.0)[3]
+    a = W.group_actions(g, 0, 150, 5)
+    assert np.array_equal(a[70:130], W.group_actions(g, 70, 60, 5))
+    assert a.min() >= 0 and a.max() < 5
+    assert np.array_equal(W.group_env_seeds(g), W.group_env_seeds(g))
+    h = W.group_horizons(g)
+    assert h.dtype == np.uint32 and (h >= 1).all()
