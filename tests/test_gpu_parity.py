@@ -302,3 +302,75 @@ def test_full_size_mixed_rom_sampled():
     g.close()
     eng.close()
     orc.close()
+
+
+def test_single_rom_at_scale_full_run():
+    """4,096 envs of one 1,024-instruction ROM for 10,000 steps with auto-reset: every
+    reward and done flag of every env against the oracle (threaded over the host's
+    cores), the last observation and the full final state; the plain kernel agrees."""
+    import os
+    import torch
+    from oracle import oracle as O
+    from paper_2510_01764_amd import octax as X
+    spec = _spec("c2")
+    E, S, K = spec.num_envs, spec.steps, 500
+    dev = torch.device("cuda")
+    orc = O.OracleBatch(spec)
+    acts = spec.actions(0, S)
+    o_rew, o_done, _ = orc.run_threaded(acts, min(16, len(os.sched_getaffinity(0))))
+    out = {}
+    for kernel in ("fused", "plain"):
+        eng = X.Engine(spec, kernel=kernel)
+        obs = torch.zeros((1, E, 4, 64, 32), dtype=torch.uint8, device=dev)
+        rew = torch.zeros((K, E), dtype=torch.float32, device=dev)
+        done = torch.zeros((K, E), dtype=torch.uint8, device=dev)
+        for c in range(S // K):
+            a = torch.from_numpy(acts[c * K:(c + 1) * K].copy()).to(dev)
+            eng.step_many(a, obs, rew, done)
+            torch.cuda.synchronize()
+            assert np.array_equal(rew.cpu().numpy(), o_rew[c * K:(c + 1) * K]), (kernel, c)
+            assert np.array_equal(done.cpu().numpy(), o_done[c * K:(c + 1) * K]), (kernel, c)
+        out[kernel] = (obs[0].cpu().numpy(), eng.get_state())
+        eng.close()
+    assert int((o_done != 0).sum()) > E, "episodes end and restart during the run"
+    compare_states(out["fused"][1], orc.get_state(), "c2 fused final state")
+    compare_states(out["plain"][1], orc.get_state(), "c2 plain final state")
+    assert np.array_equal(out["fused"][0], out["plain"][0])
+    orc.close()
+
+
+def test_draw_heavy_full_size_sampled():
+    """1,048,576 envs over 64 draw-heavy ROMs (40% DXYN, N up to 15 near the edges,
+    20 instructions per frame) in graph replays of K = 8; a sample of envs is
+    replayed on the oracle step by step (envs are independent)."""
+    import torch
+    from oracle import oracle as O
+    from paper_2510_01764_amd import octax as X
+    spec = _spec("c5")
+    E, K = spec.num_envs, 8
+    dev = torch.device("cuda")
+    eng = X.Engine(spec, kernel="fused")
+    act = torch.zeros((K, E), dtype=torch.int32, device=dev)
+    obs = torch.zeros((1, E, 4, 64, 32), dtype=torch.uint8, device=dev)
+    rew = torch.zeros((K, E), dtype=torch.float32, device=dev)
+    done = torch.zeros((K, E), dtype=torch.uint8, device=dev)
+    g = eng.graph(act, obs, rew, done)
+    sample = np.random.default_rng(11).choice(E, size=200, replace=False)
+    sample = np.concatenate([sample, [0, 1, 255, 256, E // 2, E - 2, E - 1]])
+    orc = O.OracleBatch(spec.subset(sample))
+    for rep in range(2):
+        an = spec.actions(rep * K, K)
+        act.copy_(torch.from_numpy(an))
+        g.launch()
+        torch.cuda.synchronize()
+        r_np = rew[:, sample].cpu().numpy()
+        d_np = done[:, sample].cpu().numpy()
+        for k in range(K):
+            oo, orw, od = orc.step(an[k][sample], want_obs=(k == K - 1))
+            assert np.array_equal(r_np[k], orw) and np.array_equal(d_np[k], od), (rep, k)
+        assert np.array_equal(obs[0, sample].cpu().numpy(), oo), rep
+    got = np.concatenate([eng.get_state(int(e), 1) for e in sample])
+    compare_states(got, orc.get_state(), "c5 full-size sample")
+    g.close()
+    eng.close()
+    orc.close()
