@@ -50,7 +50,9 @@ struct Shared {
     uint8_t cache[IPW][kCacheStride];
     uint32_t stage[IPW / 64][kStageEnvs][kStageStride];
     uint32_t stack[IPW][9];
-    uint8_t done[IPW];        // done bits of the step just emulated, for the writer waves
+    float rew[IPW];           // reward and done bits of the step just emulated, for the writer waves
+    uint8_t done[IPW];
+    uint8_t key[2][IPW];      // held key of step k (slot k & 1), staged by the writer waves
     uint8_t img[2][kMem];
     uint8_t tail_pad[64];
 };
@@ -58,14 +60,18 @@ struct Shared {
 // Memory of one env in the fused kernel.
 //   * pages not written since the reset read from the power-on image: the
 //     LDS copy when the block staged this ROM, else HBM;
-//   * written pages live in the env's memory in HBM (every write goes
-//     there) and up to two of them are cached in LDS: a write fills a slot
-//     (from the image for a clean page, from HBM for a written one), a read
-//     of an uncached written page fills one from HBM; slots are replaced
-//     least recently filled first;
+//   * written pages are kept in two LDS cache slots per env, write-back: a
+//     write fills a slot (from the image for a clean page, from the env's
+//     memory in HBM for a written one) and marks it modified; HBM receives a
+//     modified page only when its slot is reused and when the launch ends.
+//     A read of an uncached written page fills a slot from HBM.  Slots are
+//     replaced least recently filled first;
 //   * multi-byte accesses (fetch, FX33/FX55/FX65, DXYN rows) touch at most
 //     two pages; when both are readable from LDS all their LDS accesses are
 //     issued back to back (one round trip per instruction, not one per byte).
+// So the emulator waves touch HBM only on cache misses and resets: under the
+// observation stores of the writer waves every global access of a wave waits
+// behind them.
 template <int IPW>
 struct FusedMem {
     Shared<IPW> &sh;
@@ -74,7 +80,7 @@ struct FusedMem {
     const glb_u8 *gimg;      // power-on image in HBM
     glb_u8 *ram;             // env memory in HBM
     uint64_t dirty;
-    uint32_t tags;           // slot 0 page | valid << 6, slot 1 at bit 8, next victim at bit 16
+    uint32_t tags;           // slot 0: page | valid << 6 | modified << 7; slot 1 at bit 8; next victim at bit 16
 
     __device__ __forceinline__ lds_u8 *slot_ptr(uint32_t s) const {
         return (lds_u8 *)&sh.cache[lane][0] + 64 * s;
@@ -85,35 +91,75 @@ struct FusedMem {
         if (((tags >> 8) & 0x7F) == (p | 0x40)) return 1;
         return -1;
     }
-    // Take a slot for page p, never slot `keep` (-1: none).
-    __device__ __forceinline__ uint32_t claim(uint32_t p, int32_t keep) {
+    // Pick the slot for page p, never slot `keep` (-1: none); the slot's old
+    // tag is returned in `old`.
+    __device__ __forceinline__ uint32_t victim(int32_t keep, uint32_t &old) const {
         uint32_t s = (tags >> 16) & 1;
         if ((int32_t)s == keep) s ^= 1;
-        tags = (tags & ~(0x7Fu << (8 * s))) | ((p | 0x40) << (8 * s));
-        tags = (tags & ~(1u << 16)) | ((s ^ 1) << 16);
+        old = (tags >> (8 * s)) & 0xFF;
         return s;
     }
+    __device__ __forceinline__ void set_tag(uint32_t s, uint32_t tag) {
+        tags = (tags & ~(0xFFu << (8 * s))) | (tag << (8 * s));
+        tags = (tags & ~(1u << 16)) | ((s ^ 1) << 16);
+    }
+    // Write a modified slot's page back to HBM (16 bytes a piece, from
+    // registers read before the slot is overwritten).
+    __device__ __forceinline__ void write_back(uint32_t old, uint4 v0, uint4 v1, uint4 v2, uint4 v3) {
+        uint4 *dst = reinterpret_cast<uint4 *>((uint8_t *)ram + (old & 63) * 64);
+        dst[0] = v0;
+        dst[1] = v1;
+        dst[2] = v2;
+        dst[3] = v3;
+    }
     __device__ __forceinline__ uint32_t fill_from_ram(uint32_t p, int32_t keep) {
-        const uint32_t s = claim(p, keep);
+        uint32_t old;
+        const uint32_t s = victim(keep, old);
+        uint4 *slot = reinterpret_cast<uint4 *>(&sh.cache[lane][64 * s]);
+        // the fill loads are issued before the write-back stores, so waiting
+        // for them does not wait for those stores
         const uint4 *src = reinterpret_cast<const uint4 *>((const uint8_t *)ram + p * 64);
-        uint4 *dst = reinterpret_cast<uint4 *>(&sh.cache[lane][64 * s]);
-#pragma unroll
-        for (int q = 0; q < 4; q++) dst[q] = src[q];
+        const uint4 f0 = src[0], f1 = src[1], f2 = src[2], f3 = src[3];
+        if (old & 0x80) write_back(old, slot[0], slot[1], slot[2], slot[3]);
+        slot[0] = f0;
+        slot[1] = f1;
+        slot[2] = f2;
+        slot[3] = f3;
+        set_tag(s, p | 0x40);
         return s;
     }
     __device__ __forceinline__ uint32_t fill_from_image(uint32_t p, int32_t keep) {
-        const uint32_t s = claim(p, keep);
-        uint4 *dst = reinterpret_cast<uint4 *>(&sh.cache[lane][64 * s]);
+        uint32_t old;
+        const uint32_t s = victim(keep, old);
+        uint4 *slot = reinterpret_cast<uint4 *>(&sh.cache[lane][64 * s]);
+        if (old & 0x80) write_back(old, slot[0], slot[1], slot[2], slot[3]);
+        const uint4 *src = lidx >= 0 ? reinterpret_cast<const uint4 *>(&sh.img[lidx & 1][p * 64]) : nullptr;
         if (lidx >= 0) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(&sh.img[lidx][p * 64]);
-#pragma unroll
-            for (int q = 0; q < 4; q++) dst[q] = src[q];
+            slot[0] = src[0];
+            slot[1] = src[1];
+            slot[2] = src[2];
+            slot[3] = src[3];
         } else {
-            const uint4 *src = reinterpret_cast<const uint4 *>((const uint8_t *)gimg + p * 64);
-#pragma unroll
-            for (int q = 0; q < 4; q++) dst[q] = src[q];
+            const uint4 *g = reinterpret_cast<const uint4 *>((const uint8_t *)gimg + p * 64);
+            slot[0] = g[0];
+            slot[1] = g[1];
+            slot[2] = g[2];
+            slot[3] = g[3];
         }
+        set_tag(s, p | 0x40);
         return s;
+    }
+    // Write every modified slot back (end of the launch).
+    __device__ __forceinline__ void flush() {
+#pragma unroll
+        for (uint32_t s = 0; s < 2; s++) {
+            const uint32_t t = (tags >> (8 * s)) & 0xFF;
+            if ((t & 0xC0) == 0xC0) {
+                const uint4 *slot = reinterpret_cast<const uint4 *>(&sh.cache[lane][64 * s]);
+                write_back(t, slot[0], slot[1], slot[2], slot[3]);
+            }
+        }
+        tags &= ~0x8080u;
     }
     // One byte, any page (fills a slot for an uncached written page).
     __device__ __forceinline__ uint32_t read(uint32_t a) {
@@ -181,11 +227,10 @@ struct FusedMem {
         for (int k = 0; k < 16; k++) {
             if ((uint32_t)k < count) {
                 const uint32_t ak = (a + k) & 0xFFF;
-                const uint32_t v = byte_of(bytes, k);
-                ram[ak] = (uint8_t)v;
-                (((ak >> 6) == p0) ? c0 : c1)[ak & 63] = (uint8_t)v;
+                (((ak >> 6) == p0) ? c0 : c1)[ak & 63] = (uint8_t)byte_of(bytes, k);
             }
         }
+        tags |= (0x80u << (8 * s0)) | (0x80u << (8 * s1));
         dirty |= (1ull << p0) | (1ull << p1);
     }
     // LDS base of page p, computed with selects only (see lds_byte).
@@ -352,16 +397,30 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     if (active) {
         head = (s.misc[slot] >> 24) & 3;
         env = s.env_of[slot];
+        rom = s.rom_of[slot];
+        desc = roms.desc[rom];
+        keys = *reinterpret_cast<const u32x4 *>(roms.keys + (size_t)rom * 16);
+    }
+    const uint32_t nact = desc >> 24;
+    // Key held for an action: the ROM's key for 0 <= a < num_actions, else none.
+    auto held_key = [&](int32_t a) -> uint32_t {
+        const uint32_t ua = (uint32_t)a;
+        const uint32_t word = (ua & 8) ? ((ua & 4) ? keys.w : keys.z) : ((ua & 4) ? keys.y : keys.x);
+        return (ua < nact) ? (__builtin_amdgcn_ubfe(word, (ua & 3) * 8, 8) & 15) : kKeyNone;
+    };
+    if (!emu && active) {
+        // held keys of steps 0 and 1
+        const int32_t a0 = io.action[env];
+        const int32_t a1 = K > 1 ? io.action[(size_t)E + env] : -1;
+        sh.key[0][l] = (uint8_t)held_key(a0);
+        sh.key[1][l] = (uint8_t)held_key(a1);
     }
     if (emu && active) {
         load_core(s, slot, c, head);
-        rom = s.rom_of[slot];
-        desc = roms.desc[rom];
         t = s.t[slot];
         hor = s.horizon[slot];
         prev = s.prev[slot];
         dirty = s.dirty[slot];
-        keys = *reinterpret_cast<const u32x4 *>(roms.keys + (size_t)rom * 16);
         const uint4 *fb4 = reinterpret_cast<const uint4 *>(s.fb + (size_t)slot * 32);
 #pragma unroll
         for (int q = 0; q < 16; q++) {
@@ -377,7 +436,6 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     const int32_t lidx = (rom == brom0) ? 0 : (rom == brom1) ? 1 : -1;
     const glb_u8 *gimg = (const glb_u8 *)(roms.image + (size_t)rom * kMem);
     glb_u8 *ram = (glb_u8 *)(s.ram + (size_t)slot * kMem);
-    const uint32_t nact = desc >> 24;
     const size_t obs_step = (size_t)E * kObsBytes;
     auto obs_of = [&](uint32_t kk, uint32_t e) -> uint8_t * {
         return io.obs + (size_t)(kk % io.obs_slots) * obs_step + (size_t)e * kObsBytes;
@@ -417,29 +475,11 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     }
     __syncthreads();
 
-    u32x4 kchunk = {0, 0, 0, 0};   // held keys of 16 consecutive steps, one byte each
     FusedMem<IPW> mem{sh, l, lidx, gimg, ram, dirty, tags};
     for (uint32_t k = 0; k < K; k++) {
         // ---- emulators: step k ----
         if (emu && active) {
-            if ((k & 15) == 0) {
-                // actions of the next 16 steps -> held keys (16 = none)
-                uint32_t kb[16];
-#pragma unroll
-                for (int q = 0; q < 16; q++) {
-                    const int32_t a = (k + q < K) ? io.action[(size_t)(k + q) * E + env] : -1;
-                    const uint32_t ua = (uint32_t)a;
-                    const uint32_t word = (ua & 8) ? ((ua & 4) ? keys.w : keys.z) : ((ua & 4) ? keys.y : keys.x);
-                    kb[q] = (ua < nact) ? (__builtin_amdgcn_ubfe(word, (ua & 3) * 8, 8) & 15) : kKeyNone;
-                }
-                kchunk.x = kb[0] | (kb[1] << 8) | (kb[2] << 16) | (kb[3] << 24);
-                kchunk.y = kb[4] | (kb[5] << 8) | (kb[6] << 16) | (kb[7] << 24);
-                kchunk.z = kb[8] | (kb[9] << 8) | (kb[10] << 16) | (kb[11] << 24);
-                kchunk.w = kb[12] | (kb[13] << 8) | (kb[14] << 16) | (kb[15] << 24);
-            }
-            const uint32_t kq = (k >> 2) & 3;
-            const uint32_t kword = kq == 0 ? kchunk.x : kq == 1 ? kchunk.y : kq == 2 ? kchunk.z : kchunk.w;
-            const uint32_t key = __builtin_amdgcn_ubfe(kword, (k & 3) * 8, 8);
+            const uint32_t key = sh.key[k & 1][l];
             for (uint32_t f = 0; f < io.frame_skip; f++) {
                 for (uint32_t i = 0; i < io.ipf; i++) exec_grouped(c, mem, key);
                 tick(c);
@@ -450,8 +490,8 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             t += 1;
             const uint32_t trunc = (hor != 0) && (t >= hor);
             const uint32_t done = term | (trunc << 1);
-            io.reward[(size_t)k * E + env] = reward;
-            io.done[(size_t)k * E + env] = (uint8_t)done;
+            sh.rew[l] = reward;
+            sh.done[l] = (uint8_t)done;
             if (done) {
                 // Automatic reset (Section 3.4); the RNG stream continues.
                 mem.restore_pages();
@@ -465,13 +505,13 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 prev = score;
                 head = (head + 1) & 3;
             }
-            sh.done[l] = (uint8_t)done;
         }
         __syncthreads();   // the displays of step k are final
 
         // ---- writers: take the frames of step k, then store them ----
         uint32_t hi[32], lo[32];
         uint32_t done = 0;
+        float wrew = 0.0f;
         if (!emu) {
 #pragma unroll
             for (int r = 0; r < 32; r++) {
@@ -480,9 +520,18 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 lo[r] = (uint32_t)row;
             }
             done = active ? sh.done[l] : 0u;
+            wrew = sh.rew[l];
         }
         __syncthreads();   // the displays may change again
         const bool ring_step = k + 4 >= K;
+        // the action of step k + 2, loaded before this step's observation
+        // stores and used after them, so waiting for it waits for none of them
+        int32_t next_action = -1;
+        if (!emu && active) {
+            if (k + 2 < K) next_action = io.action[(size_t)(k + 2) * E + env];
+            io.reward[(size_t)k * E + env] = wrew;
+            io.done[(size_t)k * E + env] = (uint8_t)done;
+        }
         if (!emu && (io.obs || ring_step)) {
             head = done ? 0u : (head + 1) & 3;
             uint32_t pw[64];
@@ -537,7 +586,10 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
         } else if (!emu) {
             head = done ? 0u : (head + 1) & 3;
         }
+        // the held key of step k + 2 goes into the slot step k has finished with
+        if (!emu && active && k + 2 < K) sh.key[k & 1][l] = (uint8_t)held_key(next_action);
     }
+    if (emu && active) mem.flush();
     dirty = mem.dirty;
     tags = mem.tags;
 
