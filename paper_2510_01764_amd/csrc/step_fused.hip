@@ -31,41 +31,47 @@ typedef __attribute__((address_space(3))) uint16_t lds_u16;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
 typedef __attribute__((address_space(1))) uint8_t glb_u8;
+typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
 
 constexpr uint32_t kNoRom = 0xFFFFFFFFu;
 constexpr int kStageEnvs = 16;     // envs staged per round of the cooperative pass
 constexpr int kStageStride = 68;   // u32 per staged env (64 + 4 pad, 16-byte aligned)
-constexpr int kCacheStride = 136;  // bytes per env: two 64-byte pages + pad (spreads lanes over banks)
+// Written-page cache slots per env: three where the block's LDS share allows
+// (128 and 256 envs per block), two at 64 envs per block.
+template <int IPW>
+constexpr int cache_slots() { return IPW == 64 ? 2 : 3; }
+// bytes per env: the slots + 8 pad bytes (spreads lanes over banks)
+template <int IPW>
+constexpr int cache_stride() { return 64 * cache_slots<IPW>() + 8; }
 
 // LDS of one block.  The display of lane l is fb[l][0..31], one padded
 // 33-row stride per lane, so a lane's rows are contiguous (sprite rows are
 // addressed with immediate offsets) and lanes reading the same row index
-// spread over the banks.  The tail pad keeps reads a few bytes past the last
-// image page inside the allocation.
+// spread over the banks.  At every block size the block uses at most
+// IPW / 256 of the CU's 160 KB, so 256 envs per CU stay resident.
 constexpr int kFbStride = 33;
 
 template <int IPW>
 struct Shared {
     uint64_t fb[IPW][kFbStride];
-    uint8_t cache[IPW][kCacheStride];
+    uint8_t cache[IPW][cache_stride<IPW>()];
     uint32_t stage[IPW / 64][kStageEnvs][kStageStride];
     uint32_t stack[IPW][9];
     float rew[IPW];           // reward and done bits of the step just emulated, for the writer waves
     uint8_t done[IPW];
     uint8_t key[2][IPW];      // held key of step k (slot k & 1), staged by the writer waves
     uint8_t img[2][kMem];
-    uint8_t tail_pad[64];
 };
 
 // Memory of one env in the fused kernel.
 //   * pages not written since the reset read from the power-on image: the
 //     LDS copy when the block staged this ROM, else HBM;
-//   * written pages are kept in two LDS cache slots per env, write-back: a
-//     write fills a slot (from the image for a clean page, from the env's
-//     memory in HBM for a written one) and marks it modified; HBM receives a
-//     modified page only when its slot is reused and when the launch ends.
-//     A read of an uncached written page fills a slot from HBM.  Slots are
-//     replaced least recently filled first;
+//   * written pages are kept in two or three LDS cache slots per env,
+//     write-back: a write fills a slot (from the image for a clean page, from
+//     the env's memory in HBM for a written one) and marks it modified; HBM
+//     receives a modified page only when its slot is reused and when the
+//     launch ends.  A read of an uncached written page fills a slot from HBM.
+//     Slots are replaced least recently filled first;
 //   * multi-byte accesses (fetch, FX33/FX55/FX65, DXYN rows) touch at most
 //     two pages; when both are readable from LDS all their LDS accesses are
 //     issued back to back (one round trip per instruction, not one per byte).
@@ -80,28 +86,33 @@ struct FusedMem {
     const glb_u8 *gimg;      // power-on image in HBM
     glb_u8 *ram;             // env memory in HBM
     uint64_t dirty;
-    uint32_t tags;           // slot 0: page | valid << 6 | modified << 7; slot 1 at bit 8; next victim at bit 16
+    uint32_t tags;           // slot i at bits 8i..8i+7: page | valid << 6 | modified << 7; next victim at bit 24
+    static constexpr uint32_t kSlots = cache_slots<IPW>();
 
     __device__ __forceinline__ lds_u8 *slot_ptr(uint32_t s) const {
         return (lds_u8 *)&sh.cache[lane][0] + 64 * s;
     }
     __device__ __forceinline__ bool is_dirty(uint32_t p) const { return (dirty >> p) & 1; }
+    __device__ __forceinline__ uint32_t tag(uint32_t s) const { return (tags >> (8 * s)) & 0xFF; }
     __device__ __forceinline__ int32_t find(uint32_t p) const {
-        if ((tags & 0x7F) == (p | 0x40)) return 0;
-        if (((tags >> 8) & 0x7F) == (p | 0x40)) return 1;
+#pragma unroll
+        for (uint32_t s = 0; s < kSlots; s++)
+            if ((tag(s) & 0x7F) == (p | 0x40)) return (int32_t)s;
         return -1;
     }
     // Pick the slot for page p, never slot `keep` (-1: none); the slot's old
     // tag is returned in `old`.
+    __device__ __forceinline__ static uint32_t next_slot(uint32_t s) { return s + 1 == kSlots ? 0u : s + 1; }
     __device__ __forceinline__ uint32_t victim(int32_t keep, uint32_t &old) const {
-        uint32_t s = (tags >> 16) & 1;
-        if ((int32_t)s == keep) s ^= 1;
-        old = (tags >> (8 * s)) & 0xFF;
+        uint32_t s = (tags >> 24) & 3;
+        if ((int32_t)s == keep) s = next_slot(s);
+        old = tag(s);
         return s;
     }
-    __device__ __forceinline__ void set_tag(uint32_t s, uint32_t tag) {
-        tags = (tags & ~(0xFFu << (8 * s))) | (tag << (8 * s));
-        tags = (tags & ~(1u << 16)) | ((s ^ 1) << 16);
+    // Slots are replaced in fill order: the next victim follows the slot filled.
+    __device__ __forceinline__ void set_tag(uint32_t s, uint32_t t) {
+        tags = (tags & ~(0xFFu << (8 * s))) | (t << (8 * s));
+        tags = (tags & 0x00FFFFFFu) | (next_slot(s) << 24);
     }
     // Write a modified slot's page back to HBM (16 bytes a piece, from
     // registers read before the slot is overwritten).
@@ -116,15 +127,23 @@ struct FusedMem {
         uint32_t old;
         const uint32_t s = victim(keep, old);
         uint4 *slot = reinterpret_cast<uint4 *>(&sh.cache[lane][64 * s]);
-        // the fill loads are issued before the write-back stores, so waiting
-        // for them does not wait for those stores
+        const bool wb = old & 0x80;
+        uint4 o0 = {}, o1 = {}, o2 = {}, o3 = {};
+        if (wb) {
+            o0 = slot[0];
+            o1 = slot[1];
+            o2 = slot[2];
+            o3 = slot[3];
+        }
         const uint4 *src = reinterpret_cast<const uint4 *>((const uint8_t *)ram + p * 64);
         const uint4 f0 = src[0], f1 = src[1], f2 = src[2], f3 = src[3];
-        if (old & 0x80) write_back(old, slot[0], slot[1], slot[2], slot[3]);
         slot[0] = f0;
         slot[1] = f1;
         slot[2] = f2;
         slot[3] = f3;
+        // the write-back stores go out after the fill has arrived, so the
+        // wait for the fill does not include them
+        if (wb) write_back(old, o0, o1, o2, o3);
         set_tag(s, p | 0x40);
         return s;
     }
@@ -152,14 +171,14 @@ struct FusedMem {
     // Write every modified slot back (end of the launch).
     __device__ __forceinline__ void flush() {
 #pragma unroll
-        for (uint32_t s = 0; s < 2; s++) {
-            const uint32_t t = (tags >> (8 * s)) & 0xFF;
+        for (uint32_t s = 0; s < kSlots; s++) {
+            const uint32_t t = tag(s);
             if ((t & 0xC0) == 0xC0) {
                 const uint4 *slot = reinterpret_cast<const uint4 *>(&sh.cache[lane][64 * s]);
                 write_back(t, slot[0], slot[1], slot[2], slot[3]);
             }
         }
-        tags &= ~0x8080u;
+        tags &= ~0x808080u;
     }
     // One byte, any page (fills a slot for an uncached written page).
     __device__ __forceinline__ uint32_t read(uint32_t a) {
@@ -238,8 +257,9 @@ struct FusedMem {
         const bool d = (dirty >> p) & 1;
         const uint32_t tp = p | 0x40;
         const bool h0 = (tags & 0x7F) == tp, h1 = ((tags >> 8) & 0x7F) == tp;
-        slow = slow || (d ? !(h0 || h1) : lidx < 0);
-        return d ? slot_ptr(h1 ? 1u : 0u) : (lds_u8 *)&sh.img[lidx & 1][0] + 64 * p;
+        const bool h2 = kSlots > 2 && ((tags >> 16) & 0x7F) == tp;
+        slow = slow || (d ? !(h0 || h1 || h2) : lidx < 0);
+        return d ? slot_ptr(h1 ? 1u : h2 ? 2u : 0u) : (lds_u8 *)&sh.img[lidx & 1][0] + 64 * p;
     }
     // Rows [R0, R0 + NR) of the sprite that lie above cnt: one batch of LDS
     // reads (sprite row r at s0[r] while r < rb, else at s1[r]; display row
@@ -366,8 +386,9 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     const uint32_t E = s.num;
     const uint32_t K = io.K;
     const bool active = slot_live(s, slot);
-    // a block with no env (free range of a serving pool) has nothing to do
-    if (!__syncthreads_or(active)) return;
+    // A block with no env (free range of a serving pool) has nothing to do:
+    // the host marks it in the block's ROM table (no ROM to stage).
+    if (cfg.block_roms[blockIdx.x * 2] == kNoRom) return;
     const uint32_t live = active ? 1u : 0u;
     const uint32_t wave_slot0 = blockIdx.x * IPW + wave_base;
     const uint32_t nj = (E > wave_slot0) ? min(64u, E - wave_slot0) : 0u;   // slots of this wave
@@ -408,12 +429,31 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
         const uint32_t word = (ua & 8) ? ((ua & 4) ? keys.w : keys.z) : ((ua & 4) ? keys.y : keys.x);
         return (ua < nact) ? (__builtin_amdgcn_ubfe(word, (ua & 3) * 8, 8) & 15) : kKeyNone;
     };
+    // Writers keep the held keys of 64 consecutive steps in registers, one
+    // byte each, loaded 64 steps at a time: on CDNA a wave's loads complete
+    // in order with its stores, so each load batch waits for every
+    // observation store issued before it, once per 64 steps.
+    u32x16 kp = {};
+    auto load_keys = [&](uint32_t k0) {
+#pragma unroll
+        for (int w = 0; w < 16; w++) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                const uint32_t kk = k0 + 4 * w + b;
+                const int32_t a = kk < K ? io.action[(size_t)kk * E + env] : -1;
+                word |= held_key(a) << (8 * b);
+            }
+            kp[w] = word;
+        }
+    };
+    auto key_of_step = [&](uint32_t kk) -> uint32_t {
+        return __builtin_amdgcn_ubfe(kp[(kk >> 2) & 15], (kk & 3) * 8, 8);
+    };
     if (!emu && active) {
-        // held keys of steps 0 and 1
-        const int32_t a0 = io.action[env];
-        const int32_t a1 = K > 1 ? io.action[(size_t)E + env] : -1;
-        sh.key[0][l] = (uint8_t)held_key(a0);
-        sh.key[1][l] = (uint8_t)held_key(a1);
+        load_keys(0);
+        sh.key[0][l] = (uint8_t)key_of_step(0);
+        sh.key[1][l] = (uint8_t)key_of_step(1);
     }
     if (emu && active) {
         load_core(s, slot, c, head);
@@ -524,11 +564,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
         }
         __syncthreads();   // the displays may change again
         const bool ring_step = k + 4 >= K;
-        // the action of step k + 2, loaded before this step's observation
-        // stores and used after them, so waiting for it waits for none of them
-        int32_t next_action = -1;
         if (!emu && active) {
-            if (k + 2 < K) next_action = io.action[(size_t)(k + 2) * E + env];
             io.reward[(size_t)k * E + env] = wrew;
             io.done[(size_t)k * E + env] = (uint8_t)done;
         }
@@ -587,7 +623,10 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             head = done ? 0u : (head + 1) & 3;
         }
         // the held key of step k + 2 goes into the slot step k has finished with
-        if (!emu && active && k + 2 < K) sh.key[k & 1][l] = (uint8_t)held_key(next_action);
+        if (!emu && active && k + 2 < K) {
+            if (((k + 2) & 63) == 0) load_keys(k + 2);
+            sh.key[k & 1][l] = (uint8_t)key_of_step(k + 2);
+        }
     }
     if (emu && active) mem.flush();
     dirty = mem.dirty;

@@ -3,6 +3,9 @@
 The step kernels must not use scratch memory (a private segment turns
 register arrays into global-memory traffic and limits how many waves can be
 resident), must not spill VGPRs, and must fit their LDS in one CU (160 KB).
+A fused block of IPW envs may use at most IPW/256 of the CU's LDS, so that
+256 envs per CU (65,536 envs on 256 CUs) are resident at once at every block
+size; a few hundred bytes over the line cost a whole second round of blocks.
 """
 import os
 import re
@@ -44,3 +47,9 @@ def test_no_scratch_no_spills_lds_fits(src):
         assert int(k["private_segment_fixed_size"]) == 0, (k["name"], "uses scratch")
         assert int(k.get("vgpr_spill_count", 0)) == 0, (k["name"], "spills VGPRs")
         assert int(k["group_segment_fixed_size"]) <= 160 * 1024, (k["name"], "LDS above 160 KB")
+
+
+def test_fused_blocks_keep_256_envs_per_cu_resident():
+    for k in _kernels("step_fused.hip"):
+        ipw = int(re.search(r"kernelILi(\d+)E", k["name"]).group(1))
+        assert int(k["group_segment_fixed_size"]) <= 160 * 1024 * ipw // 256, (k["name"], k["group_segment_fixed_size"])
