@@ -34,12 +34,17 @@ typedef __attribute__((address_space(1))) uint8_t glb_u8;
 typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
 
 constexpr uint32_t kNoRom = 0xFFFFFFFFu;
-constexpr int kStageEnvs = 16;     // envs staged per round of the cooperative pass
+constexpr int kPrologueEnvs = 16;  // envs whose ring frames one prologue round loads
 constexpr int kStageStride = 68;   // u32 per staged env (64 + 4 pad, 16-byte aligned)
-// Written-page cache slots per env: three where the block's LDS share allows
-// (128 and 256 envs per block), two at 64 envs per block.
+// Written-page cache slots per env, as many as the block's LDS share allows
+// beside the two staged ROM images: four at 256 envs per block, three at
+// 128, two at 64.
 template <int IPW>
-constexpr int cache_slots() { return IPW == 64 ? 2 : 3; }
+constexpr int cache_slots() { return IPW == 64 ? 2 : IPW == 128 ? 3 : 4; }
+// Envs staged per round of the writers' cooperative pass (eight at 256 envs
+// per block, which leaves room for the fourth cache slot).
+template <int IPW>
+constexpr int stage_envs() { return IPW == 256 ? 8 : 16; }
 // bytes per env: the slots + 8 pad bytes (spreads lanes over banks)
 template <int IPW>
 constexpr int cache_stride() { return 64 * cache_slots<IPW>() + 8; }
@@ -55,7 +60,7 @@ template <int IPW>
 struct Shared {
     uint64_t fb[IPW][kFbStride];
     uint8_t cache[IPW][cache_stride<IPW>()];
-    uint32_t stage[IPW / 64][kStageEnvs][kStageStride];
+    uint32_t stage[IPW / 64][stage_envs<IPW>()][kStageStride];
     uint32_t stack[IPW][9];
     float rew[IPW];           // reward and done bits of the step just emulated, for the writer waves
     uint8_t done[IPW];
@@ -66,12 +71,14 @@ struct Shared {
 // Memory of one env in the fused kernel.
 //   * pages not written since the reset read from the power-on image: the
 //     LDS copy when the block staged this ROM, else HBM;
-//   * written pages are kept in two or three LDS cache slots per env,
+//   * written pages are kept in two to four LDS cache slots per env,
 //     write-back: a write fills a slot (from the image for a clean page, from
 //     the env's memory in HBM for a written one) and marks it modified; HBM
 //     receives a modified page only when its slot is reused and when the
 //     launch ends.  A read of an uncached written page fills a slot from HBM.
-//     Slots are replaced least recently filled first;
+//     Slots are replaced in fill order, except that an access to the slot
+//     due next moves the replacement pointer past it (a page in use is not
+//     evicted next);
 //   * multi-byte accesses (fetch, FX33/FX55/FX65, DXYN rows) touch at most
 //     two pages; when both are readable from LDS all their LDS accesses are
 //     issued back to back (one round trip per instruction, not one per byte).
@@ -86,7 +93,8 @@ struct FusedMem {
     const glb_u8 *gimg;      // power-on image in HBM
     glb_u8 *ram;             // env memory in HBM
     uint64_t dirty;
-    uint32_t tags;           // slot i at bits 8i..8i+7: page | valid << 6 | modified << 7; next victim at bit 24
+    uint32_t tags;           // slot i at bits 8i..8i+7: page | valid << 6 | modified << 7
+    uint32_t vic = 0;        // slot replaced next
     static constexpr uint32_t kSlots = cache_slots<IPW>();
 
     __device__ __forceinline__ lds_u8 *slot_ptr(uint32_t s) const {
@@ -104,7 +112,7 @@ struct FusedMem {
     // tag is returned in `old`.
     __device__ __forceinline__ static uint32_t next_slot(uint32_t s) { return s + 1 == kSlots ? 0u : s + 1; }
     __device__ __forceinline__ uint32_t victim(int32_t keep, uint32_t &old) const {
-        uint32_t s = (tags >> 24) & 3;
+        uint32_t s = vic;
         if ((int32_t)s == keep) s = next_slot(s);
         old = tag(s);
         return s;
@@ -112,7 +120,13 @@ struct FusedMem {
     // Slots are replaced in fill order: the next victim follows the slot filled.
     __device__ __forceinline__ void set_tag(uint32_t s, uint32_t t) {
         tags = (tags & ~(0xFFu << (8 * s))) | (t << (8 * s));
-        tags = (tags & 0x00FFFFFFu) | (next_slot(s) << 24);
+        vic = next_slot(s);
+    }
+    // An access to written page p: when p sits in the slot due for
+    // replacement, the replacement pointer moves on to the next slot.
+    __device__ __forceinline__ void touch(uint32_t p) {
+        const bool at_vic = is_dirty(p) & ((tag(vic) & 0x7F) == (p | 0x40));
+        vic = at_vic ? next_slot(vic) : vic;
     }
     // Write a modified slot's page back to HBM (16 bytes a piece, from
     // registers read before the slot is overwritten).
@@ -178,7 +192,7 @@ struct FusedMem {
                 write_back(t, slot[0], slot[1], slot[2], slot[3]);
             }
         }
-        tags &= ~0x808080u;
+        tags &= ~0x80808080u;
     }
     // One byte, any page (fills a slot for an uncached written page).
     __device__ __forceinline__ uint32_t read(uint32_t a) {
@@ -208,6 +222,7 @@ struct FusedMem {
         uint32_t op = ((uint32_t)*b0 << 8) | *b1;
         ret = stack_get((sp - 1) & 15);
         if (slow) op = (read(pc) << 8) | read(a1);
+        touch(pc >> 6);
         return op;
     }
     __device__ __forceinline__ u32x4 load_bytes(uint32_t a, uint32_t count) {
@@ -217,6 +232,8 @@ struct FusedMem {
         const lds_u8 *s0 = lds_page_sel(a >> 6, slow) + off;
         const lds_u8 *s1 = lds_page_sel(a_last >> 6, slow) + off - 64;
         const uint32_t rb = 64 - off;   // bytes k < rb are on the first page
+        touch(a >> 6);
+        touch(a_last >> 6);
         u32x4 v = {0, 0, 0, 0};
         if (!slow) {
             uint32_t b[16];
@@ -234,6 +251,8 @@ struct FusedMem {
     }
     __device__ __forceinline__ void store_bytes(uint32_t a, uint32_t count, u32x4 bytes) {
         const uint32_t p0 = a >> 6, p1 = ((a + count - 1) & 0xFFF) >> 6;
+        touch(p0);
+        touch(p1);
         int32_t s0 = find(p0);
         if (s0 < 0) s0 = (int32_t)(is_dirty(p0) ? fill_from_ram(p0, -1) : fill_from_image(p0, -1));
         int32_t s1 = s0;
@@ -258,8 +277,9 @@ struct FusedMem {
         const uint32_t tp = p | 0x40;
         const bool h0 = (tags & 0x7F) == tp, h1 = ((tags >> 8) & 0x7F) == tp;
         const bool h2 = kSlots > 2 && ((tags >> 16) & 0x7F) == tp;
-        slow = slow || (d ? !(h0 || h1 || h2) : lidx < 0);
-        return d ? slot_ptr(h1 ? 1u : h2 ? 2u : 0u) : (lds_u8 *)&sh.img[lidx & 1][0] + 64 * p;
+        const bool h3 = kSlots > 3 && ((tags >> 24) & 0x7F) == tp;
+        slow = slow || (d ? !(h0 || h1 || h2 || h3) : lidx < 0);
+        return d ? slot_ptr(h1 ? 1u : h2 ? 2u : h3 ? 3u : 0u) : (lds_u8 *)&sh.img[lidx & 1][0] + 64 * p;
     }
     // Rows [R0, R0 + NR) of the sprite that lie above cnt: one batch of LDS
     // reads (sprite row r at s0[r] while r < rb, else at s1[r]; display row
@@ -298,6 +318,8 @@ struct FusedMem {
         const lds_u8 *s0 = lds_page_sel(I >> 6, slow) + off;
         const lds_u8 *s1 = lds_page_sel(a_last >> 6, slow) + off - 64;
         const uint32_t rb = 64 - off;   // rows r < rb are on the first page
+        touch(I >> 6);
+        touch(a_last >> 6);
         uint64_t hit = 0;
         if (!slow) {
             hit = draw_rows<0, 4>(fbr, x0, cnt, s0, s1, rb);
@@ -485,10 +507,10 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     // observations of steps 0..2 (frame f of step k is the frame of step
     // k - 3 + f).  All loads of a chunk of envs are issued before its stores.
     if (!emu && io.obs) {
-        for (uint32_t j0 = 0; j0 < nj; j0 += kStageEnvs) {
-            uint32_t w[kStageEnvs][3];
+        for (uint32_t j0 = 0; j0 < nj; j0 += kPrologueEnvs) {
+            uint32_t w[kPrologueEnvs][3];
 #pragma unroll
-            for (int jj = 0; jj < kStageEnvs; jj++) {
+            for (int jj = 0; jj < kPrologueEnvs; jj++) {
                 const uint32_t j = min(j0 + jj, nj - 1);
                 const uint32_t jh = __builtin_amdgcn_readlane(head, j);
                 const uint32_t *ring = s.cols + (size_t)(wave_slot0 + j) * 256 + lane64;
@@ -497,7 +519,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 w[jj][2] = ring[((jh + 2) & 3) * 64];     // step -3
             }
 #pragma unroll
-            for (int jj = 0; jj < kStageEnvs; jj++) {
+            for (int jj = 0; jj < kPrologueEnvs; jj++) {
                 const uint32_t j = j0 + jj;
                 if (j >= nj) break;
                 if (!__builtin_amdgcn_readlane(live, j)) continue;
@@ -573,19 +595,20 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             uint32_t pw[64];
             rows_to_cols(hi, lo);
             pack_frame(hi, lo, pw);
-            // Cooperative pass, 16 envs per round: stage their packed frames,
+            // Cooperative pass, a few envs per round: stage their packed frames,
             // then for each env store its frame into every observation it
             // belongs to and keep the last four frames of the launch in the
             // env's ring.
-            for (uint32_t r0 = 0; r0 < nj; r0 += kStageEnvs) {
-                if (active && lane64 - r0 < (uint32_t)kStageEnvs) {
+            constexpr uint32_t kStage = stage_envs<IPW>();
+            for (uint32_t r0 = 0; r0 < nj; r0 += kStage) {
+                if (active && lane64 - r0 < kStage) {
                     uint4 *stg = reinterpret_cast<uint4 *>(sh.stage[wave][lane64 - r0]);
 #pragma unroll
                     for (int q = 0; q < 16; q++)
                         stg[q] = make_uint4(pw[4 * q], pw[4 * q + 1], pw[4 * q + 2], pw[4 * q + 3]);
                 }
                 wave_sync();
-                const uint32_t r1 = min(r0 + (uint32_t)kStageEnvs, nj);
+                const uint32_t r1 = min(r0 + kStage, nj);
                 for (uint32_t j = r0; j < r1; j++) {
                     if (!__builtin_amdgcn_readlane(live, j)) continue;
                     const uint32_t w = sh.stage[wave][j - r0][lane64];
