@@ -41,10 +41,10 @@ constexpr int kStageStride = 68;   // u32 per staged env (64 + 4 pad, 16-byte al
 // 128, two at 64.
 template <int IPW>
 constexpr int cache_slots() { return IPW == 64 ? 2 : IPW == 128 ? 3 : 4; }
-// Envs staged per round of the writers' cooperative pass (eight at 256 envs
-// per block, which leaves room for the fourth cache slot).
-template <int IPW>
-constexpr int stage_envs() { return IPW == 256 ? 8 : 16; }
+// Envs staged per round of the writers' cooperative pass (eight: room for the
+// fourth cache slot at 256 envs per block, and few registers for the frames
+// of one round).
+constexpr uint32_t kStageEnvs = 8;
 // bytes per env: the slots + 8 pad bytes (spreads lanes over banks)
 template <int IPW>
 constexpr int cache_stride() { return 64 * cache_slots<IPW>() + 8; }
@@ -60,7 +60,7 @@ template <int IPW>
 struct Shared {
     uint64_t fb[IPW][kFbStride];
     uint8_t cache[IPW][cache_stride<IPW>()];
-    uint32_t stage[IPW / 64][stage_envs<IPW>()][kStageStride];
+    uint32_t stage[IPW / 64][kStageEnvs][kStageStride];
     uint32_t stack[IPW][9];
     float rew[IPW];           // reward and done bits of the step just emulated, for the writer waves
     uint8_t done[IPW];
@@ -102,11 +102,13 @@ struct FusedMem {
     }
     __device__ __forceinline__ bool is_dirty(uint32_t p) const { return (dirty >> p) & 1; }
     __device__ __forceinline__ uint32_t tag(uint32_t s) const { return (tags >> (8 * s)) & 0xFF; }
+    // Slot holding page p, or -1.  All tag bytes are compared at once: byte s
+    // of v is zero exactly when slot s holds p (valid bit included), and the
+    // lowest zero byte is found with the borrow test of a SWAR zero-byte scan.
     __device__ __forceinline__ int32_t find(uint32_t p) const {
-#pragma unroll
-        for (uint32_t s = 0; s < kSlots; s++)
-            if ((tag(s) & 0x7F) == (p | 0x40)) return (int32_t)s;
-        return -1;
+        const uint32_t v = (tags ^ ((p | 0x40u) * 0x01010101u)) & 0x7F7F7F7Fu;
+        const uint32_t z = (v - 0x01010101u) & ~v & 0x80808080u;
+        return z ? (int32_t)(__builtin_ctz(z | 0x80000000u) >> 3) : -1;
     }
     // Pick the slot for page p, never slot `keep` (-1: none); the slot's old
     // tag is returned in `old`.
@@ -194,20 +196,21 @@ struct FusedMem {
         }
         tags &= ~0x80808080u;
     }
-    // One byte, any page (fills a slot for an uncached written page).
-    __device__ __forceinline__ uint32_t read(uint32_t a) {
-        const uint32_t p = a >> 6;
-        if (is_dirty(p)) {
-            int32_t s = find(p);
-            if (s < 0) s = (int32_t)fill_from_ram(p, -1);
-            return slot_ptr((uint32_t)s)[a & 63];
-        }
-        if (lidx >= 0) return ((const lds_u8 *)&sh.img[lidx][0])[a];
-        return gimg[a];
+    // Slow path of the selects below: make page p readable from LDS.  A
+    // written page that is not cached is filled from the env's memory in HBM,
+    // a clean page of a ROM the block has not staged from the power-on image
+    // in HBM; slot `keep` is not reused.  Returns the page's slot, or -1 for a
+    // page of the staged image.
+    __device__ __forceinline__ int32_t make_resident(uint32_t p, int32_t keep) {
+        int32_t s = find(p);
+        if (s < 0 && is_dirty(p)) s = (int32_t)fill_from_ram(p, keep);
+        else if (s < 0 && lidx < 0) s = (int32_t)fill_from_image(p, keep);
+        return s;
     }
-    // LDS address of byte a, computed with selects only: a clean page of the
-    // staged image or a cached written page.  `slow` is raised when neither
-    // holds (the address is then some other byte of the block's LDS).
+    // LDS address of byte a, computed with selects only: the cache slot of
+    // its page, else the staged image for a clean page.  `slow` is raised
+    // when neither holds (the address is then some other byte of the block's
+    // LDS).
     __device__ __forceinline__ const lds_u8 *lds_byte(uint32_t a, bool &slow) const {
         return lds_page_sel(a >> 6, slow) + (a & 63);
     }
@@ -221,31 +224,46 @@ struct FusedMem {
         const lds_u8 *b1 = lds_byte(a1, slow);
         uint32_t op = ((uint32_t)*b0 << 8) | *b1;
         ret = stack_get((sp - 1) & 15);
-        if (slow) op = (read(pc) << 8) | read(a1);
+        if (slow) {
+            make_resident(a1 >> 6, make_resident(pc >> 6, -1));
+            bool no = false;
+            op = ((uint32_t)*lds_byte(pc, no) << 8) | *lds_byte(a1, no);
+        }
         touch(pc >> 6);
         return op;
     }
+    // count (1..16) bytes from address a on (12-bit wrap), on at most two
+    // pages; byte k lands at bits 8k of the vector.  Bytes past count are
+    // left unspecified: the caller masks them.
     __device__ __forceinline__ u32x4 load_bytes(uint32_t a, uint32_t count) {
         const uint32_t off = a & 63;
-        const uint32_t a_last = (a + count - 1) & 0xFFF;
+        const uint32_t p0 = a >> 6, p1 = ((a + count - 1) & 0xFFF) >> 6;
         bool slow = false;
-        const lds_u8 *s0 = lds_page_sel(a >> 6, slow) + off;
-        const lds_u8 *s1 = lds_page_sel(a_last >> 6, slow) + off - 64;
-        const uint32_t rb = 64 - off;   // bytes k < rb are on the first page
-        touch(a >> 6);
-        touch(a_last >> 6);
+        const lds_u8 *q0 = lds_page_sel(p0, slow), *q1 = lds_page_sel(p1, slow);
+        if (slow) {
+            make_resident(p1, make_resident(p0, -1));
+            bool no = false;
+            q0 = lds_page_sel(p0, no);
+            q1 = lds_page_sel(p1, no);
+        }
+        touch(p0);
+        touch(p1);
+        // byte k is at s0[k] while k < rb, else at s1[k]; groups of four bytes
+        // are read only when a byte of the group is wanted
+        const lds_u8 *s0 = q0 + off, *s1 = q1 + off - 64;
+        const uint32_t rb = 64 - off;
         u32x4 v = {0, 0, 0, 0};
-        if (!slow) {
-            uint32_t b[16];
 #pragma unroll
-            for (int k = 0; k < 16; k++) b[k] = ((uint32_t)k < rb ? s0 : s1)[k];
+        for (int g = 0; g < 4; g++) {
+            if ((uint32_t)(4 * g) < count) {
+                uint32_t w = 0;
 #pragma unroll
-            for (int k = 0; k < 16; k++)
-                if ((uint32_t)k < count) or_byte(v, k, b[k]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 16; k++)
-                if ((uint32_t)k < count) or_byte(v, k, read((a + k) & 0xFFF));
+                for (int q = 0; q < 4; q++) {
+                    const int k = 4 * g + q;
+                    w |= (uint32_t)((uint32_t)k < rb ? s0 : s1)[k] << (8 * q);
+                }
+                v[g] = w;
+            }
         }
         return v;
     }
@@ -260,12 +278,22 @@ struct FusedMem {
             s1 = find(p1);
             if (s1 < 0) s1 = (int32_t)(is_dirty(p1) ? fill_from_ram(p1, s0) : fill_from_image(p1, s0));
         }
-        lds_u8 *c0 = slot_ptr((uint32_t)s0), *c1 = slot_ptr((uint32_t)s1);
+        // byte k goes to c0[k] while k < rb, else to c1[k]; in a group of four
+        // that some lane writes, bytes past count go to the pad bytes after
+        // the env's slots
+        const uint32_t off = a & 63;
+        const uint32_t rb = 64 - off;
+        lds_u8 *c0 = slot_ptr((uint32_t)s0) + off, *c1 = slot_ptr((uint32_t)s1) + off - 64;
+        lds_u8 *pad = (lds_u8 *)&sh.cache[lane][64 * kSlots];
 #pragma unroll
-        for (int k = 0; k < 16; k++) {
-            if ((uint32_t)k < count) {
-                const uint32_t ak = (a + k) & 0xFFF;
-                (((ak >> 6) == p0) ? c0 : c1)[ak & 63] = (uint8_t)byte_of(bytes, k);
+        for (int g = 0; g < 4; g++) {
+            if ((uint32_t)(4 * g) < count) {
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int k = 4 * g + q;
+                    lds_u8 *base = (uint32_t)k < count ? ((uint32_t)k < rb ? c0 : c1) : pad + (k & 7) - k;
+                    base[k] = (uint8_t)byte_of(bytes, k);
+                }
             }
         }
         tags |= (0x80u << (8 * s0)) | (0x80u << (8 * s1));
@@ -273,66 +301,68 @@ struct FusedMem {
     }
     // LDS base of page p, computed with selects only (see lds_byte).
     __device__ __forceinline__ lds_u8 *lds_page_sel(uint32_t p, bool &slow) const {
-        const bool d = (dirty >> p) & 1;
-        const uint32_t tp = p | 0x40;
-        const bool h0 = (tags & 0x7F) == tp, h1 = ((tags >> 8) & 0x7F) == tp;
-        const bool h2 = kSlots > 2 && ((tags >> 16) & 0x7F) == tp;
-        const bool h3 = kSlots > 3 && ((tags >> 24) & 0x7F) == tp;
-        slow = slow || (d ? !(h0 || h1 || h2 || h3) : lidx < 0);
-        return d ? slot_ptr(h1 ? 1u : h2 ? 2u : h3 ? 3u : 0u) : (lds_u8 *)&sh.img[lidx & 1][0] + 64 * p;
+        const int32_t s = find(p);
+        slow = slow | ((s < 0) & (is_dirty(p) | (lidx < 0)));
+        return s >= 0 ? slot_ptr((uint32_t)s) : (lds_u8 *)&sh.img[lidx & 1][0] + 64 * p;
     }
-    // Rows [R0, R0 + NR) of the sprite that lie above cnt: one batch of LDS
-    // reads (sprite row r at s0[r] while r < rb, else at s1[r]; display row
-    // y0 + r at fbr[r]), then the XOR and the row writes.  Rows at or past
-    // cnt are read (inside the block's LDS) but neither used nor written.
-    template <int R0, int NR>
-    __device__ __forceinline__ uint64_t draw_rows(lds_u64 *fbr, uint32_t x0, uint32_t cnt,
-                                                  const lds_u8 *s0, const lds_u8 *s1, uint32_t rb) {
+    // Window rows [W0, W0 + NR): one batch of LDS reads, then the XOR and the
+    // row writes.  Window row w is display row b + w (at fbw[w]) and sprite
+    // row w - sh0 (at s0w[w] while w < rbw, else at s1w[w]).  Bit w of vm
+    // marks the sprite's rows; the other rows get an empty mask and are
+    // written back unchanged.
+    template <int W0, int NR>
+    __device__ __forceinline__ uint64_t draw_rows(lds_u64 *fbw, uint32_t x0, uint32_t vm,
+                                                  const lds_u8 *s0w, const lds_u8 *s1w, uint32_t rbw) {
         uint32_t spr[NR];
         uint64_t row[NR];
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            spr[r] = ((uint32_t)(R0 + r) < rb ? s0 : s1)[R0 + r];
-            row[r] = fbr[R0 + r];
+            spr[r] = ((uint32_t)(W0 + r) < rbw ? s0w : s1w)[W0 + r];
+            row[r] = fbw[W0 + r];
         }
         uint64_t hit = 0;
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            if ((uint32_t)(R0 + r) < cnt) {
-                const uint64_t m = ((uint64_t)spr[r] << 56) >> x0;
-                hit |= row[r] & m;
-                fbr[R0 + r] = row[r] ^ m;
-            }
+            const uint32_t sb = spr[r] * __builtin_amdgcn_ubfe(vm, W0 + r, 1);
+            const uint64_t m = ((uint64_t)sb << 56) >> x0;
+            hit |= row[r] & m;
+            fbw[W0 + r] = row[r] ^ m;
         }
         return hit;
     }
     // DXYN at (x0, y0) = (VX & 63, VY & 31): rows below the screen are
     // clipped, pixels past x = 63 fall off the shifted mask.  Sprite bytes
-    // are at I + r (12-bit wrap), on at most two pages.
+    // are at I + r (12-bit wrap), on at most two pages.  Rows are taken in a
+    // window of 15 display rows from b = min(y0, 17), which lies inside the
+    // env's 32 rows, so every window row can be written back without a
+    // per-row condition.  Sprite rows are read from at most 14 bytes before
+    // or after the sprite (inside the block's LDS) when they are not used.
     __device__ __forceinline__ uint32_t draw(uint32_t x0, uint32_t y0, uint32_t I, uint32_t n) {
-        lds_u64 *fbr = (lds_u64 *)&sh.fb[lane][0] + y0;
         const uint32_t cnt = min(n, 32 - y0);
+        const uint32_t b = min(y0, 17u);
+        const uint32_t sh0 = y0 - b;                    // window rows above the sprite
+        const uint32_t vm = ((1u << cnt) - 1) << sh0;   // window rows of the sprite
+        lds_u64 *fbw = (lds_u64 *)&sh.fb[lane][0] + b;
         const uint32_t off = I & 63;
-        const uint32_t a_last = (I + max(cnt, 1u) - 1) & 0xFFF;
+        const uint32_t p0 = I >> 6, p1 = ((I + max(cnt, 1u) - 1) & 0xFFF) >> 6;
         bool slow = false;
-        const lds_u8 *s0 = lds_page_sel(I >> 6, slow) + off;
-        const lds_u8 *s1 = lds_page_sel(a_last >> 6, slow) + off - 64;
-        const uint32_t rb = 64 - off;   // rows r < rb are on the first page
-        touch(I >> 6);
-        touch(a_last >> 6);
-        uint64_t hit = 0;
-        if (!slow) {
-            hit = draw_rows<0, 4>(fbr, x0, cnt, s0, s1, rb);
-            if (cnt > 4) hit |= draw_rows<4, 4>(fbr, x0, cnt, s0, s1, rb);
-            if (cnt > 8) hit |= draw_rows<8, 7>(fbr, x0, cnt, s0, s1, rb);
-        } else {
-            for (uint32_t r = 0; r < cnt; r++) {
-                const uint64_t m = ((uint64_t)read((I + r) & 0xFFF) << 56) >> x0;
-                const uint64_t row = fbr[r];
-                hit |= row & m;
-                fbr[r] = row ^ m;
-            }
+        const lds_u8 *q0 = lds_page_sel(p0, slow), *q1 = lds_page_sel(p1, slow);
+        if (slow) {
+            make_resident(p1, make_resident(p0, -1));
+            bool no = false;
+            q0 = lds_page_sel(p0, no);
+            q1 = lds_page_sel(p1, no);
         }
+        touch(p0);
+        touch(p1);
+        // sprite row r = w - sh0 is at I + r: on the first page while r < 64 - off
+        const lds_u8 *s0w = q0 + off - sh0;
+        const lds_u8 *s1w = q1 + off - 64 - sh0;
+        const uint32_t rbw = 64 - off + sh0;
+        uint64_t hit = 0;
+        if (vm & 0x000Fu) hit |= draw_rows<0, 4>(fbw, x0, vm, s0w, s1w, rbw);
+        if (vm & 0x00F0u) hit |= draw_rows<4, 4>(fbw, x0, vm, s0w, s1w, rbw);
+        if (vm & 0x7F00u) hit |= draw_rows<8, 7>(fbw, x0, vm, s0w, s1w, rbw);
         return hit != 0;
     }
     __device__ __forceinline__ void clear() {
@@ -599,7 +629,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             // then for each env store its frame into every observation it
             // belongs to and keep the last four frames of the launch in the
             // env's ring.
-            constexpr uint32_t kStage = stage_envs<IPW>();
+            constexpr uint32_t kStage = kStageEnvs;
             for (uint32_t r0 = 0; r0 < nj; r0 += kStage) {
                 if (active && lane64 - r0 < kStage) {
                     uint4 *stg = reinterpret_cast<uint4 *>(sh.stage[wave][lane64 - r0]);
@@ -609,15 +639,32 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 }
                 wave_sync();
                 const uint32_t r1 = min(r0 + kStage, nj);
+                if (io.obs) {
+                    // The round's frames go into observation k + d of every
+                    // env of the round before observation k + d + 1: 2 KB
+                    // pieces 8 KB apart in one region at a time stream to HBM
+                    // faster than the four regions of one env in turn.
+                    uint32_t wj[kStage];
+#pragma unroll
+                    for (uint32_t jj = 0; jj < kStage; jj++) wj[jj] = sh.stage[wave][jj][lane64];
+#pragma unroll
+                    for (uint32_t d = 0; d < 4; d++) {
+                        if (k + d >= K) break;
+#pragma unroll
+                        for (uint32_t jj = 0; jj < kStage; jj++) {
+                            const uint32_t j = r0 + jj;
+                            if (j < r1 && __builtin_amdgcn_readlane(live, j))
+                                store_frame(obs_of(k + d, __builtin_amdgcn_readlane(env, j)) + (3 - d) * 2048,
+                                            lane64, wj[jj]);
+                        }
+                    }
+                }
                 for (uint32_t j = r0; j < r1; j++) {
                     if (!__builtin_amdgcn_readlane(live, j)) continue;
                     const uint32_t w = sh.stage[wave][j - r0][lane64];
                     const uint32_t jdone = __builtin_amdgcn_readlane(done, j);
                     if (io.obs) {
                         const uint32_t je = __builtin_amdgcn_readlane(env, j);
-#pragma unroll
-                        for (uint32_t d = 0; d < 4; d++)
-                            if (k + d < K) store_frame(obs_of(k + d, je) + (3 - d) * 2048, lane64, w);
                         if (jdone) {
                             // the frames before the reset belong to the old episode
 #pragma unroll

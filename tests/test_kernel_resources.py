@@ -3,6 +3,9 @@
 The step kernels must not use scratch memory (a private segment turns
 register arrays into global-memory traffic and limits how many waves can be
 resident), must not spill VGPRs, and must fit their LDS in one CU (160 KB).
+A fused block runs an emulator and a writer wave on every SIMD, so the fused
+kernels may use at most 256 of the SIMD's 512 registers per lane (VGPRs and
+AGPRs together).
 A fused block of IPW envs may use at most IPW/256 of the CU's LDS, so that
 256 envs per CU (65,536 envs on 256 CUs) are resident at once at every block
 size; a few hundred bytes over the line cost a whole second round of blocks.
@@ -53,3 +56,4 @@ def test_fused_blocks_keep_256_envs_per_cu_resident():
     for k in _kernels("step_fused.hip"):
         ipw = int(re.search(r"kernelILi(\d+)E", k["name"]).group(1))
         assert int(k["group_segment_fixed_size"]) <= 160 * 1024 * ipw // 256, (k["name"], k["group_segment_fixed_size"])
+        assert int(k["vgpr_count"]) <= 256, (k["name"], "two waves per SIMD need at most 256 registers", k["vgpr_count"])
