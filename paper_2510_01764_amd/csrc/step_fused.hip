@@ -65,6 +65,8 @@ struct Shared {
     float rew[IPW];           // reward and done bits of the step just emulated, for the writer waves
     uint8_t done[IPW];
     uint8_t key[2][IPW];      // held key of step k (slot k & 1), staged by the writer waves
+    uint32_t ready[IPW / 64]; // steps emulated by emulator wave w
+    uint32_t taken[IPW / 64]; // displays taken by writer wave w
     uint8_t img[2][kMem];
 };
 
@@ -406,6 +408,22 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Step counters shared by the two waves of a pair.  The fences order LDS
+// only, so the writer waves' observation stores in flight are not waited for.
+__device__ __forceinline__ void set_flag(uint32_t *f, uint32_t v) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t get_flag(const uint32_t *f) {
+    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+}
+// Wait until the flag reaches v.  The partner wave raises it within a step;
+// the bound on the number of polls only guarantees that every wave ends.
+__device__ __forceinline__ void wait_flag(const uint32_t *f, uint32_t v) {
+    for (uint32_t n = 0; n < (1u << 22) && get_flag(f) < v; n++) __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Lane l's share of one packed frame: bytes [16l, 16l+16) and [1024+16l, ...).
 __device__ __forceinline__ void store_frame(uint8_t *frame, uint32_t lane64, uint32_t w) {
     store16(frame + 16 * lane64, w & 0xFFFF);
@@ -415,12 +433,17 @@ __device__ __forceinline__ void store_frame(uint8_t *frame, uint32_t lane64, uin
 // Wave roles.  A block runs IPW envs with 2 * IPW threads: waves
 // 0 .. IPW/64 - 1 emulate (one env per lane, thread l is env l) and waves
 // IPW/64 .. 2 * IPW/64 - 1 write observations (thread IPW + l serves env l).
-// Each step ends with two block barriers: after the first the display of
-// every env is final (auto-reset included), between the two the writer waves
-// copy it into registers, after the second the emulators start the next step
-// while the writers transpose, expand and store the frame just taken.  The
-// observation stores and the emulation of the next step thus share each
-// SIMD as two waves instead of running back to back in one.
+// Emulator wave w and writer wave w form a pair that synchronises through
+// two LDS step counters instead of block barriers:
+//   * the emulator raises ready[w] to k + 1 when the display of step k is
+//     final (auto-reset included), and starts step k + 1 once taken[w] says
+//     that display has been copied;
+//   * the writer copies the display of step k into registers when ready[w]
+//     allows, raises taken[w], then transposes, expands and stores it while
+//     the emulator runs step k + 1.
+// The observation stores and the emulation thus share each SIMD as two waves,
+// and each pair runs at its own pace: a slow step of one pair does not hold
+// up the other pairs of the block.
 //
 // kRollout separates the K-step launches (graph-captured rollouts) from the
 // K = 1 launches of octax_step into two instantiations of the same code, so
@@ -565,63 +588,74 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             }
         }
     }
+    if (tid < IPW / 64) {
+        sh.ready[tid] = 0;
+        sh.taken[tid] = 0;
+    }
     __syncthreads();
 
     FusedMem<IPW> mem{sh, l, lidx, gimg, ram, dirty, tags};
-    for (uint32_t k = 0; k < K; k++) {
-        // ---- emulators: step k ----
-        if (emu && active) {
-            const uint32_t key = sh.key[k & 1][l];
-            for (uint32_t f = 0; f < io.frame_skip; f++) {
-                for (uint32_t i = 0; i < io.ipf; i++) exec_grouped(c, mem, key);
-                tick(c);
+    if (emu) {
+        for (uint32_t k = 0; k < K; k++) {
+            // the display of step k - 1 must have been copied before it changes
+            if (k > 0) wait_flag(&sh.taken[wave], k);
+            if (active) {
+                const uint32_t key = sh.key[k & 1][l];
+                for (uint32_t f = 0; f < io.frame_skip; f++) {
+                    for (uint32_t i = 0; i < io.ipf; i++) exec_grouped(c, mem, key);
+                    tick(c);
+                }
+                const int32_t score = (int32_t)vget(c.r, desc & 15);
+                const float reward = (float)(score - prev);
+                const uint32_t term = vget(c.r, (desc >> 8) & 15) == ((desc >> 16) & 0xFF);
+                t += 1;
+                const uint32_t trunc = (hor != 0) && (t >= hor);
+                const uint32_t done = term | (trunc << 1);
+                sh.rew[l] = reward;
+                sh.done[l] = (uint8_t)done;
+                if (done) {
+                    // Automatic reset (Section 3.4); the RNG stream continues.
+                    mem.restore_pages();
+                    reset_core(c);
+                    mem.clear();
+                    for (int q = 0; q < 8; q++) sh.stack[l][q] = 0;
+                    head = 0;
+                    t = 0;
+                    prev = 0;
+                } else {
+                    prev = score;
+                    head = (head + 1) & 3;
+                }
             }
-            const int32_t score = (int32_t)vget(c.r, desc & 15);
-            const float reward = (float)(score - prev);
-            const uint32_t term = vget(c.r, (desc >> 8) & 15) == ((desc >> 16) & 0xFF);
-            t += 1;
-            const uint32_t trunc = (hor != 0) && (t >= hor);
-            const uint32_t done = term | (trunc << 1);
-            sh.rew[l] = reward;
-            sh.done[l] = (uint8_t)done;
-            if (done) {
-                // Automatic reset (Section 3.4); the RNG stream continues.
-                mem.restore_pages();
-                reset_core(c);
-                mem.clear();
-                for (int q = 0; q < 8; q++) sh.stack[l][q] = 0;
-                head = 0;
-                t = 0;
-                prev = 0;
-            } else {
-                prev = score;
-                head = (head + 1) & 3;
-            }
+            set_flag(&sh.ready[wave], k + 1);
         }
-        __syncthreads();   // the displays of step k are final
-
-        // ---- writers: take the frames of step k, then store them ----
-        uint32_t hi[32], lo[32];
-        uint32_t done = 0;
-        float wrew = 0.0f;
-        if (!emu) {
+    } else {
+        for (uint32_t k = 0; k < K; k++) {
+            // Copy the display, reward and done bits of step k once final,
+            // stage the held key of step k + 2 in the key slot step k has
+            // finished with, and let the emulator go on.
+            wait_flag(&sh.ready[wave], k + 1);
+            uint32_t hi[32], lo[32];
 #pragma unroll
             for (int r = 0; r < 32; r++) {
                 const uint64_t row = sh.fb[l][31 - r];
                 hi[r] = (uint32_t)(row >> 32);
                 lo[r] = (uint32_t)row;
             }
-            done = active ? sh.done[l] : 0u;
-            wrew = sh.rew[l];
-        }
-        __syncthreads();   // the displays may change again
-        const bool ring_step = k + 4 >= K;
-        if (!emu && active) {
-            io.reward[(size_t)k * E + env] = wrew;
-            io.done[(size_t)k * E + env] = (uint8_t)done;
-        }
-        if (!emu && (io.obs || ring_step)) {
+            const uint32_t done = active ? sh.done[l] : 0u;
+            const float wrew = sh.rew[l];
+            if (active && k + 2 < K) {
+                if (((k + 2) & 63) == 0) load_keys(k + 2);
+                sh.key[k & 1][l] = (uint8_t)key_of_step(k + 2);
+            }
+            set_flag(&sh.taken[wave], k + 1);
+            const bool ring_step = k + 4 >= K;
+            if (active) {
+                io.reward[(size_t)k * E + env] = wrew;
+                io.done[(size_t)k * E + env] = (uint8_t)done;
+            }
             head = done ? 0u : (head + 1) & 3;
+            if (!(io.obs || ring_step)) continue;
             uint32_t pw[64];
             rows_to_cols(hi, lo);
             pack_frame(hi, lo, pw);
@@ -689,13 +723,6 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 }
                 wave_sync();
             }
-        } else if (!emu) {
-            head = done ? 0u : (head + 1) & 3;
-        }
-        // the held key of step k + 2 goes into the slot step k has finished with
-        if (!emu && active && k + 2 < K) {
-            if (((k + 2) & 63) == 0) load_keys(k + 2);
-            sh.key[k & 1][l] = (uint8_t)key_of_step(k + 2);
         }
     }
     if (emu && active) mem.flush();
