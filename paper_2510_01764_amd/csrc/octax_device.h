@@ -171,4 +171,14 @@ __device__ __forceinline__ void store16(uint8_t *dst, uint32_t bits) {
     store_stream(dst, spread4(bits, 0), spread4(bits, 4), spread4(bits, 8), spread4(bits, 12));
 }
 
+// The low 16 pixel bits of `bits` as 16 bytes (byte i = bit i).
+__device__ __forceinline__ u32x4 spread16(uint32_t bits) {
+    return u32x4{spread4(bits, 0), spread4(bits, 4), spread4(bits, 8), spread4(bits, 12)};
+}
+
+// 16 observation bytes at dst (16-byte aligned).
+__device__ __forceinline__ void store_obs(uint8_t *dst, u32x4 v) {
+    store_stream(dst, v.x, v.y, v.z, v.w);
+}
+
 }  // namespace octax

@@ -465,6 +465,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     // the host marks it in the block's ROM table (no ROM to stage).
     if (cfg.block_roms[blockIdx.x * 2] == kNoRom) return;
     const uint32_t live = active ? 1u : 0u;
+    const uint64_t live_bits = __builtin_amdgcn_ballot_w64(active);   // live slots of this wave
     const uint32_t wave_slot0 = blockIdx.x * IPW + wave_base;
     const uint32_t nj = (E > wave_slot0) ? min(64u, E - wave_slot0) : 0u;   // slots of this wave
 
@@ -659,6 +660,11 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             uint32_t pw[64];
             rows_to_cols(hi, lo);
             pack_frame(hi, lo, pw);
+            // frame 3 - d of observation k + d, at env 0
+            uint8_t *obs_slot[4];
+#pragma unroll
+            for (uint32_t d = 0; d < 4; d++)
+                obs_slot[d] = io.obs ? obs_of(k + d, 0) + (3 - d) * 2048 : nullptr;
             // Cooperative pass, a few envs per round: stage their packed frames,
             // then for each env store its frame into every observation it
             // belongs to and keep the last four frames of the launch in the
@@ -674,22 +680,38 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 wave_sync();
                 const uint32_t r1 = min(r0 + kStage, nj);
                 if (io.obs) {
-                    // The round's frames go into observation k + d of every
-                    // env of the round before observation k + d + 1: 2 KB
-                    // pieces 8 KB apart in one region at a time stream to HBM
-                    // faster than the four regions of one env in turn.
-                    uint32_t wj[kStage];
+                    // Each lane expands its 16 + 16 pixels of every staged
+                    // frame into bytes once, then the round's frames go into
+                    // observation k + d of every env of the round before
+                    // observation k + d + 1 (2 KB pieces 8 KB apart in one
+                    // region at a time).  The env's observation base is
+                    // wave-uniform, so a store is one scalar add and the
+                    // store itself.
+                    u32x4 x0[kStage], x1[kStage];
+                    uint64_t eo[kStage];   // observation offset of env r0 + jj
 #pragma unroll
-                    for (uint32_t jj = 0; jj < kStage; jj++) wj[jj] = sh.stage[wave][jj][lane64];
+                    for (uint32_t jj = 0; jj < kStage; jj++) {
+                        const uint32_t w = sh.stage[wave][jj][lane64];
+                        x0[jj] = spread16(w);
+                        x1[jj] = spread16(w >> 16);
+                        eo[jj] = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(env, r0 + jj) * kObsBytes;
+                    }
+                    // slots of the round that hold a live env (wave-uniform)
+                    const uint32_t rmask = (uint32_t)(live_bits >> r0) &
+                                           (__builtin_amdgcn_readfirstlane(r1 - r0) >= kStage
+                                                ? (1u << kStage) - 1
+                                                : (1u << __builtin_amdgcn_readfirstlane(r1 - r0)) - 1);
+                    const bool full = rmask == (1u << kStage) - 1;
 #pragma unroll
                     for (uint32_t d = 0; d < 4; d++) {
                         if (k + d >= K) break;
 #pragma unroll
                         for (uint32_t jj = 0; jj < kStage; jj++) {
-                            const uint32_t j = r0 + jj;
-                            if (j < r1 && __builtin_amdgcn_readlane(live, j))
-                                store_frame(obs_of(k + d, __builtin_amdgcn_readlane(env, j)) + (3 - d) * 2048,
-                                            lane64, wj[jj]);
+                            if (full || ((rmask >> jj) & 1)) {
+                                uint8_t *o = obs_slot[d] + eo[jj];
+                                store_obs(o + 16 * lane64, x0[jj]);
+                                store_obs(o + 1024 + 16 * lane64, x1[jj]);
+                            }
                         }
                     }
                 }
