@@ -61,13 +61,13 @@ struct Shared {
     uint64_t fb[IPW][kFbStride];
     uint8_t cache[IPW][cache_stride<IPW>()];
     uint32_t stage[IPW / 64][kStageEnvs][kStageStride];
+    uint8_t img[2][kMem];     // not last: a read one byte past a page stays inside the block's LDS
     uint32_t stack[IPW][9];
     float rew[IPW];           // reward and done bits of the step just emulated, for the writer waves
     uint8_t done[IPW];
     uint8_t key[2][IPW];      // held key of step k (slot k & 1), staged by the writer waves
     uint32_t ready[IPW / 64]; // steps emulated by emulator wave w
     uint32_t taken[IPW / 64]; // displays taken by writer wave w
-    uint8_t img[2][kMem];
 };
 
 // Memory of one env in the fused kernel.
@@ -108,7 +108,7 @@ struct FusedMem {
     // of v is zero exactly when slot s holds p (valid bit included), and the
     // lowest zero byte is found with the borrow test of a SWAR zero-byte scan.
     __device__ __forceinline__ int32_t find(uint32_t p) const {
-        const uint32_t v = (tags ^ ((p | 0x40u) * 0x01010101u)) & 0x7F7F7F7Fu;
+        const uint32_t v = (tags ^ __builtin_amdgcn_perm(0u, p | 0x40u, 0u)) & 0x7F7F7F7Fu;   // tag byte in all four bytes
         const uint32_t z = (v - 0x01010101u) & ~v & 0x80808080u;
         return z ? (int32_t)(__builtin_ctz(z | 0x80000000u) >> 3) : -1;
     }
@@ -217,14 +217,14 @@ struct FusedMem {
         return lds_page_sel(a >> 6, slow) + (a & 63);
     }
     // Instruction word at pc and, in the same LDS round trip, the return
-    // address stack[(sp - 1) & 15]; lanes whose code bytes are not in LDS
-    // take the fill path afterwards.
+    // address stack[(sp - 1) & 15].  Both code bytes are read from pc's page;
+    // lanes whose pc is the last byte of a page, or whose page is not in LDS,
+    // take the slow path afterwards.
     __device__ __forceinline__ uint32_t fetch(uint32_t pc, uint32_t sp, uint32_t &ret) {
         const uint32_t a1 = (pc + 1) & 0xFFF;
-        bool slow = false;
+        bool slow = (pc & 63) == 63;
         const lds_u8 *b0 = lds_byte(pc, slow);
-        const lds_u8 *b1 = lds_byte(a1, slow);
-        uint32_t op = ((uint32_t)*b0 << 8) | *b1;
+        uint32_t op = ((uint32_t)b0[0] << 8) | b0[1];
         ret = stack_get((sp - 1) & 15);
         if (slow) {
             make_resident(a1 >> 6, make_resident(pc >> 6, -1));
