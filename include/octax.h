@@ -63,7 +63,7 @@
 extern "C" {
 #endif
 
-#define OCTAX_ABI_VERSION 1u
+#define OCTAX_ABI_VERSION 2u
 #define OCTAX_QUIRKS_V1 1u
 
 #define OCTAX_MAX_ROM_BYTES 3584u   /* 0x200..0xFFF */
@@ -115,6 +115,26 @@ typedef struct octax_config {
     const uint32_t *h_horizon;     /* [E] truncation horizon, 0 = none */
     const uint64_t *h_env_seed;    /* [E] initial SplitMix64 state of each env */
     void *stream;                  /* hipStream_t for all work; NULL = null stream */
+    /* Environment wrappers (Section 3.2: start-up sequences that skip menus,
+     * no-op reset, sticky actions); zero / NULL turns each off.
+     *   sticky_q24: at every step the key held in the previous step is held
+     *     again with probability sticky_q24 / 2^24 (0..2^24); after a reset
+     *     the previous key is none.
+     *   every reset (automatic or octax_reset) runs, after power-on, one
+     *     environment step per entry of the env's ROM's start-up list with
+     *     that key held (h_startup_len [R] entries, 0..16, keys in
+     *     h_startup_keys [R][16], 0..15 or 16 = none), then a number of no-op
+     *     steps drawn uniformly from 0..noop_max (0..1000).  The frame stack
+     *     then holds the resulting display four times, the score baseline is
+     *     the score register, and terminations during these steps are ignored.
+     *   The draws come from the env's SplitMix64 stream: one at the start of
+     *     a step when sticky_q24 != 0, deciding (u >> 40) < sticky_q24; one
+     *     after the start-up steps when noop_max != 0, giving
+     *     ((u >> 32) * (noop_max + 1)) >> 32 no-op steps. */
+    uint32_t sticky_q24;
+    uint32_t noop_max;
+    const uint8_t *h_startup_len;   /* [R] or NULL */
+    const uint8_t *h_startup_keys;  /* [R][16] or NULL (with h_startup_len) */
 } octax_config;
 
 /* Architectural state of one env (get_state / set_state). */
@@ -125,7 +145,7 @@ typedef struct octax_env_state {
     uint8_t sp;             /* stack pointer 0..15 */
     uint8_t dt;             /* delay timer */
     uint8_t st;             /* sound timer */
-    uint8_t reserved;
+    uint8_t prev_key;       /* key held in the previous step (sticky actions), 16 = none */
     uint16_t stack[16];     /* return addresses */
     uint32_t t;             /* steps since the last reset */
     int32_t prev_score;     /* V[score_reg] after the previous step */
@@ -152,8 +172,9 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out);
  * Reset the envs whose d_mask byte is non-zero (all envs when d_mask is
  * NULL) to the power-on state of their ROM (Section 3.2, ROM loading and
  * initialization): memory = font + program, registers, I, stack and timers
- * zero, PC = 0x200, display and frame stack blank, step count zero.  Each
- * env's RNG stream continues.  If d_obs is not NULL the observation of every
+ * zero, PC = 0x200, display and frame stack blank, step count zero; then
+ * the reset steps of the wrappers, if any (see octax_config).  Each env's
+ * RNG stream continues.  If d_obs is not NULL the observation of every
  * env (reset or not) is written to d_obs [E][4][64][32].
  * d_mask: device uint8 [E] or NULL.  Errors: OCTAX_E_INVALID (NULL engine),
  * OCTAX_E_HIP.
@@ -284,6 +305,10 @@ typedef struct octax_pool_config {
     const uint8_t *h_term_reg;     /* [R] */
     const uint8_t *h_term_value;   /* [R] */
     void *stream;                  /* hipStream_t; NULL = null stream */
+    uint32_t sticky_q24;           /* environment wrappers, as in octax_config */
+    uint32_t noop_max;
+    const uint8_t *h_startup_len;  /* [R] or NULL */
+    const uint8_t *h_startup_keys; /* [R][16] or NULL */
 } octax_pool_config;
 
 typedef struct octax_pool octax_pool;

@@ -32,6 +32,27 @@
  * Parity notes: the font glyph bytes are the standard CHIP-8 hex font (the
  * paper fixes only their addresses); the RNG stream is pinned to the
  * published SplitMix64 definition, not to the paper's JAX keys.
+ *
+ * Environment wrappers (Section 3.2, "Environment integration": start-up
+ * sequences that skip menus, no-op reset and sticky actions).  The paper
+ * names them without defining them; the readings taken here:
+ *   - sticky actions: at every step, with probability sticky_q24 / 2^24, the
+ *     key held in the previous step is held again instead of the action's
+ *     key; after a reset the previous key is "none";
+ *   - start-up sequence: every reset runs, after power-on, one environment
+ *     step (frame_skip frames) per entry of the ROM's start-up list, with
+ *     that entry's key held;
+ *   - no-op reset: then a number of no-op steps (no key held) drawn
+ *     uniformly from 0..noop_max;
+ *   - after these steps the frame stack holds the resulting display four
+ *     times, the score baseline is the score register's value, and
+ *     terminations during them are ignored;
+ *   - the random draws come from the env's own SplitMix64 stream, in a fixed
+ *     order: one draw at the start of a step when sticky actions are on, one
+ *     draw after the start-up sequence when no-op reset is on.  A 64-bit draw
+ *     u decides stickiness as (u >> 40) < sticky_q24, and the no-op count is
+ *     ((u >> 32) * (noop_max + 1)) >> 32 (Lemire's multiply-shift range
+ *     reduction, without rejection).
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -89,7 +110,7 @@ typedef struct {
     uint8_t sp;
     uint8_t dt;
     uint8_t st;
-    uint8_t pad;
+    uint8_t prev_key;   /* key held in the previous step (sticky actions), 16 = none */
     uint16_t stack[STACK_DEPTH];
     uint32_t t;
     int32_t prev_score;
@@ -107,6 +128,7 @@ typedef struct {
     int32_t prev_score;
     uint16_t rom;
     uint32_t horizon;
+    int prev_key;                        /* key held in the previous step, -1 = none */
 } oracle_env;
 
 typedef struct {
@@ -121,6 +143,10 @@ typedef struct {
     uint8_t *term_value;
     int instr_per_frame;
     int frame_skip;
+    uint32_t sticky_q24;                 /* environment wrappers, off when zero */
+    uint32_t noop_max;
+    uint8_t *startup_len;                /* [R] */
+    uint8_t (*startup_keys)[16];         /* [R][16], 16 = no key */
     oracle_env *env;
 } oracle_batch;
 
@@ -359,13 +385,38 @@ void oracle_machine_tick(oracle_machine *m)
 /* Environment                                                          */
 /* ------------------------------------------------------------------ */
 
+/* One environment step's worth of emulation with `key` held (-1: none). */
+static void run_step_frames(const oracle_batch *b, oracle_machine *m, int key)
+{
+    for (int f = 0; f < b->frame_skip; f++) {
+        for (int k = 0; k < b->instr_per_frame; k++)
+            oracle_machine_execute(m, key);
+        oracle_machine_tick(m);
+    }
+}
+
+/* Reset: power-on, then the ROM's start-up sequence and the no-op steps of
+ * the no-op-reset wrapper (see the header). */
 static void env_reset(const oracle_batch *b, oracle_env *e)
 {
     oracle_machine_load(&e->m, b->rom[e->rom], b->rom_len[e->rom]);
+    if (b->startup_len) {
+        for (int i = 0; i < b->startup_len[e->rom]; i++) {
+            int k = b->startup_keys[e->rom][i];
+            run_step_frames(b, &e->m, k < 16 ? k : -1);
+        }
+    }
+    if (b->noop_max) {
+        uint64_t u = oracle_splitmix64_next(&e->m.rng);
+        uint64_t n = ((u >> 32) * ((uint64_t)b->noop_max + 1)) >> 32;
+        for (uint64_t i = 0; i < n; i++)
+            run_step_frames(b, &e->m, -1);
+    }
     for (int k = 0; k < 3; k++)
         memcpy(e->hist[k], e->m.disp, sizeof e->m.disp);
     e->t = 0;
     e->prev_score = e->m.v[b->score_reg[e->rom]];
+    e->prev_key = -1;
 }
 
 /* obs[k][x][y] for k = 0..3: the three stored frames then the display. */
@@ -386,15 +437,15 @@ static void env_step(const oracle_batch *b, oracle_env *e, int32_t action, uint8
     int key = -1;
     if (action >= 0 && action < b->num_actions[r])
         key = b->action_keys[r][action];
+    /* sticky actions: the previous step's key again with probability sticky_q24 / 2^24 */
+    if (b->sticky_q24 && (oracle_splitmix64_next(&e->m.rng) >> 40) < b->sticky_q24)
+        key = e->prev_key;
+    e->prev_key = key;
 
     uint8_t before[SCREEN_H][SCREEN_W];
     memcpy(before, e->m.disp, sizeof before);
 
-    for (int f = 0; f < b->frame_skip; f++) {
-        for (int k = 0; k < b->instr_per_frame; k++)
-            oracle_machine_execute(&e->m, key);
-        oracle_machine_tick(&e->m);
-    }
+    run_step_frames(b, &e->m, key);
 
     memcpy(e->hist[0], e->hist[1], sizeof before);
     memcpy(e->hist[1], e->hist[2], sizeof before);
@@ -480,7 +531,36 @@ void oracle_destroy(oracle_batch *b)
         return;
     free(b->rom); free(b->rom_len); free(b->action_keys); free(b->num_actions);
     free(b->score_reg); free(b->term_reg); free(b->term_value); free(b->env);
+    free(b->startup_len); free(b->startup_keys);
     free(b);
+}
+
+/* Configure the environment wrappers (all off after oracle_create).  They
+ * apply from the next reset and step on; callers reset after this.
+ * startup_len / startup_keys may be NULL (no start-up sequences). */
+int oracle_set_wrappers(oracle_batch *b, uint32_t sticky_q24, uint32_t noop_max,
+                        const uint8_t *startup_len, const uint8_t *startup_keys)
+{
+    if (sticky_q24 > (1u << 24) || noop_max > 1000)
+        return -1;
+    free(b->startup_len); free(b->startup_keys);
+    b->startup_len = NULL;
+    b->startup_keys = NULL;
+    if (startup_len) {
+        b->startup_len = calloc((size_t)b->num_roms, 1);
+        b->startup_keys = calloc((size_t)b->num_roms, sizeof *b->startup_keys);
+        if (!b->startup_len || !b->startup_keys)
+            return -2;
+        for (int r = 0; r < b->num_roms; r++) {
+            if (startup_len[r] > 16)
+                return -1;
+            b->startup_len[r] = startup_len[r];
+            memcpy(b->startup_keys[r], startup_keys + 16 * r, 16);
+        }
+    }
+    b->sticky_q24 = sticky_q24;
+    b->noop_max = noop_max;
+    return 0;
 }
 
 /* Reset the envs whose mask byte is non-zero (all when mask is NULL) and
@@ -576,6 +656,7 @@ void oracle_get_state(const oracle_batch *b, int first, int count, oracle_state 
         s->t = e->t;
         s->prev_score = e->prev_score;
         s->rng = e->m.rng;
+        s->prev_key = (uint8_t)(e->prev_key < 0 ? 16 : e->prev_key);
         memcpy(s->mem, e->m.mem, MEM_BYTES);
         memcpy(s->disp, e->m.disp, sizeof s->disp);
         memcpy(s->hist, e->hist, sizeof s->hist);
@@ -598,6 +679,7 @@ void oracle_set_state(oracle_batch *b, int first, int count, const oracle_state 
         e->t = s->t;
         e->prev_score = s->prev_score;
         e->m.rng = s->rng;
+        e->prev_key = s->prev_key < 16 ? s->prev_key : -1;
         memcpy(e->m.mem, s->mem, MEM_BYTES);
         for (int y = 0; y < SCREEN_H; y++)
             for (int x = 0; x < SCREEN_W; x++) {

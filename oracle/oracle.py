@@ -25,7 +25,7 @@ STATE_DTYPE = np.dtype([
     ("sp", np.uint8),
     ("dt", np.uint8),
     ("st", np.uint8),
-    ("pad", np.uint8),
+    ("prev_key", np.uint8),
     ("stack", np.uint16, (16,)),
     ("t", np.uint32),
     ("prev_score", np.int32),
@@ -78,6 +78,8 @@ def lib():
         L.oracle_splitmix64_next.restype = ctypes.c_uint64
         L.oracle_execute_batch.argtypes = [ctypes.c_uint16, i32, i32] + [P] * 7
         L.oracle_execute_states.argtypes = [P, i32, i32, i32]
+        L.oracle_set_wrappers.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, P, P]
+        L.oracle_set_wrappers.restype = i32
         assert L.oracle_state_size() == STATE_DTYPE.itemsize, "oracle_state layout mismatch"
         _lib = L
     return _lib
@@ -189,6 +191,15 @@ class OracleBatch:
         if not h:
             raise ValueError("oracle_create rejected the spec")
         self._h = h
+        if getattr(spec, "has_wrappers", False):
+            # wrappers act from the next reset on: configure, then reset all
+            sl = None if spec.startup_len is None else np.ascontiguousarray(spec.startup_len, dtype=np.uint8)
+            sk = None if spec.startup_keys is None else np.ascontiguousarray(spec.startup_keys, dtype=np.uint8)
+            self._keep.update(startup_len=sl, startup_keys=sk)
+            rc = lib().oracle_set_wrappers(h, int(spec.sticky_q24), int(spec.noop_max), _p(sl), _p(sk))
+            if rc != 0:
+                raise ValueError("oracle_set_wrappers rejected the spec")
+            lib().oracle_reset(h, None, None)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -240,5 +251,6 @@ def canonical(states: np.ndarray) -> Dict[str, np.ndarray]:
         "sp": states["sp"].astype(np.uint8), "dt": states["dt"].copy(), "st": states["st"].copy(),
         "stack": states["stack"].copy(), "t": states["t"].copy(),
         "prev_score": states["prev_score"].copy(), "rng": states["rng"].copy(),
+        "prev_key": states["prev_key"].copy(),
         "mem": states["mem"].copy(), "disp": states["disp"].copy(), "hist": states["hist"].copy(),
     }

@@ -26,6 +26,7 @@ struct Core {
     uint32_t dt;
     uint32_t st;
     uint64_t rng;
+    uint32_t pkey;   // key held in the previous step (sticky actions), kKeyNone after a reset
 };
 
 __device__ __forceinline__ void skip(Core &c) { c.pc = (c.pc + 2) & 0xFFF; }
@@ -197,6 +198,7 @@ __device__ __forceinline__ void load_core(const State &s, uint32_t slot, Core &c
     c.dt = (m >> 8) & 0xFF;
     c.st = (m >> 16) & 0xFF;
     head = (m >> 24) & 3;
+    c.pkey = ((m >> 26) & 31) ^ kKeyNone;
     c.rng = s.rng[slot];
 }
 
@@ -207,7 +209,7 @@ __device__ __forceinline__ void store_core(const State &s, uint32_t slot, const 
     s.regs[2 * E + slot] = c.r.w.z;
     s.regs[3 * E + slot] = c.r.w.w;
     s.pc_i[slot] = c.pc | (c.I << 16);
-    s.misc[slot] = c.sp | (c.dt << 8) | (c.st << 16) | (head << 24);
+    s.misc[slot] = c.sp | (c.dt << 8) | (c.st << 16) | (head << 24) | ((c.pkey ^ kKeyNone) << 26);
     s.rng[slot] = c.rng;
 }
 
@@ -219,6 +221,36 @@ __device__ __forceinline__ void reset_core(Core &c) {
     c.sp = 0;
     c.dt = 0;
     c.st = 0;
+    c.pkey = kKeyNone;
+}
+
+// Sticky actions (Section 3.2): with probability sticky_q24 / 2^24 the key
+// held in the previous step is held again instead of `key`.  One draw from
+// the env's SplitMix64 stream per step, only when the wrapper is on.
+__device__ __forceinline__ uint32_t sticky_key(const Roms &roms, Core &c, uint32_t key) {
+    if (roms.w.sticky_q24 && (uint32_t)(splitmix_next(c.rng) >> 40) < roms.w.sticky_q24) key = c.pkey;
+    c.pkey = key;
+    return key;
+}
+
+// The emulation steps of a reset, after power-on (Section 3.2): the ROM's
+// start-up sequence, one environment step per entry with its key held, then
+// the no-op reset's steps with no key held, their number drawn uniformly
+// from 0..noop_max by Lemire's multiply-shift on the top 32 bits of one
+// SplitMix64 draw.  step(key) runs one environment step.
+template <class StepFn>
+__device__ __forceinline__ void run_reset_steps(const Roms &roms, uint32_t rom, Core &c, StepFn step) {
+    if (roms.w.startup) {
+        const uint8_t *su = roms.w.startup + (size_t)rom * 17;
+        const uint32_t n = su[0];
+        for (uint32_t i = 0; i < n; i++) step((uint32_t)su[1 + i]);
+    }
+    if (roms.w.noop_max) {
+        const uint64_t u = splitmix_next(c.rng);
+        const uint32_t n = (uint32_t)(((u >> 32) * ((uint64_t)roms.w.noop_max + 1)) >> 32);
+        for (uint32_t i = 0; i < n; i++) step(kKeyNone);
+    }
+    c.pkey = kKeyNone;
 }
 
 // The held key of a step: the action's key, or none for the no-op and for

@@ -21,7 +21,7 @@ constexpr uint32_t kObsBytes = 8192;   // [4][64][32]
 struct State {
     uint32_t *regs;      // [4][E]  V0..V15, register 4w+b in byte b of regs[w][slot]
     uint32_t *pc_i;      // [E]     PC | I << 16
-    uint32_t *misc;      // [E]     SP | DT << 8 | ST << 16 | ring head << 24
+    uint32_t *misc;      // [E]     SP | DT << 8 | ST << 16 | ring head << 24 | (previous key ^ 16) << 26
     uint32_t *stack;     // [E][8]  16 return addresses, two per word (entry 2k in the low half)
     uint32_t *t;         // [E]     steps since reset
     int32_t *prev;       // [E]     V[score_reg] after the previous step
@@ -43,10 +43,23 @@ __device__ __forceinline__ bool slot_live(const State &s, uint32_t slot) {
 }
 
 // Per-ROM tables.
+// Environment wrappers (Section 3.2: start-up sequences that skip menus,
+// no-op reset, sticky actions), all off when zero / null, and the emulation
+// rate the steps of a reset run at.
+struct Wrap {
+    const uint8_t *startup;   // [R][17]: start-up steps (0..16), then the key held in each (16 = none)
+    uint32_t sticky_q24;      // P(the previous step's key is held again) * 2^24, 0..2^24
+    uint32_t noop_max;        // no-op steps after a reset: uniform in 0..noop_max
+    uint32_t reset_steps;     // nonzero when a reset runs emulation steps (start-up or no-op)
+    uint32_t ipf;             // instructions per frame
+    uint32_t frame_skip;      // frames per step
+};
+
 struct Roms {
     const uint8_t *image;    // [R][4096] power-on memory: font at 0x50, program at 0x200
     const uint8_t *keys;     // [R][16]
     const uint32_t *desc;    // [R] score_reg | term_reg << 8 | term_value << 16 | num_actions << 24
+    Wrap w;
 };
 
 // ---------------------------------------------------------------------------
@@ -88,14 +101,14 @@ __device__ __forceinline__ void set_vf(Regs &r, uint32_t f) { r.w.w = (r.w.w & 0
 // 64-bit finaliser (xor-shift 30, multiply, xor-shift 27, multiply,
 // xor-shift 31) of the new state.  CXNN keeps the top byte.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t rnd_byte(uint64_t &s) {
+__device__ __forceinline__ uint64_t splitmix_next(uint64_t &s) {
     s += 0x9E3779B97F4A7C15ull;
     uint64_t z = s;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z ^= z >> 31;
-    return (uint32_t)(z >> 56);
+    return z ^ (z >> 31);
 }
+__device__ __forceinline__ uint32_t rnd_byte(uint64_t &s) { return (uint32_t)(splitmix_next(s) >> 56); }
 
 // 16-byte observation store.  Plain stores: on MI355X they stream to HBM
 // faster than stores with the nontemporal hint (measured with the

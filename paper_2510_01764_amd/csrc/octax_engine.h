@@ -26,6 +26,7 @@ struct octax_engine {
     octax::State s{};
     octax::Roms roms{};
     uint32_t *d_block_roms = nullptr;                 // [blocks][2] for the current tuning
+    uint8_t *d_startup = nullptr;                     // [R][17] start-up sequences (Wrap::startup)
     uint32_t *d_slot_scratch = nullptr;               // slot lists for get/set_state
     octax::RawState *d_raw = nullptr;
     uint32_t raw_capacity = 0;
@@ -58,6 +59,14 @@ namespace octax {
 // Record the message of a failure for octax_last_error and return code.
 int32_t fail(int32_t code, const std::string &msg);
 int32_t hip_fail(hipError_t e, const char *what);
+
+// Check the environment-wrapper fields of a config and build the [R][17]
+// start-up table (count, then 16 keys); returns an error message or null.
+const char *check_wrappers(uint32_t sticky_q24, uint32_t noop_max, const uint8_t *h_startup_len,
+                           const uint8_t *h_startup_keys, uint32_t R, std::vector<uint8_t> &table);
+// The wrapper parameters of a Roms (d_table: the device copy of the table).
+Wrap make_wrap(const uint8_t *d_table, const std::vector<uint8_t> &table, uint32_t sticky_q24,
+               uint32_t noop_max, uint32_t ipf, uint32_t frame_skip);
 
 // Fill table[2b], table[2b+1] with the two most frequent ROMs among the
 // (occupied) slots of block b (0xFFFFFFFF = none); blocks of envs_per_block.

@@ -42,6 +42,39 @@ int32_t octax::hip_fail(hipError_t e, const char *what) {
     return fail(OCTAX_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+const char *octax::check_wrappers(uint32_t sticky_q24, uint32_t noop_max, const uint8_t *h_startup_len,
+                                  const uint8_t *h_startup_keys, uint32_t R, std::vector<uint8_t> &table) {
+    if (sticky_q24 > (1u << 24)) return "sticky_q24 > 2^24";
+    if (noop_max > 1000) return "noop_max > 1000";
+    if (!h_startup_len != !h_startup_keys) return "h_startup_len and h_startup_keys must both be given or both NULL";
+    table.assign(17 * (size_t)R, 0);
+    if (!h_startup_len) return nullptr;
+    for (uint32_t r = 0; r < R; r++) {
+        if (h_startup_len[r] > 16) return "start-up sequence longer than 16 steps";
+        table[17 * (size_t)r] = h_startup_len[r];
+        for (uint32_t i = 0; i < 16; i++) {
+            const uint8_t k = h_startup_keys[16 * (size_t)r + i];
+            if (i < h_startup_len[r] && k > 16) return "start-up key > 16";
+            table[17 * (size_t)r + 1 + i] = k > 16 ? 16 : k;
+        }
+    }
+    return nullptr;
+}
+
+octax::Wrap octax::make_wrap(const uint8_t *d_table, const std::vector<uint8_t> &table, uint32_t sticky_q24,
+                             uint32_t noop_max, uint32_t ipf, uint32_t frame_skip) {
+    Wrap w{};
+    bool any_startup = false;
+    for (size_t r = 0; r < table.size(); r += 17) any_startup = any_startup || table[r] > 0;
+    w.startup = any_startup ? d_table : nullptr;
+    w.sticky_q24 = sticky_q24;
+    w.noop_max = noop_max;
+    w.reset_steps = (any_startup || noop_max) ? 1u : 0u;
+    w.ipf = ipf;
+    w.frame_skip = frame_skip;
+    return w;
+}
+
 void octax::block_rom_table(const octax_engine *g, std::vector<uint32_t> &table) {
     const uint32_t ipw = g->envs_per_block;
     const uint32_t blocks = (g->E + ipw - 1) / ipw;
@@ -138,6 +171,7 @@ void raw_to_canonical(const RawState &r, octax_env_state &o) {
     o.dt = (uint8_t)(r.misc >> 8);
     o.st = (uint8_t)(r.misc >> 16);
     const uint32_t head = (r.misc >> 24) & 3;
+    o.prev_key = (uint8_t)(((r.misc >> 26) & 31) ^ 16);
     for (int k = 0; k < 16; k++) o.stack[k] = (uint16_t)((r.stack[k >> 1] >> (16 * (k & 1))) & 0xFFFF);
     o.t = r.t;
     o.prev_score = r.prev;
@@ -159,7 +193,8 @@ void canonical_to_raw(const octax_env_state &o, RawState &r) {
     for (int k = 0; k < 16; k++) r.regs[k >> 2] |= (uint32_t)o.v[k] << (8 * (k & 3));
     r.pc_i = (o.pc & 0xFFFu) | ((uint32_t)(o.i & 0xFFFu) << 16);
     const uint32_t head = 3;
-    r.misc = (o.sp & 15u) | ((uint32_t)o.dt << 8) | ((uint32_t)o.st << 16) | (head << 24);
+    r.misc = (o.sp & 15u) | ((uint32_t)o.dt << 8) | ((uint32_t)o.st << 16) | (head << 24) |
+             (((o.prev_key < 16 ? o.prev_key : 16u) ^ 16u) << 26);
     for (int k = 0; k < 16; k++) r.stack[k >> 1] |= (uint32_t)(o.stack[k] & 0xFFFu) << (16 * (k & 1));
     r.t = o.t;
     r.prev = o.prev_score;
@@ -212,6 +247,10 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     }
     for (uint32_t e = 0; e < E; e++)
         if (cfg->h_env_rom[e] >= R) return fail(OCTAX_E_INVALID, "octax_create: env_rom >= num_roms");
+    std::vector<uint8_t> startup;
+    if (const char *err = octax::check_wrappers(cfg->sticky_q24, cfg->noop_max, cfg->h_startup_len,
+                                                cfg->h_startup_keys, R, startup))
+        return fail(OCTAX_E_INVALID, std::string("octax_create: ") + err);
 
     octax_engine *g = new (std::nothrow) octax_engine;
     if (!g) return fail(OCTAX_E_NOMEM, "octax_create: out of host memory");
@@ -286,6 +325,8 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     TRY(g->alloc(&d_img, (size_t)R * kMem));
     TRY(g->alloc(&d_keys, 16 * (size_t)R));
     TRY(g->alloc(&d_desc, R));
+    TRY(g->alloc(&g->d_startup, startup.size()));
+    TRY(hipMemcpy(g->d_startup, startup.data(), startup.size(), hipMemcpyHostToDevice));
     TRY(hipMemcpy(rom_of, g->rom_of.data(), 4 * (size_t)E, hipMemcpyHostToDevice));
     TRY(hipMemcpy(hor, horizon.data(), 4 * (size_t)E, hipMemcpyHostToDevice));
     TRY(hipMemcpy(env_of, g->env_of.data(), 4 * (size_t)E, hipMemcpyHostToDevice));
@@ -300,6 +341,7 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     g->roms.image = d_img;
     g->roms.keys = d_keys;
     g->roms.desc = d_desc;
+    g->roms.w = octax::make_wrap(g->d_startup, startup, cfg->sticky_q24, cfg->noop_max, g->ipf, g->frame_skip);
     TRY(upload_block_roms(g));
     TRY(launch_reset(g->s, g->roms, nullptr, true, g->stream));
     TRY(hipStreamSynchronize(g->stream));

@@ -38,6 +38,11 @@ hipError_t launch_reset(const State &s, const Roms &r, const uint8_t *mask, bool
 // The same for slots [first, first + count) only.
 hipError_t launch_reset_range(const State &s, const Roms &r, const uint8_t *mask, bool full_ram,
                               uint32_t first, uint32_t count, hipStream_t st);
+// The emulation steps of a reset (start-up sequence, no-op reset) after
+// power-on, for the slots of [first, first + count) selected by mask; a no-op
+// when the wrappers run no steps.  launch_reset_range calls it.
+hipError_t launch_reset_steps(const State &s, const Roms &r, const uint8_t *mask, uint32_t first,
+                              uint32_t count, hipStream_t st);
 // Write the observation of every env from its frame ring.
 hipError_t launch_observe(const State &s, uint8_t *obs, hipStream_t st);
 

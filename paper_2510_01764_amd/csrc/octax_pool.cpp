@@ -137,6 +137,10 @@ int32_t octax_pool_create(const octax_pool_config *cfg, octax_pool **out) {
     ec.h_horizon = horizon.data();
     ec.h_env_seed = seed.data();
     ec.stream = cfg->stream;
+    ec.sticky_q24 = cfg->sticky_q24;
+    ec.noop_max = cfg->noop_max;
+    ec.h_startup_len = cfg->h_startup_len;
+    ec.h_startup_keys = cfg->h_startup_keys;
 
     octax_pool *p = new (std::nothrow) octax_pool;
     if (!p) return fail(OCTAX_E_NOMEM, "octax_pool_create: out of host memory");

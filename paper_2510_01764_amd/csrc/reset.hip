@@ -81,7 +81,9 @@ hipError_t launch_reset_range(const State &s, const Roms &r, const uint8_t *mask
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reset_regs_kernel, dim3((count + 255) / 256), dim3(256), 0, st, s, mask, first, count);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reset_steps(s, r, mask, first, count, st);
 }
 
 hipError_t launch_observe(const State &s, uint8_t *obs, hipStream_t st) {

@@ -601,7 +601,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             // the display of step k - 1 must have been copied before it changes
             if (k > 0) wait_flag(&sh.taken[wave], k);
             if (active) {
-                const uint32_t key = sh.key[k & 1][l];
+                const uint32_t key = sticky_key(roms, c, sh.key[k & 1][l]);
                 for (uint32_t f = 0; f < io.frame_skip; f++) {
                     for (uint32_t i = 0; i < io.ipf; i++) exec_grouped(c, mem, key);
                     tick(c);
@@ -620,9 +620,17 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                     reset_core(c);
                     mem.clear();
                     for (int q = 0; q < 8; q++) sh.stack[l][q] = 0;
+                    if (roms.w.reset_steps) {
+                        run_reset_steps(roms, rom, c, [&](uint32_t rkey) {
+                            for (uint32_t f = 0; f < io.frame_skip; f++) {
+                                for (uint32_t i = 0; i < io.ipf; i++) exec_grouped(c, mem, rkey);
+                                tick(c);
+                            }
+                        });
+                    }
                     head = 0;
                     t = 0;
-                    prev = 0;
+                    prev = (int32_t)vget(c.r, desc & 15);   // the score after the reset's steps
                 } else {
                     prev = score;
                     head = (head + 1) & 3;
@@ -722,24 +730,26 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                     if (io.obs) {
                         const uint32_t je = __builtin_amdgcn_readlane(env, j);
                         if (jdone) {
-                            // the frames before the reset belong to the old episode
+                            // the frames before the reset belong to the old episode:
+                            // the stack restarts with the display after the reset
 #pragma unroll
                             for (uint32_t d = 0; d < 3; d++)
 #pragma unroll
                                 for (uint32_t f = 0; f < 3 - d; f++)
-                                    if (k + d < K) store_frame(obs_of(k + d, je) + f * 2048, lane64, 0);
+                                    if (k + d < K) store_frame(obs_of(k + d, je) + f * 2048, lane64, w);
                         }
                     }
                     // the last four frames of the launch stay in the ring; a
-                    // reset blanks the three slots before the new head
+                    // reset fills the three slots before the new head with
+                    // the display after the reset
                     if (ring_step) {
                         const uint32_t jh = __builtin_amdgcn_readlane(head, j);
                         uint32_t *ring = s.cols + (size_t)(wave_slot0 + j) * 256 + lane64;
                         ring[jh * 64] = w;
                         if (jdone) {
-                            ring[((jh + 1) & 3) * 64] = 0;
-                            ring[((jh + 2) & 3) * 64] = 0;
-                            ring[((jh + 3) & 3) * 64] = 0;
+                            ring[((jh + 1) & 3) * 64] = w;
+                            ring[((jh + 2) & 3) * 64] = w;
+                            ring[((jh + 3) & 3) * 64] = w;
                         }
                     }
                 }

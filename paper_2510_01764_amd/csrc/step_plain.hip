@@ -62,6 +62,27 @@ struct PlainMem {
     }
 };
 
+// One environment step of emulation with `key` held.
+__device__ __forceinline__ void plain_env_step(Core &c, PlainMem &mem, uint32_t key, uint32_t ipf, uint32_t fs) {
+    for (uint32_t f = 0; f < fs; f++) {
+        for (uint32_t i = 0; i < ipf; i++) exec_one(c, mem, key);
+        tick(c);
+    }
+}
+
+// The display in frame-ring order (see pack_frame).
+__device__ __forceinline__ void pack_display(const uint64_t *fb, uint32_t pw[64]) {
+    uint32_t hi[32], lo[32];
+#pragma unroll
+    for (int r = 0; r < 32; r++) {
+        const uint64_t row = fb[31 - r];
+        hi[r] = (uint32_t)(row >> 32);
+        lo[r] = (uint32_t)row;
+    }
+    rows_to_cols(hi, lo);
+    pack_frame(hi, lo, pw);
+}
+
 __global__ __launch_bounds__(256) void step_plain_kernel(State s, Roms roms, StepIO io, uint32_t k) {
     const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
     if (!slot_live(s, slot)) return;
@@ -73,14 +94,11 @@ __global__ __launch_bounds__(256) void step_plain_kernel(State s, Roms roms, Ste
     Core c;
     uint32_t head;
     load_core(s, slot, c, head);
-    const uint32_t key = action_key(roms, rom, desc, io.action[(size_t)k * E + env]);
+    const uint32_t key = sticky_key(roms, c, action_key(roms, rom, desc, io.action[(size_t)k * E + env]));
     PlainMem mem{s.ram + (size_t)slot * kMem, s.fb + (size_t)slot * 32, s.stack + (size_t)slot * 8,
                  s.dirty[slot]};
 
-    for (uint32_t f = 0; f < io.frame_skip; f++) {
-        for (uint32_t i = 0; i < io.ipf; i++) exec_one(c, mem, key);
-        tick(c);
-    }
+    plain_env_step(c, mem, key, io.ipf, io.frame_skip);
 
     const int32_t score = (int32_t)vget(c.r, desc & 15);
     int32_t prev = s.prev[slot];
@@ -97,7 +115,8 @@ __global__ __launch_bounds__(256) void step_plain_kernel(State s, Roms roms, Ste
     uint8_t *obs = io.obs ? io.obs + ((size_t)(k % io.obs_slots) * E + env) * kObsBytes : nullptr;
     if (done) {
         // Automatic reset (Section 3.4): restore the pages written since the
-        // last reset, clear everything else; the RNG stream continues.
+        // last reset, clear everything else; the RNG stream continues.  Then
+        // the reset's emulation steps (start-up sequence, no-op reset).
         const uint8_t *img = roms.image + (size_t)rom * kMem;
         uint64_t d = mem.dirty;
         while (d) {
@@ -111,47 +130,43 @@ __global__ __launch_bounds__(256) void step_plain_kernel(State s, Roms roms, Ste
         reset_core(c);
         mem.clear();
         for (int q = 0; q < 8; q++) mem.stack[q] = 0;
-        uint4 *r4 = reinterpret_cast<uint4 *>(ring);
-        for (int q = 0; q < 64; q++) r4[q] = make_uint4(0, 0, 0, 0);
+        if (roms.w.reset_steps)
+            run_reset_steps(roms, rom, c, [&](uint32_t rk) { plain_env_step(c, mem, rk, io.ipf, io.frame_skip); });
         head = 0;
         t = 0;
-        prev = 0;
-        if (obs) {
-            for (int q = 0; q < 512; q++) store_stream(obs + 16 * q, 0, 0, 0, 0);
-        }
+        prev = (int32_t)vget(c.r, desc & 15);   // the score after the reset's steps
     } else {
         prev = score;
-        uint32_t hi[32], lo[32];
-#pragma unroll
-        for (int r = 0; r < 32; r++) {
-            const uint64_t row = mem.fb[31 - r];
-            hi[r] = (uint32_t)(row >> 32);
-            lo[r] = (uint32_t)row;
-        }
-        rows_to_cols(hi, lo);
-        uint32_t pw[64];
-        pack_frame(hi, lo, pw);
         head = (head + 1) & 3;
-        uint4 *dst = reinterpret_cast<uint4 *>(ring + head * 64);
+    }
+    uint32_t pw[64];
+    pack_display(mem.fb, pw);
+    // The frame ring gets the new display; after a reset the stack restarts
+    // with it in all four slots.
 #pragma unroll
-        for (int q = 0; q < 16; q++) dst[q] = make_uint4(pw[4 * q], pw[4 * q + 1], pw[4 * q + 2], pw[4 * q + 3]);
-        if (obs) {
-            // frames 0..2: the three older ring entries, oldest first
-            for (uint32_t fr = 0; fr < 3; fr++) {
-                const uint32_t *src = ring + ((head + 1 + fr) & 3) * 64;
-                uint8_t *o = obs + fr * 2048;
-                for (int w = 0; w < 64; w++) {
-                    const uint32_t word = src[w];
-                    store16(o + 16 * w, word & 0xFFFF);
-                    store16(o + 1024 + 16 * w, word >> 16);
-                }
-            }
-            uint8_t *o = obs + 3 * 2048;
+    for (uint32_t q = 0; q < 4; q++) {
+        if (done || q == head) {
+            uint4 *dst = reinterpret_cast<uint4 *>(ring + q * 64);
 #pragma unroll
+            for (int w = 0; w < 16; w++) dst[w] = make_uint4(pw[4 * w], pw[4 * w + 1], pw[4 * w + 2], pw[4 * w + 3]);
+        }
+    }
+    if (obs) {
+        // frames 0..2: the three older ring entries, oldest first, then the display
+        for (uint32_t fr = 0; fr < 3; fr++) {
+            const uint32_t *src = ring + ((head + 1 + fr) & 3) * 64;
+            uint8_t *o = obs + fr * 2048;
             for (int w = 0; w < 64; w++) {
-                store16(o + 16 * w, pw[w] & 0xFFFF);
-                store16(o + 1024 + 16 * w, pw[w] >> 16);
+                const uint32_t word = src[w];
+                store16(o + 16 * w, word & 0xFFFF);
+                store16(o + 1024 + 16 * w, word >> 16);
             }
+        }
+        uint8_t *o = obs + 3 * 2048;
+#pragma unroll
+        for (int w = 0; w < 64; w++) {
+            store16(o + 16 * w, pw[w] & 0xFFFF);
+            store16(o + 1024 + 16 * w, pw[w] >> 16);
         }
     }
     store_core(s, slot, c, head);
@@ -160,7 +175,42 @@ __global__ __launch_bounds__(256) void step_plain_kernel(State s, Roms roms, Ste
     s.dirty[slot] = mem.dirty;
 }
 
+// The emulation steps of a reset (start-up sequence, no-op reset) for the
+// slots [first, first + count) whose env has mask[env] != 0, after power-on;
+// then the score baseline and the frame ring (the display four times).
+__global__ __launch_bounds__(256) void reset_steps_kernel(State s, Roms roms, const uint8_t *mask,
+                                                          uint32_t first, uint32_t count) {
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= count) return;
+    const uint32_t slot = first + k;
+    if (slot >= s.num) return;
+    if (mask && !mask[s.env_of[slot]]) return;
+    const uint32_t rom = s.rom_of[slot];
+    const uint32_t desc = roms.desc[rom];
+    Core c;
+    uint32_t head;
+    load_core(s, slot, c, head);
+    PlainMem mem{s.ram + (size_t)slot * kMem, s.fb + (size_t)slot * 32, s.stack + (size_t)slot * 8,
+                 s.dirty[slot]};
+    run_reset_steps(roms, rom, c, [&](uint32_t rk) { plain_env_step(c, mem, rk, roms.w.ipf, roms.w.frame_skip); });
+    uint32_t pw[64];
+    pack_display(mem.fb, pw);
+    uint4 *ring = reinterpret_cast<uint4 *>(s.cols + (size_t)slot * 256);
+    for (uint32_t q = 0; q < 4; q++)
+        for (int w = 0; w < 16; w++) ring[q * 16 + w] = make_uint4(pw[4 * w], pw[4 * w + 1], pw[4 * w + 2], pw[4 * w + 3]);
+    store_core(s, slot, c, head);
+    s.prev[slot] = (int32_t)vget(c.r, desc & 15);
+    s.dirty[slot] = mem.dirty;
+}
+
 }  // namespace
+
+hipError_t launch_reset_steps(const State &s, const Roms &r, const uint8_t *mask, uint32_t first,
+                              uint32_t count, hipStream_t st) {
+    if (count == 0 || !r.w.reset_steps) return hipSuccess;
+    hipLaunchKernelGGL(reset_steps_kernel, dim3((count + 255) / 256), dim3(256), 0, st, s, r, mask, first, count);
+    return hipGetLastError();
+}
 
 hipError_t launch_step_plain(const State &s, const Roms &r, const StepIO &io, hipStream_t st) {
     const uint32_t blocks = (s.num + 255) / 256;

@@ -16,7 +16,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liboctax.so")
 
-OCTAX_ABI_VERSION = 1
+OCTAX_ABI_VERSION = 2
 OCTAX_QUIRKS_V1 = 1
 OCTAX_OK = 0
 OCTAX_E_INVALID = -1
@@ -59,6 +59,8 @@ class octax_config(ctypes.Structure):
         ("h_score_reg", ctypes.c_void_p), ("h_term_reg", ctypes.c_void_p),
         ("h_term_value", ctypes.c_void_p), ("h_horizon", ctypes.c_void_p),
         ("h_env_seed", ctypes.c_void_p), ("stream", ctypes.c_void_p),
+        ("sticky_q24", ctypes.c_uint32), ("noop_max", ctypes.c_uint32),
+        ("h_startup_len", ctypes.c_void_p), ("h_startup_keys", ctypes.c_void_p),
     ]
 
 
@@ -73,18 +75,31 @@ class octax_pool_config(ctypes.Structure):
         ("h_num_actions", ctypes.c_void_p), ("h_score_reg", ctypes.c_void_p),
         ("h_term_reg", ctypes.c_void_p), ("h_term_value", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
+        ("sticky_q24", ctypes.c_uint32), ("noop_max", ctypes.c_uint32),
+        ("h_startup_len", ctypes.c_void_p), ("h_startup_keys", ctypes.c_void_p),
     ]
 
 
 # octax_env_state as a numpy structured dtype (C layout, natural alignment).
 ENV_STATE_DTYPE = np.dtype([
     ("v", np.uint8, (16,)), ("i", np.uint16), ("pc", np.uint16), ("sp", np.uint8),
-    ("dt", np.uint8), ("st", np.uint8), ("reserved", np.uint8), ("stack", np.uint16, (16,)),
+    ("dt", np.uint8), ("st", np.uint8), ("prev_key", np.uint8), ("stack", np.uint16, (16,)),
     ("t", np.uint32), ("prev_score", np.int32), ("rng", np.uint64), ("ram", np.uint8, (4096,)),
     ("fb", np.uint64, (32,)), ("hist", np.uint64, (3, 32)),
 ], align=True)
 
 _lib = None
+
+
+def _set_wrappers(cfg, spec, keep: dict) -> None:
+    """The environment-wrapper fields of a config from a spec (all off when absent)."""
+    cfg.sticky_q24 = int(getattr(spec, "sticky_q24", 0))
+    cfg.noop_max = int(getattr(spec, "noop_max", 0))
+    if getattr(spec, "startup_len", None) is not None:
+        keep["startup_len"] = np.ascontiguousarray(spec.startup_len, dtype=np.uint8)
+        keep["startup_keys"] = np.ascontiguousarray(spec.startup_keys, dtype=np.uint8)
+        cfg.h_startup_len = keep["startup_len"].ctypes.data
+        cfg.h_startup_keys = keep["startup_keys"].ctypes.data
 
 
 def library() -> ctypes.CDLL:
@@ -226,6 +241,7 @@ class Engine:
         cfg.h_horizon = keep["hor"].ctypes.data
         cfg.h_env_seed = keep["seed"].ctypes.data
         cfg.stream = _stream_handle(stream)
+        _set_wrappers(cfg, spec, keep)
         h = ctypes.c_void_p()
         _check(L.octax_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -386,6 +402,8 @@ class Pool:
         cfg.h_term_reg = keep["treg"].ctypes.data
         cfg.h_term_value = keep["tval"].ctypes.data
         cfg.stream = _stream_handle(stream)
+        _set_wrappers(cfg, spec, keep)
+        self._keep = keep
         h = ctypes.c_void_p()
         _check(L.octax_pool_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -451,6 +469,7 @@ def canonical(states: np.ndarray) -> dict:
         "sp": states["sp"].astype(np.uint8), "dt": states["dt"].copy(), "st": states["st"].copy(),
         "stack": states["stack"].copy(), "t": states["t"].copy(),
         "prev_score": states["prev_score"].copy(), "rng": states["rng"].copy(),
+        "prev_key": states["prev_key"].copy(),
         "mem": states["ram"].copy(), "disp": unpack_rows(states["fb"]),
         "hist": unpack_rows(states["hist"]),
     }

@@ -218,6 +218,18 @@ class EnvSpec:
     frame_skip: int
     steps: int                   # length of the workload's run
     action_seed: int
+    # Environment wrappers (Section 3.2), all off by default: sticky-action
+    # probability in units of 2^-24, the no-op-reset maximum, and per ROM a
+    # start-up sequence of held keys (one env step each, 16 = no key).
+    sticky_q24: int = 0
+    noop_max: int = 0
+    startup_len: Optional[np.ndarray] = None    # uint8 [R], 0..16
+    startup_keys: Optional[np.ndarray] = None   # uint8 [R, 16]
+
+    @property
+    def has_wrappers(self) -> bool:
+        return bool(self.sticky_q24 or self.noop_max or
+                    (self.startup_len is not None and int(np.max(self.startup_len, initial=0)) > 0))
 
     @property
     def num_envs(self) -> int:

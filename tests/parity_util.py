@@ -1,7 +1,7 @@
 """Side-by-side runs of the HIP engine and the CPU oracle on the same inputs."""
 import numpy as np
 
-FIELDS = ("v", "i", "pc", "sp", "dt", "st", "stack", "t", "prev_score", "rng", "mem", "disp", "hist")
+FIELDS = ("v", "i", "pc", "sp", "dt", "st", "stack", "t", "prev_score", "rng", "prev_key", "mem", "disp", "hist")
 
 
 def compare_states(gpu_states, oracle_states, where=""):

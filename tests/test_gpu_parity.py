@@ -240,7 +240,7 @@ def test_snapshot_restore_continues_exactly():
     ost = orc.get_state()
     from paper_2510_01764_amd.octax import canonical
     c = canonical(snap)
-    for f in ("v", "i", "pc", "sp", "dt", "st", "stack", "t", "prev_score", "rng"):
+    for f in ("v", "i", "pc", "sp", "dt", "st", "stack", "t", "prev_score", "rng", "prev_key"):
         ost[f] = c[f]
     ost["mem"] = c["mem"]
     ost["disp"] = c["disp"]
