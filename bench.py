@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-wrappers", action="store_true",
+                    help="skip the leg with sticky actions, no-op reset and start-up sequences")
     ap.add_argument("--tune", choices=["auto", "default"], default="auto")
     ap.add_argument("--serving-groups", type=int, default=2000,
                     help="groups of the serving run (0 = skip it)")
@@ -243,6 +245,29 @@ def main():
         gp.close()
         engp.close()
 
+    # the same workload with the environment wrappers of Section 3.2 on
+    wrappers = None
+    if not args.no_wrappers:
+        wspec = W.with_wrappers(spec, sticky=0.25, noop_max=30, startup_max=3, seed=1)
+        engw = X.Engine(wspec, kernel="fused", envs_per_block=tuning["envs_per_block"],
+                        rom_in_lds=tuning["rom_in_lds"], stream=stream)
+        gw = engw.graph(act, obs, rew, done)
+        time_replays(torch, stream, gw, act, act_pool, 1, 0)
+        stream.synchronize()
+        n_w = max(2, args.steps // 4)
+        t0 = time.perf_counter()
+        time_replays(torch, stream, gw, act, act_pool, n_w, args.warmup)
+        stream.synchronize()
+        wwall = time.perf_counter() - t0
+        resets = float((done != 0).float().mean().item())
+        wrappers = {"value": E * K * n_w / wwall, "ms_per_step": wwall * 1e3 / n_w, "replays": n_w,
+                    "sticky_prob": 0.25, "noop_max": 30,
+                    "startup_steps": [int(x) for x in wspec.startup_len],
+                    "resets_per_env_step": resets}
+        log(f"wrappers: {wrappers['value'] / 1e6:.1f} M env steps/s ({wrappers['ms_per_step']:.2f} ms per replay)")
+        gw.close()
+        engw.close()
+
     serving = None
     if args.serving_groups > 0:
         serving = serving_run(args, lat, log)
@@ -281,6 +306,7 @@ def main():
         "replay_ms_p99": float(np.percentile(replay_ms, 99)),
         "plain": plain,
         "fused_over_plain": (value / plain["value"]) if plain else None,
+        "wrappers": wrappers,
         "calib_write_GBs": write_gbs,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

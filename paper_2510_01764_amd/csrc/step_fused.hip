@@ -447,8 +447,10 @@ __device__ __forceinline__ void store_frame(uint8_t *frame, uint32_t lane64, uin
 //
 // kRollout separates the K-step launches (graph-captured rollouts) from the
 // K = 1 launches of octax_step into two instantiations of the same code, so
-// profiles report them apart.
-template <int IPW, bool kRollout>
+// profiles report them apart.  kResetSteps instantiates the emulation steps
+// of a reset (start-up sequence, no-op reset); without those wrappers the
+// kernel carries no second copy of the instruction cycle.
+template <int IPW, bool kRollout, bool kResetSteps>
 __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms, StepIO io, FusedCfg cfg) {
     __shared__ Shared<IPW> sh;
     const uint32_t tid = threadIdx.x;
@@ -620,7 +622,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                     reset_core(c);
                     mem.clear();
                     for (int q = 0; q < 8; q++) sh.stack[l][q] = 0;
-                    if (roms.w.reset_steps) {
+                    if (kResetSteps) {
                         run_reset_steps(roms, rom, c, [&](uint32_t rkey) {
                             for (uint32_t f = 0; f < io.frame_skip; f++) {
                                 for (uint32_t i = 0; i < io.ipf; i++) exec_grouped(c, mem, rkey);
@@ -778,14 +780,19 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     }
 }
 
-template <int IPW>
-hipError_t launch_ipw(const State &s, const Roms &r, const StepIO &io, const FusedCfg &f, hipStream_t st) {
+template <int IPW, bool kResetSteps>
+hipError_t launch_variant(const State &s, const Roms &r, const StepIO &io, const FusedCfg &f, hipStream_t st) {
     const uint32_t blocks = (s.num + IPW - 1) / IPW;
     if (io.K == 1)
-        hipLaunchKernelGGL((step_fused_kernel<IPW, false>), dim3(blocks), dim3(2 * IPW), 0, st, s, r, io, f);
+        hipLaunchKernelGGL((step_fused_kernel<IPW, false, kResetSteps>), dim3(blocks), dim3(2 * IPW), 0, st, s, r, io, f);
     else
-        hipLaunchKernelGGL((step_fused_kernel<IPW, true>), dim3(blocks), dim3(2 * IPW), 0, st, s, r, io, f);
+        hipLaunchKernelGGL((step_fused_kernel<IPW, true, kResetSteps>), dim3(blocks), dim3(2 * IPW), 0, st, s, r, io, f);
     return hipGetLastError();
+}
+
+template <int IPW>
+hipError_t launch_ipw(const State &s, const Roms &r, const StepIO &io, const FusedCfg &f, hipStream_t st) {
+    return r.w.reset_steps ? launch_variant<IPW, true>(s, r, io, f, st) : launch_variant<IPW, false>(s, r, io, f, st);
 }
 
 }  // namespace

@@ -3,7 +3,7 @@
   python -m paper_2510_01764_amd.profile_summary stats <rocprof dir> <out.txt> --command "..."
       per-kernel call count and duration statistics (from --kernel-trace --stats)
   python -m paper_2510_01764_amd.profile_summary traffic <fetch dir> <write dir> <out.json>
-      --calib-bytes N --kernel step_fused_kernel<256, true> --command-fetch "..." --command-write "..."
+      --calib-bytes N --kernel "step_fused_kernel<256, true, false>" --command-fetch "..." --command-write "..."
       HBM bytes per launch of one kernel from FETCH_SIZE and WRITE_SIZE counter runs, each
       scaled by what the same counter reads for the calibration copy kernel of known size.
 """

@@ -262,6 +262,26 @@ class EnvSpec:
             env_seed=self.env_seed[envs].copy())
 
 
+def with_wrappers(spec: EnvSpec, sticky: float = 0.25, noop_max: int = 30, startup_max: int = 3,
+                  seed: int = 0) -> EnvSpec:
+    """The spec with the environment wrappers of Section 3.2 switched on.
+
+    Sticky actions with probability ``sticky`` (rounded to a multiple of
+    2^-24), no-op reset with up to ``noop_max`` no-op steps, and per ROM a
+    start-up sequence of 0..startup_max steps, each holding one of the ROM's
+    action keys or none, drawn from ``seed``.
+    """
+    R = spec.num_roms
+    rng = np.random.Generator(np.random.PCG64([seed, 11]))
+    lens = rng.integers(0, startup_max + 1, size=R).astype(np.uint8)
+    akeys = np.asarray(spec.action_keys)
+    nact = np.asarray(spec.num_actions).astype(np.int64)
+    picks = (rng.random((R, 16)) * (nact[:, None] + 1)).astype(np.int64)   # nact = no key
+    keys = np.where(picks < nact[:, None], akeys[np.arange(R)[:, None], np.minimum(picks, 15)], 16)
+    return dataclasses.replace(spec, sticky_q24=int(round(sticky * (1 << 24))), noop_max=int(noop_max),
+                               startup_len=lens, startup_keys=keys.astype(np.uint8))
+
+
 def _descriptors(n_roms: int, keys: Sequence[Sequence[int]]):
     action_keys = np.zeros((n_roms, 16), dtype=np.uint8)
     num_actions = np.zeros(n_roms, dtype=np.uint8)

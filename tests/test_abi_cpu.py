@@ -36,8 +36,9 @@ def test_struct_layouts_match_header():
     import subprocess
     import tempfile
     src = ('#include <stdio.h>\n#include <stddef.h>\n#include "octax.h"\n'
-           'int main(){printf("%zu %zu %zu %zu\\n", sizeof(octax_config), sizeof(octax_env_state),'
-           ' offsetof(octax_env_state, ram), offsetof(octax_config, h_rom_data));}\n')
+           'int main(){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(octax_config), sizeof(octax_env_state),'
+           ' offsetof(octax_env_state, ram), offsetof(octax_config, h_rom_data),'
+           ' offsetof(octax_config, sticky_q24), offsetof(octax_env_state, prev_key));}\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
@@ -48,6 +49,8 @@ def test_struct_layouts_match_header():
     assert int(out[1]) == X.ENV_STATE_DTYPE.itemsize
     assert int(out[2]) == X.ENV_STATE_DTYPE.fields["ram"][1]
     assert int(out[3]) == X.octax_config.h_rom_data.offset
+    assert int(out[4]) == X.octax_config.sticky_q24.offset
+    assert int(out[5]) == X.ENV_STATE_DTYPE.fields["prev_key"][1]
 
 
 def _cfg(**over):
@@ -82,6 +85,25 @@ def test_create_rejects_bad_config_without_gpu(field, value):
     rc = L.octax_create(ctypes.byref(c), ctypes.byref(h))
     assert rc == X.OCTAX_E_INVALID and not h.value
     assert L.octax_last_error().decode()
+
+
+def test_create_rejects_bad_wrappers_without_gpu():
+    import numpy as np
+    L = X.library()
+    h = ctypes.c_void_p()
+    for over in (dict(sticky_q24=(1 << 24) + 1), dict(noop_max=1001)):
+        c, keep = _cfg(**over)
+        assert L.octax_create(ctypes.byref(c), ctypes.byref(h)) == X.OCTAX_E_INVALID, over
+        assert L.octax_last_error().decode()
+    lens, keys = np.array([17], np.uint8), np.zeros(16, np.uint8)
+    c, keep = _cfg(h_startup_len=lens.ctypes.data, h_startup_keys=keys.ctypes.data)
+    assert L.octax_create(ctypes.byref(c), ctypes.byref(h)) == X.OCTAX_E_INVALID
+    lens[0], keys[0] = 1, 17
+    c, keep = _cfg(h_startup_len=lens.ctypes.data, h_startup_keys=keys.ctypes.data)
+    assert L.octax_create(ctypes.byref(c), ctypes.byref(h)) == X.OCTAX_E_INVALID
+    c, keep = _cfg(h_startup_len=lens.ctypes.data)            # keys missing
+    assert L.octax_create(ctypes.byref(c), ctypes.byref(h)) == X.OCTAX_E_INVALID
+    assert not h.value
 
 
 def test_create_rejects_long_rom_and_bad_rom_index():
