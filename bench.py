@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-wrappers", action="store_true",
                     help="skip the leg with sticky actions, no-op reset and start-up sequences")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the leg with every quirk flag and per-ROM game descriptors")
     ap.add_argument("--tune", choices=["auto", "default"], default="auto")
     ap.add_argument("--serving-groups", type=int, default=2000,
                     help="groups of the serving run (0 = skip it)")
@@ -245,28 +247,45 @@ def main():
         gp.close()
         engp.close()
 
+    def variant_leg(vspec):
+        """Graph replays of the same workload under another spec; (env steps/s, ms per replay, replays)."""
+        engv = X.Engine(vspec, kernel="fused", envs_per_block=tuning["envs_per_block"],
+                        rom_in_lds=tuning["rom_in_lds"], stream=stream)
+        gv = engv.graph(act, obs, rew, done)
+        time_replays(torch, stream, gv, act, act_pool, 1, 0)
+        stream.synchronize()
+        n_v = max(2, args.steps // 4)
+        t0 = time.perf_counter()
+        time_replays(torch, stream, gv, act, act_pool, n_v, args.warmup)
+        stream.synchronize()
+        vwall = time.perf_counter() - t0
+        resets = float((done != 0).float().mean().item())
+        gv.close()
+        engv.close()
+        return {"value": E * K * n_v / vwall, "ms_per_step": vwall * 1e3 / n_v, "replays": n_v,
+                "resets_per_env_step": resets}
+
     # the same workload with the environment wrappers of Section 3.2 on
     wrappers = None
     if not args.no_wrappers:
         wspec = W.with_wrappers(spec, sticky=0.25, noop_max=30, startup_max=3, seed=1)
-        engw = X.Engine(wspec, kernel="fused", envs_per_block=tuning["envs_per_block"],
-                        rom_in_lds=tuning["rom_in_lds"], stream=stream)
-        gw = engw.graph(act, obs, rew, done)
-        time_replays(torch, stream, gw, act, act_pool, 1, 0)
-        stream.synchronize()
-        n_w = max(2, args.steps // 4)
-        t0 = time.perf_counter()
-        time_replays(torch, stream, gw, act, act_pool, n_w, args.warmup)
-        stream.synchronize()
-        wwall = time.perf_counter() - t0
-        resets = float((done != 0).float().mean().item())
-        wrappers = {"value": E * K * n_w / wwall, "ms_per_step": wwall * 1e3 / n_w, "replays": n_w,
-                    "sticky_prob": 0.25, "noop_max": 30,
-                    "startup_steps": [int(x) for x in wspec.startup_len],
-                    "resets_per_env_step": resets}
+        wrappers = variant_leg(wspec)
+        wrappers.update({"sticky_prob": 0.25, "noop_max": 30,
+                         "startup_steps": [int(x) for x in wspec.startup_len]})
         log(f"wrappers: {wrappers['value'] / 1e6:.1f} M env steps/s ({wrappers['ms_per_step']:.2f} ms per replay)")
-        gw.close()
-        engw.close()
+
+    # ... and with the quirk flags and per-ROM game descriptors (Section 3.3).
+    # Display wait stays off: it cuts the instructions run per frame, so the
+    # leg would no longer time the same emulation work.
+    profile = None
+    if not args.no_profile:
+        qspec = W.with_profile(spec, quirks=0x3F, seed=1)
+        profile = variant_leg(qspec)
+        profile.update({"quirks": qspec.quirks, "display_wait": False,
+                        "score_mode": [int(x) for x in qspec.score_mode],
+                        "term_op": [int(x) for x in qspec.term_op],
+                        "term2_op": [int(x) for x in qspec.term2_op]})
+        log(f"profile: {profile['value'] / 1e6:.1f} M env steps/s ({profile['ms_per_step']:.2f} ms per replay)")
 
     serving = None
     if args.serving_groups > 0:
@@ -307,12 +326,13 @@ def main():
         "plain": plain,
         "fused_over_plain": (value / plain["value"]) if plain else None,
         "wrappers": wrappers,
+        "profile": profile,
         "calib_write_GBs": write_gbs,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": f"step_fused_kernel<{tuning['envs_per_block']}>",
+            "kernel": f"step_fused_kernel<{tuning['envs_per_block']}, true, false, false>",
             "algorithmic_bytes_per_launch": algo_per_launch,
             "kernel_ms": kernel_ms,
         },

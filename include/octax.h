@@ -34,8 +34,10 @@
  * step (0 <= a < num_actions: action_keys[rom][a]; any other value: no key);
  * frame_skip frames of instr_per_frame instructions, each frame followed by a
  * timer tick; the new frame joins the observation stack (oldest first, the
- * current display last); reward = V[score_reg] - previous V[score_reg] as a
- * float; terminated = (V[term_reg] == term_value); truncated = (steps since
+ * current display last); reward = score - previous score as a float, the
+ * score being V[score_reg] (or a function of it, see h_score_mode);
+ * terminated = (V[term_reg] == term_value) (or other clauses, see
+ * h_term_op); truncated = (steps since
  * reset >= horizon, when horizon > 0); done = terminated | truncated << 1;
  * on done the env is reset (its RNG stream is not reseeded) and the
  * observation returned is that of the reset state.
@@ -63,8 +65,29 @@
 extern "C" {
 #endif
 
-#define OCTAX_ABI_VERSION 2u
+#define OCTAX_ABI_VERSION 3u
 #define OCTAX_QUIRKS_V1 1u
+
+/* Quirk flags, OR-ed with OCTAX_QUIRKS_V1 in the config's quirks field.
+ * Games written for later interpreters (SUPER-CHIP and others; the paper's
+ * Appendix B lists the variants and Section 3.3 its game set) rely on some
+ * of them; each switches one behaviour of the profile above, for every env
+ * of the engine:
+ *   SHIFT_VX      8XY6 / 8XYE shift VX in place (VY is not read);
+ *   MEM_KEEP_I    FX55 / FX65 leave I unchanged;
+ *   JUMP_VX       BNNN jumps to XNN + VX, X being the second nibble;
+ *   NO_VF_RESET   8XY1 / 8XY2 / 8XY3 leave VF unchanged;
+ *   PIXEL_WRAP    DXYN draws all N rows and wraps pixels past the right or
+ *                 bottom edge to the other side instead of clipping them;
+ *   DISPLAY_WAIT  a DXYN ends its frame: the instructions left in that
+ *                 frame's instr_per_frame budget are not run (the VIP waits
+ *                 for the display interrupt, which starts the next frame). */
+#define OCTAX_QUIRK_SHIFT_VX (1u << 1)
+#define OCTAX_QUIRK_MEM_KEEP_I (1u << 2)
+#define OCTAX_QUIRK_JUMP_VX (1u << 3)
+#define OCTAX_QUIRK_NO_VF_RESET (1u << 4)
+#define OCTAX_QUIRK_PIXEL_WRAP (1u << 5)
+#define OCTAX_QUIRK_DISPLAY_WAIT (1u << 6)
 
 #define OCTAX_MAX_ROM_BYTES 3584u   /* 0x200..0xFFF */
 #define OCTAX_OBS_BYTES 8192u       /* 4 * 64 * 32 */
@@ -95,7 +118,7 @@ typedef struct octax_config {
     uint32_t num_roms;         /* R >= 1 */
     uint32_t instr_per_frame;  /* instructions per 60 Hz frame, 1..1000 */
     uint32_t frame_skip;       /* frames per step, 1..64 (paper default 4) */
-    uint32_t quirks;           /* must be OCTAX_QUIRKS_V1 */
+    uint32_t quirks;           /* OCTAX_QUIRKS_V1 | any OCTAX_QUIRK_* flags */
     uint32_t kernel;           /* enum octax_kernel */
     uint32_t placement;        /* enum octax_placement */
     uint32_t envs_per_block;   /* fused kernel: envs per workgroup (0 = default) */
@@ -135,6 +158,28 @@ typedef struct octax_config {
     uint32_t noop_max;
     const uint8_t *h_startup_len;   /* [R] or NULL */
     const uint8_t *h_startup_keys;  /* [R][16] or NULL (with h_startup_len) */
+    /* Game descriptors beyond a score register and one == test, in the
+     * forms the paper's game list prints (Section 3.3; Appendix C.3); NULL
+     * keeps the plain forms.  With V = V[score_reg]:
+     *   h_score_mode [R] with h_score_arg [R] (given together):
+     *     0  score = V;
+     *     1  score = V / 10 - V % 10 (Pong: two players' points in one
+     *        register, player minus opponent);
+     *     2  score = -(V + V[h_score_arg]) (Airplane: -V[11] - V[12]);
+     *     3  score = V if V <= h_score_arg, else 0 (Shooting Stars' cap).
+     *   Termination is two clauses, OR-ed, each comparing a register with a
+     *   constant by op 0 = never, 1 ==, 2 >=, 3 !=, 4 = either decimal digit
+     *   (V / 10 or V % 10) equals it:
+     *     h_term_op [R]: the op of V[term_reg] against term_value (NULL: ==);
+     *     h_term2_op, h_term2_reg, h_term2_value [R] (given together): a
+     *     second clause V[h_term2_reg] op h_term2_value (Space Flight:
+     *     V[9] == 0 or V[12] >= 0x3E). */
+    const uint8_t *h_score_mode;    /* [R] 0..3 or NULL */
+    const uint8_t *h_score_arg;     /* [R] register 0..15 (mode 2) or cap (mode 3) */
+    const uint8_t *h_term_op;       /* [R] 0..4 or NULL */
+    const uint8_t *h_term2_op;      /* [R] 0..4 or NULL */
+    const uint8_t *h_term2_reg;     /* [R] 0..15 */
+    const uint8_t *h_term2_value;   /* [R] */
 } octax_config;
 
 /* Architectural state of one env (get_state / set_state). */
@@ -148,7 +193,7 @@ typedef struct octax_env_state {
     uint8_t prev_key;       /* key held in the previous step (sticky actions), 16 = none */
     uint16_t stack[16];     /* return addresses */
     uint32_t t;             /* steps since the last reset */
-    int32_t prev_score;     /* V[score_reg] after the previous step */
+    int32_t prev_score;     /* score (see h_score_mode) after the previous step */
     uint64_t rng;           /* SplitMix64 state */
     uint8_t ram[4096];      /* memory */
     uint64_t fb[32];        /* display row y: bit (63 - x) is pixel (x, y) */
@@ -164,7 +209,8 @@ typedef struct octax_graph octax_graph;
  * resets every env (Section 3.2, ROM loading and initialization).  On
  * success *out owns the engine; on failure *out is NULL and nothing leaks.
  * Errors: OCTAX_E_INVALID (any field out of range, ROM too long, env_rom
- * >= R, wrong abi_version or quirks), OCTAX_E_NOMEM, OCTAX_E_HIP.
+ * >= R, wrong abi_version, quirks without OCTAX_QUIRKS_V1 or with unknown
+ * flags), OCTAX_E_NOMEM, OCTAX_E_HIP.
  */
 int32_t octax_create(const octax_config *cfg, octax_engine **out);
 
@@ -293,7 +339,7 @@ typedef struct octax_pool_config {
     uint32_t num_roms;         /* R >= 1 */
     uint32_t instr_per_frame;  /* 1..1000 */
     uint32_t frame_skip;       /* 1..64 */
-    uint32_t quirks;           /* must be OCTAX_QUIRKS_V1 */
+    uint32_t quirks;           /* OCTAX_QUIRKS_V1 | any OCTAX_QUIRK_* flags */
     uint32_t envs_per_block;   /* fused kernel tuning: 64, 128 or 256 (0 = 256) */
     uint64_t pool_bytes;       /* device-memory budget of the env slots */
     const uint8_t *h_rom_data;     /* as in octax_config */
@@ -309,6 +355,12 @@ typedef struct octax_pool_config {
     uint32_t noop_max;
     const uint8_t *h_startup_len;  /* [R] or NULL */
     const uint8_t *h_startup_keys; /* [R][16] or NULL */
+    const uint8_t *h_score_mode;   /* game descriptors, as in octax_config */
+    const uint8_t *h_score_arg;
+    const uint8_t *h_term_op;
+    const uint8_t *h_term2_op;
+    const uint8_t *h_term2_reg;
+    const uint8_t *h_term2_value;
 } octax_pool_config;
 
 typedef struct octax_pool octax_pool;

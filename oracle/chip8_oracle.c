@@ -47,13 +47,46 @@
  *   - after these steps the frame stack holds the resulting display four
  *     times, the score baseline is the score register's value, and
  *     terminations during them are ignored;
+ *   - (see below for the quirk flags)
  *   - the random draws come from the env's own SplitMix64 stream, in a fixed
  *     order: one draw at the start of a step when sticky actions are on, one
  *     draw after the start-up sequence when no-op reset is on.  A 64-bit draw
  *     u decides stickiness as (u >> 40) < sticky_q24, and the no-op count is
  *     ((u >> 32) * (noop_max + 1)) >> 32 (Lemire's multiply-shift range
  *     reduction, without rejection).
+ *
+ * Quirk flags and game descriptors (the variants real games need; Section
+ * 3.3 and Appendix B).  The base profile is the VIP one above; each flag
+ * switches one behaviour to the SUPER-CHIP / later-interpreter one:
+ *   QUIRK_SHIFT_VX      8XY6 / 8XYE shift VX in place (VY is not read);
+ *   QUIRK_MEM_KEEP_I    FX55 / FX65 leave I unchanged;
+ *   QUIRK_JUMP_VX       BNNN jumps to XNN + VX (X = the second nibble);
+ *   QUIRK_NO_VF_RESET   8XY1 / 8XY2 / 8XY3 leave VF unchanged;
+ *   QUIRK_PIXEL_WRAP    sprite pixels past the right or bottom edge wrap to
+ *                       the other side instead of being clipped;
+ *   QUIRK_DISPLAY_WAIT  a DXYN ends the frame: the instructions left in the
+ *                       frame's budget are not run (the interpreter waits
+ *                       for the display interrupt that starts the next one).
+ * Score modes (the forms the game list of Appendix C.3 prints), V = V[score_reg]:
+ *   0  V;
+ *   1  (V // 10) - (V % 10), Pong's player-minus-opponent score;
+ *   2  -(V + V[score_arg]), Airplane's -V[11] - V[12];
+ *   3  V when V <= score_arg, else 0, Shooting Stars' cap at 128.
+ * Termination: up to two clauses, OR-ed, each a test of one register against
+ * a constant with op 0 = never, 1 ==, 2 >=, 3 !=, 4 = either decimal digit
+ * (V // 10 or V % 10) equals it (Pong: either score reaches 9).  The first
+ * clause is V[term_reg] op term_value, op == unless term_op says otherwise;
+ * the second V[term2_reg] op2 term2_value (Space Flight, Airplane, Flight
+ * Runner).
  */
+#define QUIRK_BASE 1u
+#define QUIRK_SHIFT_VX (1u << 1)
+#define QUIRK_MEM_KEEP_I (1u << 2)
+#define QUIRK_JUMP_VX (1u << 3)
+#define QUIRK_NO_VF_RESET (1u << 4)
+#define QUIRK_PIXEL_WRAP (1u << 5)
+#define QUIRK_DISPLAY_WAIT (1u << 6)
+#define QUIRK_ALL 0x7Fu
 #include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -99,6 +132,7 @@ typedef struct {
     uint8_t mem[MEM_BYTES];
     uint8_t disp[SCREEN_H][SCREEN_W]; /* disp[y][x] is 0 or 1 */
     uint64_t rng;                     /* SplitMix64 state */
+    uint32_t quirks;                  /* QUIRK_* flags; 0 or QUIRK_BASE = the VIP profile */
 } oracle_machine;
 
 /* Exported snapshot of one environment.  Field order is part of the
@@ -147,6 +181,13 @@ typedef struct {
     uint32_t noop_max;
     uint8_t *startup_len;                /* [R] */
     uint8_t (*startup_keys)[16];         /* [R][16], 16 = no key */
+    uint32_t quirks;
+    uint8_t *score_mode;                 /* [R] or NULL (all 0) */
+    uint8_t *score_arg;                  /* [R]: register (mode 2) or cap (mode 3) */
+    uint8_t *term_op;                    /* [R] or NULL (all 1, ==) */
+    uint8_t *term2_op;                   /* [R]: 0 none, 1 ==, 2 >=, 3 !=, 4 digit == ; or NULL */
+    uint8_t *term2_reg;
+    uint8_t *term2_value;
     oracle_env *env;
 } oracle_batch;
 
@@ -197,16 +238,23 @@ static void draw_sprite(oracle_machine *m, int x, int y, int n)
 {
     int x0 = m->v[x] % SCREEN_W;
     int y0 = m->v[y] % SCREEN_H;
+    int wrap = (m->quirks & QUIRK_PIXEL_WRAP) != 0;
     int collided = 0;
     for (int row = 0; row < n; row++) {
         int py = y0 + row;
-        if (py >= SCREEN_H)
-            break;
+        if (py >= SCREEN_H) {
+            if (!wrap)
+                break;
+            py -= SCREEN_H;
+        }
         uint8_t bits = m->mem[(m->i + row) & 0xFFF];
         for (int col = 0; col < 8; col++) {
             int px = x0 + col;
-            if (px >= SCREEN_W)
-                break;
+            if (px >= SCREEN_W) {
+                if (!wrap)
+                    break;
+                px -= SCREEN_W;
+            }
             int sprite_pixel = (bits >> (7 - col)) & 1;
             if (sprite_pixel) {
                 if (m->disp[py][px] == 1)
@@ -274,9 +322,9 @@ void oracle_machine_execute(oracle_machine *m, int key)
         int vx = V[x], vy = V[y];
         switch (n) {
         case 0x0: V[x] = (uint8_t)vy; break;
-        case 0x1: V[x] = (uint8_t)(vx | vy); V[0xF] = 0; break;
-        case 0x2: V[x] = (uint8_t)(vx & vy); V[0xF] = 0; break;
-        case 0x3: V[x] = (uint8_t)(vx ^ vy); V[0xF] = 0; break;
+        case 0x1: V[x] = (uint8_t)(vx | vy); if (!(m->quirks & QUIRK_NO_VF_RESET)) V[0xF] = 0; break;
+        case 0x2: V[x] = (uint8_t)(vx & vy); if (!(m->quirks & QUIRK_NO_VF_RESET)) V[0xF] = 0; break;
+        case 0x3: V[x] = (uint8_t)(vx ^ vy); if (!(m->quirks & QUIRK_NO_VF_RESET)) V[0xF] = 0; break;
         case 0x4: {
             int sum = vx + vy;
             V[x] = (uint8_t)(sum % 256);
@@ -290,8 +338,9 @@ void oracle_machine_execute(oracle_machine *m, int key)
             break;
         }
         case 0x6: {
-            int out = vy % 2;
-            V[x] = (uint8_t)(vy / 2);
+            int src = (m->quirks & QUIRK_SHIFT_VX) ? vx : vy;
+            int out = src % 2;
+            V[x] = (uint8_t)(src / 2);
             V[0xF] = (uint8_t)out;
             break;
         }
@@ -302,8 +351,9 @@ void oracle_machine_execute(oracle_machine *m, int key)
             break;
         }
         case 0xE: {
-            int out = vy / 128;
-            V[x] = (uint8_t)((vy * 2) % 256);
+            int src = (m->quirks & QUIRK_SHIFT_VX) ? vx : vy;
+            int out = src / 128;
+            V[x] = (uint8_t)((src * 2) % 256);
             V[0xF] = (uint8_t)out;
             break;
         }
@@ -318,8 +368,8 @@ void oracle_machine_execute(oracle_machine *m, int key)
     case 0xA:                                     /* LD I, NNN */
         m->i = (uint16_t)nnn;
         break;
-    case 0xB:                                     /* JP V0, NNN */
-        m->pc = (uint16_t)((nnn + V[0]) & 0xFFF);
+    case 0xB:                                     /* JP V0, NNN (JP VX, XNN with QUIRK_JUMP_VX) */
+        m->pc = (uint16_t)((nnn + ((m->quirks & QUIRK_JUMP_VX) ? V[x] : V[0])) & 0xFFF);
         break;
     case 0xC:                                     /* RND VX, NN */
         V[x] = (uint8_t)((oracle_splitmix64_next(&m->rng) >> 56) & (uint64_t)nn);
@@ -359,12 +409,14 @@ void oracle_machine_execute(oracle_machine *m, int key)
         case 0x55:                                /* LD [I], V0..VX */
             for (int k = 0; k <= x; k++)
                 m->mem[(m->i + k) & 0xFFF] = V[k];
-            m->i = (uint16_t)((m->i + x + 1) & 0xFFF);
+            if (!(m->quirks & QUIRK_MEM_KEEP_I))
+                m->i = (uint16_t)((m->i + x + 1) & 0xFFF);
             break;
         case 0x65:                                /* LD V0..VX, [I] */
             for (int k = 0; k <= x; k++)
                 V[k] = m->mem[(m->i + k) & 0xFFF];
-            m->i = (uint16_t)((m->i + x + 1) & 0xFFF);
+            if (!(m->quirks & QUIRK_MEM_KEEP_I))
+                m->i = (uint16_t)((m->i + x + 1) & 0xFFF);
             break;
         default: break;
         }
@@ -389,10 +441,59 @@ void oracle_machine_tick(oracle_machine *m)
 static void run_step_frames(const oracle_batch *b, oracle_machine *m, int key)
 {
     for (int f = 0; f < b->frame_skip; f++) {
-        for (int k = 0; k < b->instr_per_frame; k++)
+        for (int k = 0; k < b->instr_per_frame; k++) {
+            int draws = (m->mem[m->pc] >> 4) == 0xD;
             oracle_machine_execute(m, key);
+            if (draws && (m->quirks & QUIRK_DISPLAY_WAIT))
+                break;
+        }
         oracle_machine_tick(m);
     }
+}
+
+/* Score of an env (Section 3.3), in the ROM's score mode (see the header). */
+static int32_t env_score(const oracle_batch *b, const oracle_env *e)
+{
+    int r = e->rom;
+    int v = e->m.v[b->score_reg[r]];
+    int mode = b->score_mode ? b->score_mode[r] : 0;
+    switch (mode) {
+    case 1:
+        return v / 10 - v % 10;
+    case 2:
+        return -(v + e->m.v[b->score_arg[r] & 15]);
+    case 3:
+        return v <= b->score_arg[r] ? v : 0;
+    default:
+        return v;
+    }
+}
+
+/* One termination clause: register value v against constant c. */
+static int clause_holds(int op, int v, int c)
+{
+    switch (op) {
+    case 1:
+        return v == c;
+    case 2:
+        return v >= c;
+    case 3:
+        return v != c;
+    case 4:
+        return v / 10 == c || v % 10 == c;
+    default:
+        return 0;
+    }
+}
+
+/* Termination (Section 3.3): either clause holds. */
+static int env_terminated(const oracle_batch *b, const oracle_env *e)
+{
+    int r = e->rom;
+    int t = clause_holds(b->term_op ? b->term_op[r] : 1, e->m.v[b->term_reg[r]], b->term_value[r]);
+    if (b->term2_op)
+        t = t || clause_holds(b->term2_op[r], e->m.v[b->term2_reg[r]], b->term2_value[r]);
+    return t;
 }
 
 /* Reset: power-on, then the ROM's start-up sequence and the no-op steps of
@@ -415,7 +516,7 @@ static void env_reset(const oracle_batch *b, oracle_env *e)
     for (int k = 0; k < 3; k++)
         memcpy(e->hist[k], e->m.disp, sizeof e->m.disp);
     e->t = 0;
-    e->prev_score = e->m.v[b->score_reg[e->rom]];
+    e->prev_score = env_score(b, e);
     e->prev_key = -1;
 }
 
@@ -451,11 +552,11 @@ static void env_step(const oracle_batch *b, oracle_env *e, int32_t action, uint8
     memcpy(e->hist[1], e->hist[2], sizeof before);
     memcpy(e->hist[2], before, sizeof before);
 
-    int32_t score = e->m.v[b->score_reg[r]];
+    int32_t score = env_score(b, e);
     *reward = (float)(score - e->prev_score);
     e->prev_score = score;
 
-    int terminated = e->m.v[b->term_reg[r]] == b->term_value[r];
+    int terminated = env_terminated(b, e);
     e->t += 1;
     int truncated = e->horizon > 0 && e->t >= e->horizon;
     *done = (uint8_t)(terminated | (truncated << 1));
@@ -532,7 +633,61 @@ void oracle_destroy(oracle_batch *b)
     free(b->rom); free(b->rom_len); free(b->action_keys); free(b->num_actions);
     free(b->score_reg); free(b->term_reg); free(b->term_value); free(b->env);
     free(b->startup_len); free(b->startup_keys);
+    free(b->score_mode); free(b->score_arg); free(b->term_op);
+    free(b->term2_op); free(b->term2_reg); free(b->term2_value);
     free(b);
+}
+
+/* Configure the quirk flags and the game descriptors (score mode and its
+ * argument, the ops of both termination clauses, the second clause's register
+ * and constant; see the header).  score_mode and score_arg come together, as
+ * do term2_op, term2_reg and term2_value; any group may be NULL.  Out-of-range
+ * values change nothing and return -1.  They apply from the next reset and
+ * step on; callers reset after this. */
+static uint8_t *copy_bytes(const uint8_t *src, int n, int *fail)
+{
+    uint8_t *dst = NULL;
+    if (src) {
+        dst = malloc((size_t)n);
+        if (dst)
+            memcpy(dst, src, (size_t)n);
+        else
+            *fail = 1;
+    }
+    return dst;
+}
+
+int oracle_set_profile(oracle_batch *b, uint32_t quirks, const uint8_t *score_mode, const uint8_t *score_arg,
+                       const uint8_t *term_op, const uint8_t *term2_op, const uint8_t *term2_reg,
+                       const uint8_t *term2_value)
+{
+    int R = b->num_roms, fail = 0;
+    if ((quirks & ~QUIRK_ALL) || !(quirks & QUIRK_BASE))
+        return -1;
+    if (!score_mode != !score_arg || !term2_op != !term2_reg || !term2_op != !term2_value)
+        return -1;
+    for (int r = 0; r < R; r++) {
+        if (score_mode && (score_mode[r] > 3 || (score_mode[r] == 2 && score_arg[r] > 15)))
+            return -1;
+        if (term_op && term_op[r] > 4)
+            return -1;
+        if (term2_op && (term2_op[r] > 4 || term2_reg[r] > 15))
+            return -1;
+    }
+    free(b->score_mode); free(b->score_arg); free(b->term_op);
+    free(b->term2_op); free(b->term2_reg); free(b->term2_value);
+    b->score_mode = copy_bytes(score_mode, R, &fail);
+    b->score_arg = copy_bytes(score_arg, R, &fail);
+    b->term_op = copy_bytes(term_op, R, &fail);
+    b->term2_op = copy_bytes(term2_op, R, &fail);
+    b->term2_reg = copy_bytes(term2_reg, R, &fail);
+    b->term2_value = copy_bytes(term2_value, R, &fail);
+    if (fail)
+        return -2;
+    b->quirks = quirks;
+    for (int e = 0; e < b->num_envs; e++)
+        b->env[e].m.quirks = quirks;
+    return 0;
 }
 
 /* Configure the environment wrappers (all off after oracle_create).  They
@@ -696,6 +851,9 @@ int oracle_machine_size(void) { return (int)sizeof(oracle_machine); }
 /* Single-machine access for unit tests of individual instructions. */
 oracle_machine *oracle_machine_new(void) { return calloc(1, sizeof(oracle_machine)); }
 void oracle_machine_free(oracle_machine *m) { free(m); }
+/* Quirk flags of a single machine (QUIRK_*; a new machine has none, which
+ * behaves as the base profile). */
+void oracle_machine_set_quirks(oracle_machine *m, uint32_t quirks) { m->quirks = quirks; }
 void oracle_machine_to_state(const oracle_machine *m, oracle_state *s)
 {
     memset(s, 0, sizeof *s);

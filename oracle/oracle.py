@@ -69,6 +69,7 @@ def lib():
         L.oracle_state_size.restype = i32
         L.oracle_machine_new.restype = P
         L.oracle_machine_free.argtypes = [P]
+        L.oracle_machine_set_quirks.argtypes = [P, ctypes.c_uint32]
         L.oracle_machine_load.argtypes = [P, P, ctypes.c_uint32]
         L.oracle_machine_execute.argtypes = [P, i32]
         L.oracle_machine_tick.argtypes = [P]
@@ -80,6 +81,8 @@ def lib():
         L.oracle_execute_states.argtypes = [P, i32, i32, i32]
         L.oracle_set_wrappers.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, P, P]
         L.oracle_set_wrappers.restype = i32
+        L.oracle_set_profile.argtypes = [P, ctypes.c_uint32, P, P, P, P, P, P]
+        L.oracle_set_profile.restype = i32
         assert L.oracle_state_size() == STATE_DTYPE.itemsize, "oracle_state layout mismatch"
         _lib = L
     return _lib
@@ -126,8 +129,9 @@ def blank_state(rom: bytes = b"") -> np.ndarray:
 class Machine:
     """One bare CHIP-8 machine: load, execute single instructions, tick timers."""
 
-    def __init__(self, rom: bytes = b""):
+    def __init__(self, rom: bytes = b"", quirks: int = 1):
         self._h = lib().oracle_machine_new()
+        lib().oracle_machine_set_quirks(self._h, int(quirks))
         self.load(rom)
 
     def __del__(self):
@@ -191,14 +195,22 @@ class OracleBatch:
         if not h:
             raise ValueError("oracle_create rejected the spec")
         self._h = h
+        # quirk flags, game descriptors and wrappers act from the next reset
+        # on: configure, then reset all
+        u8 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.uint8)
+        if getattr(spec, "has_profile", False):
+            arrs = [u8(spec.score_mode), u8(spec.score_arg), u8(spec.term_op),
+                    u8(spec.term2_op), u8(spec.term2_reg), u8(spec.term2_value)]
+            self._keep["profile"] = arrs
+            if lib().oracle_set_profile(h, int(spec.quirks), *[_p(a) for a in arrs]) != 0:
+                raise ValueError("oracle_set_profile rejected the spec")
         if getattr(spec, "has_wrappers", False):
-            # wrappers act from the next reset on: configure, then reset all
-            sl = None if spec.startup_len is None else np.ascontiguousarray(spec.startup_len, dtype=np.uint8)
-            sk = None if spec.startup_keys is None else np.ascontiguousarray(spec.startup_keys, dtype=np.uint8)
+            sl, sk = u8(spec.startup_len), u8(spec.startup_keys)
             self._keep.update(startup_len=sl, startup_keys=sk)
             rc = lib().oracle_set_wrappers(h, int(spec.sticky_q24), int(spec.noop_max), _p(sl), _p(sk))
             if rc != 0:
                 raise ValueError("oracle_set_wrappers rejected the spec")
+        if getattr(spec, "has_profile", False) or getattr(spec, "has_wrappers", False):
             lib().oracle_reset(h, None, None)
 
     def close(self):

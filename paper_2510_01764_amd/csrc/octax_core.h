@@ -57,8 +57,19 @@ __device__ __forceinline__ void or_byte(u32x4 &v, int k, uint32_t b) {
     else v.w |= s;
 }
 
+// Quirk flags (octax.h): bit 0 is the VIP base profile, bits 1..6 switch one
+// behaviour each to the SUPER-CHIP / later-interpreter one.
+constexpr uint32_t kQuirkShiftVx = 1u << 1;    // 8XY6 / 8XYE shift VX in place
+constexpr uint32_t kQuirkMemKeepI = 1u << 2;   // FX55 / FX65 leave I unchanged
+constexpr uint32_t kQuirkJumpVx = 1u << 3;     // BNNN jumps to XNN + VX
+constexpr uint32_t kQuirkNoVfReset = 1u << 4;  // 8XY1/2/3 leave VF unchanged
+constexpr uint32_t kQuirkPixelWrap = 1u << 5;  // sprites wrap at the right and bottom edges
+constexpr uint32_t kQuirkDisplayWait = 1u << 6; // a DXYN ends the frame's instructions
+
+// One instruction; returns whether it was a DXYN (the display-wait quirk ends
+// the frame after one).
 template <class Mem>
-__device__ __forceinline__ void exec_one(Core &c, Mem &mem, uint32_t key) {
+__device__ __forceinline__ bool exec_one(Core &c, Mem &mem, uint32_t key, uint32_t quirks = 0) {
     const uint32_t op = mem.fetch(c.pc);
     c.pc = (c.pc + 2) & 0xFFF;
     const uint32_t x = (op >> 8) & 0xF;
@@ -103,16 +114,18 @@ __device__ __forceinline__ void exec_one(Core &c, Mem &mem, uint32_t key) {
     case 0x8: {
         uint32_t res = 0, flag = 0;
         bool write = true, has_flag = true;
+        const bool keep_vf = quirks & kQuirkNoVfReset;
+        const uint32_t ssrc = (quirks & kQuirkShiftVx) ? vx : vy;   // shift source
         switch (n) {
         case 0x0: res = vy; has_flag = false; break;
-        case 0x1: res = vx | vy; flag = 0; break;
-        case 0x2: res = vx & vy; flag = 0; break;
-        case 0x3: res = vx ^ vy; flag = 0; break;
+        case 0x1: res = vx | vy; flag = 0; has_flag = !keep_vf; break;
+        case 0x2: res = vx & vy; flag = 0; has_flag = !keep_vf; break;
+        case 0x3: res = vx ^ vy; flag = 0; has_flag = !keep_vf; break;
         case 0x4: res = vx + vy; flag = res >> 8; break;
         case 0x5: res = vx - vy; flag = vx >= vy; break;
-        case 0x6: res = vy >> 1; flag = vy & 1; break;
+        case 0x6: res = ssrc >> 1; flag = ssrc & 1; break;
         case 0x7: res = vy - vx; flag = vy >= vx; break;
-        case 0xE: res = vy << 1; flag = vy >> 7; break;
+        case 0xE: res = ssrc << 1; flag = ssrc >> 7; break;
         default: write = false; break;
         }
         if (write) {
@@ -128,13 +141,13 @@ __device__ __forceinline__ void exec_one(Core &c, Mem &mem, uint32_t key) {
         c.I = nnn;
         break;
     case 0xB:
-        c.pc = (nnn + (c.r.w.x & 0xFF)) & 0xFFF;
+        c.pc = (nnn + ((quirks & kQuirkJumpVx) ? vx : (c.r.w.x & 0xFF))) & 0xFFF;
         break;
     case 0xC:
         vset(c.r, x, rnd_byte(c.rng) & nn);
         break;
     case 0xD:
-        set_vf(c.r, mem.draw(vx & 63, vy & 31, c.I, n));
+        set_vf(c.r, mem.draw(vx & 63, vy & 31, c.I, n, (quirks & kQuirkPixelWrap) != 0));
         break;
     case 0xE:
         if (nn == 0x9E) {
@@ -162,19 +175,20 @@ __device__ __forceinline__ void exec_one(Core &c, Mem &mem, uint32_t key) {
         case 0x55:
             // V0..VX are packed in memory order in the register vector
             mem.store_bytes(c.I, x + 1, c.r.w);
-            c.I = (c.I + x + 1) & 0xFFF;
+            if (!(quirks & kQuirkMemKeepI)) c.I = (c.I + x + 1) & 0xFFF;
             break;
         case 0x65: {
             const u32x4 b = mem.load_bytes(c.I, x + 1);
             const u32x4 m = byte_mask(x + 1);
             c.r.w = (c.r.w & ~m) | (b & m);
-            c.I = (c.I + x + 1) & 0xFFF;
+            if (!(quirks & kQuirkMemKeepI)) c.I = (c.I + x + 1) & 0xFFF;
             break;
         }
         default: break;
         }
         break;
     }
+    return (op >> 12) == 0xD;
 }
 
 // One 60 Hz tick of the delay and sound timers.
@@ -222,6 +236,38 @@ __device__ __forceinline__ void reset_core(Core &c) {
     c.dt = 0;
     c.st = 0;
     c.pkey = kKeyNone;
+}
+
+// Game descriptors beyond desc (Section 3.3 and the game list of Appendix
+// C.3), packed per ROM: score mode (bits 0..1) | score argument << 2 |
+// op of the first termination clause << 10 | op of the second << 13 |
+// second clause's register << 16 | its constant << 24.  kDesc2Default is the
+// plain form (score V[score_reg], termination V[term_reg] == term_value).
+constexpr uint32_t kDesc2Default = 1u << 10;
+
+// Score: mode 0 V, 1 (V / 10) - (V % 10), 2 -(V + V[arg]), 3 V if V <= arg else 0,
+// with V = V[score_reg].
+__device__ __forceinline__ int32_t score_of(const Regs &r, uint32_t desc, uint32_t desc2) {
+    const uint32_t v = vget(r, desc & 15);
+    const uint32_t mode = desc2 & 3, arg = (desc2 >> 2) & 0xFF;
+    if (mode == 0) return (int32_t)v;
+    if (mode == 1) return (int32_t)(v / 10) - (int32_t)(v % 10);
+    if (mode == 2) return -(int32_t)(v + vget(r, arg & 15));
+    return v <= arg ? (int32_t)v : 0;
+}
+
+// One termination clause on register value v and constant k: op 0 never,
+// 1 ==, 2 >=, 3 !=, 4 either decimal digit of v equals k.
+__device__ __forceinline__ bool clause_holds(uint32_t op, uint32_t v, uint32_t k) {
+    return (op == 1 && v == k) || (op == 2 && v >= k) || (op == 3 && v != k) ||
+           (op == 4 && (v / 10 == k || v % 10 == k));
+}
+
+// Termination: the first clause (V[term_reg] against term_value) or the second.
+__device__ __forceinline__ uint32_t terminated_of(const Regs &r, uint32_t desc, uint32_t desc2) {
+    const bool t1 = clause_holds((desc2 >> 10) & 7, vget(r, (desc >> 8) & 15), (desc >> 16) & 0xFF);
+    const bool t2 = clause_holds((desc2 >> 13) & 7, vget(r, (desc2 >> 16) & 15), desc2 >> 24);
+    return (t1 || t2) ? 1u : 0u;
 }
 
 // Sticky actions (Section 3.2): with probability sticky_q24 / 2^24 the key

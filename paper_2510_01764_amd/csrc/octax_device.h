@@ -59,6 +59,12 @@ struct Roms {
     const uint8_t *image;    // [R][4096] power-on memory: font at 0x50, program at 0x200
     const uint8_t *keys;     // [R][16]
     const uint32_t *desc;    // [R] score_reg | term_reg << 8 | term_value << 16 | num_actions << 24
+    // Game descriptors beyond desc, or null (all zero): [R] score mode |
+    // term2 op << 2 | term2 reg << 4 | term2 value << 8 (score mode 1 = BCD
+    // difference; term2 op 0 none, 1 ==, 2 >=).
+    const uint32_t *desc2;
+    uint32_t quirks;         // quirk flags of the whole batch (bit 0 = the VIP base profile)
+    uint32_t profile;        // nonzero when quirks != base or desc2 is set
     Wrap w;
 };
 

@@ -64,6 +64,10 @@ int32_t hip_fail(hipError_t e, const char *what);
 // start-up table (count, then 16 keys); returns an error message or null.
 const char *check_wrappers(uint32_t sticky_q24, uint32_t noop_max, const uint8_t *h_startup_len,
                            const uint8_t *h_startup_keys, uint32_t R, std::vector<uint8_t> &table);
+// Check the quirk flags and game descriptors of a config and build the [R]
+// desc2 table (left empty when no descriptor array is given); returns an
+// error message or null.
+const char *check_profile(const octax_config *cfg, std::vector<uint32_t> &desc2);
 // The wrapper parameters of a Roms (d_table: the device copy of the table).
 Wrap make_wrap(const uint8_t *d_table, const std::vector<uint8_t> &table, uint32_t sticky_q24,
                uint32_t noop_max, uint32_t ipf, uint32_t frame_skip);

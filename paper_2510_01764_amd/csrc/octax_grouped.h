@@ -44,8 +44,9 @@ __device__ __forceinline__ void vset_if(Regs &r, uint32_t x, uint32_t val, bool 
     r.w.w = pick(q == 3, (r.w.w & ~m) | s, r.w.w);
 }
 
+// One instruction; returns whether it was a DXYN (for the display-wait quirk).
 template <class Mem>
-__device__ __forceinline__ void exec_grouped(Core &c, Mem &mem, uint32_t key) {
+__device__ __forceinline__ bool exec_grouped(Core &c, Mem &mem, uint32_t key, uint32_t quirks = 0) {
     uint32_t ret;   // stack[(SP - 1) & 15]
     const uint32_t op = mem.fetch(c.pc, c.sp, ret);
     const uint32_t pc2 = (c.pc + 2) & 0xFFF;
@@ -60,7 +61,7 @@ __device__ __forceinline__ void exec_grouped(Core &c, Mem &mem, uint32_t key) {
     const bool isF = h == 0xF;
 
     // ---- memory, display, stack and random classes (read the old I and V) ----
-    if (h == 0xD) set_vf(c.r, mem.draw(vx & 63, vy & 31, c.I, n));
+    if (h == 0xD) set_vf(c.r, mem.draw(vx & 63, vy & 31, c.I, n, (quirks & kQuirkPixelWrap) != 0));
     if (isF & ((nn == 0x33) | (nn == 0x55))) {
         // FX33: three BCD digits of VX; FX55: V0..VX (in memory order in the register vector)
         const bool bcd = nn == 0x33;
@@ -83,14 +84,15 @@ __device__ __forceinline__ void exec_grouped(Core &c, Mem &mem, uint32_t key) {
     // 5 SUB, 6 SHR, 7 SUBN), then E SHL.
     const bool n1 = n & 1, n2 = n & 2, n4 = n & 4, nE = n == 0xE;
     const uint32_t sum = vx + vy;
+    const uint32_t ss = pick(quirks & kQuirkShiftVx, vx, vy);   // shift source
     const uint32_t r01 = pick(n1, vx | vy, vy);
     const uint32_t r23 = pick(n1, vx ^ vy, vx & vy);
     const uint32_t r45 = pick(n1, vx - vy, sum);
-    const uint32_t r67 = pick(n1, vy - vx, vy >> 1);
-    const uint32_t r8 = pick(nE, vy << 1, pick(n4, pick(n2, r67, r45), pick(n2, r23, r01)));
+    const uint32_t r67 = pick(n1, vy - vx, ss >> 1);
+    const uint32_t r8 = pick(nE, ss << 1, pick(n4, pick(n2, r67, r45), pick(n2, r23, r01)));
     const uint32_t f45 = pick(n1, (uint32_t)(vx >= vy), sum >> 8);
-    const uint32_t f67 = pick(n1, (uint32_t)(vy >= vx), vy & 1);
-    const uint32_t f8 = pick(nE, vy >> 7, pick(n4, pick(n2, f67, f45), 0u));
+    const uint32_t f67 = pick(n1, (uint32_t)(vy >= vx), ss & 1);
+    const uint32_t f8 = pick(nE, ss >> 7, pick(n4, pick(n2, f67, f45), 0u));
     const bool alu_ok = (n <= 0x7) | nE;
     const bool key_held = key < 16;
     const uint32_t resF = pick(nn == 0x07, c.dt, key);
@@ -98,7 +100,8 @@ __device__ __forceinline__ void exec_grouped(Core &c, Mem &mem, uint32_t key) {
     const bool wr = (h == 0x6) | (h == 0x7) | ((h == 0x8) & alu_ok) | (h == 0xC) |
                     (isF & ((nn == 0x07) | ((nn == 0x0A) & key_held)));
     vset_if(c.r, x, res, wr);
-    const bool wf = (h == 0x8) & alu_ok & (n != 0);   // the flag is written after the result
+    // the flag is written after the result; 8XY1/2/3 keep VF with the quirk
+    const bool wf = (h == 0x8) & alu_ok & (n != 0) & !((quirks & kQuirkNoVfReset) && (n <= 3));
     c.r.w.w = pick(wf, (c.r.w.w & 0x00FFFFFFu) | (f8 << 24), c.r.w.w);
 
     // ---- PC, SP, I, timers ----
@@ -112,7 +115,8 @@ __device__ __forceinline__ void exec_grouped(Core &c, Mem &mem, uint32_t key) {
     const uint32_t rhs = pick(cmp_nn, nn, pick(cmp_vy, vy, kx));
     const bool neg = (h == 0x4) | (h == 0x9) | ((h == 0xE) & (nn == 0xA1));
     const bool skip = (cmp_nn | cmp_vy | cmp_key) & ((lhs == rhs) != neg);
-    const uint32_t v0 = c.r.w.x & 0xFF;   // BNNN writes no register: this is V0 before it
+    // BNNN writes no register: this is V0 (or VX with the quirk) before it
+    const uint32_t v0 = pick(quirks & kQuirkJumpVx, vx, c.r.w.x & 0xFF);
     const bool ret_op = op == 0x00EE;
     const bool wait_key = isF & (nn == 0x0A) & !key_held;
     const uint32_t seq = pick(wait_key, c.pc, pick(skip, (pc2 + 2) & 0xFFF, pc2));
@@ -121,10 +125,11 @@ __device__ __forceinline__ void exec_grouped(Core &c, Mem &mem, uint32_t key) {
     const uint32_t I = c.I;
     const uint32_t iF = pick(nn == 0x1E, (I + vx) & 0xFFF,
                              pick(nn == 0x29, kFont + 5 * kx,
-                                  pick((nn == 0x55) | (nn == 0x65), (I + x + 1) & 0xFFF, I)));
+                                  pick(((nn == 0x55) | (nn == 0x65)) & !(quirks & kQuirkMemKeepI), (I + x + 1) & 0xFFF, I)));
     c.I = pick(h == 0xA, nnn, pick(isF, iF, I));
     c.dt = pick(isF & (nn == 0x15), vx, c.dt);
     c.st = pick(isF & (nn == 0x18), vx, c.st);
+    return h == 0xD;
 }
 
 }  // namespace octax

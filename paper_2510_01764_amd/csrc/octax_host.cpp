@@ -61,6 +61,41 @@ const char *octax::check_wrappers(uint32_t sticky_q24, uint32_t noop_max, const 
     return nullptr;
 }
 
+const char *octax::check_profile(const octax_config *cfg, std::vector<uint32_t> &desc2) {
+    const uint32_t R = cfg->num_roms;
+    if (!(cfg->quirks & OCTAX_QUIRKS_V1)) return "quirks must include OCTAX_QUIRKS_V1";
+    if (cfg->quirks & ~0x7Fu) return "unknown quirk flag";
+    if (!cfg->h_score_mode != !cfg->h_score_arg) return "h_score_mode and h_score_arg must be given together";
+    const bool t2 = cfg->h_term2_op || cfg->h_term2_reg || cfg->h_term2_value;
+    if (t2 && !(cfg->h_term2_op && cfg->h_term2_reg && cfg->h_term2_value))
+        return "h_term2_op, h_term2_reg and h_term2_value must be given together";
+    desc2.clear();
+    if (!cfg->h_score_mode && !cfg->h_term_op && !t2) return nullptr;
+    desc2.assign(R, 0);
+    for (uint32_t r = 0; r < R; r++) {
+        uint32_t mode = 0, arg = 0, op1 = 1, op2 = 0, reg2 = 0, val2 = 0;
+        if (cfg->h_score_mode) {
+            mode = cfg->h_score_mode[r];
+            arg = cfg->h_score_arg[r];
+            if (mode > 3) return "score mode > 3";
+            if (mode == 2 && arg > 15) return "score mode 2 needs a register index 0..15 in h_score_arg";
+        }
+        if (cfg->h_term_op) {
+            op1 = cfg->h_term_op[r];
+            if (op1 > 4) return "termination op > 4";
+        }
+        if (t2) {
+            op2 = cfg->h_term2_op[r];
+            reg2 = cfg->h_term2_reg[r];
+            val2 = cfg->h_term2_value[r];
+            if (op2 > 4) return "term2 op > 4";
+            if (reg2 > 15) return "term2 register index > 15";
+        }
+        desc2[r] = mode | (arg << 2) | (op1 << 10) | (op2 << 13) | (reg2 << 16) | (val2 << 24);
+    }
+    return nullptr;
+}
+
 octax::Wrap octax::make_wrap(const uint8_t *d_table, const std::vector<uint8_t> &table, uint32_t sticky_q24,
                              uint32_t noop_max, uint32_t ipf, uint32_t frame_skip) {
     Wrap w{};
@@ -222,7 +257,6 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     *out = nullptr;
     if (!cfg) return fail(OCTAX_E_INVALID, "octax_create: cfg is NULL");
     if (cfg->abi_version != OCTAX_ABI_VERSION) return fail(OCTAX_E_INVALID, "octax_create: abi_version mismatch");
-    if (cfg->quirks != OCTAX_QUIRKS_V1) return fail(OCTAX_E_INVALID, "octax_create: quirks must be OCTAX_QUIRKS_V1");
     const uint32_t E = cfg->num_envs, R = cfg->num_roms;
     if (E == 0 || E > (1u << 26)) return fail(OCTAX_E_INVALID, "octax_create: num_envs out of range");
     if (R == 0 || R > 65535) return fail(OCTAX_E_INVALID, "octax_create: num_roms out of range");
@@ -250,6 +284,9 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     std::vector<uint8_t> startup;
     if (const char *err = octax::check_wrappers(cfg->sticky_q24, cfg->noop_max, cfg->h_startup_len,
                                                 cfg->h_startup_keys, R, startup))
+        return fail(OCTAX_E_INVALID, std::string("octax_create: ") + err);
+    std::vector<uint32_t> desc2;
+    if (const char *err = octax::check_profile(cfg, desc2))
         return fail(OCTAX_E_INVALID, std::string("octax_create: ") + err);
 
     octax_engine *g = new (std::nothrow) octax_engine;
@@ -295,7 +332,7 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     }
 
     hipError_t e = hipSuccess;
-    uint32_t *rom_of = nullptr, *hor = nullptr, *env_of = nullptr, *d_desc = nullptr;
+    uint32_t *rom_of = nullptr, *hor = nullptr, *env_of = nullptr, *d_desc = nullptr, *d_desc2 = nullptr;
     uint8_t *d_img = nullptr, *d_keys = nullptr;
 #define TRY(x)                                                    \
     do {                                                          \
@@ -334,6 +371,10 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     TRY(hipMemcpy(d_img, image.data(), image.size(), hipMemcpyHostToDevice));
     TRY(hipMemcpy(d_keys, cfg->h_action_keys, 16 * (size_t)R, hipMemcpyHostToDevice));
     TRY(hipMemcpy(d_desc, desc.data(), 4 * (size_t)R, hipMemcpyHostToDevice));
+    if (!desc2.empty()) {
+        TRY(g->alloc(&d_desc2, R));
+        TRY(hipMemcpy(d_desc2, desc2.data(), 4 * (size_t)R, hipMemcpyHostToDevice));
+    }
     g->s.rom_of = rom_of;
     g->s.horizon = hor;
     g->s.env_of = env_of;
@@ -341,6 +382,9 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     g->roms.image = d_img;
     g->roms.keys = d_keys;
     g->roms.desc = d_desc;
+    g->roms.desc2 = d_desc2;
+    g->roms.quirks = cfg->quirks;
+    g->roms.profile = (cfg->quirks != OCTAX_QUIRKS_V1 || d_desc2) ? 1u : 0u;
     g->roms.w = octax::make_wrap(g->d_startup, startup, cfg->sticky_q24, cfg->noop_max, g->ipf, g->frame_skip);
     TRY(upload_block_roms(g));
     TRY(launch_reset(g->s, g->roms, nullptr, true, g->stream));

@@ -141,6 +141,12 @@ int32_t octax_pool_create(const octax_pool_config *cfg, octax_pool **out) {
     ec.noop_max = cfg->noop_max;
     ec.h_startup_len = cfg->h_startup_len;
     ec.h_startup_keys = cfg->h_startup_keys;
+    ec.h_score_mode = cfg->h_score_mode;
+    ec.h_score_arg = cfg->h_score_arg;
+    ec.h_term_op = cfg->h_term_op;
+    ec.h_term2_op = cfg->h_term2_op;
+    ec.h_term2_reg = cfg->h_term2_reg;
+    ec.h_term2_value = cfg->h_term2_value;
 
     octax_pool *p = new (std::nothrow) octax_pool;
     if (!p) return fail(OCTAX_E_NOMEM, "octax_pool_create: out of host memory");

@@ -367,6 +367,37 @@ struct FusedMem {
         if (vm & 0x7F00u) hit |= draw_rows<8, 7>(fbw, x0, vm, s0w, s1w, rbw);
         return hit != 0;
     }
+    // DXYN with the pixel-wrap quirk: all n rows are drawn, row y0 + r at
+    // (y0 + r) & 31, and the sprite byte is rotated so that pixels past
+    // x = 63 land at the left edge.  A loop over the env's own rows.
+    __device__ __forceinline__ uint32_t draw_wrap(uint32_t x0, uint32_t y0, uint32_t I, uint32_t n) {
+        const uint32_t off = I & 63;
+        const uint32_t p0 = I >> 6, p1 = ((I + max(n, 1u) - 1) & 0xFFF) >> 6;
+        bool slow = false;
+        const lds_u8 *q0 = lds_page_sel(p0, slow), *q1 = lds_page_sel(p1, slow);
+        if (slow) {
+            make_resident(p1, make_resident(p0, -1));
+            bool no = false;
+            q0 = lds_page_sel(p0, no);
+            q1 = lds_page_sel(p1, no);
+        }
+        touch(p0);
+        touch(p1);
+        lds_u64 *fb = (lds_u64 *)&sh.fb[lane][0];
+        uint64_t hit = 0;
+        for (uint32_t r = 0; r < n; r++) {
+            const uint32_t sb = off + r < 64 ? q0[off + r] : q1[off + r - 64];
+            const uint64_t m = __builtin_rotateright64((uint64_t)sb << 56, x0);
+            const uint32_t yy = (y0 + r) & 31;
+            const uint64_t row = fb[yy];
+            hit |= row & m;
+            fb[yy] = row ^ m;
+        }
+        return hit != 0;
+    }
+    __device__ __forceinline__ uint32_t draw(uint32_t x0, uint32_t y0, uint32_t I, uint32_t n, bool wrap) {
+        return wrap ? draw_wrap(x0, y0, I, n) : draw(x0, y0, I, n);
+    }
     __device__ __forceinline__ void clear() {
         lds_u64 *fb = (lds_u64 *)&sh.fb[lane][0];
 #pragma unroll
@@ -424,6 +455,25 @@ __device__ __forceinline__ void wait_flag(const uint32_t *f, uint32_t v) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// One environment step of emulation with `key` held: frame_skip frames of
+// ipf instructions, each followed by a timer tick.  With the display-wait
+// quirk (kProfile variants only) a lane's DXYN ends its frame: the lane sits
+// out the frame's remaining instruction slots.
+template <bool kProfile, class Mem>
+__device__ __forceinline__ void run_frames(Core &c, Mem &mem, uint32_t key, uint32_t ipf, uint32_t fs,
+                                           uint32_t quirks) {
+    for (uint32_t f = 0; f < fs; f++) {
+        bool run = true;
+        for (uint32_t i = 0; i < ipf; i++) {
+            if (!kProfile || run) {
+                const bool drew = exec_grouped(c, mem, key, quirks);
+                run = !(drew && (quirks & kQuirkDisplayWait));
+            }
+        }
+        tick(c);
+    }
+}
+
 // Lane l's share of one packed frame: bytes [16l, 16l+16) and [1024+16l, ...).
 __device__ __forceinline__ void store_frame(uint8_t *frame, uint32_t lane64, uint32_t w) {
     store16(frame + 16 * lane64, w & 0xFFFF);
@@ -449,8 +499,10 @@ __device__ __forceinline__ void store_frame(uint8_t *frame, uint32_t lane64, uin
 // K = 1 launches of octax_step into two instantiations of the same code, so
 // profiles report them apart.  kResetSteps instantiates the emulation steps
 // of a reset (start-up sequence, no-op reset); without those wrappers the
-// kernel carries no second copy of the instruction cycle.
-template <int IPW, bool kRollout, bool kResetSteps>
+// kernel carries no second copy of the instruction cycle.  kProfile
+// instantiates the quirk flags and the extra game descriptors (score mode,
+// second termination clause); without them those selects fold away.
+template <int IPW, bool kRollout, bool kResetSteps, bool kProfile>
 __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms, StepIO io, FusedCfg cfg) {
     __shared__ Shared<IPW> sh;
     const uint32_t tid = threadIdx.x;
@@ -487,7 +539,8 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     }
 
     Core c;
-    uint32_t head = 0, env = 0, rom = 0, desc = 0, t = 0, hor = 0, tags = 0;
+    uint32_t head = 0, env = 0, rom = 0, desc = 0, desc2 = kDesc2Default, t = 0, hor = 0, tags = 0;
+    const uint32_t quirks = kProfile ? roms.quirks : 0u;   // 0: the base profile
     int32_t prev = 0;
     uint64_t dirty = 0;
     u32x4 keys = {0, 0, 0, 0};   // the ROM's 16 action keys, one byte each
@@ -498,6 +551,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
         env = s.env_of[slot];
         rom = s.rom_of[slot];
         desc = roms.desc[rom];
+        if (kProfile && roms.desc2) desc2 = roms.desc2[rom];
         keys = *reinterpret_cast<const u32x4 *>(roms.keys + (size_t)rom * 16);
     }
     const uint32_t nact = desc >> 24;
@@ -604,13 +658,10 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             if (k > 0) wait_flag(&sh.taken[wave], k);
             if (active) {
                 const uint32_t key = sticky_key(roms, c, sh.key[k & 1][l]);
-                for (uint32_t f = 0; f < io.frame_skip; f++) {
-                    for (uint32_t i = 0; i < io.ipf; i++) exec_grouped(c, mem, key);
-                    tick(c);
-                }
-                const int32_t score = (int32_t)vget(c.r, desc & 15);
+                run_frames<kProfile>(c, mem, key, io.ipf, io.frame_skip, quirks);
+                const int32_t score = score_of(c.r, desc, desc2);
                 const float reward = (float)(score - prev);
-                const uint32_t term = vget(c.r, (desc >> 8) & 15) == ((desc >> 16) & 0xFF);
+                const uint32_t term = terminated_of(c.r, desc, desc2);
                 t += 1;
                 const uint32_t trunc = (hor != 0) && (t >= hor);
                 const uint32_t done = term | (trunc << 1);
@@ -624,15 +675,12 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                     for (int q = 0; q < 8; q++) sh.stack[l][q] = 0;
                     if (kResetSteps) {
                         run_reset_steps(roms, rom, c, [&](uint32_t rkey) {
-                            for (uint32_t f = 0; f < io.frame_skip; f++) {
-                                for (uint32_t i = 0; i < io.ipf; i++) exec_grouped(c, mem, rkey);
-                                tick(c);
-                            }
+                            run_frames<kProfile>(c, mem, rkey, io.ipf, io.frame_skip, quirks);
                         });
                     }
                     head = 0;
                     t = 0;
-                    prev = (int32_t)vget(c.r, desc & 15);   // the score after the reset's steps
+                    prev = score_of(c.r, desc, desc2);   // the score after the reset's steps
                 } else {
                     prev = score;
                     head = (head + 1) & 3;
@@ -780,19 +828,25 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     }
 }
 
-template <int IPW, bool kResetSteps>
+template <int IPW, bool kResetSteps, bool kProfile>
 hipError_t launch_variant(const State &s, const Roms &r, const StepIO &io, const FusedCfg &f, hipStream_t st) {
     const uint32_t blocks = (s.num + IPW - 1) / IPW;
     if (io.K == 1)
-        hipLaunchKernelGGL((step_fused_kernel<IPW, false, kResetSteps>), dim3(blocks), dim3(2 * IPW), 0, st, s, r, io, f);
+        hipLaunchKernelGGL((step_fused_kernel<IPW, false, kResetSteps, kProfile>), dim3(blocks), dim3(2 * IPW), 0, st,
+                           s, r, io, f);
     else
-        hipLaunchKernelGGL((step_fused_kernel<IPW, true, kResetSteps>), dim3(blocks), dim3(2 * IPW), 0, st, s, r, io, f);
+        hipLaunchKernelGGL((step_fused_kernel<IPW, true, kResetSteps, kProfile>), dim3(blocks), dim3(2 * IPW), 0, st,
+                           s, r, io, f);
     return hipGetLastError();
 }
 
 template <int IPW>
 hipError_t launch_ipw(const State &s, const Roms &r, const StepIO &io, const FusedCfg &f, hipStream_t st) {
-    return r.w.reset_steps ? launch_variant<IPW, true>(s, r, io, f, st) : launch_variant<IPW, false>(s, r, io, f, st);
+    if (r.profile)
+        return r.w.reset_steps ? launch_variant<IPW, true, true>(s, r, io, f, st)
+                               : launch_variant<IPW, false, true>(s, r, io, f, st);
+    return r.w.reset_steps ? launch_variant<IPW, true, false>(s, r, io, f, st)
+                           : launch_variant<IPW, false, false>(s, r, io, f, st);
 }
 
 }  // namespace

@@ -36,13 +36,16 @@ struct PlainMem {
         }
     }
     // XOR rows of the sprite onto the display; bits past x = 63 fall off the
-    // right of the shifted mask, rows past y = 31 are skipped.
-    __device__ __forceinline__ uint32_t draw(uint32_t x0, uint32_t y0, uint32_t I, uint32_t n) {
+    // right of the shifted mask, rows past y = 31 are skipped.  With the
+    // pixel-wrap quirk the byte is rotated instead and rows wrap to the top.
+    __device__ __forceinline__ uint32_t draw(uint32_t x0, uint32_t y0, uint32_t I, uint32_t n, bool wrap) {
         uint64_t hit = 0;
         for (uint32_t r = 0; r < n; r++) {
-            const uint32_t yy = y0 + r;
-            if (yy >= 32) break;
-            const uint64_t m = ((uint64_t)ram[(I + r) & 0xFFF] << 56) >> x0;
+            uint32_t yy = y0 + r;
+            if (yy >= 32 && !wrap) break;
+            yy &= 31;
+            const uint64_t s = (uint64_t)ram[(I + r) & 0xFFF] << 56;
+            const uint64_t m = wrap ? __builtin_rotateright64(s, x0) : s >> x0;
             const uint64_t row = fb[yy];
             hit |= row & m;
             fb[yy] = row ^ m;
@@ -63,9 +66,11 @@ struct PlainMem {
 };
 
 // One environment step of emulation with `key` held.
-__device__ __forceinline__ void plain_env_step(Core &c, PlainMem &mem, uint32_t key, uint32_t ipf, uint32_t fs) {
+__device__ __forceinline__ void plain_env_step(Core &c, PlainMem &mem, uint32_t key, uint32_t ipf, uint32_t fs,
+                                               uint32_t quirks) {
     for (uint32_t f = 0; f < fs; f++) {
-        for (uint32_t i = 0; i < ipf; i++) exec_one(c, mem, key);
+        for (uint32_t i = 0; i < ipf; i++)
+            if (exec_one(c, mem, key, quirks) && (quirks & kQuirkDisplayWait)) break;   // waits for the next frame
         tick(c);
     }
 }
@@ -90,6 +95,7 @@ __global__ __launch_bounds__(256) void step_plain_kernel(State s, Roms roms, Ste
     const uint32_t env = s.env_of[slot];
     const uint32_t rom = s.rom_of[slot];
     const uint32_t desc = roms.desc[rom];
+    const uint32_t desc2 = roms.desc2 ? roms.desc2[rom] : kDesc2Default;
 
     Core c;
     uint32_t head;
@@ -98,12 +104,12 @@ __global__ __launch_bounds__(256) void step_plain_kernel(State s, Roms roms, Ste
     PlainMem mem{s.ram + (size_t)slot * kMem, s.fb + (size_t)slot * 32, s.stack + (size_t)slot * 8,
                  s.dirty[slot]};
 
-    plain_env_step(c, mem, key, io.ipf, io.frame_skip);
+    plain_env_step(c, mem, key, io.ipf, io.frame_skip, roms.quirks);
 
-    const int32_t score = (int32_t)vget(c.r, desc & 15);
+    const int32_t score = score_of(c.r, desc, desc2);
     int32_t prev = s.prev[slot];
     const float reward = (float)(score - prev);
-    const uint32_t term = vget(c.r, (desc >> 8) & 15) == ((desc >> 16) & 0xFF);
+    const uint32_t term = terminated_of(c.r, desc, desc2);
     uint32_t t = s.t[slot] + 1;
     const uint32_t hor = s.horizon[slot];
     const uint32_t trunc = (hor != 0) && (t >= hor);
@@ -131,10 +137,10 @@ __global__ __launch_bounds__(256) void step_plain_kernel(State s, Roms roms, Ste
         mem.clear();
         for (int q = 0; q < 8; q++) mem.stack[q] = 0;
         if (roms.w.reset_steps)
-            run_reset_steps(roms, rom, c, [&](uint32_t rk) { plain_env_step(c, mem, rk, io.ipf, io.frame_skip); });
+            run_reset_steps(roms, rom, c, [&](uint32_t rk) { plain_env_step(c, mem, rk, io.ipf, io.frame_skip, roms.quirks); });
         head = 0;
         t = 0;
-        prev = (int32_t)vget(c.r, desc & 15);   // the score after the reset's steps
+        prev = score_of(c.r, desc, desc2);   // the score after the reset's steps
     } else {
         prev = score;
         head = (head + 1) & 3;
@@ -187,19 +193,20 @@ __global__ __launch_bounds__(256) void reset_steps_kernel(State s, Roms roms, co
     if (mask && !mask[s.env_of[slot]]) return;
     const uint32_t rom = s.rom_of[slot];
     const uint32_t desc = roms.desc[rom];
+    const uint32_t desc2 = roms.desc2 ? roms.desc2[rom] : kDesc2Default;
     Core c;
     uint32_t head;
     load_core(s, slot, c, head);
     PlainMem mem{s.ram + (size_t)slot * kMem, s.fb + (size_t)slot * 32, s.stack + (size_t)slot * 8,
                  s.dirty[slot]};
-    run_reset_steps(roms, rom, c, [&](uint32_t rk) { plain_env_step(c, mem, rk, roms.w.ipf, roms.w.frame_skip); });
+    run_reset_steps(roms, rom, c, [&](uint32_t rk) { plain_env_step(c, mem, rk, roms.w.ipf, roms.w.frame_skip, roms.quirks); });
     uint32_t pw[64];
     pack_display(mem.fb, pw);
     uint4 *ring = reinterpret_cast<uint4 *>(s.cols + (size_t)slot * 256);
     for (uint32_t q = 0; q < 4; q++)
         for (int w = 0; w < 16; w++) ring[q * 16 + w] = make_uint4(pw[4 * w], pw[4 * w + 1], pw[4 * w + 2], pw[4 * w + 3]);
     store_core(s, slot, c, head);
-    s.prev[slot] = (int32_t)vget(c.r, desc & 15);
+    s.prev[slot] = score_of(c.r, desc, desc2);
     s.dirty[slot] = mem.dirty;
 }
 

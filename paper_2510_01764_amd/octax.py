@@ -16,8 +16,14 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liboctax.so")
 
-OCTAX_ABI_VERSION = 2
+OCTAX_ABI_VERSION = 3
 OCTAX_QUIRKS_V1 = 1
+OCTAX_QUIRK_SHIFT_VX = 1 << 1
+OCTAX_QUIRK_MEM_KEEP_I = 1 << 2
+OCTAX_QUIRK_JUMP_VX = 1 << 3
+OCTAX_QUIRK_NO_VF_RESET = 1 << 4
+OCTAX_QUIRK_PIXEL_WRAP = 1 << 5
+OCTAX_QUIRK_DISPLAY_WAIT = 1 << 6
 OCTAX_OK = 0
 OCTAX_E_INVALID = -1
 OCTAX_E_NOMEM = -2
@@ -61,6 +67,9 @@ class octax_config(ctypes.Structure):
         ("h_env_seed", ctypes.c_void_p), ("stream", ctypes.c_void_p),
         ("sticky_q24", ctypes.c_uint32), ("noop_max", ctypes.c_uint32),
         ("h_startup_len", ctypes.c_void_p), ("h_startup_keys", ctypes.c_void_p),
+        ("h_score_mode", ctypes.c_void_p), ("h_score_arg", ctypes.c_void_p),
+        ("h_term_op", ctypes.c_void_p), ("h_term2_op", ctypes.c_void_p),
+        ("h_term2_reg", ctypes.c_void_p), ("h_term2_value", ctypes.c_void_p),
     ]
 
 
@@ -77,6 +86,9 @@ class octax_pool_config(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("sticky_q24", ctypes.c_uint32), ("noop_max", ctypes.c_uint32),
         ("h_startup_len", ctypes.c_void_p), ("h_startup_keys", ctypes.c_void_p),
+        ("h_score_mode", ctypes.c_void_p), ("h_score_arg", ctypes.c_void_p),
+        ("h_term_op", ctypes.c_void_p), ("h_term2_op", ctypes.c_void_p),
+        ("h_term2_reg", ctypes.c_void_p), ("h_term2_value", ctypes.c_void_p),
     ]
 
 
@@ -92,7 +104,8 @@ _lib = None
 
 
 def _set_wrappers(cfg, spec, keep: dict) -> None:
-    """The environment-wrapper fields of a config from a spec (all off when absent)."""
+    """The environment-wrapper, quirk and game-descriptor fields of a config
+    from a spec (all off when absent)."""
     cfg.sticky_q24 = int(getattr(spec, "sticky_q24", 0))
     cfg.noop_max = int(getattr(spec, "noop_max", 0))
     if getattr(spec, "startup_len", None) is not None:
@@ -100,6 +113,12 @@ def _set_wrappers(cfg, spec, keep: dict) -> None:
         keep["startup_keys"] = np.ascontiguousarray(spec.startup_keys, dtype=np.uint8)
         cfg.h_startup_len = keep["startup_len"].ctypes.data
         cfg.h_startup_keys = keep["startup_keys"].ctypes.data
+    # quirk flags and game descriptors
+    cfg.quirks = int(getattr(spec, "quirks", OCTAX_QUIRKS_V1))
+    for f in ("score_mode", "score_arg", "term_op", "term2_op", "term2_reg", "term2_value"):
+        if getattr(spec, f, None) is not None:
+            keep[f] = np.ascontiguousarray(getattr(spec, f), dtype=np.uint8)
+            setattr(cfg, "h_" + f, keep[f].ctypes.data)
 
 
 def library() -> ctypes.CDLL:

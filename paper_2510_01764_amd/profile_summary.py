@@ -3,7 +3,7 @@
   python -m paper_2510_01764_amd.profile_summary stats <rocprof dir> <out.txt> --command "..."
       per-kernel call count and duration statistics (from --kernel-trace --stats)
   python -m paper_2510_01764_amd.profile_summary traffic <fetch dir> <write dir> <out.json>
-      --calib-bytes N --kernel "step_fused_kernel<256, true, false>" --command-fetch "..." --command-write "..."
+      --calib-bytes N --kernel "step_fused_kernel<256, true, false, false>" --command-fetch "..." --command-write "..."
       HBM bytes per launch of one kernel from FETCH_SIZE and WRITE_SIZE counter runs, each
       scaled by what the same counter reads for the calibration copy kernel of known size.
 """
@@ -32,10 +32,20 @@ def stats(d, out, command):
     for f in _find(d, "*kernel_stats.csv"):
         with open(f) as fh:
             rows += list(csv.DictReader(fh))
+    def short(name):
+        # namespace prefix and argument list dropped; template arguments kept
+        name = name.replace("void ", "", 1).replace("octax::(anonymous namespace)::", "")
+        depth = 0
+        for i, ch in enumerate(name):
+            depth += (ch == "<") - (ch == ">")
+            if ch == "(" and depth == 0:
+                return name[:i]
+        return name
+
     lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
-             f"{'kernel':<70} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_ms':>10} {'pct':>6}"]
+             f"{'kernel':<56} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_ms':>10} {'pct':>6}"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
-        lines.append(f"{r['Name'][:70]:<70} {int(r['Calls']):>6} {float(r['AverageNs'])/1e3:>10.1f} "
+        lines.append(f"{short(r['Name'])[:56]:<56} {int(r['Calls']):>6} {float(r['AverageNs'])/1e3:>10.1f} "
                      f"{float(r['MinNs'])/1e3:>10.1f} {float(r['MaxNs'])/1e3:>10.1f} "
                      f"{float(r['TotalDurationNs'])/1e6:>10.2f} {float(r['Percentage']):>6.2f}")
     text = "\n".join(lines) + "\n"

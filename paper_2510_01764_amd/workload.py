@@ -226,6 +226,25 @@ class EnvSpec:
     startup_len: Optional[np.ndarray] = None    # uint8 [R], 0..16
     startup_keys: Optional[np.ndarray] = None   # uint8 [R, 16]
 
+    # Quirk flags (bit 0 = the VIP base profile, bits 1..6 switch single
+    # behaviours, see octax.h) and game descriptors per ROM: score mode
+    # (0 V[score_reg], 1 BCD difference, 2 negated sum with V[score_arg],
+    # 3 capped at score_arg), the op of the termination clause (0 never,
+    # 1 ==, 2 >=, 3 !=, 4 either decimal digit ==; None = ==) and a second
+    # clause V[term2_reg] term2_op term2_value.
+    quirks: int = 1
+    score_mode: Optional[np.ndarray] = None     # uint8 [R]
+    score_arg: Optional[np.ndarray] = None      # uint8 [R], with score_mode
+    term_op: Optional[np.ndarray] = None        # uint8 [R]
+    term2_op: Optional[np.ndarray] = None       # uint8 [R]
+    term2_reg: Optional[np.ndarray] = None      # uint8 [R]
+    term2_value: Optional[np.ndarray] = None    # uint8 [R]
+
+    @property
+    def has_profile(self) -> bool:
+        return bool(self.quirks != 1 or self.score_mode is not None or self.term_op is not None
+                    or self.term2_op is not None)
+
     @property
     def has_wrappers(self) -> bool:
         return bool(self.sticky_q24 or self.noop_max or
@@ -280,6 +299,31 @@ def with_wrappers(spec: EnvSpec, sticky: float = 0.25, noop_max: int = 30, start
     keys = np.where(picks < nact[:, None], akeys[np.arange(R)[:, None], np.minimum(picks, 15)], 16)
     return dataclasses.replace(spec, sticky_q24=int(round(sticky * (1 << 24))), noop_max=int(noop_max),
                                startup_len=lens, startup_keys=keys.astype(np.uint8))
+
+
+def with_profile(spec: EnvSpec, quirks: int = 0x7F, seed: int = 0) -> EnvSpec:
+    """The spec with quirk flags and per-ROM game descriptors (Section 3.3).
+
+    ``quirks`` is the flag word (bit 0, the base profile, is always set).
+    Per ROM, drawn from ``seed``: a score mode 0..3 with its argument (a
+    register for the negated sum, a cap in 64..255 for the capped score); the
+    first clause's op (== mostly, else never, either-digit == or !=); and a
+    second clause - none, == a random value, >= a value in 0xE0..0xFF, or
+    either-digit == - on a random register, so that the clauses end some
+    episodes without ending all of them.
+    """
+    R = spec.num_roms
+    rng = np.random.Generator(np.random.PCG64([seed, 13]))
+    mode = rng.integers(0, 4, size=R)
+    arg = np.where(mode == 2, rng.integers(0, 16, size=R), rng.integers(64, 256, size=R))
+    op1 = rng.choice([1, 0, 4, 3], size=R, p=[0.5, 0.15, 0.2, 0.15])
+    op2 = rng.choice([0, 1, 2, 4], size=R)
+    value = np.where(op2 == 2, rng.integers(0xE0, 0x100, size=R),
+                     np.where(op2 == 4, rng.integers(0, 10, size=R), rng.integers(0, 0x100, size=R)))
+    u8 = lambda a: np.asarray(a).astype(np.uint8)
+    return dataclasses.replace(spec, quirks=int(quirks) | 1, score_mode=u8(mode), score_arg=u8(arg),
+                               term_op=u8(op1), term2_op=u8(op2),
+                               term2_reg=u8(rng.integers(0, 16, size=R)), term2_value=u8(value))
 
 
 def _descriptors(n_roms: int, keys: Sequence[Sequence[int]]):

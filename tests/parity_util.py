@@ -66,3 +66,46 @@ class Pair:
     def close(self):
         self.eng.close()
         self.orc.close()
+
+
+def run_rollouts(spec, kernel, K, launches, envs_per_block=256, graph=False):
+    """K-step launches (or graph replays) of the engine beside the oracle:
+    rewards, done flags and observations compared at every step, the full
+    architectural state after every launch.  Returns the number of resets."""
+    import torch
+    from oracle import oracle as O
+    from paper_2510_01764_amd import octax as X
+    E = spec.num_envs
+    dev = torch.device("cuda")
+    eng = X.Engine(spec, kernel=kernel, envs_per_block=envs_per_block)
+    orc = O.OracleBatch(spec)
+    compare_states(eng.get_state(), orc.get_state(), f"{kernel} after create")
+    act = torch.zeros((K, E), dtype=torch.int32, device=dev)
+    obs = torch.zeros((K, E, 4, 64, 32), dtype=torch.uint8, device=dev)
+    rew = torch.zeros((K, E), dtype=torch.float32, device=dev)
+    done = torch.zeros((K, E), dtype=torch.uint8, device=dev)
+    g = eng.graph(act, obs, rew, done) if graph else None
+    resets = 0
+    for rep in range(launches):
+        an = spec.actions(rep * K, K)
+        act.copy_(torch.from_numpy(an))
+        if g is not None:
+            g.launch()
+        else:
+            eng.step_many(act, obs, rew, done)
+        torch.cuda.synchronize()
+        r_np, d_np, o_np = rew.cpu().numpy(), done.cpu().numpy(), obs.cpu().numpy()
+        for k in range(K):
+            oo, orw, od = orc.step(an[k])
+            assert np.array_equal(r_np[k], orw), (kernel, rep, k, np.nonzero(r_np[k] != orw)[0][:8])
+            assert np.array_equal(d_np[k], od), (kernel, rep, k, np.nonzero(d_np[k] != od)[0][:8])
+            if not np.array_equal(o_np[k], oo):
+                bad = np.unique(np.nonzero(o_np[k] != oo)[0])
+                raise AssertionError(f"{kernel} launch {rep} step {k}: obs differs at envs {bad[:8]}")
+            resets += int((od != 0).sum())
+        compare_states(eng.get_state(), orc.get_state(), f"{kernel} launch {rep}")
+    if g is not None:
+        g.close()
+    eng.close()
+    orc.close()
+    return resets

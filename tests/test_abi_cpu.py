@@ -38,7 +38,8 @@ def test_struct_layouts_match_header():
     src = ('#include <stdio.h>\n#include <stddef.h>\n#include "octax.h"\n'
            'int main(){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(octax_config), sizeof(octax_env_state),'
            ' offsetof(octax_env_state, ram), offsetof(octax_config, h_rom_data),'
-           ' offsetof(octax_config, sticky_q24), offsetof(octax_env_state, prev_key));}\n')
+           ' offsetof(octax_config, sticky_q24), offsetof(octax_env_state, prev_key));'
+           ' printf("%zu %zu\\n", offsetof(octax_config, h_score_mode), offsetof(octax_config, h_term2_value));}\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
@@ -50,6 +51,8 @@ def test_struct_layouts_match_header():
     assert int(out[2]) == X.ENV_STATE_DTYPE.fields["ram"][1]
     assert int(out[3]) == X.octax_config.h_rom_data.offset
     assert int(out[4]) == X.octax_config.sticky_q24.offset
+    assert int(out[6]) == X.octax_config.h_score_mode.offset
+    assert int(out[7]) == X.octax_config.h_term2_value.offset
     assert int(out[5]) == X.ENV_STATE_DTYPE.fields["prev_key"][1]
 
 
@@ -74,7 +77,7 @@ def _cfg(**over):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("abi_version", 99), ("quirks", 2), ("num_envs", 0), ("num_roms", 0), ("instr_per_frame", 0),
+    ("abi_version", 99), ("abi_version", 2), ("quirks", 2), ("quirks", 0), ("quirks", 1 | (1 << 7)), ("num_envs", 0), ("num_roms", 0), ("instr_per_frame", 0),
     ("frame_skip", 0), ("frame_skip", 65), ("kernel", 7), ("placement", 9), ("envs_per_block", 96),
     ("lanes_per_env", 4), ("h_env_seed", None),
 ])
@@ -104,6 +107,31 @@ def test_create_rejects_bad_wrappers_without_gpu():
     c, keep = _cfg(h_startup_len=lens.ctypes.data)            # keys missing
     assert L.octax_create(ctypes.byref(c), ctypes.byref(h)) == X.OCTAX_E_INVALID
     assert not h.value
+
+
+def test_create_rejects_bad_descriptors_without_gpu():
+    import numpy as np
+    L = X.library()
+    h = ctypes.c_void_p()
+    u = lambda v: np.array([v], np.uint8)
+    bad = [
+        dict(h_score_mode=u(4), h_score_arg=u(0)),                       # no such score mode
+        dict(h_score_mode=u(2), h_score_arg=u(16)),                      # negated sum needs a register
+        dict(h_score_mode=u(1)),                                         # argument missing
+        dict(h_term_op=u(5)),
+        dict(h_term2_op=u(1), h_term2_reg=u(3)),                         # constant missing
+        dict(h_term2_op=u(5), h_term2_reg=u(3), h_term2_value=u(9)),
+        dict(h_term2_op=u(2), h_term2_reg=u(16), h_term2_value=u(9)),
+        dict(quirks=1 | (1 << 7)),
+    ]
+    for over in bad:
+        arrs = {k: v for k, v in over.items() if isinstance(v, np.ndarray)}
+        fields = {k: (v.ctypes.data if isinstance(v, np.ndarray) else v) for k, v in over.items()}
+        c, keep = _cfg(**fields)
+        assert L.octax_create(ctypes.byref(c), ctypes.byref(h)) == X.OCTAX_E_INVALID, over
+        assert L.octax_last_error().decode(), over
+        assert not h.value
+        del arrs
 
 
 def test_create_rejects_long_rom_and_bad_rom_index():
@@ -140,7 +168,8 @@ def test_pool_config_layout_matches_header():
     import tempfile
     src = ('#include <stdio.h>\n#include <stddef.h>\n#include "octax.h"\n'
            'int main(){printf("%zu %zu %zu\\n", sizeof(octax_pool_config),'
-           ' offsetof(octax_pool_config, pool_bytes), offsetof(octax_pool_config, stream));}\n')
+           ' offsetof(octax_pool_config, pool_bytes), offsetof(octax_pool_config, stream));'
+           ' printf("%zu\\n", offsetof(octax_pool_config, h_term2_value));}\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "p.c")
         open(c, "w").write(src)
@@ -150,6 +179,7 @@ def test_pool_config_layout_matches_header():
     assert int(out[0]) == ctypes.sizeof(X.octax_pool_config)
     assert int(out[1]) == X.octax_pool_config.pool_bytes.offset
     assert int(out[2]) == X.octax_pool_config.stream.offset
+    assert int(out[3]) == X.octax_pool_config.h_term2_value.offset
 
 
 def _pool_cfg(**over):
@@ -170,8 +200,8 @@ def _pool_cfg(**over):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("abi_version", 3), ("num_roms", 0), ("pool_bytes", 100), ("instr_per_frame", 0),
-    ("quirks", 0), ("envs_per_block", 100), ("h_num_actions", None),
+    ("abi_version", 99), ("num_roms", 0), ("pool_bytes", 100), ("instr_per_frame", 0),
+    ("quirks", 0), ("quirks", 0x81), ("envs_per_block", 100), ("h_num_actions", None),
 ])
 def test_pool_create_rejects_bad_config_without_gpu(field, value):
     L = X.library()

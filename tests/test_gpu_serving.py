@@ -78,14 +78,17 @@ def test_pool_admit_retire_and_info():
     pool.close()
 
 
-@pytest.mark.parametrize("depth,wrappers", [(1, False), (2, False), (2, True)])
-def test_groups_in_the_mix_match_groups_alone(depth, wrappers):
+@pytest.mark.parametrize("depth,wrappers,profile", [(1, False, False), (2, False, False), (2, True, False),
+                                                   (2, False, True)])
+def test_groups_in_the_mix_match_groups_alone(depth, wrappers, profile):
     from oracle import oracle as O
     from paper_2510_01764_amd import serving as S
     from paper_2510_01764_amd import workload as W
     spec = W.make_config("c4")
     if wrappers:   # sticky actions, no-op reset and start-up sequences at every admission and reset
         spec = W.with_wrappers(spec, sticky=0.25, noop_max=6, startup_max=3, seed=2)
+    if profile:    # every quirk flag and per-ROM game descriptors
+        spec = W.with_profile(spec, quirks=0x7F, seed=3)
     groups = W.serving_groups(18, rate=3000.0, seed=21, n_roms=32, max_size=400,
                               min_steps=20, max_steps=70)
     be = S.PoolBackend(spec, pool_bytes=700 * 5470, depth=depth)
