@@ -138,6 +138,8 @@ def main():
                     help="skip the leg with sticky actions, no-op reset and start-up sequences")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the leg with every quirk flag and per-ROM game descriptors")
+    ap.add_argument("--no-programs", action="store_true",
+                    help="skip the leg on the Target Shooter programs")
     ap.add_argument("--tune", choices=["auto", "default"], default="auto")
     ap.add_argument("--serving-groups", type=int, default=2000,
                     help="groups of the serving run (0 = skip it)")
@@ -247,16 +249,17 @@ def main():
         gp.close()
         engp.close()
 
-    def variant_leg(vspec):
-        """Graph replays of the same workload under another spec; (env steps/s, ms per replay, replays)."""
+    def variant_leg(vspec, pool=None):
+        """Graph replays of the same launch shape under another spec; (env steps/s, ms per replay, replays)."""
+        pool = act_pool if pool is None else pool
         engv = X.Engine(vspec, kernel="fused", envs_per_block=tuning["envs_per_block"],
                         rom_in_lds=tuning["rom_in_lds"], stream=stream)
         gv = engv.graph(act, obs, rew, done)
-        time_replays(torch, stream, gv, act, act_pool, 1, 0)
+        time_replays(torch, stream, gv, act, pool, 1, 0)
         stream.synchronize()
         n_v = max(2, args.steps // 4)
         t0 = time.perf_counter()
-        time_replays(torch, stream, gv, act, act_pool, n_v, args.warmup)
+        time_replays(torch, stream, gv, act, pool, n_v, args.warmup)
         stream.synchronize()
         vwall = time.perf_counter() - t0
         resets = float((done != 0).float().mean().item())
@@ -286,6 +289,17 @@ def main():
                         "term_op": [int(x) for x in qspec.term_op],
                         "term2_op": [int(x) for x in qspec.term2_op]})
         log(f"profile: {profile['value'] / 1e6:.1f} M env steps/s ({profile['ms_per_step']:.2f} ms per replay)")
+
+    # a second workload: the three Target Shooter levels (Octo programs
+    # assembled in-tree), 65,536 envs, uniform random actions over its 5 keys
+    shooter = None
+    if not args.no_programs and E == 65536:
+        tspec = W.make_config("ts")
+        tpool = torch.from_numpy(tspec.actions(0, n_pool * K).reshape(n_pool, K, E)).to(dev)
+        shooter = variant_leg(tspec, tpool)
+        shooter.update({"workload": "Target Shooter levels 1-3, 65,536 envs, a third each, keys 5 7 8 9 6, "
+                                    "score V2, done V3 == 1, geometric horizons mean 500"})
+        log(f"target shooter: {shooter['value'] / 1e6:.1f} M env steps/s ({shooter['ms_per_step']:.2f} ms per replay)")
 
     serving = None
     if args.serving_groups > 0:
@@ -327,6 +341,7 @@ def main():
         "fused_over_plain": (value / plain["value"]) if plain else None,
         "wrappers": wrappers,
         "profile": profile,
+        "target_shooter": shooter,
         "calib_write_GBs": write_gbs,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

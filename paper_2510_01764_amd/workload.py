@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import Dict, List, Optional, Sequence
 
 import numpy as np
@@ -353,6 +354,10 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
             serving module); here E is a placeholder of one env per ROM.
     ``c5``  1,048,576 envs over 64 draw-heavy ROMs (40% DXYN, N up to 15,
             edge-biased coordinates), ipf 20, geometric horizons.
+    ``ts``  65,536 envs over the three Target Shooter levels (written in Octo
+            for this repository, see programs/), a third of the envs each in
+            random order, keys 5 7 8 9 6, score V2, done when V3 == 1, ipf 10,
+            geometric horizons (mean 500).
     ``num_envs`` and ``steps`` override the sizes (for tests at small scale).
     """
     name = name.lower()
@@ -366,6 +371,8 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
         seed, E, R, L, keys, ipf, steps_ = 3, 32, 32, None, KEYS_8, 10, 200
     elif name == "c5":
         seed, E, R, L, keys, ipf, steps_ = 4, 1 << 20, 64, None, KEYS_8, 20, 1000
+    elif name == "ts":
+        seed, E, R, L, keys, ipf, steps_ = 5, 65536, 3, None, KEYS_5, 10, 64
     else:
         raise KeyError(name)
     if num_envs is not None:
@@ -375,6 +382,9 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
     rng = np.random.Generator(np.random.PCG64(seed))
     roms: List[bytes] = []
     for r_ in range(R):
+        if name == "ts":
+            roms = target_shooter_roms()
+            break
         if L is not None:
             n, mix = L[r_], OpcodeMix()
         elif name == "c5":
@@ -400,6 +410,8 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
         env_rom = (np.arange(E) % R).astype(np.uint16)
         env_rom = env_rom[rng.permutation(E)]
     akeys, nact, sreg, treg, tval = _descriptors(R, [keys] * R)
+    if name == "ts":   # score V2, game over when V3 == 1 (the Target Shooter wrapper)
+        sreg[:], treg[:], tval[:] = 2, 3, 1
     if name in ("c1", "c2"):
         horizon = np.full(E, 1000, dtype=np.uint32)
     else:
@@ -409,6 +421,19 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
                    score_reg=sreg, term_reg=treg, term_value=tval, horizon=horizon,
                    env_seed=env_seed, instr_per_frame=ipf, frame_skip=4, steps=steps_,
                    action_seed=seed + 7919)
+
+
+PROGRAMS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "programs")
+
+
+def target_shooter_roms() -> List[bytes]:
+    """The three Target Shooter levels, assembled from their Octo sources."""
+    from . import octo
+    out = []
+    for level in (1, 2, 3):
+        with open(os.path.join(PROGRAMS, f"target_shooter_l{level}.8o")) as f:
+            out.append(octo.assemble(f.read()))
+    return out
 
 
 def custom_spec(roms: Sequence[bytes], num_envs: int = 1, *, keys: Sequence[int] = KEYS_5,
