@@ -140,6 +140,7 @@ def main():
                     help="skip the leg with every quirk flag and per-ROM game descriptors")
     ap.add_argument("--no-programs", action="store_true",
                     help="skip the leg on the Target Shooter programs")
+    ap.add_argument("--no-schip", action="store_true", help="skip the SUPER-CHIP leg")
     ap.add_argument("--tune", choices=["auto", "default"], default="auto")
     ap.add_argument("--serving-groups", type=int, default=2000,
                     help="groups of the serving run (0 = skip it)")
@@ -301,6 +302,35 @@ def main():
                                     "score V2, done V3 == 1, geometric horizons mean 500"})
         log(f"target shooter: {shooter['value'] / 1e6:.1f} M env steps/s ({shooter['ms_per_step']:.2f} ms per replay)")
 
+    # SUPER-CHIP (128x64, (4, 128, 64) observations): 16,384 envs on the
+    # plain lane-per-env kernel, in the same observation bytes per launch
+    schip = None
+    if not args.no_schip and E * 8192 >= 16384 * 32768:
+        sspec = W.make_config("s1")
+        Es = sspec.num_envs
+        sobs = obs.view(-1)[: K * Es * 32768].view(K, Es, 4, 128, 64)
+        spool = torch.from_numpy(sspec.actions(0, n_pool * K).reshape(n_pool, K, Es)).to(dev)
+        sact = torch.empty((K, Es), dtype=torch.int32, device=dev)
+        srew = torch.empty((K, Es), dtype=torch.float32, device=dev)
+        sdone = torch.empty((K, Es), dtype=torch.uint8, device=dev)
+        engs = X.Engine(sspec, kernel="plain", stream=stream)
+        gs = engs.graph(sact, sobs, srew, sdone)
+        time_replays(torch, stream, gs, sact, spool, 1, 0)
+        stream.synchronize()
+        n_s = max(2, args.steps // 4)
+        t0 = time.perf_counter()
+        time_replays(torch, stream, gs, sact, spool, n_s, args.warmup)
+        stream.synchronize()
+        swall = time.perf_counter() - t0
+        schip = {"value": Es * K * n_s / swall, "ms_per_step": swall * 1e3 / n_s, "replays": n_s,
+                 "obs_GBs": Es * K * n_s * 32768 / swall / 1e9, "kernel": "plain (lane per env)",
+                 "workload": "SUPER-CHIP: 16,384 envs over 8 generated programs with 12% SUPER-CHIP "
+                             "instructions, 64 steps per graph replay, ipf 10, frame skip 4, "
+                             "4x128x64 uint8 obs, geometric horizons mean 500"}
+        log(f"schip: {schip['value'] / 1e6:.1f} M env steps/s ({schip['ms_per_step']:.2f} ms per replay)")
+        gs.close()
+        engs.close()
+
     serving = None
     if args.serving_groups > 0:
         serving = serving_run(args, lat, log)
@@ -342,6 +372,7 @@ def main():
         "wrappers": wrappers,
         "profile": profile,
         "target_shooter": shooter,
+        "schip": schip,
         "calib_write_GBs": write_gbs,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

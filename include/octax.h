@@ -65,7 +65,7 @@
 extern "C" {
 #endif
 
-#define OCTAX_ABI_VERSION 3u
+#define OCTAX_ABI_VERSION 4u
 #define OCTAX_QUIRKS_V1 1u
 
 /* Quirk flags, OR-ed with OCTAX_QUIRKS_V1 in the config's quirks field.
@@ -104,6 +104,12 @@ enum octax_status {
 enum octax_kernel {
     OCTAX_KERNEL_PLAIN = 0, /* one env per lane, state through HBM every step */
     OCTAX_KERNEL_FUSED = 1  /* K steps per launch, LDS-staged ROM and display, coalesced obs */
+};
+
+/* Platforms. */
+enum octax_platform {
+    OCTAX_PLATFORM_CHIP8 = 0,    /* 64x32 display, the profile above */
+    OCTAX_PLATFORM_SCHIP = 1     /* SUPER-CHIP: 128x64 display and its instructions (see octax_config) */
 };
 
 /* Placement of envs in the engine's state slots. */
@@ -180,7 +186,30 @@ typedef struct octax_config {
     const uint8_t *h_term2_op;      /* [R] 0..4 or NULL */
     const uint8_t *h_term2_reg;     /* [R] 0..15 */
     const uint8_t *h_term2_value;   /* [R] */
+    /* Platform (enum octax_platform).  SUPER-CHIP is the extension Section 5
+     * names: a 128x64 display (the 64x32 mode draws 2x2 blocks on it) and the
+     * instructions 00CN (scroll down N rows), 00FB / 00FC (scroll right /
+     * left 4 columns; scroll amounts are in pixels of the current mode),
+     * 00FD (stop: the program stays on that instruction), 00FE / 00FF (64x32
+     * / 128x64 mode, display cleared), DXY0 (16x16 sprite, 32 bytes),
+     * FX30 (I = 8x10 glyph of digit VX & 15, 10 bytes each at 0x0A0) and
+     * FX75 / FX85 (store / load V0..V(min(X, 7)) in eight flag registers).
+     * Power-on is the 64x32 mode with the flag registers cleared.
+     * Observations are uint8 [E][4][128][64] = [env][frame][x][y].
+     * SUPER-CHIP engines run on OCTAX_KERNEL_PLAIN only and take no
+     * start-up sequences or no-op resets (OCTAX_E_INVALID otherwise). */
+    uint32_t platform;
+    uint32_t reserved2;
 } octax_config;
+
+/* SUPER-CHIP part of one env's state (octax_get_schip_state). */
+typedef struct octax_schip_state {
+    uint32_t hires;           /* 1: 128x64 mode */
+    uint8_t rpl[8];           /* flag registers of FX75 / FX85 */
+    uint32_t reserved;
+    uint64_t fb[64][2];       /* display row y: fb[y][0] holds x 0..63, fb[y][1] x 64..127, bit 63 - (x mod 64) */
+    uint64_t hist[3][64][2];  /* the three frames before fb, oldest first, same packing */
+} octax_schip_state;
 
 /* Architectural state of one env (get_state / set_state). */
 typedef struct octax_env_state {
@@ -213,6 +242,15 @@ typedef struct octax_graph octax_graph;
  * flags), OCTAX_E_NOMEM, OCTAX_E_HIP.
  */
 int32_t octax_create(const octax_config *cfg, octax_engine **out);
+
+/*
+ * SUPER-CHIP state of envs [first, first + count) into h_out[0..count): mode,
+ * flag registers, 128x64 display and the three previous frames (the
+ * registers, memory and timers come from octax_get_state).  Synchronizes.
+ * Errors: OCTAX_E_INVALID (NULL engine or output, range outside 0..E, or a
+ * CHIP-8 engine), OCTAX_E_HIP.
+ */
+int32_t octax_get_schip_state(octax_engine *g, uint32_t first, uint32_t count, octax_schip_state *h_out);
 
 /*
  * Reset the envs whose d_mask byte is non-zero (all envs when d_mask is

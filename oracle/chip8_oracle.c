@@ -120,6 +120,57 @@ static const uint8_t oracle_font[80] = {
     0xF0, 0x80, 0xF0, 0x80, 0x80, /* F */
 };
 
+/* SUPER-CHIP (the platform extension Section 5 names: a 128x64 display and
+ * extra instructions).  The readings taken, in the terms of the Octo
+ * manual's SUPER-CHIP mode:
+ *   - the display is 128x64; in the 64x32 (low-resolution) mode each pixel
+ *     is a 2x2 block of it, and 00FE / 00FF switch to 64x32 / 128x64 and
+ *     clear the display; power-on is 64x32;
+ *   - DXYN draws 8xN at (VX mod W, VY mod H) of the current mode (W x H),
+ *     DXY0 a 16x16 sprite of 32 bytes (two per row); clipping, wrapping and
+ *     VF (1 iff a lit pixel was turned off) as for CHIP-8;
+ *   - 00CN scrolls down N rows, 00FB right and 00FC left 4 columns, in
+ *     pixels of the current mode; 00FD stops the program (it stays on that
+ *     instruction);
+ *   - FX30 points I at the 8x10 glyph of digit VX & 15 (16 glyphs, 10 bytes
+ *     each, at BIGFONT_ADDR); FX75 / FX85 store / load V0..V(min(X, 7)) to
+ *     and from eight flag registers, cleared at power-on;
+ *   - observations are (4, 128, 64).
+ * All other instructions are those of the CHIP-8 profile, quirk flags
+ * included. */
+#define HSCREEN_W 128
+#define HSCREEN_H 64
+#define BIGFONT_ADDR 0x0A0
+
+/* The 8x10 digit glyphs 0..F of FX30 (drawn for this oracle; the paper fixes
+ * none), ten rows each, bit 7 = leftmost pixel. */
+static const uint8_t oracle_bigfont[160] = {
+    0x3C, 0x66, 0xC3, 0xC3, 0xC3, 0xC3, 0xC3, 0xC3, 0x66, 0x3C, /* 0 */
+    0x18, 0x38, 0x78, 0x18, 0x18, 0x18, 0x18, 0x18, 0x18, 0x7E, /* 1 */
+    0x7E, 0xC3, 0x03, 0x03, 0x06, 0x1C, 0x30, 0x60, 0xC0, 0xFF, /* 2 */
+    0x7E, 0xC3, 0x03, 0x03, 0x3E, 0x03, 0x03, 0x03, 0xC3, 0x7E, /* 3 */
+    0x06, 0x0E, 0x1E, 0x36, 0x66, 0xC6, 0xFF, 0x06, 0x06, 0x06, /* 4 */
+    0xFF, 0xC0, 0xC0, 0xC0, 0xFE, 0x03, 0x03, 0x03, 0xC3, 0x7E, /* 5 */
+    0x3E, 0x60, 0xC0, 0xC0, 0xFE, 0xC3, 0xC3, 0xC3, 0xC3, 0x7E, /* 6 */
+    0xFF, 0x03, 0x06, 0x0C, 0x18, 0x30, 0x30, 0x30, 0x30, 0x30, /* 7 */
+    0x7E, 0xC3, 0xC3, 0xC3, 0x7E, 0xC3, 0xC3, 0xC3, 0xC3, 0x7E, /* 8 */
+    0x7E, 0xC3, 0xC3, 0xC3, 0xC3, 0x7F, 0x03, 0x03, 0x06, 0x7C, /* 9 */
+    0x3C, 0x66, 0xC3, 0xC3, 0xC3, 0xFF, 0xC3, 0xC3, 0xC3, 0xC3, /* A */
+    0xFE, 0xC3, 0xC3, 0xC3, 0xFE, 0xC3, 0xC3, 0xC3, 0xC3, 0xFE, /* B */
+    0x7E, 0xC3, 0xC0, 0xC0, 0xC0, 0xC0, 0xC0, 0xC0, 0xC3, 0x7E, /* C */
+    0xFC, 0xC6, 0xC3, 0xC3, 0xC3, 0xC3, 0xC3, 0xC3, 0xC6, 0xFC, /* D */
+    0xFF, 0xC0, 0xC0, 0xC0, 0xFC, 0xC0, 0xC0, 0xC0, 0xC0, 0xFF, /* E */
+    0xFF, 0xC0, 0xC0, 0xC0, 0xFC, 0xC0, 0xC0, 0xC0, 0xC0, 0xC0, /* F */
+};
+
+/* SUPER-CHIP part of a machine, allocated only for SUPER-CHIP machines. */
+typedef struct {
+    uint8_t hires;                       /* 1: 128x64 mode */
+    uint8_t rpl[8];                      /* FX75 / FX85 flag registers */
+    uint8_t hd[HSCREEN_H][HSCREEN_W];    /* hd[y][x] is 0 or 1 */
+    uint8_t hist[3][HSCREEN_H][HSCREEN_W]; /* the env's three previous frames, oldest first */
+} oracle_schip;
+
 /* One emulated machine (Appendix B.2). */
 typedef struct {
     uint8_t v[16];
@@ -133,6 +184,7 @@ typedef struct {
     uint8_t disp[SCREEN_H][SCREEN_W]; /* disp[y][x] is 0 or 1 */
     uint64_t rng;                     /* SplitMix64 state */
     uint32_t quirks;                  /* QUIRK_* flags; 0 or QUIRK_BASE = the VIP profile */
+    oracle_schip *sx;                 /* SUPER-CHIP state, NULL for a CHIP-8 machine */
 } oracle_machine;
 
 /* Exported snapshot of one environment.  Field order is part of the
@@ -188,8 +240,15 @@ typedef struct {
     uint8_t *term2_op;                   /* [R]: 0 none, 1 ==, 2 >=, 3 !=, 4 digit == ; or NULL */
     uint8_t *term2_reg;
     uint8_t *term2_value;
+    int schip;                           /* 1: SUPER-CHIP machines */
     oracle_env *env;
 } oracle_batch;
+
+/* Observation bytes of one env: (4, 64, 32), or (4, 128, 64) for SUPER-CHIP. */
+static size_t obs_bytes(const oracle_batch *b)
+{
+    return b->schip ? 4 * HSCREEN_W * HSCREEN_H : 4 * SCREEN_W * SCREEN_H;
+}
 
 /* ------------------------------------------------------------------ */
 /* Random bytes for CXNN: SplitMix64.  The state advances by the golden */
@@ -226,6 +285,103 @@ void oracle_machine_load(oracle_machine *m, const uint8_t *rom, uint32_t len)
     memcpy(m->mem + FONT_ADDR, oracle_font, sizeof oracle_font);
     memcpy(m->mem + PROGRAM_ADDR, rom, len);
     memset(m->disp, 0, sizeof m->disp);
+    if (m->sx) {
+        memcpy(m->mem + BIGFONT_ADDR, oracle_bigfont, sizeof oracle_bigfont);
+        m->sx->hires = 0;
+        memset(m->sx->rpl, 0, sizeof m->sx->rpl);
+        memset(m->sx->hd, 0, sizeof m->sx->hd);
+    }
+}
+
+/* SUPER-CHIP DXYN / DXY0 (see the SUPER-CHIP notes above). */
+static void schip_draw(oracle_machine *m, int x, int y, int n)
+{
+    oracle_schip *sx = m->sx;
+    int scale = sx->hires ? 1 : 2;
+    int W = HSCREEN_W / scale, H = HSCREEN_H / scale;
+    int w = n == 0 ? 16 : 8, h = n == 0 ? 16 : n;
+    int x0 = m->v[x] % W, y0 = m->v[y] % H;
+    int wrap = (m->quirks & QUIRK_PIXEL_WRAP) != 0;
+    int collided = 0;
+    for (int row = 0; row < h; row++) {
+        int py = y0 + row;
+        if (py >= H) {
+            if (!wrap)
+                break;
+            py -= H;
+        }
+        for (int col = 0; col < w; col++) {
+            int px = x0 + col;
+            if (px >= W) {
+                if (!wrap)
+                    break;
+                px -= W;
+            }
+            uint8_t bits = m->mem[(m->i + row * (w / 8) + col / 8) & 0xFFF];
+            if (!((bits >> (7 - col % 8)) & 1))
+                continue;
+            for (int dy = 0; dy < scale; dy++)
+                for (int dx = 0; dx < scale; dx++) {
+                    uint8_t *p = &sx->hd[py * scale + dy][px * scale + dx];
+                    if (*p)
+                        collided = 1;
+                    *p ^= 1;
+                }
+        }
+    }
+    m->v[0xF] = (uint8_t)collided;
+}
+
+/* SUPER-CHIP 00CN / 00FB / 00FC: move the display down, right or left by
+ * (dy, dx) physical pixels, clearing what comes in. */
+static void schip_scroll(oracle_schip *sx, int dy, int dx)
+{
+    uint8_t out[HSCREEN_H][HSCREEN_W];
+    for (int y = 0; y < HSCREEN_H; y++)
+        for (int x = 0; x < HSCREEN_W; x++) {
+            int sy = y - dy, sx_ = x - dx;
+            out[y][x] = (sy >= 0 && sy < HSCREEN_H && sx_ >= 0 && sx_ < HSCREEN_W) ? sx->hd[sy][sx_] : 0;
+        }
+    memcpy(sx->hd, out, sizeof out);
+}
+
+/* The SUPER-CHIP instructions; returns 1 when op was one of them. */
+static int schip_execute(oracle_machine *m, uint16_t op)
+{
+    oracle_schip *sx = m->sx;
+    int x = (op >> 8) & 0xF, scale = sx->hires ? 1 : 2;
+    if ((op & 0xFFF0) == 0x00C0) {                /* SCD N */
+        schip_scroll(sx, (op & 0xF) * scale, 0);
+        return 1;
+    }
+    switch (op) {
+    case 0x00E0: memset(sx->hd, 0, sizeof sx->hd); return 1;
+    case 0x00FB: schip_scroll(sx, 0, 4 * scale); return 1;
+    case 0x00FC: schip_scroll(sx, 0, -4 * scale); return 1;
+    case 0x00FD: m->pc = (uint16_t)((m->pc + MEM_BYTES - 2) & 0xFFF); return 1;
+    case 0x00FE: sx->hires = 0; memset(sx->hd, 0, sizeof sx->hd); return 1;
+    case 0x00FF: sx->hires = 1; memset(sx->hd, 0, sizeof sx->hd); return 1;
+    default: break;
+    }
+    if ((op >> 12) == 0xD) {
+        schip_draw(m, x, (op >> 4) & 0xF, op & 0xF);
+        return 1;
+    }
+    if ((op & 0xF0FF) == 0xF030) {
+        m->i = (uint16_t)(BIGFONT_ADDR + 10 * (m->v[x] % 16));
+        return 1;
+    }
+    if ((op & 0xF0FF) == 0xF075 || (op & 0xF0FF) == 0xF085) {
+        int top = x < 7 ? x : 7;
+        for (int k = 0; k <= top; k++) {
+            if ((op & 0xFF) == 0x75)
+                sx->rpl[k] = m->v[k];
+            else
+                m->v[k] = sx->rpl[k];
+        }
+        return 1;
+    }
+    return 0;
 }
 
 static void skip_next(oracle_machine *m) { m->pc = (uint16_t)((m->pc + 2) & 0xFFF); }
@@ -273,6 +429,8 @@ void oracle_machine_execute(oracle_machine *m, int key)
     /* fetch: big-endian 16-bit word at PC, then PC += 2 */
     uint16_t op = (uint16_t)((m->mem[m->pc] << 8) | m->mem[(m->pc + 1) & 0xFFF]);
     m->pc = (uint16_t)((m->pc + 2) & 0xFFF);
+    if (m->sx && schip_execute(m, op))
+        return;
 
     /* decode */
     int x = (op >> 8) & 0xF;
@@ -515,6 +673,9 @@ static void env_reset(const oracle_batch *b, oracle_env *e)
     }
     for (int k = 0; k < 3; k++)
         memcpy(e->hist[k], e->m.disp, sizeof e->m.disp);
+    if (e->m.sx)
+        for (int k = 0; k < 3; k++)
+            memcpy(e->m.sx->hist[k], e->m.sx->hd, sizeof e->m.sx->hd);
     e->t = 0;
     e->prev_score = env_score(b, e);
     e->prev_key = -1;
@@ -523,6 +684,16 @@ static void env_reset(const oracle_batch *b, oracle_env *e)
 /* obs[k][x][y] for k = 0..3: the three stored frames then the display. */
 static void env_observe(const oracle_env *e, uint8_t *obs)
 {
+    if (e->m.sx) {                    /* SUPER-CHIP: obs[k][x][y], 128 x 64 */
+        const oracle_schip *sx = e->m.sx;
+        for (int k = 0; k < 4; k++) {
+            const uint8_t(*frame)[HSCREEN_W] = (k < 3) ? sx->hist[k] : sx->hd;
+            for (int x = 0; x < HSCREEN_W; x++)
+                for (int y = 0; y < HSCREEN_H; y++)
+                    obs[(k * HSCREEN_W + x) * HSCREEN_H + y] = frame[y][x];
+        }
+        return;
+    }
     for (int k = 0; k < 4; k++) {
         const uint8_t(*frame)[SCREEN_W] = (k < 3) ? e->hist[k] : e->m.disp;
         for (int x = 0; x < SCREEN_W; x++)
@@ -545,6 +716,12 @@ static void env_step(const oracle_batch *b, oracle_env *e, int32_t action, uint8
 
     uint8_t before[SCREEN_H][SCREEN_W];
     memcpy(before, e->m.disp, sizeof before);
+    oracle_schip *sx = e->m.sx;
+    if (sx) {                         /* the SUPER-CHIP frame history moves the same way */
+        memcpy(sx->hist[0], sx->hist[1], sizeof sx->hd);
+        memcpy(sx->hist[1], sx->hist[2], sizeof sx->hd);
+        memcpy(sx->hist[2], sx->hd, sizeof sx->hd);
+    }
 
     run_step_frames(b, &e->m, key);
 
@@ -630,6 +807,8 @@ void oracle_destroy(oracle_batch *b)
 {
     if (!b)
         return;
+    for (int e = 0; e < b->num_envs; e++)
+        free(b->env[e].m.sx);
     free(b->rom); free(b->rom_len); free(b->action_keys); free(b->num_actions);
     free(b->score_reg); free(b->term_reg); free(b->term_value); free(b->env);
     free(b->startup_len); free(b->startup_keys);
@@ -726,7 +905,7 @@ void oracle_reset(oracle_batch *b, const uint8_t *mask, uint8_t *obs)
         if (!mask || mask[e])
             env_reset(b, &b->env[e]);
         if (obs)
-            env_observe(&b->env[e], obs + (size_t)e * 4 * SCREEN_W * SCREEN_H);
+            env_observe(&b->env[e], obs + (size_t)e * obs_bytes(b));
     }
 }
 
@@ -735,8 +914,7 @@ void oracle_step(oracle_batch *b, const int32_t *action, uint8_t *obs, float *re
                  uint8_t *done)
 {
     for (int e = 0; e < b->num_envs; e++)
-        env_step(b, &b->env[e], action[e],
-                 obs ? obs + (size_t)e * 4 * SCREEN_W * SCREEN_H : NULL, &reward[e], &done[e]);
+        env_step(b, &b->env[e], action[e], obs ? obs + (size_t)e * obs_bytes(b) : NULL, &reward[e], &done[e]);
 }
 
 typedef struct {
@@ -755,7 +933,7 @@ static void *run_shard(void *arg)
     for (int k = 0; k < s->steps; k++)
         for (int e = s->first; e < s->last; e++)
             env_step(s->b, &s->b->env[e], s->action[(size_t)k * E + e],
-                     s->obs + (size_t)e * 4 * SCREEN_W * SCREEN_H,
+                     s->obs + (size_t)e * obs_bytes(s->b),
                      &s->reward[(size_t)k * E + e], &s->done[(size_t)k * E + e]);
     return NULL;
 }
@@ -850,7 +1028,77 @@ int oracle_machine_size(void) { return (int)sizeof(oracle_machine); }
 
 /* Single-machine access for unit tests of individual instructions. */
 oracle_machine *oracle_machine_new(void) { return calloc(1, sizeof(oracle_machine)); }
-void oracle_machine_free(oracle_machine *m) { free(m); }
+void oracle_machine_free(oracle_machine *m)
+{
+    if (m)
+        free(m->sx);
+    free(m);
+}
+
+/* SUPER-CHIP view of one machine or env (tests): mode, flag registers,
+ * display and, for an env, its three previous frames. */
+typedef struct {
+    uint8_t hires;
+    uint8_t rpl[8];
+    uint8_t hd[HSCREEN_H][HSCREEN_W];
+    uint8_t hist[3][HSCREEN_H][HSCREEN_W];
+} oracle_schip_view;
+
+int oracle_schip_view_size(void) { return (int)sizeof(oracle_schip_view); }
+
+/* Make a single machine a SUPER-CHIP one (or back); reload it after this. */
+int oracle_machine_set_platform(oracle_machine *m, int schip)
+{
+    free(m->sx);
+    m->sx = schip ? calloc(1, sizeof(oracle_schip)) : NULL;
+    return (schip && !m->sx) ? -2 : 0;
+}
+
+static void schip_to_view(const oracle_schip *sx, oracle_schip_view *v)
+{
+    v->hires = sx->hires;
+    memcpy(v->rpl, sx->rpl, sizeof v->rpl);
+    memcpy(v->hd, sx->hd, sizeof v->hd);
+    memcpy(v->hist, sx->hist, sizeof v->hist);
+}
+
+int oracle_machine_get_schip(const oracle_machine *m, oracle_schip_view *v)
+{
+    if (!m->sx)
+        return -1;
+    schip_to_view(m->sx, v);
+    return 0;
+}
+
+int oracle_machine_set_schip(oracle_machine *m, const oracle_schip_view *v)
+{
+    if (!m->sx)
+        return -1;
+    m->sx->hires = v->hires ? 1 : 0;
+    memcpy(m->sx->rpl, v->rpl, sizeof v->rpl);
+    for (int y = 0; y < HSCREEN_H; y++)
+        for (int x = 0; x < HSCREEN_W; x++)
+            m->sx->hd[y][x] = v->hd[y][x] & 1;
+    return 0;
+}
+
+/* Make every env of a batch a SUPER-CHIP machine (schip = 1) or a CHIP-8
+ * one; applies from the next reset on, so callers reset after this. */
+int oracle_set_platform(oracle_batch *b, int schip)
+{
+    for (int e = 0; e < b->num_envs; e++)
+        if (oracle_machine_set_platform(&b->env[e].m, schip) != 0)
+            return -2;
+    b->schip = schip ? 1 : 0;
+    return 0;
+}
+
+void oracle_get_schip(const oracle_batch *b, int first, int count, oracle_schip_view *out)
+{
+    for (int k = 0; k < count; k++)
+        if (b->env[first + k].m.sx)
+            schip_to_view(b->env[first + k].m.sx, &out[k]);
+}
 /* Quirk flags of a single machine (QUIRK_*; a new machine has none, which
  * behaves as the base profile). */
 void oracle_machine_set_quirks(oracle_machine *m, uint32_t quirks) { m->quirks = quirks; }

@@ -83,9 +83,27 @@ def lib():
         L.oracle_set_wrappers.restype = i32
         L.oracle_set_profile.argtypes = [P, ctypes.c_uint32, P, P, P, P, P, P]
         L.oracle_set_profile.restype = i32
+        L.oracle_set_platform.argtypes = [P, i32]
+        L.oracle_set_platform.restype = i32
+        L.oracle_get_schip.argtypes = [P, i32, i32, P]
+        L.oracle_machine_set_platform.argtypes = [P, i32]
+        L.oracle_machine_set_platform.restype = i32
+        L.oracle_machine_get_schip.argtypes = [P, P]
+        L.oracle_machine_get_schip.restype = i32
+        L.oracle_machine_set_schip.argtypes = [P, P]
+        L.oracle_machine_set_schip.restype = i32
+        L.oracle_schip_view_size.restype = i32
+        assert L.oracle_schip_view_size() == SCHIP_DTYPE.itemsize, "oracle_schip_view layout mismatch"
         assert L.oracle_state_size() == STATE_DTYPE.itemsize, "oracle_state layout mismatch"
         _lib = L
     return _lib
+
+
+# SUPER-CHIP view of one env or machine: mode, flag registers, 128x64
+# display hd[y][x] and, for an env, its three previous frames.
+SCHIP_DTYPE = np.dtype([
+    ("hires", np.uint8), ("rpl", np.uint8, (8,)), ("hd", np.uint8, (64, 128)), ("hist", np.uint8, (3, 64, 128)),
+])
 
 
 def _p(a: Optional[np.ndarray]):
@@ -127,12 +145,27 @@ def blank_state(rom: bytes = b"") -> np.ndarray:
 
 
 class Machine:
-    """One bare CHIP-8 machine: load, execute single instructions, tick timers."""
+    """One bare CHIP-8 (or SUPER-CHIP) machine: load, execute single
+    instructions, tick timers."""
 
-    def __init__(self, rom: bytes = b"", quirks: int = 1):
+    def __init__(self, rom: bytes = b"", quirks: int = 1, schip: bool = False):
         self._h = lib().oracle_machine_new()
         lib().oracle_machine_set_quirks(self._h, int(quirks))
+        if schip and lib().oracle_machine_set_platform(self._h, 1) != 0:
+            raise MemoryError("oracle_machine_set_platform")
         self.load(rom)
+
+    def schip(self) -> np.ndarray:
+        """SUPER-CHIP view (hires, rpl, hd); raises for a CHIP-8 machine."""
+        v = np.zeros(1, dtype=SCHIP_DTYPE)
+        if lib().oracle_machine_get_schip(self._h, _p(v)) != 0:
+            raise ValueError("not a SUPER-CHIP machine")
+        return v[0]
+
+    def set_schip(self, view: np.ndarray):
+        a = np.array([view], dtype=SCHIP_DTYPE)
+        if lib().oracle_machine_set_schip(self._h, _p(a)) != 0:
+            raise ValueError("not a SUPER-CHIP machine")
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -210,7 +243,11 @@ class OracleBatch:
             rc = lib().oracle_set_wrappers(h, int(spec.sticky_q24), int(spec.noop_max), _p(sl), _p(sk))
             if rc != 0:
                 raise ValueError("oracle_set_wrappers rejected the spec")
-        if getattr(spec, "has_profile", False) or getattr(spec, "has_wrappers", False):
+        self.schip = int(getattr(spec, "platform", 0)) == 1
+        if self.schip and lib().oracle_set_platform(h, 1) != 0:
+            raise MemoryError("oracle_set_platform")
+        self.obs_shape = (4, 128, 64) if self.schip else (4, 64, 32)
+        if getattr(spec, "has_profile", False) or getattr(spec, "has_wrappers", False) or self.schip:
             lib().oracle_reset(h, None, None)
 
     def close(self):
@@ -221,7 +258,7 @@ class OracleBatch:
     __del__ = close
 
     def reset(self, mask: Optional[np.ndarray] = None, want_obs: bool = True):
-        obs = np.zeros((self.E, 4, 64, 32), dtype=np.uint8) if want_obs else None
+        obs = np.zeros((self.E,) + self.obs_shape, dtype=np.uint8) if want_obs else None
         m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
         lib().oracle_reset(self._h, _p(m), _p(obs))
         return obs
@@ -229,7 +266,7 @@ class OracleBatch:
     def step(self, actions: np.ndarray, want_obs: bool = True):
         a = np.ascontiguousarray(actions, dtype=np.int32)
         assert a.shape == (self.E,)
-        obs = np.zeros((self.E, 4, 64, 32), dtype=np.uint8) if want_obs else None
+        obs = np.zeros((self.E,) + self.obs_shape, dtype=np.uint8) if want_obs else None
         rew = np.zeros(self.E, dtype=np.float32)
         done = np.zeros(self.E, dtype=np.uint8)
         lib().oracle_step(self._h, _p(a), _p(obs), _p(rew), _p(done))
@@ -239,7 +276,7 @@ class OracleBatch:
         """Steps over actions [K][E] on `threads` POSIX threads; returns (reward, done, threads)."""
         a = np.ascontiguousarray(actions, dtype=np.int32)
         K = a.shape[0]
-        obs = np.zeros((self.E, 4, 64, 32), dtype=np.uint8)
+        obs = np.zeros((self.E,) + self.obs_shape, dtype=np.uint8)
         rew = np.zeros((K, self.E), dtype=np.float32)
         done = np.zeros((K, self.E), dtype=np.uint8)
         used = lib().oracle_run_threaded(self._h, K, _p(a), _p(obs), _p(rew), _p(done), threads)
@@ -254,6 +291,14 @@ class OracleBatch:
     def set_state(self, first: int, states: np.ndarray):
         s = np.ascontiguousarray(states, dtype=STATE_DTYPE)
         lib().oracle_set_state(self._h, first, len(s), _p(s))
+
+    def get_schip(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        """SUPER-CHIP views (hires, rpl, display, previous frames) of envs."""
+        assert self.schip, "not a SUPER-CHIP batch"
+        count = self.E - first if count is None else count
+        out = np.zeros(count, dtype=SCHIP_DTYPE)
+        lib().oracle_get_schip(self._h, first, count, _p(out))
+        return out
 
 
 def canonical(states: np.ndarray) -> Dict[str, np.ndarray]:

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "liboctax.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["octax_host.cpp", "octax_pool.cpp", "step_plain.hip", "step_fused.hip", "reset.hip", "calib.hip"]
+SOURCES = ["octax_host.cpp", "octax_pool.cpp", "step_plain.hip", "step_schip.hip", "step_fused.hip", "reset.hip", "calib.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -13,6 +13,8 @@ constexpr uint32_t kProgram = 0x200;
 constexpr uint32_t kFont = 0x050;
 constexpr uint32_t kKeyNone = 16;      // "no key held"
 constexpr uint32_t kObsBytes = 8192;   // [4][64][32]
+constexpr uint32_t kSchipObsBytes = 32768;   // SUPER-CHIP: [4][128][64]
+constexpr uint32_t kBigFont = 0x0A0;          // SUPER-CHIP 8x10 digit glyphs, 10 bytes each
 
 // Env state in device memory, one entry per slot (see octax_host.cpp for the
 // byte budget).  Small per-env fields are stored field-major ([field][slot])
@@ -30,6 +32,11 @@ struct State {
     uint64_t *fb;        // [E][32] display rows, bit 63 - x = pixel (x, y)
     uint32_t *cols;      // [E][4][64] frame ring of packed frames (see pack_frame), slot = misc head
     uint8_t *ram;        // [E][4096]
+    // SUPER-CHIP engines only (null otherwise):
+    uint64_t *hfb;       // [E][64][2] 128x64 display: row y = hfb[2y] (x 0..63) and hfb[2y+1]
+                         //            (x 64..127), bit 63 - (x mod 64) = pixel (x, y)
+    uint64_t *hring;     // [E][4][128] frame ring of displays in the same row form, slot = misc head
+    uint32_t *sx;        // [E][4] word 0: 1 = 128x64 mode; words 1, 2: flag registers 0..7, one byte each
     const uint32_t *rom_of;   // [E] ROM id
     const uint32_t *horizon;  // [E]
     const uint32_t *env_of;   // [E] env index (output position) of each slot
@@ -65,6 +72,7 @@ struct Roms {
     const uint32_t *desc2;
     uint32_t quirks;         // quirk flags of the whole batch (bit 0 = the VIP base profile)
     uint32_t profile;        // nonzero when quirks != base or desc2 is set
+    uint32_t schip;          // 1: SUPER-CHIP platform (128x64 display, its instructions)
     Wrap w;
 };
 

@@ -17,6 +17,7 @@ struct octax_engine {
     uint32_t kernel = OCTAX_KERNEL_PLAIN;
     uint32_t placement = OCTAX_PLACE_IDENTITY;
     uint32_t envs_per_block = 256, rom_in_lds = 1;
+    uint32_t schip = 0;                               // platform: 1 = SUPER-CHIP
     hipStream_t stream = nullptr;
     int device = 0;
     uint64_t device_bytes = 0;

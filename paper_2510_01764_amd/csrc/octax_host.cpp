@@ -31,6 +31,27 @@ const uint8_t kFontBytes[80] = {
     0xF0, 0x80, 0xF0, 0x80, 0x80,
 };
 
+// The SUPER-CHIP 8x10 digit glyphs 0..F of FX30, at 0x0A0 (ten rows per
+// glyph, bit 7 = leftmost pixel; the glyph shapes are this library's own).
+const uint8_t kBigFontBytes[160] = {
+    0x3C, 0x66, 0xC3, 0xC3, 0xC3, 0xC3, 0xC3, 0xC3, 0x66, 0x3C,   // 0
+    0x18, 0x38, 0x78, 0x18, 0x18, 0x18, 0x18, 0x18, 0x18, 0x7E,   // 1
+    0x7E, 0xC3, 0x03, 0x03, 0x06, 0x1C, 0x30, 0x60, 0xC0, 0xFF,   // 2
+    0x7E, 0xC3, 0x03, 0x03, 0x3E, 0x03, 0x03, 0x03, 0xC3, 0x7E,   // 3
+    0x06, 0x0E, 0x1E, 0x36, 0x66, 0xC6, 0xFF, 0x06, 0x06, 0x06,   // 4
+    0xFF, 0xC0, 0xC0, 0xC0, 0xFE, 0x03, 0x03, 0x03, 0xC3, 0x7E,   // 5
+    0x3E, 0x60, 0xC0, 0xC0, 0xFE, 0xC3, 0xC3, 0xC3, 0xC3, 0x7E,   // 6
+    0xFF, 0x03, 0x06, 0x0C, 0x18, 0x30, 0x30, 0x30, 0x30, 0x30,   // 7
+    0x7E, 0xC3, 0xC3, 0xC3, 0x7E, 0xC3, 0xC3, 0xC3, 0xC3, 0x7E,   // 8
+    0x7E, 0xC3, 0xC3, 0xC3, 0xC3, 0x7F, 0x03, 0x03, 0x06, 0x7C,   // 9
+    0x3C, 0x66, 0xC3, 0xC3, 0xC3, 0xFF, 0xC3, 0xC3, 0xC3, 0xC3,   // A
+    0xFE, 0xC3, 0xC3, 0xC3, 0xFE, 0xC3, 0xC3, 0xC3, 0xC3, 0xFE,   // B
+    0x7E, 0xC3, 0xC0, 0xC0, 0xC0, 0xC0, 0xC0, 0xC0, 0xC3, 0x7E,   // C
+    0xFC, 0xC6, 0xC3, 0xC3, 0xC3, 0xC3, 0xC3, 0xC3, 0xC6, 0xFC,   // D
+    0xFF, 0xC0, 0xC0, 0xC0, 0xFC, 0xC0, 0xC0, 0xC0, 0xC0, 0xFF,   // E
+    0xFF, 0xC0, 0xC0, 0xC0, 0xFC, 0xC0, 0xC0, 0xC0, 0xC0, 0xC0,   // F
+};
+
 }  // namespace
 
 int32_t octax::fail(int32_t code, const std::string &msg) {
@@ -160,6 +181,7 @@ hipError_t upload_block_roms(octax_engine *g) {
 hipError_t octax::launch_steps(octax_engine *g, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
                                uint32_t obs_slots, float *d_reward, uint8_t *d_done, hipStream_t st) {
     StepIO io{d_action, d_obs, d_reward, d_done, K, obs_slots ? obs_slots : 1, g->ipf, g->frame_skip};
+    if (g->schip) return launch_step_schip(g->s, g->roms, io, st);
     if (g->kernel == OCTAX_KERNEL_FUSED) {
         FusedCfg f{g->envs_per_block, g->rom_in_lds, g->d_block_roms};
         return launch_step_fused(g->s, g->roms, io, f, st);
@@ -288,6 +310,12 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     std::vector<uint32_t> desc2;
     if (const char *err = octax::check_profile(cfg, desc2))
         return fail(OCTAX_E_INVALID, std::string("octax_create: ") + err);
+    if (cfg->platform > OCTAX_PLATFORM_SCHIP) return fail(OCTAX_E_INVALID, "octax_create: unknown platform");
+    const bool schip = cfg->platform == OCTAX_PLATFORM_SCHIP;
+    if (schip && cfg->kernel != OCTAX_KERNEL_PLAIN)
+        return fail(OCTAX_E_INVALID, "octax_create: SUPER-CHIP engines run on the plain kernel");
+    if (schip && (cfg->noop_max || cfg->h_startup_len))
+        return fail(OCTAX_E_INVALID, "octax_create: SUPER-CHIP engines take no start-up sequences or no-op resets");
 
     octax_engine *g = new (std::nothrow) octax_engine;
     if (!g) return fail(OCTAX_E_NOMEM, "octax_create: out of host memory");
@@ -299,6 +327,7 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     g->placement = cfg->placement;
     g->envs_per_block = ipw;
     g->rom_in_lds = cfg->rom_in_lds ? 1 : 0;
+    g->schip = schip ? 1 : 0;
     g->stream = static_cast<hipStream_t>(cfg->stream);
     (void)hipGetDevice(&g->device);
 
@@ -327,6 +356,7 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
         uint8_t *m = image.data() + (size_t)r * kMem;
         std::memcpy(m + kFont, kFontBytes, sizeof kFontBytes);
         std::memcpy(m + kProgram, cfg->h_rom_data + cfg->h_rom_offset[r], cfg->h_rom_len[r]);
+        if (schip) std::memcpy(m + kBigFont, kBigFontBytes, sizeof kBigFontBytes);
         desc[r] = cfg->h_score_reg[r] | ((uint32_t)cfg->h_term_reg[r] << 8) |
                   ((uint32_t)cfg->h_term_value[r] << 16) | ((uint32_t)cfg->h_num_actions[r] << 24);
     }
@@ -356,6 +386,11 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     TRY(g->alloc(&g->s.fb, 32 * (size_t)E));
     TRY(g->alloc(&g->s.cols, 256 * (size_t)E));
     TRY(g->alloc(&g->s.ram, (size_t)kMem * E));
+    if (schip) {
+        TRY(g->alloc(&g->s.hfb, 128 * (size_t)E));
+        TRY(g->alloc(&g->s.hring, 512 * (size_t)E));
+        TRY(g->alloc(&g->s.sx, 4 * (size_t)E));
+    }
     TRY(g->alloc(&rom_of, E));
     TRY(g->alloc(&hor, E));
     TRY(g->alloc(&env_of, E));
@@ -385,9 +420,11 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     g->roms.desc2 = d_desc2;
     g->roms.quirks = cfg->quirks;
     g->roms.profile = (cfg->quirks != OCTAX_QUIRKS_V1 || d_desc2) ? 1u : 0u;
+    g->roms.schip = g->schip;
     g->roms.w = octax::make_wrap(g->d_startup, startup, cfg->sticky_q24, cfg->noop_max, g->ipf, g->frame_skip);
     TRY(upload_block_roms(g));
     TRY(launch_reset(g->s, g->roms, nullptr, true, g->stream));
+    if (schip) TRY(launch_schip_reset(g->s, nullptr, 0, E, g->stream));
     TRY(hipStreamSynchronize(g->stream));
 #undef TRY
     *out = g;
@@ -406,8 +443,35 @@ int32_t octax_destroy(octax_engine *g) {
 int32_t octax_reset(octax_engine *g, const uint8_t *d_mask, uint8_t *d_obs) {
     if (!g) return fail(OCTAX_E_INVALID, "octax_reset: engine is NULL");
     hipError_t e = launch_reset(g->s, g->roms, d_mask, false, g->stream);
-    if (e == hipSuccess && d_obs) e = launch_observe(g->s, d_obs, g->stream);
+    if (e == hipSuccess && g->schip) e = launch_schip_reset(g->s, d_mask, 0, g->E, g->stream);
+    if (e == hipSuccess && d_obs)
+        e = g->schip ? launch_schip_observe(g->s, d_obs, g->stream) : launch_observe(g->s, d_obs, g->stream);
     return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_reset");
+}
+
+int32_t octax_get_schip_state(octax_engine *g, uint32_t first, uint32_t count, octax_schip_state *h_out) {
+    if (!g || (!h_out && count)) return fail(OCTAX_E_INVALID, "octax_get_schip_state: NULL argument");
+    if (!g->schip) return fail(OCTAX_E_INVALID, "octax_get_schip_state: not a SUPER-CHIP engine");
+    if ((uint64_t)first + count > g->E) return fail(OCTAX_E_INVALID, "octax_get_schip_state: range outside 0..E");
+    hipError_t e = hipStreamSynchronize(g->stream);
+    std::vector<uint64_t> ring(512);
+    for (uint32_t k = 0; k < count && e == hipSuccess; k++) {
+        const uint32_t slot = g->slot_of[first + k];
+        uint32_t misc = 0, sx[4] = {0, 0, 0, 0};
+        octax_schip_state &o = h_out[k];
+        e = hipMemcpy(&misc, g->s.misc + slot, 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(sx, g->s.sx + 4 * (size_t)slot, 16, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(o.fb, g->s.hfb + 128 * (size_t)slot, 1024, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(ring.data(), g->s.hring + 512 * (size_t)slot, 4096, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) break;
+        o.hires = sx[0];
+        std::memcpy(o.rpl, &sx[1], 8);
+        o.reserved = 0;
+        const uint32_t head = (misc >> 24) & 3;
+        for (uint32_t h = 0; h < 3; h++)   // ring slot head - 3 + h holds frame h
+            std::memcpy(o.hist[h], ring.data() + 128 * ((head + 1 + h) & 3), 1024);
+    }
+    return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_get_schip_state");
 }
 
 int32_t octax_step(octax_engine *g, const int32_t *d_action, uint8_t *d_obs, float *d_reward,
@@ -516,6 +580,8 @@ int32_t octax_set_state(octax_engine *g, uint32_t first, uint32_t count, const o
 
 int32_t octax_set_kernel(octax_engine *g, uint32_t kernel) {
     if (!g || kernel > OCTAX_KERNEL_FUSED) return fail(OCTAX_E_INVALID, "octax_set_kernel: bad argument");
+    if (g->schip && kernel != OCTAX_KERNEL_PLAIN)
+        return fail(OCTAX_E_INVALID, "octax_set_kernel: SUPER-CHIP engines run on the plain kernel");
     g->kernel = kernel;
     return OCTAX_OK;
 }

@@ -1,0 +1,309 @@
+// SUPER-CHIP step (the platform extension the paper names in Section 5: a
+// 128x64 display and extra instructions) as two kernels per env step:
+//   * emulation, lane per env like the plain kernel (state, memory and the
+//     1 KB display in HBM), in 64-thread blocks so that a batch of a few
+//     thousand envs still puts a wave on every CU; it ends by writing the
+//     display into the env's frame ring;
+//   * observations, one 256-thread block per (env, frame): the frame's 1 KB
+//     is staged in LDS and each thread writes 32 bytes of one column, so a
+//     block's stores cover the frame's 8 KB of (4, 128, 64) observation
+//     contiguously.
+//
+// The SUPER-CHIP instructions and the readings taken for them:
+//   00CN  scroll the display down N rows        (pixels of the current mode;
+//   00FB  scroll right 4 columns                 a 64x32-mode pixel is a 2x2
+//   00FC  scroll left 4 columns                  block of the 128x64 display)
+//   00FD  stop: the program stays on this instruction
+//   00FE  64x32 mode, display cleared;  00FF  128x64 mode, display cleared
+//   DXYN  8xN sprite at (VX mod W, VY mod H) of the current mode; DXY0 a
+//         16x16 sprite of 32 bytes; clipping, wrapping and VF as for CHIP-8
+//   FX30  I = the 8x10 glyph of digit VX & 15 (10 bytes each at kBigFont)
+//   FX75  flag registers 0..min(X, 7) = V0..; FX85 the reverse
+// Every other instruction is the CHIP-8 one (exec_one), quirk flags included.
+#include "octax_core.h"
+#include "octax_kernels.h"
+#include "octax_plain_mem.h"
+
+namespace octax {
+namespace {
+
+typedef unsigned __int128 u128;
+
+// Each bit of a 16-bit pattern twice (bit i -> bits 2i and 2i + 1): a row of
+// a 64x32-mode sprite on the 128x64 display.
+__device__ __forceinline__ uint32_t double_bits(uint32_t b) {
+    uint32_t x = b & 0xFFFF;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x | (x << 1);
+}
+
+__device__ __forceinline__ u128 rotr128(u128 v, uint32_t s) {
+    return s ? (v >> s) | (v << (128 - s)) : v;
+}
+
+struct SchipMem : PlainMem {
+    uint64_t *hd;      // [64][2] display rows
+    uint32_t hires;
+    uint32_t rpl0, rpl1;   // flag registers 0..3 and 4..7, byte k = register k
+
+    // Row y as a 128-bit word, pixel x at bit 127 - x.
+    __device__ __forceinline__ u128 row(uint32_t y) const {
+        return ((u128)hd[2 * y] << 64) | hd[2 * y + 1];
+    }
+    __device__ __forceinline__ void set_row(uint32_t y, u128 v) {
+        hd[2 * y] = (uint64_t)(v >> 64);
+        hd[2 * y + 1] = (uint64_t)v;
+    }
+    __device__ __forceinline__ uint32_t scale() const { return hires ? 1u : 2u; }
+
+    // DXYN / DXY0 with the raw register values (see the header).
+    __device__ __forceinline__ uint32_t draw_s(uint32_t vx, uint32_t vy, uint32_t I, uint32_t n, bool wrap) {
+        const uint32_t sc = scale();
+        const uint32_t W = 128 / sc, H = 64 / sc;
+        const uint32_t x0 = vx & (W - 1), y0 = vy & (H - 1);
+        const bool big = n == 0;
+        const uint32_t h = big ? 16 : n;
+        const uint32_t pw = 16 * sc;   // physical width of a 16-pixel sprite row
+        const uint32_t X = x0 * sc;
+        u128 hit = 0;
+        for (uint32_t r = 0; r < h; r++) {
+            uint32_t py = y0 + r;
+            if (py >= H) {
+                if (!wrap) break;
+                py -= H;
+            }
+            uint32_t bits = big ? ((uint32_t)ram[(I + 2 * r) & 0xFFF] << 8) | ram[(I + 2 * r + 1) & 0xFFF]
+                                : (uint32_t)ram[(I + r) & 0xFFF] << 8;
+            if (sc == 2) bits = double_bits(bits);
+            const u128 P = (u128)bits << (128 - pw);
+            const u128 m = wrap ? rotr128(P, X) : (P >> X);
+            for (uint32_t d = 0; d < sc; d++) {
+                const uint32_t y = py * sc + d;
+                const u128 rw = row(y);
+                hit |= rw & m;
+                set_row(y, rw ^ m);
+            }
+        }
+        return hit != 0;
+    }
+    // Scrolls by physical pixels.
+    __device__ __forceinline__ void scroll_down(uint32_t s) {
+        for (int y = 63; y >= 0; y--) set_row((uint32_t)y, (uint32_t)y >= s ? row((uint32_t)y - s) : (u128)0);
+    }
+    __device__ __forceinline__ void scroll_right(uint32_t s) {
+        for (uint32_t y = 0; y < 64; y++) set_row(y, row(y) >> s);
+    }
+    __device__ __forceinline__ void scroll_left(uint32_t s) {
+        for (uint32_t y = 0; y < 64; y++) set_row(y, row(y) << s);
+    }
+    // The CHIP-8 entry points used by exec_one; DXYN and 00E0 never reach it
+    // (exec_schip takes them), these keep its interface whole.
+    __device__ __forceinline__ uint32_t draw(uint32_t x0, uint32_t y0, uint32_t I, uint32_t n, bool wrap) {
+        return draw_s(x0, y0, I, n, wrap);
+    }
+    __device__ __forceinline__ void clear() {
+        for (uint32_t q = 0; q < 128; q++) hd[q] = 0;
+    }
+};
+
+// One SUPER-CHIP instruction; returns whether it was a DXYN.
+__device__ __forceinline__ bool exec_schip(Core &c, SchipMem &mem, uint32_t key, uint32_t quirks) {
+    const uint32_t op = mem.fetch(c.pc);
+    const uint32_t pc2 = (c.pc + 2) & 0xFFF;
+    const uint32_t x = (op >> 8) & 0xF;
+    const uint32_t sc = mem.scale();
+    if ((op & 0xFFF0) == 0x00C0) {
+        mem.scroll_down((op & 0xF) * sc);
+        c.pc = pc2;
+        return false;
+    }
+    switch (op) {
+    case 0x00E0: mem.clear(); c.pc = pc2; return false;
+    case 0x00FB: mem.scroll_right(4 * sc); c.pc = pc2; return false;
+    case 0x00FC: mem.scroll_left(4 * sc); c.pc = pc2; return false;
+    case 0x00FD: return false;   // stopped: PC stays
+    case 0x00FE: mem.hires = 0; mem.clear(); c.pc = pc2; return false;
+    case 0x00FF: mem.hires = 1; mem.clear(); c.pc = pc2; return false;
+    default: break;
+    }
+    if ((op >> 12) == 0xD) {
+        set_vf(c.r, mem.draw_s(vget(c.r, x), vget(c.r, (op >> 4) & 0xF), c.I, op & 0xF,
+                               (quirks & kQuirkPixelWrap) != 0));
+        c.pc = pc2;
+        return true;
+    }
+    const uint32_t low = op & 0xF0FF;
+    if (low == 0xF030) {
+        c.I = kBigFont + 10 * (vget(c.r, x) & 15);
+        c.pc = pc2;
+        return false;
+    }
+    if (low == 0xF075 || low == 0xF085) {
+        const u32x4 m = byte_mask(min(x, 7u) + 1);   // bytes 0..min(X, 7) of V0..V7
+        if (low == 0xF075) {
+            mem.rpl0 = (mem.rpl0 & ~m.x) | (c.r.w.x & m.x);
+            mem.rpl1 = (mem.rpl1 & ~m.y) | (c.r.w.y & m.y);
+        } else {
+            c.r.w.x = (c.r.w.x & ~m.x) | (mem.rpl0 & m.x);
+            c.r.w.y = (c.r.w.y & ~m.y) | (mem.rpl1 & m.y);
+        }
+        c.pc = pc2;
+        return false;
+    }
+    return exec_one(c, mem, key, quirks);
+}
+
+__device__ __forceinline__ void schip_env_step(Core &c, SchipMem &mem, uint32_t key, uint32_t ipf, uint32_t fs,
+                                               uint32_t quirks) {
+    for (uint32_t f = 0; f < fs; f++) {
+        for (uint32_t i = 0; i < ipf; i++)
+            if (exec_schip(c, mem, key, quirks) && (quirks & kQuirkDisplayWait)) break;
+        tick(c);
+    }
+}
+
+__global__ __launch_bounds__(64) void step_schip_kernel(State s, Roms roms, StepIO io, uint32_t k) {
+    const uint32_t slot = blockIdx.x * 64 + threadIdx.x;
+    if (!slot_live(s, slot)) return;
+    const uint32_t E = s.num;
+    const uint32_t env = s.env_of[slot];
+    const uint32_t rom = s.rom_of[slot];
+    const uint32_t desc = roms.desc[rom];
+    const uint32_t desc2 = roms.desc2 ? roms.desc2[rom] : kDesc2Default;
+
+    Core c;
+    uint32_t head;
+    load_core(s, slot, c, head);
+    const uint32_t key = sticky_key(roms, c, action_key(roms, rom, desc, io.action[(size_t)k * E + env]));
+    uint32_t *sx = s.sx + (size_t)slot * 4;
+    SchipMem mem;
+    mem.ram = s.ram + (size_t)slot * kMem;
+    mem.fb = nullptr;
+    mem.stack = s.stack + (size_t)slot * 8;
+    mem.dirty = s.dirty[slot];
+    mem.hd = s.hfb + (size_t)slot * 128;
+    mem.hires = sx[0];
+    mem.rpl0 = sx[1];
+    mem.rpl1 = sx[2];
+
+    schip_env_step(c, mem, key, io.ipf, io.frame_skip, roms.quirks);
+
+    const int32_t score = score_of(c.r, desc, desc2);
+    int32_t prev = s.prev[slot];
+    const float reward = (float)(score - prev);
+    const uint32_t term = terminated_of(c.r, desc, desc2);
+    uint32_t t = s.t[slot] + 1;
+    const uint32_t hor = s.horizon[slot];
+    const uint32_t trunc = (hor != 0) && (t >= hor);
+    const uint32_t done = term | (trunc << 1);
+    io.reward[(size_t)k * E + env] = reward;
+    io.done[(size_t)k * E + env] = (uint8_t)done;
+
+    if (done) {
+        // Automatic reset (Section 3.4): power-on state, RNG stream continued.
+        const uint8_t *img = roms.image + (size_t)rom * kMem;
+        uint64_t d = mem.dirty;
+        while (d) {
+            const uint32_t p = __builtin_ctzll(d);
+            d &= d - 1;
+            const uint4 *src = reinterpret_cast<const uint4 *>(img + p * 64);
+            uint4 *dst = reinterpret_cast<uint4 *>(mem.ram + p * 64);
+            for (int q = 0; q < 4; q++) dst[q] = src[q];
+        }
+        mem.dirty = 0;
+        reset_core(c);
+        mem.clear();
+        mem.hires = 0;
+        mem.rpl0 = mem.rpl1 = 0;
+        for (int q = 0; q < 8; q++) mem.stack[q] = 0;
+        head = 0;
+        t = 0;
+        prev = score_of(c.r, desc, desc2);
+    } else {
+        prev = score;
+        head = (head + 1) & 3;
+    }
+    // The frame ring gets the new display; after a reset all four slots do.
+    uint4 *ring = reinterpret_cast<uint4 *>(s.hring + (size_t)slot * 512);
+    const uint4 *disp = reinterpret_cast<const uint4 *>(mem.hd);
+    for (uint32_t q = 0; q < 4; q++)
+        if (done || q == head)
+            for (int w = 0; w < 64; w++) ring[q * 64 + w] = disp[w];
+    store_core(s, slot, c, head);
+    s.t[slot] = t;
+    s.prev[slot] = prev;
+    s.dirty[slot] = mem.dirty;
+    sx[0] = mem.hires;
+    sx[1] = mem.rpl0;
+    sx[2] = mem.rpl1;
+}
+
+// Power-on of the SUPER-CHIP part of the selected slots: display, frame
+// ring, mode and flag registers.
+__global__ __launch_bounds__(256) void schip_reset_kernel(State s, const uint8_t *mask, uint32_t first,
+                                                          uint32_t count) {
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= count) return;
+    const uint32_t slot = first + k;
+    if (slot >= s.num) return;
+    if (mask && !mask[s.env_of[slot]]) return;
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    uint4 *hd = reinterpret_cast<uint4 *>(s.hfb + (size_t)slot * 128);
+    for (int q = 0; q < 64; q++) hd[q] = z;
+    uint4 *ring = reinterpret_cast<uint4 *>(s.hring + (size_t)slot * 512);
+    for (int q = 0; q < 256; q++) ring[q] = z;
+    reinterpret_cast<uint4 *>(s.sx)[slot] = z;
+}
+
+// Observations ([E][4][128][64]) of every env from its frame ring: block
+// (slot, frame); thread t writes rows 32 (t & 1) .. + 31 of column t >> 1.
+__global__ __launch_bounds__(256) void schip_obs_kernel(State s, uint8_t *obs) {
+    __shared__ uint64_t rows[128];
+    const uint32_t slot = blockIdx.x >> 2, fr = blockIdx.x & 3;
+    if (!slot_live(s, slot)) return;   // uniform over the block
+    const uint32_t t = threadIdx.x;
+    const uint32_t head = s.misc[slot] >> 24 & 3;
+    const uint64_t *f = s.hring + (size_t)slot * 512 + ((head + 1 + fr) & 3) * 128;
+    if (t < 128) rows[t] = f[t];
+    __syncthreads();
+    const uint32_t x = t >> 1, h = t & 1;
+    const uint32_t sh = 63 - (x & 63), half = x >> 6;
+    uint32_t col = 0;
+#pragma unroll
+    for (int r = 0; r < 32; r++) col |= (uint32_t)((rows[2 * (32 * h + r) + half] >> sh) & 1) << r;
+    store_column(obs + (size_t)s.env_of[slot] * kSchipObsBytes + fr * 8192 + x * 64 + 32 * h, col);
+}
+
+}  // namespace
+
+hipError_t launch_step_schip(const State &s, const Roms &r, const StepIO &io, hipStream_t st) {
+    const uint32_t blocks = (s.num + 63) / 64;
+    for (uint32_t k = 0; k < io.K; k++) {
+        hipLaunchKernelGGL(step_schip_kernel, dim3(blocks), dim3(64), 0, st, s, r, io, k);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (io.obs) {
+            e = launch_schip_observe(s, io.obs + (size_t)(k % io.obs_slots) * s.num * kSchipObsBytes, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_schip_reset(const State &s, const uint8_t *mask, uint32_t first, uint32_t count,
+                              hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(schip_reset_kernel, dim3((count + 255) / 256), dim3(256), 0, st, s, mask, first, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_schip_observe(const State &s, uint8_t *obs, hipStream_t st) {
+    if (s.num == 0) return hipSuccess;
+    hipLaunchKernelGGL(schip_obs_kernel, dim3(s.num * 4), dim3(256), 0, st, s, obs);
+    return hipGetLastError();
+}
+
+}  // namespace octax

@@ -16,7 +16,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liboctax.so")
 
-OCTAX_ABI_VERSION = 3
+OCTAX_ABI_VERSION = 4
 OCTAX_QUIRKS_V1 = 1
 OCTAX_QUIRK_SHIFT_VX = 1 << 1
 OCTAX_QUIRK_MEM_KEEP_I = 1 << 2
@@ -31,6 +31,8 @@ OCTAX_E_HIP = -3
 OCTAX_E_STATE = -4
 OCTAX_KERNEL_PLAIN = 0
 OCTAX_KERNEL_FUSED = 1
+OCTAX_PLATFORM_CHIP8 = 0
+OCTAX_PLATFORM_SCHIP = 1
 OCTAX_PLACE_IDENTITY = 0
 OCTAX_PLACE_BY_ROM = 1
 OBS_BYTES = 8192
@@ -39,7 +41,7 @@ EXPORTED = (
     "octax_create", "octax_reset", "octax_step", "octax_step_many", "octax_graph_create",
     "octax_graph_launch", "octax_graph_destroy", "octax_get_state", "octax_set_state",
     "octax_set_kernel", "octax_set_tuning", "octax_set_stream", "octax_info", "octax_destroy",
-    "octax_last_error", "octax_calib_write", "octax_calib_copy",
+    "octax_last_error", "octax_calib_write", "octax_calib_copy", "octax_get_schip_state",
     "octax_pool_slot_bytes", "octax_pool_create", "octax_pool_admit", "octax_pool_retire",
     "octax_pool_step", "octax_pool_info", "octax_pool_get_state", "octax_pool_destroy",
 )
@@ -70,6 +72,7 @@ class octax_config(ctypes.Structure):
         ("h_score_mode", ctypes.c_void_p), ("h_score_arg", ctypes.c_void_p),
         ("h_term_op", ctypes.c_void_p), ("h_term2_op", ctypes.c_void_p),
         ("h_term2_reg", ctypes.c_void_p), ("h_term2_value", ctypes.c_void_p),
+        ("platform", ctypes.c_uint32), ("reserved2", ctypes.c_uint32),
     ]
 
 
@@ -98,6 +101,12 @@ ENV_STATE_DTYPE = np.dtype([
     ("dt", np.uint8), ("st", np.uint8), ("prev_key", np.uint8), ("stack", np.uint16, (16,)),
     ("t", np.uint32), ("prev_score", np.int32), ("rng", np.uint64), ("ram", np.uint8, (4096,)),
     ("fb", np.uint64, (32,)), ("hist", np.uint64, (3, 32)),
+], align=True)
+
+# octax_schip_state: the SUPER-CHIP part of one env's state.
+SCHIP_STATE_DTYPE = np.dtype([
+    ("hires", np.uint32), ("rpl", np.uint8, (8,)), ("reserved", np.uint32),
+    ("fb", np.uint64, (64, 2)), ("hist", np.uint64, (3, 64, 2)),
 ], align=True)
 
 _lib = None
@@ -139,6 +148,7 @@ def library() -> ctypes.CDLL:
         "octax_graph_launch": ([P], i32),
         "octax_graph_destroy": ([P], i32),
         "octax_get_state": ([P, u32, u32, P], i32),
+        "octax_get_schip_state": ([P, u32, u32, P], i32),
         "octax_set_state": ([P, u32, u32, P], i32),
         "octax_set_kernel": ([P, u32], i32),
         "octax_set_tuning": ([P, u32, u32], i32),
@@ -210,7 +220,7 @@ class Engine:
     """One liboctax engine built from a ``workload.EnvSpec``.
 
     Output buffers are torch tensors on the engine's device: obs uint8
-    [E, 4, 64, 32] (or [slots, E, 4, 64, 32]), reward float32 [E] ([K, E]),
+    [E, 4, 64, 32] ([E, 4, 128, 64] for SUPER-CHIP; [slots, E, ...] for K steps), reward float32 [E] ([K, E]),
     done uint8 [E] ([K, E]); actions int32 [E] ([K, E]).
     """
 
@@ -261,11 +271,14 @@ class Engine:
         cfg.h_env_seed = keep["seed"].ctypes.data
         cfg.stream = _stream_handle(stream)
         _set_wrappers(cfg, spec, keep)
+        cfg.platform = int(getattr(spec, "platform", OCTAX_PLATFORM_CHIP8))
         h = ctypes.c_void_p()
         _check(L.octax_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
         self.kernel = kernel
         self.placement = placement
+        self.schip = cfg.platform == OCTAX_PLATFORM_SCHIP
+        self.obs_shape = (4, 128, 64) if self.schip else (4, 64, 32)
 
     @property
     def handle(self):
@@ -299,13 +312,13 @@ class Engine:
     def reset(self, mask=None, obs=None):
         import torch
         self._need(mask, torch.uint8, (self.E,), "mask")
-        self._need(obs, torch.uint8, (self.E, 4, 64, 32), "obs")
+        self._need(obs, torch.uint8, (self.E,) + self.obs_shape, "obs")
         _check(library().octax_reset(self._h, _ptr(mask), _ptr(obs)))
 
     def step(self, action, obs, reward, done):
         import torch
         self._need(action, torch.int32, (self.E,), "action")
-        self._need(obs, torch.uint8, (self.E, 4, 64, 32), "obs")
+        self._need(obs, torch.uint8, (self.E,) + self.obs_shape, "obs")
         self._need(reward, torch.float32, (self.E,), "reward")
         self._need(done, torch.uint8, (self.E,), "done")
         _check(library().octax_step(self._h, _ptr(action), _ptr(obs), _ptr(reward), _ptr(done)))
@@ -315,7 +328,7 @@ class Engine:
         K = int(action.shape[0])
         self._need(action, torch.int32, (K, self.E), "action")
         slots = 0 if obs is None else int(obs.shape[0])
-        self._need(obs, torch.uint8, (slots, self.E, 4, 64, 32), "obs")
+        self._need(obs, torch.uint8, (slots, self.E) + self.obs_shape, "obs")
         self._need(reward, torch.float32, (K, self.E), "reward")
         self._need(done, torch.uint8, (K, self.E), "done")
         _check(library().octax_step_many(self._h, K, _ptr(action), _ptr(obs), slots,
@@ -326,7 +339,7 @@ class Engine:
         K = int(action.shape[0])
         self._need(action, torch.int32, (K, self.E), "action")
         slots = 0 if obs is None else int(obs.shape[0])
-        self._need(obs, torch.uint8, (slots, self.E, 4, 64, 32), "obs")
+        self._need(obs, torch.uint8, (slots, self.E) + self.obs_shape, "obs")
         self._need(reward, torch.float32, (K, self.E), "reward")
         self._need(done, torch.uint8, (K, self.E), "done")
         g = ctypes.c_void_p()
@@ -343,6 +356,13 @@ class Engine:
     def set_state(self, first: int, states: np.ndarray):
         s = np.ascontiguousarray(states, dtype=ENV_STATE_DTYPE)
         _check(library().octax_set_state(self._h, first, len(s), s.ctypes.data))
+
+    def get_schip_state(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        """SUPER-CHIP mode, flag registers, display and previous frames of envs."""
+        count = self.E - first if count is None else int(count)
+        out = np.zeros(count, dtype=SCHIP_STATE_DTYPE)
+        _check(library().octax_get_schip_state(self._h, first, count, out.ctypes.data))
+        return out
 
     def set_kernel(self, kernel: str):
         _check(library().octax_set_kernel(self._h, {"plain": 0, "fused": 1}[kernel]))

@@ -176,6 +176,36 @@ def gen_rom(seed: int, n_instr: int, mix: OpcodeMix = OpcodeMix(),
     return bytes(out)
 
 
+def gen_schip_rom(seed: int, n_instr: int, mix: OpcodeMix = OpcodeMix(),
+                  action_keys: Sequence[int] = KEYS_8, share: float = 0.12) -> bytes:
+    """A SUPER-CHIP program: a generated CHIP-8 program (gen_rom) in which a
+    share of the slots (not the final jump) is replaced by SUPER-CHIP
+    instructions - mode switches 00FE / 00FF, scrolls 00CN / 00FB / 00FC,
+    16x16 sprites DXY0, big digits FX30, flag registers FX75 / FX85 and,
+    rarely, the stop instruction 00FD.  Half of the programs switch to the
+    128x64 mode in their first instruction.
+    """
+    out = bytearray(gen_rom(seed, n_instr, mix, action_keys))
+    rng = np.random.Generator(np.random.PCG64([seed, 17]))
+    kinds = ("lores", "hires", "scd", "scr", "scl", "big", "digit", "save", "load", "stop")
+    p = np.array([0.01, 0.01, 0.08, 0.06, 0.06, 0.45, 0.18, 0.08, 0.07, 0.002])
+    for i in range(n_instr - 1):
+        if i == 0:
+            if rng.random() < 0.5:
+                out[0:2] = bytes(_enc(0x00FF))
+            continue
+        if rng.random() >= share:
+            continue
+        k = kinds[int(rng.choice(len(kinds), p=p / p.sum()))]
+        x, y = int(rng.integers(0, 16)), int(rng.integers(0, 16))
+        op = {"lores": 0x00FE, "hires": 0x00FF, "scd": 0x00C0 | int(rng.integers(1, 16)),
+              "scr": 0x00FB, "scl": 0x00FC, "big": 0xD000 | (x << 8) | (y << 4),
+              "digit": 0xF030 | (x << 8), "save": 0xF075 | (x << 8), "load": 0xF085 | (x << 8),
+              "stop": 0x00FD}[k]
+        out[2 * i:2 * i + 2] = bytes(_enc(op))
+    return bytes(out)
+
+
 def opcode_class(op: int) -> str:
     """Classify one opcode into the generator's classes (for mix checks)."""
     hi = op >> 12
@@ -240,6 +270,10 @@ class EnvSpec:
     term2_op: Optional[np.ndarray] = None       # uint8 [R]
     term2_reg: Optional[np.ndarray] = None      # uint8 [R]
     term2_value: Optional[np.ndarray] = None    # uint8 [R]
+
+    # Platform: 0 = CHIP-8 (64x32), 1 = SUPER-CHIP (128x64 display, its extra
+    # instructions, (4, 128, 64) observations).
+    platform: int = 0
 
     @property
     def has_profile(self) -> bool:
@@ -354,6 +388,9 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
             serving module); here E is a placeholder of one env per ROM.
     ``c5``  1,048,576 envs over 64 draw-heavy ROMs (40% DXYN, N up to 15,
             edge-biased coordinates), ipf 20, geometric horizons.
+    ``s1``  SUPER-CHIP: 16,384 envs over 8 programs of 256..1792 instructions
+            with 12% SUPER-CHIP instructions (gen_schip_rom), 8 keys, ipf 10,
+            geometric horizons (mean 500), (4, 128, 64) observations.
     ``ts``  65,536 envs over the three Target Shooter levels (written in Octo
             for this repository, see programs/), a third of the envs each in
             random order, keys 5 7 8 9 6, score V2, done when V3 == 1, ipf 10,
@@ -373,6 +410,8 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
         seed, E, R, L, keys, ipf, steps_ = 4, 1 << 20, 64, None, KEYS_8, 20, 1000
     elif name == "ts":
         seed, E, R, L, keys, ipf, steps_ = 5, 65536, 3, None, KEYS_5, 10, 64
+    elif name == "s1":
+        seed, E, R, L, keys, ipf, steps_ = 6, 16384, 8, None, KEYS_8, 10, 64
     else:
         raise KeyError(name)
     if num_envs is not None:
@@ -401,7 +440,10 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
                                base.timer, base.rnd, base.misc])
             others = others / others.sum() * rest
             mix = OpcodeMix(draw, *others[:5], branch, *others[5:])
-        roms.append(gen_rom(seed * 1000 + r_, n, mix, keys))
+        if name == "s1":
+            roms.append(gen_schip_rom(seed * 1000 + r_, n, mix, keys))
+        else:
+            roms.append(gen_rom(seed * 1000 + r_, n, mix, keys))
     if R == 1:
         env_rom = np.zeros(E, dtype=np.uint16)
     else:
@@ -420,7 +462,7 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
     return EnvSpec(name=name, roms=roms, env_rom=env_rom, action_keys=akeys, num_actions=nact,
                    score_reg=sreg, term_reg=treg, term_value=tval, horizon=horizon,
                    env_seed=env_seed, instr_per_frame=ipf, frame_skip=4, steps=steps_,
-                   action_seed=seed + 7919)
+                   action_seed=seed + 7919, platform=1 if name == "s1" else 0)
 
 
 PROGRAMS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "programs")

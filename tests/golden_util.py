@@ -103,3 +103,19 @@ def splitmix_vectors():
 def lit_pixels(disp_yx: np.ndarray):
     ys, xs = np.nonzero(disp_yx)
     return {(int(x), int(y)) for x, y in zip(xs, ys)}
+
+
+def big_font_pictures() -> np.ndarray:
+    """[16][10][8] pixel pictures of the SUPER-CHIP digit glyphs."""
+    out = np.zeros((16, 10, 8), dtype=np.uint8)
+    glyph, row = -1, 0
+    for line in open(os.path.join(GOLDEN, "big_font_glyphs.txt")):
+        line = line.strip()
+        if not line or line.startswith("#") and not set(line) <= {"#", "."}:
+            continue
+        if len(line) == 1:
+            glyph, row = int(line, 16), 0
+            continue
+        out[glyph, row] = [c == "#" for c in line]
+        row += 1
+    return out

@@ -68,6 +68,22 @@ class Pair:
         self.orc.close()
 
 
+def schip_pixels(fb):
+    """octax_schip_state rows [..., 64, 2] (uint64, bit 63 - (x mod 64)) -> pixels [..., 64, 128]."""
+    b = np.ascontiguousarray(fb, dtype=">u8").view(np.uint8)
+    return np.unpackbits(b, axis=-1).reshape(fb.shape[:-2] + (64, 128))
+
+
+def compare_schip(gpu_sx, oracle_sx, where=""):
+    """SUPER-CHIP parts of the state: mode, flag registers, display, previous frames."""
+    assert np.array_equal(gpu_sx["hires"], oracle_sx["hires"].astype(np.uint32)), f"{where}: hires differs"
+    assert np.array_equal(gpu_sx["rpl"], oracle_sx["rpl"]), f"{where}: flag registers differ"
+    hd = schip_pixels(gpu_sx["fb"])
+    if not np.array_equal(hd, oracle_sx["hd"]):
+        raise AssertionError(f"{where}: display differs at envs {np.unique(np.nonzero(hd != oracle_sx['hd'])[0])[:8]}")
+    assert np.array_equal(schip_pixels(gpu_sx["hist"]), oracle_sx["hist"]), f"{where}: frame history differs"
+
+
 def run_rollouts(spec, kernel, K, launches, envs_per_block=256, graph=False):
     """K-step launches (or graph replays) of the engine beside the oracle:
     rewards, done flags and observations compared at every step, the full
@@ -81,7 +97,7 @@ def run_rollouts(spec, kernel, K, launches, envs_per_block=256, graph=False):
     orc = O.OracleBatch(spec)
     compare_states(eng.get_state(), orc.get_state(), f"{kernel} after create")
     act = torch.zeros((K, E), dtype=torch.int32, device=dev)
-    obs = torch.zeros((K, E, 4, 64, 32), dtype=torch.uint8, device=dev)
+    obs = torch.zeros((K, E) + eng.obs_shape, dtype=torch.uint8, device=dev)
     rew = torch.zeros((K, E), dtype=torch.float32, device=dev)
     done = torch.zeros((K, E), dtype=torch.uint8, device=dev)
     g = eng.graph(act, obs, rew, done) if graph else None
@@ -104,6 +120,8 @@ def run_rollouts(spec, kernel, K, launches, envs_per_block=256, graph=False):
                 raise AssertionError(f"{kernel} launch {rep} step {k}: obs differs at envs {bad[:8]}")
             resets += int((od != 0).sum())
         compare_states(eng.get_state(), orc.get_state(), f"{kernel} launch {rep}")
+        if eng.schip:
+            compare_schip(eng.get_schip_state(), orc.get_schip(), f"{kernel} launch {rep}")
     if g is not None:
         g.close()
     eng.close()

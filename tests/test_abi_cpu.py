@@ -39,7 +39,9 @@ def test_struct_layouts_match_header():
            'int main(){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(octax_config), sizeof(octax_env_state),'
            ' offsetof(octax_env_state, ram), offsetof(octax_config, h_rom_data),'
            ' offsetof(octax_config, sticky_q24), offsetof(octax_env_state, prev_key));'
-           ' printf("%zu %zu\\n", offsetof(octax_config, h_score_mode), offsetof(octax_config, h_term2_value));}\n')
+           ' printf("%zu %zu\\n", offsetof(octax_config, h_score_mode), offsetof(octax_config, h_term2_value));'
+           ' printf("%zu %zu %zu\\n", offsetof(octax_config, platform), sizeof(octax_schip_state),'
+           ' offsetof(octax_schip_state, fb));}\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
@@ -53,6 +55,9 @@ def test_struct_layouts_match_header():
     assert int(out[4]) == X.octax_config.sticky_q24.offset
     assert int(out[6]) == X.octax_config.h_score_mode.offset
     assert int(out[7]) == X.octax_config.h_term2_value.offset
+    assert int(out[8]) == X.octax_config.platform.offset
+    assert int(out[9]) == X.SCHIP_STATE_DTYPE.itemsize
+    assert int(out[10]) == X.SCHIP_STATE_DTYPE.fields["fb"][1]
     assert int(out[5]) == X.ENV_STATE_DTYPE.fields["prev_key"][1]
 
 
@@ -132,6 +137,21 @@ def test_create_rejects_bad_descriptors_without_gpu():
         assert L.octax_last_error().decode(), over
         assert not h.value
         del arrs
+
+
+def test_create_rejects_bad_platform_combinations_without_gpu():
+    import numpy as np
+    L = X.library()
+    h = ctypes.c_void_p()
+    lens, keys = np.array([1], np.uint8), np.zeros(16, np.uint8)
+    for over in (dict(platform=2), dict(platform=1, kernel=X.OCTAX_KERNEL_FUSED),
+                 dict(platform=1, noop_max=3),
+                 dict(platform=1, h_startup_len=lens.ctypes.data, h_startup_keys=keys.ctypes.data)):
+        c, keep = _cfg(**over)
+        assert L.octax_create(ctypes.byref(c), ctypes.byref(h)) == X.OCTAX_E_INVALID, over
+        assert L.octax_last_error().decode(), over
+        assert not h.value
+    assert L.octax_get_schip_state(None, 0, 0, None) == X.OCTAX_E_INVALID
 
 
 def test_create_rejects_long_rom_and_bad_rom_index():

@@ -42,7 +42,7 @@ def _kernels(src):
     return kernels
 
 
-@pytest.mark.parametrize("src", ["step_fused.hip", "step_plain.hip", "reset.hip", "calib.hip"])
+@pytest.mark.parametrize("src", ["step_fused.hip", "step_plain.hip", "step_schip.hip", "reset.hip", "calib.hip"])
 def test_no_scratch_no_spills_lds_fits(src):
     ks = _kernels(src)
     assert ks, src
