@@ -4,10 +4,10 @@
 //     1 KB display in HBM), in 64-thread blocks so that a batch of a few
 //     thousand envs still puts a wave on every CU; it ends by writing the
 //     display into the env's frame ring;
-//   * observations, one 256-thread block per (env, frame): the frame's 1 KB
-//     is staged in LDS and each thread writes 32 bytes of one column, so a
-//     block's stores cover the frame's 8 KB of (4, 128, 64) observation
-//     contiguously.
+//   * observations, one 256-thread block per env: the env's frame ring
+//     (4 KB) is staged in LDS and, frame by frame, each thread writes 32 bytes
+//     of one column, so a block's stores cover the env's 32 KB of (4, 128, 64)
+//     observation contiguously.
 //
 // The SUPER-CHIP instructions and the readings taken for them:
 //   00CN  scroll the display down N rows        (pixels of the current mode;
@@ -59,7 +59,11 @@ struct SchipMem : PlainMem {
     }
     __device__ __forceinline__ uint32_t scale() const { return hires ? 1u : 2u; }
 
-    // DXYN / DXY0 with the raw register values (see the header).
+    // DXYN / DXY0 with the raw register values (see the header).  Memory
+    // bytes may alias the display for the compiler, so the loads are batched
+    // by hand: all sprite bytes first, then the display rows of four sprite
+    // rows at a time before any of their stores (the rows of one draw are
+    // distinct, so this order changes no result).
     __device__ __forceinline__ uint32_t draw_s(uint32_t vx, uint32_t vy, uint32_t I, uint32_t n, bool wrap) {
         const uint32_t sc = scale();
         const uint32_t W = 128 / sc, H = 64 / sc;
@@ -68,36 +72,68 @@ struct SchipMem : PlainMem {
         const uint32_t h = big ? 16 : n;
         const uint32_t pw = 16 * sc;   // physical width of a 16-pixel sprite row
         const uint32_t X = x0 * sc;
+        // sprite rows drawn: all h when wrapping, else those above the bottom edge
+        const uint32_t rows = wrap ? h : min(h, H - y0);
+        uint32_t bits[16];
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            uint32_t b = 0;
+            if ((uint32_t)r < rows)
+                b = big ? ((uint32_t)ram[(I + 2 * r) & 0xFFF] << 8) | ram[(I + 2 * r + 1) & 0xFFF]
+                        : (uint32_t)ram[(I + r) & 0xFFF] << 8;
+            bits[r] = b;
+        }
         u128 hit = 0;
-        for (uint32_t r = 0; r < h; r++) {
-            uint32_t py = y0 + r;
-            if (py >= H) {
-                if (!wrap) break;
-                py -= H;
+#pragma unroll
+        for (int r0 = 0; r0 < 16; r0 += 4) {
+            if ((uint32_t)r0 >= rows) continue;   // (fully unrolled: the arrays stay in registers)
+            u128 cur[8];
+            uint32_t ys[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) {           // j = 2 * (sprite row - r0) + d
+                const uint32_t r = r0 + j / 2, d = j & 1;
+                uint32_t py = y0 + r;
+                py = py >= H ? py - H : py;
+                ys[j] = py * sc + d;
+                cur[j] = (r < rows && d < sc) ? row(ys[j]) : (u128)0;
             }
-            uint32_t bits = big ? ((uint32_t)ram[(I + 2 * r) & 0xFFF] << 8) | ram[(I + 2 * r + 1) & 0xFFF]
-                                : (uint32_t)ram[(I + r) & 0xFFF] << 8;
-            if (sc == 2) bits = double_bits(bits);
-            const u128 P = (u128)bits << (128 - pw);
-            const u128 m = wrap ? rotr128(P, X) : (P >> X);
-            for (uint32_t d = 0; d < sc; d++) {
-                const uint32_t y = py * sc + d;
-                const u128 rw = row(y);
-                hit |= rw & m;
-                set_row(y, rw ^ m);
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const uint32_t r = r0 + j / 2, d = j & 1;
+                if (r < rows && d < sc) {
+                    const uint32_t b = sc == 2 ? double_bits(bits[r0 + j / 2]) : bits[r0 + j / 2];
+                    const u128 P = (u128)b << (128 - pw);
+                    const u128 m = wrap ? rotr128(P, X) : (P >> X);
+                    hit |= cur[j] & m;
+                    set_row(ys[j], cur[j] ^ m);
+                }
             }
         }
         return hit != 0;
     }
-    // Scrolls by physical pixels.
+    // Scrolls by physical pixels, eight rows at a time: a chunk's loads come
+    // before its stores, and scrolling down goes bottom-up, so no row is read
+    // after it was written.
     __device__ __forceinline__ void scroll_down(uint32_t s) {
-        for (int y = 63; y >= 0; y--) set_row((uint32_t)y, (uint32_t)y >= s ? row((uint32_t)y - s) : (u128)0);
+        for (int y0 = 56; y0 >= 0; y0 -= 8) {
+            u128 v[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const uint32_t y = (uint32_t)(y0 + j);
+                v[j] = y >= s ? row(y - s) : (u128)0;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; j++) set_row((uint32_t)(y0 + j), v[j]);
+        }
     }
-    __device__ __forceinline__ void scroll_right(uint32_t s) {
-        for (uint32_t y = 0; y < 64; y++) set_row(y, row(y) >> s);
-    }
-    __device__ __forceinline__ void scroll_left(uint32_t s) {
-        for (uint32_t y = 0; y < 64; y++) set_row(y, row(y) << s);
+    __device__ __forceinline__ void scroll_side(uint32_t s, bool right) {
+        for (uint32_t y0 = 0; y0 < 64; y0 += 8) {
+            u128 v[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) v[j] = row(y0 + j);
+#pragma unroll
+            for (int j = 0; j < 8; j++) set_row(y0 + j, right ? v[j] >> s : v[j] << s);
+        }
     }
     // The CHIP-8 entry points used by exec_one; DXYN and 00E0 never reach it
     // (exec_schip takes them), these keep its interface whole.
@@ -122,8 +158,8 @@ __device__ __forceinline__ bool exec_schip(Core &c, SchipMem &mem, uint32_t key,
     }
     switch (op) {
     case 0x00E0: mem.clear(); c.pc = pc2; return false;
-    case 0x00FB: mem.scroll_right(4 * sc); c.pc = pc2; return false;
-    case 0x00FC: mem.scroll_left(4 * sc); c.pc = pc2; return false;
+    case 0x00FB: mem.scroll_side(4 * sc, true); c.pc = pc2; return false;
+    case 0x00FC: mem.scroll_side(4 * sc, false); c.pc = pc2; return false;
     case 0x00FD: return false;   // stopped: PC stays
     case 0x00FE: mem.hires = 0; mem.clear(); c.pc = pc2; return false;
     case 0x00FF: mem.hires = 1; mem.clear(); c.pc = pc2; return false;
@@ -229,9 +265,16 @@ __global__ __launch_bounds__(64) void step_schip_kernel(State s, Roms roms, Step
     // The frame ring gets the new display; after a reset all four slots do.
     uint4 *ring = reinterpret_cast<uint4 *>(s.hring + (size_t)slot * 512);
     const uint4 *disp = reinterpret_cast<const uint4 *>(mem.hd);
-    for (uint32_t q = 0; q < 4; q++)
-        if (done || q == head)
-            for (int w = 0; w < 64; w++) ring[q * 64 + w] = disp[w];
+    for (uint32_t q = 0; q < 4; q++) {
+        if (!(done || q == head)) continue;
+        for (int w = 0; w < 64; w += 8) {   // eight loads, then their stores
+            const uint4 a0 = disp[w], a1 = disp[w + 1], a2 = disp[w + 2], a3 = disp[w + 3];
+            const uint4 a4 = disp[w + 4], a5 = disp[w + 5], a6 = disp[w + 6], a7 = disp[w + 7];
+            uint4 *dst = ring + q * 64 + w;
+            dst[0] = a0; dst[1] = a1; dst[2] = a2; dst[3] = a3;
+            dst[4] = a4; dst[5] = a5; dst[6] = a6; dst[7] = a7;
+        }
+    }
     store_core(s, slot, c, head);
     s.t[slot] = t;
     s.prev[slot] = prev;
@@ -258,23 +301,30 @@ __global__ __launch_bounds__(256) void schip_reset_kernel(State s, const uint8_t
     reinterpret_cast<uint4 *>(s.sx)[slot] = z;
 }
 
-// Observations ([E][4][128][64]) of every env from its frame ring: block
-// (slot, frame); thread t writes rows 32 (t & 1) .. + 31 of column t >> 1.
+// Observations ([E][4][128][64]) of every env from its frame ring: block =
+// slot; for each frame, thread t writes rows 32 (t & 1) .. + 31 of column
+// t >> 1.
 __global__ __launch_bounds__(256) void schip_obs_kernel(State s, uint8_t *obs) {
-    __shared__ uint64_t rows[128];
-    const uint32_t slot = blockIdx.x >> 2, fr = blockIdx.x & 3;
+    __shared__ uint64_t ring[512];
+    const uint32_t slot = blockIdx.x;
     if (!slot_live(s, slot)) return;   // uniform over the block
     const uint32_t t = threadIdx.x;
     const uint32_t head = s.misc[slot] >> 24 & 3;
-    const uint64_t *f = s.hring + (size_t)slot * 512 + ((head + 1 + fr) & 3) * 128;
-    if (t < 128) rows[t] = f[t];
+    const uint64_t *src = s.hring + (size_t)slot * 512;
+    ring[t] = src[t];
+    ring[256 + t] = src[256 + t];
     __syncthreads();
     const uint32_t x = t >> 1, h = t & 1;
     const uint32_t sh = 63 - (x & 63), half = x >> 6;
-    uint32_t col = 0;
+    uint8_t *o = obs + (size_t)s.env_of[slot] * kSchipObsBytes + x * 64 + 32 * h;
 #pragma unroll
-    for (int r = 0; r < 32; r++) col |= (uint32_t)((rows[2 * (32 * h + r) + half] >> sh) & 1) << r;
-    store_column(obs + (size_t)s.env_of[slot] * kSchipObsBytes + fr * 8192 + x * 64 + 32 * h, col);
+    for (uint32_t fr = 0; fr < 4; fr++) {
+        const uint64_t *rows = ring + ((head + 1 + fr) & 3) * 128;
+        uint32_t col = 0;
+#pragma unroll
+        for (int r = 0; r < 32; r++) col |= (uint32_t)((rows[2 * (32 * h + r) + half] >> sh) & 1) << r;
+        store_column(o + fr * 8192, col);
+    }
 }
 
 }  // namespace
@@ -302,7 +352,7 @@ hipError_t launch_schip_reset(const State &s, const uint8_t *mask, uint32_t firs
 
 hipError_t launch_schip_observe(const State &s, uint8_t *obs, hipStream_t st) {
     if (s.num == 0) return hipSuccess;
-    hipLaunchKernelGGL(schip_obs_kernel, dim3(s.num * 4), dim3(256), 0, st, s, obs);
+    hipLaunchKernelGGL(schip_obs_kernel, dim3(s.num), dim3(256), 0, st, s, obs);
     return hipGetLastError();
 }
 

@@ -388,7 +388,7 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
             serving module); here E is a placeholder of one env per ROM.
     ``c5``  1,048,576 envs over 64 draw-heavy ROMs (40% DXYN, N up to 15,
             edge-biased coordinates), ipf 20, geometric horizons.
-    ``s1``  SUPER-CHIP: 16,384 envs over 8 programs of 256..1792 instructions
+    ``s1``  SUPER-CHIP: 65,536 envs over 8 programs of 256..1792 instructions
             with 12% SUPER-CHIP instructions (gen_schip_rom), 8 keys, ipf 10,
             geometric horizons (mean 500), (4, 128, 64) observations.
     ``ts``  65,536 envs over the three Target Shooter levels (written in Octo
@@ -411,7 +411,7 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
     elif name == "ts":
         seed, E, R, L, keys, ipf, steps_ = 5, 65536, 3, None, KEYS_5, 10, 64
     elif name == "s1":
-        seed, E, R, L, keys, ipf, steps_ = 6, 16384, 8, None, KEYS_8, 10, 64
+        seed, E, R, L, keys, ipf, steps_ = 6, 65536, 8, None, KEYS_8, 10, 16
     else:
         raise KeyError(name)
     if num_envs is not None:
