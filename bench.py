@@ -324,9 +324,15 @@ def main():
         time_replays(torch, stream, gs, sact, spool, n_s, args.warmup)
         stream.synchronize()
         swall = time.perf_counter() - t0
+        # algorithmic bytes per env step: the 32 KB observation, reward, done and action
+        s_bytes = 32768 + 4 + 1 + 4
+        s_achieved = Es * Ks * n_s * s_bytes / swall / 1e9
         schip = {"value": Es * Ks * n_s / swall, "ms_per_step": swall * 1e3 / n_s, "replays": n_s,
                  "obs_GBs": Es * Ks * n_s * 32768 / swall / 1e9,
-                 "kernel": "lane-per-env emulation + block-per-frame observations",
+                 "roofline": {"bound": "hbm", "achieved": s_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": s_achieved / HBM_PEAK_GBS, "bytes_per_env_step": s_bytes,
+                              "timing": "wall clock over the timed replays"},
+                 "kernel": "emulation of step k beside the observations of step k - 1, one launch per step",
                  "workload": f"SUPER-CHIP: 65,536 envs over 8 generated programs with 12% SUPER-CHIP "
                              f"instructions, {Ks} steps per graph replay, ipf 10, frame skip 4, "
                              f"4x128x64 uint8 obs, geometric horizons mean 500"}

@@ -35,8 +35,9 @@ struct State {
     // SUPER-CHIP engines only (null otherwise):
     uint64_t *hfb;       // [E][64][2] 128x64 display: row y = hfb[2y] (x 0..63) and hfb[2y+1]
                          //            (x 64..127), bit 63 - (x mod 64) = pixel (x, y)
-    uint64_t *hring;     // [E][4][128] frame ring of displays in the same row form, slot = misc head
-    uint32_t *sx;        // [E][4] word 0: 1 = 128x64 mode; words 1, 2: flag registers 0..7, one byte each
+    uint64_t *hring;     // [E][5][128] frame ring of displays in the same row form
+    uint32_t *sx;        // [E][4] word 0: 1 = 128x64 mode; words 1, 2: flag registers 0..7, one byte each;
+                         //        word 3: ring slot of the display and per-step observation info
     const uint32_t *rom_of;   // [E] ROM id
     const uint32_t *horizon;  // [E]
     const uint32_t *env_of;   // [E] env index (output position) of each slot

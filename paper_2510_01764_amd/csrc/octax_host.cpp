@@ -388,7 +388,7 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     TRY(g->alloc(&g->s.ram, (size_t)kMem * E));
     if (schip) {
         TRY(g->alloc(&g->s.hfb, 128 * (size_t)E));
-        TRY(g->alloc(&g->s.hring, 512 * (size_t)E));
+        TRY(g->alloc(&g->s.hring, 640 * (size_t)E));
         TRY(g->alloc(&g->s.sx, 4 * (size_t)E));
     }
     TRY(g->alloc(&rom_of, E));
@@ -454,22 +454,26 @@ int32_t octax_get_schip_state(octax_engine *g, uint32_t first, uint32_t count, o
     if (!g->schip) return fail(OCTAX_E_INVALID, "octax_get_schip_state: not a SUPER-CHIP engine");
     if ((uint64_t)first + count > g->E) return fail(OCTAX_E_INVALID, "octax_get_schip_state: range outside 0..E");
     hipError_t e = hipStreamSynchronize(g->stream);
-    std::vector<uint64_t> ring(512);
+    std::vector<uint64_t> ring(640);
     for (uint32_t k = 0; k < count && e == hipSuccess; k++) {
         const uint32_t slot = g->slot_of[first + k];
-        uint32_t misc = 0, sx[4] = {0, 0, 0, 0};
+        uint32_t t = 0, sx[4] = {0, 0, 0, 0};
         octax_schip_state &o = h_out[k];
-        e = hipMemcpy(&misc, g->s.misc + slot, 4, hipMemcpyDeviceToHost);
+        e = hipMemcpy(&t, g->s.t + slot, 4, hipMemcpyDeviceToHost);
         if (e == hipSuccess) e = hipMemcpy(sx, g->s.sx + 4 * (size_t)slot, 16, hipMemcpyDeviceToHost);
         if (e == hipSuccess) e = hipMemcpy(o.fb, g->s.hfb + 128 * (size_t)slot, 1024, hipMemcpyDeviceToHost);
-        if (e == hipSuccess) e = hipMemcpy(ring.data(), g->s.hring + 512 * (size_t)slot, 4096, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(ring.data(), g->s.hring + 640 * (size_t)slot, 5120, hipMemcpyDeviceToHost);
         if (e != hipSuccess) break;
         o.hires = sx[0];
         std::memcpy(o.rpl, &sx[1], 8);
         o.reserved = 0;
-        const uint32_t head = (misc >> 24) & 3;
-        for (uint32_t h = 0; h < 3; h++)   // ring slot head - 3 + h holds frame h
-            std::memcpy(o.hist[h], ring.data() + 128 * ((head + 1 + h) & 3), 1024);
+        // five ring slots, the display in slot head; frames from before the
+        // env's last reset show the reset display
+        const uint32_t head = (sx[3] >> 16) & 7;
+        for (uint32_t h = 0; h < 3; h++) {
+            const uint32_t age = std::min(3 - h, t);
+            std::memcpy(o.hist[h], ring.data() + 128 * ((head + 5 - age) % 5), 1024);
+        }
     }
     return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_get_schip_state");
 }

@@ -1,13 +1,17 @@
 // SUPER-CHIP step (the platform extension the paper names in Section 5: a
 // 128x64 display and extra instructions) as two kernels per env step:
 //   * emulation, lane per env like the plain kernel (state, memory and the
-//     1 KB display in HBM), in 64-thread blocks so that a batch of a few
-//     thousand envs still puts a wave on every CU; it ends by writing the
-//     display into the env's frame ring;
-//   * observations, one 256-thread block per env: the env's frame ring
-//     (4 KB) is staged in LDS and, frame by frame, each thread writes 32 bytes
-//     of one column, so a block's stores cover the env's 32 KB of (4, 128, 64)
-//     observation contiguously.
+//     1 KB display in HBM), in 64-thread blocks; it ends by writing the
+//     display into the env's five-slot frame ring;
+//   * observations, one 64-thread block per env: the env's frame ring is
+//     staged in LDS and each thread writes 32-byte half columns, so a
+//     block's stores cover the env's 32 KB of (4, 128, 64) observation
+//     contiguously.
+// Both run in one launch per step, the emulation of step k beside the
+// observations of step k - 1: emulation is latency-bound and the stores are
+// bandwidth-bound, so they overlap.  The ring has five slots so that the
+// emulation of step k never writes a frame the observations of step k - 1
+// read.
 //
 // The SUPER-CHIP instructions and the readings taken for them:
 //   00CN  scroll the display down N rows        (pixels of the current mode;
@@ -201,8 +205,25 @@ __device__ __forceinline__ void schip_env_step(Core &c, SchipMem &mem, uint32_t 
     }
 }
 
-__global__ __launch_bounds__(64) void step_schip_kernel(State s, Roms roms, StepIO io, uint32_t k) {
-    const uint32_t slot = blockIdx.x * 64 + threadIdx.x;
+// Word 3 of an env's State::sx: bits 16..18 = frame-ring slot of the
+// current display; bits 0..7 / 8..15 = what the observation of the last
+// even / odd step needs (ring slot of its display | min(steps since reset,
+// 3) << 3).  The observation of step k reads its byte while the emulation of
+// step k + 1 writes the other one.
+constexpr uint32_t kRingSlots = 5;
+__device__ __forceinline__ uint32_t ring_head(uint32_t w3) { return (w3 >> 16) & 7; }
+
+// Ring slot of observation frame f (0 = oldest) for a display in slot head,
+// t steps after the env's last reset: frames from before the reset show the
+// reset display.
+__device__ __forceinline__ uint32_t frame_slot(uint32_t head, uint32_t t, uint32_t f) {
+    const uint32_t age = min(3 - f, t);
+    return (head + kRingSlots - age) % kRingSlots;
+}
+
+// Emulation of env step k for one slot.
+__device__ __forceinline__ void schip_emulate(const State &s, const Roms &roms, const StepIO &io, uint32_t k,
+                                              uint32_t slot) {
     if (!slot_live(s, slot)) return;
     const uint32_t E = s.num;
     const uint32_t env = s.env_of[slot];
@@ -211,10 +232,11 @@ __global__ __launch_bounds__(64) void step_schip_kernel(State s, Roms roms, Step
     const uint32_t desc2 = roms.desc2 ? roms.desc2[rom] : kDesc2Default;
 
     Core c;
-    uint32_t head;
-    load_core(s, slot, c, head);
+    uint32_t unused_head;   // the CHIP-8 ring head of misc; SUPER-CHIP keeps its own in sx word 3
+    load_core(s, slot, c, unused_head);
     const uint32_t key = sticky_key(roms, c, action_key(roms, rom, desc, io.action[(size_t)k * E + env]));
     uint32_t *sx = s.sx + (size_t)slot * 4;
+    const uint32_t w3 = sx[3];
     SchipMem mem;
     mem.ram = s.ram + (size_t)slot * kMem;
     mem.fb = nullptr;
@@ -255,27 +277,28 @@ __global__ __launch_bounds__(64) void step_schip_kernel(State s, Roms roms, Step
         mem.hires = 0;
         mem.rpl0 = mem.rpl1 = 0;
         for (int q = 0; q < 8; q++) mem.stack[q] = 0;
-        head = 0;
         t = 0;
         prev = score_of(c.r, desc, desc2);
     } else {
         prev = score;
-        head = (head + 1) & 3;
     }
-    // The frame ring gets the new display; after a reset all four slots do.
-    uint4 *ring = reinterpret_cast<uint4 *>(s.hring + (size_t)slot * 512);
+    // The new display goes into the next ring slot; the observations of the
+    // reset step and the three after it read the reset display for the
+    // frames from before the reset (frame_slot), so a reset writes one slot.
+    const uint32_t head = (ring_head(w3) + 1) % kRingSlots;
+    uint4 *ring = reinterpret_cast<uint4 *>(s.hring + ((size_t)slot * kRingSlots + head) * 128);
     const uint4 *disp = reinterpret_cast<const uint4 *>(mem.hd);
-    for (uint32_t q = 0; q < 4; q++) {
-        if (!(done || q == head)) continue;
-        for (int w = 0; w < 64; w += 8) {   // eight loads, then their stores
-            const uint4 a0 = disp[w], a1 = disp[w + 1], a2 = disp[w + 2], a3 = disp[w + 3];
-            const uint4 a4 = disp[w + 4], a5 = disp[w + 5], a6 = disp[w + 6], a7 = disp[w + 7];
-            uint4 *dst = ring + q * 64 + w;
-            dst[0] = a0; dst[1] = a1; dst[2] = a2; dst[3] = a3;
-            dst[4] = a4; dst[5] = a5; dst[6] = a6; dst[7] = a7;
-        }
+    for (int w = 0; w < 64; w += 8) {   // eight loads, then their stores
+        const uint4 a0 = disp[w], a1 = disp[w + 1], a2 = disp[w + 2], a3 = disp[w + 3];
+        const uint4 a4 = disp[w + 4], a5 = disp[w + 5], a6 = disp[w + 6], a7 = disp[w + 7];
+        uint4 *dst = ring + w;
+        dst[0] = a0; dst[1] = a1; dst[2] = a2; dst[3] = a3;
+        dst[4] = a4; dst[5] = a5; dst[6] = a6; dst[7] = a7;
     }
-    store_core(s, slot, c, head);
+    const uint32_t sh = 8 * (k & 1);
+    const uint32_t info = head | (min(t, 3u) << 3);
+    sx[3] = (w3 & ~(0xFFu << sh) & ~(7u << 16)) | (info << sh) | (head << 16);
+    store_core(s, slot, c, 0);
     s.t[slot] = t;
     s.prev[slot] = prev;
     s.dirty[slot] = mem.dirty;
@@ -284,8 +307,52 @@ __global__ __launch_bounds__(64) void step_schip_kernel(State s, Roms roms, Step
     sx[2] = mem.rpl1;
 }
 
+// Observations of one env (a 64-thread block): its ring (5 KB) staged in
+// LDS, then for each frame each thread writes the 32 bytes of four half
+// columns (column x, rows 32h .. 32h + 31 for unit u = 2x + h), so every
+// store instruction of the block covers 2 KB of observation contiguously.
+__device__ __forceinline__ void schip_observe_env(const State &s, uint8_t *obs, uint32_t slot, uint32_t head,
+                                                  uint32_t t) {
+    __shared__ uint64_t ring[kRingSlots * 128];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t *src = s.hring + (size_t)slot * kRingSlots * 128;
+#pragma unroll
+    for (uint32_t q = 0; q < kRingSlots * 2; q++) ring[tid + 64 * q] = src[tid + 64 * q];
+    __syncthreads();
+    uint8_t *o = obs + (size_t)s.env_of[slot] * kSchipObsBytes;
+#pragma unroll
+    for (uint32_t f = 0; f < 4; f++) {
+        const uint64_t *rows = ring + frame_slot(head, t, f) * 128;
+#pragma unroll
+        for (uint32_t u = 0; u < 4; u++) {
+            const uint32_t unit = tid + 64 * u, x = unit >> 1, h = unit & 1;
+            const uint32_t sh = 63 - (x & 63), half = x >> 6;
+            uint32_t col = 0;
+#pragma unroll
+            for (int r = 0; r < 32; r++) col |= (uint32_t)((rows[2 * (32 * h + r) + half] >> sh) & 1) << r;
+            store_column(o + f * 8192 + x * 64 + 32 * h, col);
+        }
+    }
+}
+
+// Launch j of a K-step run: blocks [0, emu_blocks) emulate step j (j < K),
+// the next E blocks (when obs_step >= 0) write the observations of step
+// j - 1.  The two parts overlap: emulation is latency-bound, the
+// observations are store-bound.
+__global__ __launch_bounds__(64) void schip_launch_kernel(State s, Roms roms, StepIO io, uint32_t j,
+                                                          uint32_t emu_blocks, uint8_t *obs_step) {
+    if (blockIdx.x < emu_blocks) {
+        schip_emulate(s, roms, io, j, blockIdx.x * 64 + threadIdx.x);
+        return;
+    }
+    const uint32_t slot = blockIdx.x - emu_blocks;
+    if (!slot_live(s, slot)) return;   // uniform over the block
+    const uint32_t info = (s.sx[(size_t)slot * 4 + 3] >> (8 * ((j - 1) & 1))) & 0xFF;
+    schip_observe_env(s, obs_step, slot, info & 7, info >> 3);
+}
+
 // Power-on of the SUPER-CHIP part of the selected slots: display, frame
-// ring, mode and flag registers.
+// ring, mode, flag registers and ring bookkeeping.
 __global__ __launch_bounds__(256) void schip_reset_kernel(State s, const uint8_t *mask, uint32_t first,
                                                           uint32_t count) {
     const uint32_t k = blockIdx.x * 256 + threadIdx.x;
@@ -296,49 +363,30 @@ __global__ __launch_bounds__(256) void schip_reset_kernel(State s, const uint8_t
     const uint4 z = make_uint4(0, 0, 0, 0);
     uint4 *hd = reinterpret_cast<uint4 *>(s.hfb + (size_t)slot * 128);
     for (int q = 0; q < 64; q++) hd[q] = z;
-    uint4 *ring = reinterpret_cast<uint4 *>(s.hring + (size_t)slot * 512);
-    for (int q = 0; q < 256; q++) ring[q] = z;
+    uint4 *ring = reinterpret_cast<uint4 *>(s.hring + (size_t)slot * kRingSlots * 128);
+    for (uint32_t q = 0; q < kRingSlots * 64; q++) ring[q] = z;
     reinterpret_cast<uint4 *>(s.sx)[slot] = z;
 }
 
-// Observations ([E][4][128][64]) of every env from its frame ring: block =
-// slot; for each frame, thread t writes rows 32 (t & 1) .. + 31 of column
-// t >> 1.
-__global__ __launch_bounds__(256) void schip_obs_kernel(State s, uint8_t *obs) {
-    __shared__ uint64_t ring[512];
+// Observations of every env from its current ring state (octax_reset).
+__global__ __launch_bounds__(64) void schip_observe_kernel(State s, uint8_t *obs) {
     const uint32_t slot = blockIdx.x;
-    if (!slot_live(s, slot)) return;   // uniform over the block
-    const uint32_t t = threadIdx.x;
-    const uint32_t head = s.misc[slot] >> 24 & 3;
-    const uint64_t *src = s.hring + (size_t)slot * 512;
-    ring[t] = src[t];
-    ring[256 + t] = src[256 + t];
-    __syncthreads();
-    const uint32_t x = t >> 1, h = t & 1;
-    const uint32_t sh = 63 - (x & 63), half = x >> 6;
-    uint8_t *o = obs + (size_t)s.env_of[slot] * kSchipObsBytes + x * 64 + 32 * h;
-#pragma unroll
-    for (uint32_t fr = 0; fr < 4; fr++) {
-        const uint64_t *rows = ring + ((head + 1 + fr) & 3) * 128;
-        uint32_t col = 0;
-#pragma unroll
-        for (int r = 0; r < 32; r++) col |= (uint32_t)((rows[2 * (32 * h + r) + half] >> sh) & 1) << r;
-        store_column(o + fr * 8192, col);
-    }
+    if (!slot_live(s, slot)) return;
+    schip_observe_env(s, obs, slot, ring_head(s.sx[(size_t)slot * 4 + 3]), s.t[slot]);
 }
 
 }  // namespace
 
 hipError_t launch_step_schip(const State &s, const Roms &r, const StepIO &io, hipStream_t st) {
-    const uint32_t blocks = (s.num + 63) / 64;
-    for (uint32_t k = 0; k < io.K; k++) {
-        hipLaunchKernelGGL(step_schip_kernel, dim3(blocks), dim3(64), 0, st, s, r, io, k);
+    const uint32_t emu = (s.num + 63) / 64;
+    for (uint32_t j = 0; j <= io.K; j++) {
+        const uint32_t eb = j < io.K ? emu : 0;
+        uint8_t *obs = (io.obs && j >= 1) ? io.obs + (size_t)((j - 1) % io.obs_slots) * s.num * kSchipObsBytes : nullptr;
+        const uint32_t blocks = eb + (obs ? s.num : 0);
+        if (blocks == 0) continue;
+        hipLaunchKernelGGL(schip_launch_kernel, dim3(blocks), dim3(64), 0, st, s, r, io, j, eb, obs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        if (io.obs) {
-            e = launch_schip_observe(s, io.obs + (size_t)(k % io.obs_slots) * s.num * kSchipObsBytes, st);
-            if (e != hipSuccess) return e;
-        }
     }
     return hipSuccess;
 }
@@ -352,7 +400,7 @@ hipError_t launch_schip_reset(const State &s, const uint8_t *mask, uint32_t firs
 
 hipError_t launch_schip_observe(const State &s, uint8_t *obs, hipStream_t st) {
     if (s.num == 0) return hipSuccess;
-    hipLaunchKernelGGL(schip_obs_kernel, dim3(s.num), dim3(256), 0, st, s, obs);
+    hipLaunchKernelGGL(schip_observe_kernel, dim3(s.num), dim3(64), 0, st, s, obs);
     return hipGetLastError();
 }
 
