@@ -247,6 +247,9 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out);
  * SUPER-CHIP state of envs [first, first + count) into h_out[0..count): mode,
  * flag registers, 128x64 display and the three previous frames (the
  * registers, memory and timers come from octax_get_state).  Synchronizes.
+ * There is no setter for this part: octax_set_state writes the CHIP-8
+ * registers, memory and timers of a SUPER-CHIP env and leaves its display,
+ * mode and flag registers as they are.
  * Errors: OCTAX_E_INVALID (NULL engine or output, range outside 0..E, or a
  * CHIP-8 engine), OCTAX_E_HIP.
  */
