@@ -97,3 +97,10 @@ def test_schip_big_font_in_memory():
     want = np.packbits(big_font_pictures(), axis=2)[:, :, 0]
     assert all(np.array_equal(m, want) for m in mem)
     eng.close()
+
+
+def test_schip_sticky_actions():
+    from paper_2510_01764_amd import workload as W
+    spec = dataclasses.replace(_s1(640, seed=6), sticky_q24=int(0.3 * (1 << 24)))
+    assert spec.has_wrappers and spec.noop_max == 0 and spec.startup_len is None
+    run_rollouts(spec, "plain", K=12, launches=2)

@@ -204,3 +204,22 @@ def test_env_observations_and_reset():
             assert np.array_equal(o[d != 0, f], o[d != 0, 3])
         prev.append(v["hd"].copy())
     assert sum(int(p.sum()) for p in prev) > 0
+
+
+def test_schip_program_generator():
+    """gen_schip_rom is deterministic, keeps the final jump, and emits every
+    SUPER-CHIP instruction kind over a workload's programs."""
+    a = W.gen_schip_rom(7, 1000)
+    assert a == W.gen_schip_rom(7, 1000) and a != W.gen_schip_rom(8, 1000)
+    assert a[-2:] == bytes([0x12, 0x00])
+    spec = W.make_config("s1", num_envs=8)
+    ops = [(r[i] << 8) | r[i + 1] for r in spec.roms for i in range(0, len(r), 2)]
+    seen = {
+        "00FE": any(op == 0x00FE for op in ops), "00FF": any(op == 0x00FF for op in ops),
+        "00CN": any(op & 0xFFF0 == 0x00C0 for op in ops), "00FB": 0x00FB in ops, "00FC": 0x00FC in ops,
+        "DXY0": any(op & 0xF00F == 0xD000 for op in ops), "FX30": any(op & 0xF0FF == 0xF030 for op in ops),
+        "FX75": any(op & 0xF0FF == 0xF075 for op in ops), "FX85": any(op & 0xF0FF == 0xF085 for op in ops),
+        "00FD": 0x00FD in ops,
+    }
+    assert all(seen.values()), seen
+    assert spec.platform == 1 and spec.num_envs == 8
