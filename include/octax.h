@@ -196,8 +196,8 @@ typedef struct octax_config {
      * FX75 / FX85 (store / load V0..V(min(X, 7)) in eight flag registers).
      * Power-on is the 64x32 mode with the flag registers cleared.
      * Observations are uint8 [E][4][128][64] = [env][frame][x][y].
-     * SUPER-CHIP engines run on OCTAX_KERNEL_PLAIN only and take no
-     * start-up sequences or no-op resets (OCTAX_E_INVALID otherwise). */
+     * SUPER-CHIP engines are created with OCTAX_KERNEL_PLAIN (they run
+     * their own lane-per-env kernels; OCTAX_E_INVALID otherwise). */
     uint32_t platform;
     uint32_t reserved2;
 } octax_config;

@@ -314,8 +314,6 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     const bool schip = cfg->platform == OCTAX_PLATFORM_SCHIP;
     if (schip && cfg->kernel != OCTAX_KERNEL_PLAIN)
         return fail(OCTAX_E_INVALID, "octax_create: SUPER-CHIP engines run on the plain kernel");
-    if (schip && (cfg->noop_max || cfg->h_startup_len))
-        return fail(OCTAX_E_INVALID, "octax_create: SUPER-CHIP engines take no start-up sequences or no-op resets");
 
     octax_engine *g = new (std::nothrow) octax_engine;
     if (!g) return fail(OCTAX_E_NOMEM, "octax_create: out of host memory");
@@ -424,7 +422,6 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     g->roms.w = octax::make_wrap(g->d_startup, startup, cfg->sticky_q24, cfg->noop_max, g->ipf, g->frame_skip);
     TRY(upload_block_roms(g));
     TRY(launch_reset(g->s, g->roms, nullptr, true, g->stream));
-    if (schip) TRY(launch_schip_reset(g->s, nullptr, 0, E, g->stream));
     TRY(hipStreamSynchronize(g->stream));
 #undef TRY
     *out = g;
@@ -443,7 +440,6 @@ int32_t octax_destroy(octax_engine *g) {
 int32_t octax_reset(octax_engine *g, const uint8_t *d_mask, uint8_t *d_obs) {
     if (!g) return fail(OCTAX_E_INVALID, "octax_reset: engine is NULL");
     hipError_t e = launch_reset(g->s, g->roms, d_mask, false, g->stream);
-    if (e == hipSuccess && g->schip) e = launch_schip_reset(g->s, d_mask, 0, g->E, g->stream);
     if (e == hipSuccess && d_obs)
         e = g->schip ? launch_schip_observe(g->s, d_obs, g->stream) : launch_observe(g->s, d_obs, g->stream);
     return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_reset");

@@ -45,11 +45,12 @@ hipError_t launch_reset_steps(const State &s, const Roms &r, const uint8_t *mask
                               uint32_t count, hipStream_t st);
 // Write the observation of every env from its frame ring.
 hipError_t launch_observe(const State &s, uint8_t *obs, hipStream_t st);
-// SUPER-CHIP: K steps of the lane-per-env kernel; power-on of the display,
-// frame ring, mode and flag registers of the selected slots; observations
-// ([E][4][128][64]) from the frame ring.
+// SUPER-CHIP: K steps; power-on of the display, frame ring, mode and flag
+// registers of the selected slots of [first, first + count), then the
+// reset's emulation steps (launch_reset_range calls it after the CHIP-8
+// part); observations ([E][4][128][64]) from the frame ring.
 hipError_t launch_step_schip(const State &s, const Roms &r, const StepIO &io, hipStream_t st);
-hipError_t launch_schip_reset(const State &s, const uint8_t *mask, uint32_t first, uint32_t count,
+hipError_t launch_schip_reset(const State &s, const Roms &r, const uint8_t *mask, uint32_t first, uint32_t count,
                               hipStream_t st);
 hipError_t launch_schip_observe(const State &s, uint8_t *obs, hipStream_t st);
 

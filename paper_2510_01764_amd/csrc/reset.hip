@@ -83,6 +83,7 @@ hipError_t launch_reset_range(const State &s, const Roms &r, const uint8_t *mask
     hipLaunchKernelGGL(reset_regs_kernel, dim3((count + 255) / 256), dim3(256), 0, st, s, mask, first, count);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (r.schip) return launch_schip_reset(s, r, mask, first, count, st);
     return launch_reset_steps(s, r, mask, first, count, st);
 }
 

@@ -221,6 +221,34 @@ __device__ __forceinline__ uint32_t frame_slot(uint32_t head, uint32_t t, uint32
     return (head + kRingSlots - age) % kRingSlots;
 }
 
+// The memory policy of slot's env, its display mode and flag registers.
+__device__ __forceinline__ SchipMem schip_mem(const State &s, uint32_t slot) {
+    const uint32_t *sx = s.sx + (size_t)slot * 4;
+    SchipMem mem;
+    mem.ram = s.ram + (size_t)slot * kMem;
+    mem.fb = nullptr;
+    mem.stack = s.stack + (size_t)slot * 8;
+    mem.dirty = s.dirty[slot];
+    mem.hd = s.hfb + (size_t)slot * 128;
+    mem.hires = sx[0];
+    mem.rpl0 = sx[1];
+    mem.rpl1 = sx[2];
+    return mem;
+}
+
+// Copy the display into ring slot `head`: eight loads, then their stores.
+__device__ __forceinline__ void ring_put(const State &s, uint32_t slot, uint32_t head, const uint64_t *hd) {
+    uint4 *ring = reinterpret_cast<uint4 *>(s.hring + ((size_t)slot * kRingSlots + head) * 128);
+    const uint4 *disp = reinterpret_cast<const uint4 *>(hd);
+    for (int w = 0; w < 64; w += 8) {
+        const uint4 a0 = disp[w], a1 = disp[w + 1], a2 = disp[w + 2], a3 = disp[w + 3];
+        const uint4 a4 = disp[w + 4], a5 = disp[w + 5], a6 = disp[w + 6], a7 = disp[w + 7];
+        uint4 *dst = ring + w;
+        dst[0] = a0; dst[1] = a1; dst[2] = a2; dst[3] = a3;
+        dst[4] = a4; dst[5] = a5; dst[6] = a6; dst[7] = a7;
+    }
+}
+
 // Emulation of env step k for one slot.
 __device__ __forceinline__ void schip_emulate(const State &s, const Roms &roms, const StepIO &io, uint32_t k,
                                               uint32_t slot) {
@@ -237,15 +265,7 @@ __device__ __forceinline__ void schip_emulate(const State &s, const Roms &roms, 
     const uint32_t key = sticky_key(roms, c, action_key(roms, rom, desc, io.action[(size_t)k * E + env]));
     uint32_t *sx = s.sx + (size_t)slot * 4;
     const uint32_t w3 = sx[3];
-    SchipMem mem;
-    mem.ram = s.ram + (size_t)slot * kMem;
-    mem.fb = nullptr;
-    mem.stack = s.stack + (size_t)slot * 8;
-    mem.dirty = s.dirty[slot];
-    mem.hd = s.hfb + (size_t)slot * 128;
-    mem.hires = sx[0];
-    mem.rpl0 = sx[1];
-    mem.rpl1 = sx[2];
+    SchipMem mem = schip_mem(s, slot);
 
     schip_env_step(c, mem, key, io.ipf, io.frame_skip, roms.quirks);
 
@@ -277,6 +297,10 @@ __device__ __forceinline__ void schip_emulate(const State &s, const Roms &roms, 
         mem.hires = 0;
         mem.rpl0 = mem.rpl1 = 0;
         for (int q = 0; q < 8; q++) mem.stack[q] = 0;
+        if (roms.w.reset_steps)   // start-up sequence and no-op reset
+            run_reset_steps(roms, rom, c, [&](uint32_t rk) {
+                schip_env_step(c, mem, rk, io.ipf, io.frame_skip, roms.quirks);
+            });
         t = 0;
         prev = score_of(c.r, desc, desc2);
     } else {
@@ -286,15 +310,7 @@ __device__ __forceinline__ void schip_emulate(const State &s, const Roms &roms, 
     // reset step and the three after it read the reset display for the
     // frames from before the reset (frame_slot), so a reset writes one slot.
     const uint32_t head = (ring_head(w3) + 1) % kRingSlots;
-    uint4 *ring = reinterpret_cast<uint4 *>(s.hring + ((size_t)slot * kRingSlots + head) * 128);
-    const uint4 *disp = reinterpret_cast<const uint4 *>(mem.hd);
-    for (int w = 0; w < 64; w += 8) {   // eight loads, then their stores
-        const uint4 a0 = disp[w], a1 = disp[w + 1], a2 = disp[w + 2], a3 = disp[w + 3];
-        const uint4 a4 = disp[w + 4], a5 = disp[w + 5], a6 = disp[w + 6], a7 = disp[w + 7];
-        uint4 *dst = ring + w;
-        dst[0] = a0; dst[1] = a1; dst[2] = a2; dst[3] = a3;
-        dst[4] = a4; dst[5] = a5; dst[6] = a6; dst[7] = a7;
-    }
+    ring_put(s, slot, head, mem.hd);
     const uint32_t sh = 8 * (k & 1);
     const uint32_t info = head | (min(t, 3u) << 3);
     sx[3] = (w3 & ~(0xFFu << sh) & ~(7u << 16)) | (info << sh) | (head << 16);
@@ -368,6 +384,37 @@ __global__ __launch_bounds__(256) void schip_reset_kernel(State s, const uint8_t
     reinterpret_cast<uint4 *>(s.sx)[slot] = z;
 }
 
+// The emulation steps of a reset (start-up sequence, no-op reset) for the
+// selected slots, after their power-on (CHIP-8 part and SUPER-CHIP part);
+// the resulting display goes into ring slot 0, which the power-on made the
+// display's slot with no step since the reset.
+__global__ __launch_bounds__(64) void schip_reset_steps_kernel(State s, Roms roms, const uint8_t *mask,
+                                                               uint32_t first, uint32_t count) {
+    const uint32_t k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= count) return;
+    const uint32_t slot = first + k;
+    if (slot >= s.num) return;
+    if (mask && !mask[s.env_of[slot]]) return;
+    const uint32_t rom = s.rom_of[slot];
+    const uint32_t desc = roms.desc[rom];
+    const uint32_t desc2 = roms.desc2 ? roms.desc2[rom] : kDesc2Default;
+    Core c;
+    uint32_t unused_head;
+    load_core(s, slot, c, unused_head);
+    SchipMem mem = schip_mem(s, slot);
+    run_reset_steps(roms, rom, c, [&](uint32_t rk) {
+        schip_env_step(c, mem, rk, roms.w.ipf, roms.w.frame_skip, roms.quirks);
+    });
+    ring_put(s, slot, 0, mem.hd);
+    store_core(s, slot, c, 0);
+    s.prev[slot] = score_of(c.r, desc, desc2);
+    s.dirty[slot] = mem.dirty;
+    uint32_t *sx = s.sx + (size_t)slot * 4;
+    sx[0] = mem.hires;
+    sx[1] = mem.rpl0;
+    sx[2] = mem.rpl1;
+}
+
 // Observations of every env from its current ring state (octax_reset).
 __global__ __launch_bounds__(64) void schip_observe_kernel(State s, uint8_t *obs) {
     const uint32_t slot = blockIdx.x;
@@ -391,10 +438,13 @@ hipError_t launch_step_schip(const State &s, const Roms &r, const StepIO &io, hi
     return hipSuccess;
 }
 
-hipError_t launch_schip_reset(const State &s, const uint8_t *mask, uint32_t first, uint32_t count,
+hipError_t launch_schip_reset(const State &s, const Roms &r, const uint8_t *mask, uint32_t first, uint32_t count,
                               hipStream_t st) {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(schip_reset_kernel, dim3((count + 255) / 256), dim3(256), 0, st, s, mask, first, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !r.w.reset_steps) return e;
+    hipLaunchKernelGGL(schip_reset_steps_kernel, dim3((count + 63) / 64), dim3(64), 0, st, s, r, mask, first, count);
     return hipGetLastError();
 }
 

@@ -145,8 +145,8 @@ def test_create_rejects_bad_platform_combinations_without_gpu():
     h = ctypes.c_void_p()
     lens, keys = np.array([1], np.uint8), np.zeros(16, np.uint8)
     for over in (dict(platform=2), dict(platform=1, kernel=X.OCTAX_KERNEL_FUSED),
-                 dict(platform=1, noop_max=3),
-                 dict(platform=1, h_startup_len=lens.ctypes.data, h_startup_keys=keys.ctypes.data)):
+                 dict(platform=1, kernel=X.OCTAX_KERNEL_FUSED, noop_max=3,
+                      h_startup_len=lens.ctypes.data, h_startup_keys=keys.ctypes.data)):
         c, keep = _cfg(**over)
         assert L.octax_create(ctypes.byref(c), ctypes.byref(h)) == X.OCTAX_E_INVALID, over
         assert L.octax_last_error().decode(), over

@@ -104,3 +104,39 @@ def test_schip_sticky_actions():
     spec = dataclasses.replace(_s1(640, seed=6), sticky_q24=int(0.3 * (1 << 24)))
     assert spec.has_wrappers and spec.noop_max == 0 and spec.startup_len is None
     run_rollouts(spec, "plain", K=12, launches=2)
+
+
+def test_schip_with_every_wrapper_and_masked_reset():
+    """Start-up sequences, no-op resets and sticky actions on SUPER-CHIP envs:
+    in automatic resets during K-step launches and in octax_reset."""
+    import torch
+    from oracle import oracle as O
+    from paper_2510_01764_amd import octax as X
+    from paper_2510_01764_amd import workload as W
+    spec = W.with_wrappers(_s1(720, seed=7, mean_horizon=30.0), sticky=0.2, noop_max=6, startup_max=3, seed=3)
+    resets = run_rollouts(spec, "plain", K=12, launches=3)
+    assert resets > 100
+    dev = torch.device("cuda")
+    eng = X.Engine(spec, kernel="plain")
+    orc = O.OracleBatch(spec)
+    compare_states(eng.get_state(), orc.get_state(), "schip wrappers after create")
+    compare_schip(eng.get_schip_state(), orc.get_schip(), "schip wrappers after create")
+    E = spec.num_envs
+    act = torch.zeros(E, dtype=torch.int32, device=dev)
+    rew = torch.zeros(E, dtype=torch.float32, device=dev)
+    done = torch.zeros(E, dtype=torch.uint8, device=dev)
+    acts = spec.actions(0, 6)
+    for k in range(6):
+        act.copy_(torch.from_numpy(acts[k]))
+        eng.step(act, None, rew, done)
+        orc.step(acts[k], want_obs=False)
+    mask = (np.arange(E) % 3 == 0).astype(np.uint8)
+    obs = torch.zeros((E, 4, 128, 64), dtype=torch.uint8, device=dev)
+    eng.reset(torch.from_numpy(mask).to(dev), obs)
+    oo = orc.reset(mask)
+    torch.cuda.synchronize()
+    assert np.array_equal(obs.cpu().numpy(), oo)
+    compare_states(eng.get_state(), orc.get_state(), "schip wrappers masked reset")
+    compare_schip(eng.get_schip_state(), orc.get_schip(), "schip wrappers masked reset")
+    eng.close()
+    orc.close()
