@@ -23,8 +23,10 @@
 //         16x16 sprite of 32 bytes; clipping, wrapping and VF as for CHIP-8
 //   FX30  I = the 8x10 glyph of digit VX & 15 (10 bytes each at kBigFont)
 //   FX75  flag registers 0..min(X, 7) = V0..; FX85 the reverse
-// Every other instruction is the CHIP-8 one (exec_one), quirk flags included.
+// Every other instruction is the CHIP-8 one (exec_grouped), quirk flags
+// included.
 #include "octax_core.h"
+#include "octax_grouped.h"
 #include "octax_kernels.h"
 #include "octax_plain_mem.h"
 
@@ -50,8 +52,30 @@ __device__ __forceinline__ u128 rotr128(u128 v, uint32_t s) {
 
 struct SchipMem : PlainMem {
     uint64_t *hd;      // [64][2] display rows
+    const uint8_t *img;    // the ROM's power-on image
     uint32_t hires;
     uint32_t rpl0, rpl1;   // flag registers 0..3 and 4..7, byte k = register k
+
+    // Memory reads: a page not written since the reset equals the ROM's
+    // power-on image, which all envs of the ROM share (it stays in cache);
+    // written pages come from the env's own memory.
+    __device__ __forceinline__ uint32_t rd(uint32_t a) const {
+        a &= 0xFFF;
+        return ((dirty >> (a >> 6)) & 1) ? ram[a] : img[a];
+    }
+    __device__ __forceinline__ uint32_t fetch(uint32_t pc) const { return (rd(pc) << 8) | rd(pc + 1); }
+    // The grouped cycle's fetch: the word at pc and the top of the stack.
+    __device__ __forceinline__ uint32_t fetch(uint32_t pc, uint32_t sp, uint32_t &ret) const {
+        ret = stack_get((sp - 1) & 15);
+        return fetch(pc);
+    }
+    __device__ __forceinline__ u32x4 load_bytes(uint32_t a, uint32_t count) const {
+        u32x4 v = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            if ((uint32_t)k < count) or_byte(v, k, rd(a + k));
+        return v;
+    }
 
     // Row y as a 128-bit word, pixel x at bit 127 - x.
     __device__ __forceinline__ u128 row(uint32_t y) const {
@@ -82,9 +106,7 @@ struct SchipMem : PlainMem {
 #pragma unroll
         for (int r = 0; r < 16; r++) {
             uint32_t b = 0;
-            if ((uint32_t)r < rows)
-                b = big ? ((uint32_t)ram[(I + 2 * r) & 0xFFF] << 8) | ram[(I + 2 * r + 1) & 0xFFF]
-                        : (uint32_t)ram[(I + r) & 0xFFF] << 8;
+            if ((uint32_t)r < rows) b = big ? (rd(I + 2 * r) << 8) | rd(I + 2 * r + 1) : rd(I + r) << 8;
             bits[r] = b;
         }
         u128 hit = 0;
@@ -139,8 +161,8 @@ struct SchipMem : PlainMem {
             for (int j = 0; j < 8; j++) set_row(y0 + j, right ? v[j] >> s : v[j] << s);
         }
     }
-    // The CHIP-8 entry points used by exec_one; DXYN and 00E0 never reach it
-    // (exec_schip takes them), these keep its interface whole.
+    // The CHIP-8 entry points of the instruction cycle; DXYN and 00E0 never
+    // reach it (exec_schip takes them), these keep its interface whole.
     __device__ __forceinline__ uint32_t draw(uint32_t x0, uint32_t y0, uint32_t I, uint32_t n, bool wrap) {
         return draw_s(x0, y0, I, n, wrap);
     }
@@ -193,7 +215,9 @@ __device__ __forceinline__ bool exec_schip(Core &c, SchipMem &mem, uint32_t key,
         c.pc = pc2;
         return false;
     }
-    return exec_one(c, mem, key, quirks);
+    // every other instruction: the branch-free grouped CHIP-8 cycle, so a
+    // wave pays for one pass rather than for each handler its lanes need
+    return exec_grouped(c, mem, key, quirks);
 }
 
 __device__ __forceinline__ void schip_env_step(Core &c, SchipMem &mem, uint32_t key, uint32_t ipf, uint32_t fs,
@@ -222,7 +246,7 @@ __device__ __forceinline__ uint32_t frame_slot(uint32_t head, uint32_t t, uint32
 }
 
 // The memory policy of slot's env, its display mode and flag registers.
-__device__ __forceinline__ SchipMem schip_mem(const State &s, uint32_t slot) {
+__device__ __forceinline__ SchipMem schip_mem(const State &s, uint32_t slot, const uint8_t *img) {
     const uint32_t *sx = s.sx + (size_t)slot * 4;
     SchipMem mem;
     mem.ram = s.ram + (size_t)slot * kMem;
@@ -230,6 +254,7 @@ __device__ __forceinline__ SchipMem schip_mem(const State &s, uint32_t slot) {
     mem.stack = s.stack + (size_t)slot * 8;
     mem.dirty = s.dirty[slot];
     mem.hd = s.hfb + (size_t)slot * 128;
+    mem.img = img;
     mem.hires = sx[0];
     mem.rpl0 = sx[1];
     mem.rpl1 = sx[2];
@@ -265,7 +290,7 @@ __device__ __forceinline__ void schip_emulate(const State &s, const Roms &roms, 
     const uint32_t key = sticky_key(roms, c, action_key(roms, rom, desc, io.action[(size_t)k * E + env]));
     uint32_t *sx = s.sx + (size_t)slot * 4;
     const uint32_t w3 = sx[3];
-    SchipMem mem = schip_mem(s, slot);
+    SchipMem mem = schip_mem(s, slot, roms.image + (size_t)rom * kMem);
 
     schip_env_step(c, mem, key, io.ipf, io.frame_skip, roms.quirks);
 
@@ -401,7 +426,7 @@ __global__ __launch_bounds__(64) void schip_reset_steps_kernel(State s, Roms rom
     Core c;
     uint32_t unused_head;
     load_core(s, slot, c, unused_head);
-    SchipMem mem = schip_mem(s, slot);
+    SchipMem mem = schip_mem(s, slot, roms.image + (size_t)rom * kMem);
     run_reset_steps(roms, rom, c, [&](uint32_t rk) {
         schip_env_step(c, mem, rk, roms.w.ipf, roms.w.frame_skip, roms.quirks);
     });
