@@ -102,36 +102,37 @@ struct SchipMem : PlainMem {
         const uint32_t X = x0 * sc;
         // sprite rows drawn: all h when wrapping, else those above the bottom edge
         const uint32_t rows = wrap ? h : min(h, H - y0);
-        uint32_t bits[16];
-#pragma unroll
-        for (int r = 0; r < 16; r++) {
-            uint32_t b = 0;
-            if ((uint32_t)r < rows) b = big ? (rd(I + 2 * r) << 8) | rd(I + 2 * r + 1) : rd(I + r) << 8;
-            bits[r] = b;
-        }
         u128 hit = 0;
 #pragma unroll
         for (int r0 = 0; r0 < 16; r0 += 4) {
             if ((uint32_t)r0 >= rows) continue;   // (fully unrolled: the arrays stay in registers)
-            u128 cur[8];
-            uint32_t ys[8];
+            // this chunk's sprite bytes, then its display rows, then the stores
+            uint32_t bits[4];
+            u128 cur[4][2];
+            uint32_t y[4];
 #pragma unroll
-            for (int j = 0; j < 8; j++) {           // j = 2 * (sprite row - r0) + d
-                const uint32_t r = r0 + j / 2, d = j & 1;
+            for (int i = 0; i < 4; i++) {
+                const uint32_t r = r0 + i;
+                bits[i] = r < rows ? (big ? (rd(I + 2 * r) << 8) | rd(I + 2 * r + 1) : rd(I + r) << 8) : 0u;
                 uint32_t py = y0 + r;
                 py = py >= H ? py - H : py;
-                ys[j] = py * sc + d;
-                cur[j] = (r < rows && d < sc) ? row(ys[j]) : (u128)0;
+                y[i] = py * sc;
+#pragma unroll
+                for (int d = 0; d < 2; d++)
+                    cur[i][d] = (r < rows && (uint32_t)d < sc) ? row(y[i] + d) : (u128)0;
             }
 #pragma unroll
-            for (int j = 0; j < 8; j++) {
-                const uint32_t r = r0 + j / 2, d = j & 1;
-                if (r < rows && d < sc) {
-                    const uint32_t b = sc == 2 ? double_bits(bits[r0 + j / 2]) : bits[r0 + j / 2];
-                    const u128 P = (u128)b << (128 - pw);
-                    const u128 m = wrap ? rotr128(P, X) : (P >> X);
-                    hit |= cur[j] & m;
-                    set_row(ys[j], cur[j] ^ m);
+            for (int i = 0; i < 4; i++) {
+                if ((uint32_t)(r0 + i) >= rows) continue;
+                const uint32_t b = sc == 2 ? double_bits(bits[i]) : bits[i];
+                const u128 P = (u128)b << (128 - pw);
+                const u128 m = wrap ? rotr128(P, X) : (P >> X);
+#pragma unroll
+                for (int d = 0; d < 2; d++) {
+                    if ((uint32_t)d < sc) {
+                        hit |= cur[i][d] & m;
+                        set_row(y[i] + d, cur[i][d] ^ m);
+                    }
                 }
             }
         }
