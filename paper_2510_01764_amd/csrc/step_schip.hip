@@ -1,17 +1,16 @@
 // SUPER-CHIP step (the platform extension the paper names in Section 5: a
-// 128x64 display and extra instructions) as two kernels per env step:
+// 128x64 display and extra instructions) with two kinds of block:
 //   * emulation, lane per env like the plain kernel (state, memory and the
-//     1 KB display in HBM), in 64-thread blocks; it ends by writing the
+//     1 KB display in HBM), 64 envs per block; it ends by writing the
 //     display into the env's five-slot frame ring;
 //   * observations, one 64-thread block per env: the env's frame ring is
 //     staged in LDS and each thread writes 32-byte half columns, so a
 //     block's stores cover the env's 32 KB of (4, 128, 64) observation
 //     contiguously.
-// Both run in one launch per step, the emulation of step k beside the
-// observations of step k - 1: emulation is latency-bound and the stores are
-// bandwidth-bound, so they overlap.  The ring has five slots so that the
-// emulation of step k never writes a frame the observations of step k - 1
-// read.
+// One launch per step holds the emulation of step k and the observation
+// blocks of step k - 1, so the two can share the machine; the ring has five
+// slots so that the emulation of step k never writes a frame the
+// observations of step k - 1 read.
 //
 // The SUPER-CHIP instructions and the readings taken for them:
 //   00CN  scroll the display down N rows        (pixels of the current mode;
@@ -378,9 +377,8 @@ __device__ __forceinline__ void schip_observe_env(const State &s, uint8_t *obs, 
 }
 
 // Launch j of a K-step run: blocks [0, emu_blocks) emulate step j (j < K),
-// the next E blocks (when obs_step >= 0) write the observations of step
-// j - 1.  The two parts overlap: emulation is latency-bound, the
-// observations are store-bound.
+// the next E blocks (when obs_step is set) write the observations of step
+// j - 1.
 __global__ __launch_bounds__(64) void schip_launch_kernel(State s, Roms roms, StepIO io, uint32_t j,
                                                           uint32_t emu_blocks, uint8_t *obs_step) {
     if (blockIdx.x < emu_blocks) {
