@@ -60,7 +60,8 @@ struct SchipMem : PlainMem {
     // written pages come from the env's own memory.
     __device__ __forceinline__ uint32_t rd(uint32_t a) const {
         a &= 0xFFF;
-        return ((dirty >> (a >> 6)) & 1) ? ram[a] : img[a];
+        const uint8_t *base = ((dirty >> (a >> 6)) & 1) ? ram : img;   // one load either way
+        return base[a];
     }
     __device__ __forceinline__ uint32_t fetch(uint32_t pc) const { return (rd(pc) << 8) | rd(pc + 1); }
     // The grouped cycle's fetch: the word at pc and the top of the stack.
@@ -91,7 +92,8 @@ struct SchipMem : PlainMem {
     // by hand: all sprite bytes first, then the display rows of four sprite
     // rows at a time before any of their stores (the rows of one draw are
     // distinct, so this order changes no result).
-    __device__ __forceinline__ uint32_t draw_s(uint32_t vx, uint32_t vy, uint32_t I, uint32_t n, bool wrap) {
+    template <bool wrap>
+    __device__ __forceinline__ uint32_t draw_s(uint32_t vx, uint32_t vy, uint32_t I, uint32_t n) {
         const uint32_t sc = scale();
         const uint32_t W = 128 / sc, H = 64 / sc;
         const uint32_t x0 = vx & (W - 1), y0 = vy & (H - 1);
@@ -164,7 +166,7 @@ struct SchipMem : PlainMem {
     // The CHIP-8 entry points of the instruction cycle; DXYN and 00E0 never
     // reach it (exec_schip takes them), these keep its interface whole.
     __device__ __forceinline__ uint32_t draw(uint32_t x0, uint32_t y0, uint32_t I, uint32_t n, bool wrap) {
-        return draw_s(x0, y0, I, n, wrap);
+        return wrap ? draw_s<true>(x0, y0, I, n) : draw_s<false>(x0, y0, I, n);
     }
     __device__ __forceinline__ void clear() {
         for (uint32_t q = 0; q < 128; q++) hd[q] = 0;
@@ -192,8 +194,10 @@ __device__ __forceinline__ bool exec_schip(Core &c, SchipMem &mem, uint32_t key,
     default: break;
     }
     if ((op >> 12) == 0xD) {
-        set_vf(c.r, mem.draw_s(vget(c.r, x), vget(c.r, (op >> 4) & 0xF), c.I, op & 0xF,
-                               (quirks & kQuirkPixelWrap) != 0));
+        // the wrap flag is the batch's, so this branch is uniform
+        const uint32_t vx = vget(c.r, x), vy = vget(c.r, (op >> 4) & 0xF);
+        set_vf(c.r, (quirks & kQuirkPixelWrap) ? mem.draw_s<true>(vx, vy, c.I, op & 0xF)
+                                               : mem.draw_s<false>(vx, vy, c.I, op & 0xF));
         c.pc = pc2;
         return true;
     }
