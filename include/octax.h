@@ -53,7 +53,8 @@
  *     engine's stream; create, destroy, get_state and set_state synchronize.
  *   - Every output is a pure function of the config and the call sequence;
  *     it does not depend on the kernel, the tuning or the env placement.
- *   - Observation layout: uint8 [E][4][64][32] = [env][frame][x][y], values
+ *   - Observation layout: uint8 [E][4][64][32] = [env][frame][x][y] (SUPER-CHIP
+ *     engines: [E][4][128][64], see octax_config.platform), values
  *     0/1, frame 3 the newest.
  */
 #ifndef OCTAX_H
@@ -91,6 +92,7 @@ extern "C" {
 
 #define OCTAX_MAX_ROM_BYTES 3584u   /* 0x200..0xFFF */
 #define OCTAX_OBS_BYTES 8192u       /* 4 * 64 * 32 */
+#define OCTAX_SCHIP_OBS_BYTES 32768u /* 4 * 128 * 64, SUPER-CHIP engines */
 
 enum octax_status {
     OCTAX_OK = 0,
@@ -262,7 +264,8 @@ int32_t octax_get_schip_state(octax_engine *g, uint32_t first, uint32_t count, o
  * zero, PC = 0x200, display and frame stack blank, step count zero; then
  * the reset steps of the wrappers, if any (see octax_config).  Each env's
  * RNG stream continues.  If d_obs is not NULL the observation of every
- * env (reset or not) is written to d_obs [E][4][64][32].
+ * env (reset or not) is written to d_obs [E][4][64][32] ([E][4][128][64]
+ * for SUPER-CHIP).
  * d_mask: device uint8 [E] or NULL.  Errors: OCTAX_E_INVALID (NULL engine),
  * OCTAX_E_HIP.
  */
@@ -272,7 +275,8 @@ int32_t octax_reset(octax_engine *eng, const uint8_t *d_mask, uint8_t *d_obs);
  * One environment step of every env (Section 3.2, Environment integration;
  * Section 3.3 reward and termination; Section 3.4 automatic reset).
  * d_action: device int32 [E]; out-of-range values are the no-op.
- * d_obs: device uint8 [E][4][64][32] (may be NULL: not written).
+ * d_obs: device uint8 [E][4][64][32], [E][4][128][64] for SUPER-CHIP (may be
+ * NULL: not written).
  * d_reward: device float [E]; d_done: device uint8 [E], bit 0 terminated,
  * bit 1 truncated.  Errors: OCTAX_E_INVALID (NULL engine/action/reward/done),
  * OCTAX_E_HIP.
@@ -281,9 +285,11 @@ int32_t octax_step(octax_engine *eng, const int32_t *d_action, uint8_t *d_obs,
                    float *d_reward, uint8_t *d_done);
 
 /*
- * K consecutive environment steps in one launch (the same semantics as K
- * octax_step calls).  d_action: device int32 [K][E]; d_reward: float [K][E];
- * d_done: uint8 [K][E]; d_obs: uint8 [obs_slots][E][4][64][32] where step k
+ * K consecutive environment steps (the same semantics as K octax_step
+ * calls): one launch for the fused kernel, one per step for the plain
+ * kernel, K + 1 for SUPER-CHIP.  d_action: device int32 [K][E]; d_reward: float [K][E];
+ * d_done: uint8 [K][E]; d_obs: uint8 [obs_slots][E][4][64][32] (per-env
+ * shape [4][128][64] for SUPER-CHIP) where step k
  * writes slot k % obs_slots (obs_slots = K keeps the whole rollout,
  * obs_slots = 1 keeps the last), or NULL.
  * Errors: OCTAX_E_INVALID (K == 0, obs_slots == 0 with d_obs, NULL
