@@ -287,11 +287,12 @@ int32_t octax_step(octax_engine *eng, const int32_t *d_action, uint8_t *d_obs,
 /*
  * K consecutive environment steps (the same semantics as K octax_step
  * calls): one launch for the fused kernel, one per step for the plain
- * kernel, K + 1 for SUPER-CHIP with observations (K without).  d_action: device int32 [K][E]; d_reward: float [K][E];
- * d_done: uint8 [K][E]; d_obs: uint8 [obs_slots][E][4][64][32] (per-env
- * shape [4][128][64] for SUPER-CHIP) where step k
- * writes slot k % obs_slots (obs_slots = K keeps the whole rollout,
- * obs_slots = 1 keeps the last), or NULL.
+ * kernel, K + 1 for SUPER-CHIP with observations (K without).
+ * d_action: device int32 [K][E]; d_reward: float [K][E]; d_done: uint8
+ * [K][E]; d_obs: uint8 [obs_slots][E][4][64][32] (per-env shape
+ * [4][128][64] for SUPER-CHIP) where step k writes slot k % obs_slots
+ * (obs_slots = K keeps the whole rollout, obs_slots = 1 keeps the last),
+ * or NULL.
  * Errors: OCTAX_E_INVALID (K == 0, obs_slots == 0 with d_obs, NULL
  * arguments), OCTAX_E_HIP.
  */
