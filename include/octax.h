@@ -246,6 +246,19 @@ typedef struct octax_graph octax_graph;
 int32_t octax_create(const octax_config *cfg, octax_engine **out);
 
 /*
+ * Digest of every env's state: d_out[env] = 64-bit FNV-1a (Fowler-Noll-Vo;
+ * offset basis 0xcbf29ce484222325, prime 0x100000001b3, XOR then multiply
+ * per byte) over the env's octax_env_state, i.e. over exactly the bytes
+ * octax_get_state would return for it, in their order (for SUPER-CHIP
+ * engines: the CHIP-8 part of the state).  A cheap whole-batch parity and
+ * determinism check: equal digests for equal states, computed on the device
+ * without copying the state out.  Asynchronous on the engine's stream.
+ * d_out: device uint64 [E].  Errors: OCTAX_E_INVALID (NULL engine or
+ * output), OCTAX_E_HIP.
+ */
+int32_t octax_digest(octax_engine *g, uint64_t *d_out);
+
+/*
  * SUPER-CHIP state of envs [first, first + count) into h_out[0..count): mode,
  * flag registers, 128x64 display and the three previous frames (the
  * registers, memory and timers come from octax_get_state).  Synchronizes.

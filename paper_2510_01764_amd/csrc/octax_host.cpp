@@ -445,6 +445,12 @@ int32_t octax_reset(octax_engine *g, const uint8_t *d_mask, uint8_t *d_obs) {
     return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_reset");
 }
 
+int32_t octax_digest(octax_engine *g, uint64_t *d_out) {
+    if (!g || !d_out) return fail(OCTAX_E_INVALID, "octax_digest: NULL engine or output");
+    hipError_t e = launch_digest(g->s, d_out, g->stream);
+    return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_digest");
+}
+
 int32_t octax_get_schip_state(octax_engine *g, uint32_t first, uint32_t count, octax_schip_state *h_out) {
     if (!g || (!h_out && count)) return fail(OCTAX_E_INVALID, "octax_get_schip_state: NULL argument");
     if (!g->schip) return fail(OCTAX_E_INVALID, "octax_get_schip_state: not a SUPER-CHIP engine");

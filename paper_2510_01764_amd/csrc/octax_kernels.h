@@ -45,6 +45,8 @@ hipError_t launch_reset_steps(const State &s, const Roms &r, const uint8_t *mask
                               uint32_t count, hipStream_t st);
 // Write the observation of every env from its frame ring.
 hipError_t launch_observe(const State &s, uint8_t *obs, hipStream_t st);
+// 64-bit FNV-1a of every env's state in octax_env_state form, at its env index.
+hipError_t launch_digest(const State &s, uint64_t *out, hipStream_t st);
 // SUPER-CHIP: K steps; power-on of the display, frame ring, mode and flag
 // registers of the selected slots of [first, first + count), then the
 // reset's emulation steps (launch_reset_range calls it after the CHIP-8

@@ -69,6 +69,60 @@ __global__ __launch_bounds__(256) void observe_kernel(State s, uint8_t *obs) {
 
 }  // namespace
 
+// 64-bit FNV-1a (Fowler, Noll and Vo: offset basis 0xcbf29ce484222325,
+// prime 0x100000001b3; each byte is XOR-ed in, then the hash multiplied).
+__device__ __forceinline__ void fnv_bytes(uint64_t &h, uint64_t w, int n) {
+    for (int i = 0; i < n; i++) {
+        h ^= (w >> (8 * i)) & 0xFF;
+        h *= 0x100000001b3ull;
+    }
+}
+
+// One thread per slot: the digest of the env's state in octax_env_state form
+// (the bytes octax_get_state returns, in that order), written at its env.
+__global__ __launch_bounds__(256) void digest_kernel(State s, uint64_t *out) {
+    const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
+    if (!slot_live(s, slot)) return;
+    const uint32_t E = s.num;
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (int w = 0; w < 4; w++) fnv_bytes(h, s.regs[w * E + slot], 4);   // V0..VF
+    const uint32_t pc_i = s.pc_i[slot], misc = s.misc[slot];
+    fnv_bytes(h, (pc_i >> 16) & 0xFFF, 2);                                // I
+    fnv_bytes(h, pc_i & 0xFFF, 2);                                        // PC
+    fnv_bytes(h, misc & 15, 1);                                           // SP
+    fnv_bytes(h, (misc >> 8) & 0xFF, 1);                                  // DT
+    fnv_bytes(h, (misc >> 16) & 0xFF, 1);                                 // ST
+    fnv_bytes(h, ((misc >> 26) & 31) ^ 16, 1);                            // previous key
+    for (int w = 0; w < 8; w++) fnv_bytes(h, s.stack[(size_t)slot * 8 + w], 4);
+    fnv_bytes(h, s.t[slot], 4);
+    fnv_bytes(h, (uint32_t)s.prev[slot], 4);
+    fnv_bytes(h, s.rng[slot], 8);
+    const uint64_t *ram = reinterpret_cast<const uint64_t *>(s.ram + (size_t)slot * kMem);
+    for (int q = 0; q < 512; q++) fnv_bytes(h, ram[q], 8);
+    for (int y = 0; y < 32; y++) fnv_bytes(h, s.fb[(size_t)slot * 32 + y], 8);
+    // the three earlier frames, oldest first, from the packed frame ring:
+    // pixel (x, y) is bit (x >= 32 ? 16 : 0) + (y & 15) of word 2 (x & 31) + (y >> 4)
+    const uint32_t head = (misc >> 24) & 3;
+    for (uint32_t f = 0; f < 3; f++) {
+        const uint32_t *frame = s.cols + (size_t)slot * 256 + ((head + 1 + f) & 3) * 64;
+        for (uint32_t y = 0; y < 32; y++) {
+            uint64_t row = 0;
+            for (uint32_t x = 0; x < 64; x++) {
+                const uint32_t bit = (frame[2 * (x & 31) + (y >> 4)] >> ((x >= 32 ? 16 : 0) + (y & 15))) & 1;
+                row |= (uint64_t)bit << (63 - x);
+            }
+            fnv_bytes(h, row, 8);
+        }
+    }
+    out[s.env_of[slot]] = h;
+}
+
+hipError_t launch_digest(const State &s, uint64_t *out, hipStream_t st) {
+    if (s.num == 0) return hipSuccess;
+    hipLaunchKernelGGL(digest_kernel, dim3((s.num + 255) / 256), dim3(256), 0, st, s, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset(const State &s, const Roms &r, const uint8_t *mask, bool full_ram,
                         hipStream_t st) {
     return launch_reset_range(s, r, mask, full_ram, 0, s.num, st);

@@ -41,7 +41,7 @@ EXPORTED = (
     "octax_create", "octax_reset", "octax_step", "octax_step_many", "octax_graph_create",
     "octax_graph_launch", "octax_graph_destroy", "octax_get_state", "octax_set_state",
     "octax_set_kernel", "octax_set_tuning", "octax_set_stream", "octax_info", "octax_destroy",
-    "octax_last_error", "octax_calib_write", "octax_calib_copy", "octax_get_schip_state",
+    "octax_last_error", "octax_calib_write", "octax_calib_copy", "octax_get_schip_state", "octax_digest",
     "octax_pool_slot_bytes", "octax_pool_create", "octax_pool_admit", "octax_pool_retire",
     "octax_pool_step", "octax_pool_info", "octax_pool_get_state", "octax_pool_destroy",
 )
@@ -149,6 +149,7 @@ def library() -> ctypes.CDLL:
         "octax_graph_destroy": ([P], i32),
         "octax_get_state": ([P, u32, u32, P], i32),
         "octax_get_schip_state": ([P, u32, u32, P], i32),
+        "octax_digest": ([P, P], i32),
         "octax_set_state": ([P, u32, u32, P], i32),
         "octax_set_kernel": ([P, u32], i32),
         "octax_set_tuning": ([P, u32, u32], i32),
@@ -356,6 +357,13 @@ class Engine:
     def set_state(self, first: int, states: np.ndarray):
         s = np.ascontiguousarray(states, dtype=ENV_STATE_DTYPE)
         _check(library().octax_set_state(self._h, first, len(s), s.ctypes.data))
+
+    def digest(self, out):
+        """64-bit FNV-1a of every env's state (octax_env_state bytes) into a
+        device int64 tensor [E] (the bits of the uint64 digests)."""
+        import torch
+        self._need(out, torch.int64, (self.E,), "out")
+        _check(library().octax_digest(self._h, _ptr(out)))
 
     def get_schip_state(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
         """SUPER-CHIP mode, flag registers, display and previous frames of envs."""

@@ -127,3 +127,29 @@ def run_rollouts(spec, kernel, K, launches, envs_per_block=256, graph=False):
     eng.close()
     orc.close()
     return resets
+
+
+def fnv1a64(rows):
+    """64-bit FNV-1a of each row of a uint8 matrix [n][m] (vectorised)."""
+    rows = np.ascontiguousarray(rows, dtype=np.uint8)
+    h = np.full(rows.shape[0], 0xCBF29CE484222325, dtype=np.uint64)
+    prime = np.uint64(0x100000001B3)
+    with np.errstate(over="ignore"):
+        for j in range(rows.shape[1]):
+            h ^= rows[:, j].astype(np.uint64)
+            h *= prime
+    return h
+
+
+def oracle_env_state_bytes(states):
+    """Oracle states as octax_env_state records (the bytes octax_get_state
+    returns), for digest comparisons."""
+    from paper_2510_01764_amd import octax as X
+    out = np.zeros(len(states), dtype=X.ENV_STATE_DTYPE)
+    for f in ("v", "i", "pc", "sp", "dt", "st", "prev_key", "stack", "t", "prev_score", "rng"):
+        out[f] = states[f]
+    out["ram"] = states["mem"]
+    rows = lambda d: np.packbits(np.ascontiguousarray(d, dtype=np.uint8), axis=-1).view(">u8")[..., 0]
+    out["fb"] = rows(states["disp"])
+    out["hist"] = rows(states["hist"])
+    return out

@@ -1,0 +1,56 @@
+"""octax_digest on the GPU: the device digest equals 64-bit FNV-1a over the
+octax_get_state bytes and over the oracle's state, and the digest stream of a
+run is the same for both kernels (results do not depend on the kernel)."""
+import numpy as np
+import pytest
+
+from tests.parity_util import fnv1a64, oracle_env_state_bytes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2510_01764_amd import octax
+    octax.library()
+    return torch
+
+
+def _digest(eng):
+    import torch
+    out = torch.zeros(eng.E, dtype=torch.int64, device="cuda")
+    eng.digest(out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint64)
+
+
+def test_digest_matches_state_bytes_and_oracle():
+    import torch
+    from oracle import oracle as O
+    from paper_2510_01764_amd import octax as X
+    from paper_2510_01764_amd import workload as W
+    spec = W.make_config("c3", num_envs=900)
+    orc = O.OracleBatch(spec)
+    engines = {k: X.Engine(spec, kernel=k) for k in ("fused", "plain")}
+    K = 8
+    act = torch.zeros((K, spec.num_envs), dtype=torch.int32, device="cuda")
+    rew = torch.zeros((K, spec.num_envs), dtype=torch.float32, device="cuda")
+    done = torch.zeros((K, spec.num_envs), dtype=torch.uint8, device="cuda")
+    for rep in range(3):
+        an = spec.actions(rep * K, K)
+        act.copy_(torch.from_numpy(an))
+        for eng in engines.values():
+            eng.step_many(act, None, rew, done)
+        for k in range(K):
+            orc.step(an[k], want_obs=False)
+        want = fnv1a64(oracle_env_state_bytes(orc.get_state()).view(np.uint8).reshape(spec.num_envs, -1))
+        for name, eng in engines.items():
+            got = _digest(eng)
+            raw = eng.get_state().view(np.uint8).reshape(spec.num_envs, -1)
+            assert np.array_equal(got, fnv1a64(raw)), (name, rep)
+            assert np.array_equal(got, want), (name, rep, np.nonzero(got != want)[0][:8])
+    for eng in engines.values():
+        eng.close()
+    orc.close()
