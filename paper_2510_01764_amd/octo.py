@@ -69,10 +69,6 @@ class _Asm:
         self.blocks: List[dict] = []
 
     # -- token helpers -------------------------------------------------
-    def peek(self, k: int = 0) -> Optional[str]:
-        p = self.pos + k
-        return self.toks[p][0] if p < len(self.toks) else None
-
     def line(self) -> int:
         p = min(self.pos, len(self.toks) - 1)
         return self.toks[p][1] if self.toks else 0
