@@ -27,6 +27,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 ALGO_BYTES_PER_ENV_STEP = 8192 + 4 + 1 + 4   # obs + reward + done + action
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_fused_c3_traffic.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "step_fused_c3_valu.json")
+# integer vector-ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane operations per second
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 KERNEL_SOURCES = ["step_fused.hip", "octax_grouped.h", "octax_core.h", "octax_device.h", "octax_kernels.h"]
 
 
@@ -40,6 +43,19 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, "paper_2510_01764_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def measured_valu():
+    """Vector-ALU lane operations per launch from the committed counter
+    summary, if it was taken on the kernel source as it is now; else None."""
+    try:
+        with open(VALU_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("valu_lane_ops_per_launch")
 
 
 def measured_traffic():
@@ -66,8 +82,14 @@ def cpu_baseline(spec, sample_envs: int, sample_steps: int):
     _, _, used = orc.run_threaded(acts, cores)
     dt = time.perf_counter() - t0
     orc.close()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": sample_envs * sample_steps / dt, "unit": "env steps/s", "cores": int(used),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model,
             "sample": f"first {sample_envs} envs of the workload x {sample_steps} steps, observations "
                       f"materialised every step, {used} POSIX threads, {dt:.2f} s wall"}
 
@@ -347,6 +369,7 @@ def main():
     algo_per_launch = E * K * ALGO_BYTES_PER_ENV_STEP
     achieved = algo_per_launch / (kernel_ms * 1e-3) / 1e9
     traffic = measured_traffic()
+    valu_ops = measured_valu()
     out = {
         "metric": "env steps/s @65,536 envs mixed-ROM (fused vs plain), p99 step latency",
         "value": value,
@@ -391,6 +414,11 @@ def main():
             "algorithmic_bytes_per_launch": algo_per_launch,
             "kernel_ms": kernel_ms,
         },
+        # the other roofline of the path: integer vector ALU, from the committed
+        # SQ_INSTS_VALU counter summary of the same kernel (null if stale)
+        "valu": (None if valu_ops is None else {
+            "achieved": valu_ops / (kernel_ms * 1e-3), "peak": VALU_PEAK_LANE_OPS, "unit": "lane ops/s",
+            "frac": valu_ops / (kernel_ms * 1e-3) / VALU_PEAK_LANE_OPS, "lane_ops_per_launch": valu_ops}),
         "context": "paper: 350,000 env steps/s (Pong, constant action, RTX 3090) - other hardware and workload",
     }
     if serving is not None:

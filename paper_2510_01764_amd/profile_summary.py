@@ -2,6 +2,9 @@
 
   python -m paper_2510_01764_amd.profile_summary stats <rocprof dir> <out.txt> --command "..."
       per-kernel call count and duration statistics (from --kernel-trace --stats)
+  python -m paper_2510_01764_amd.profile_summary valu <pmc dir> <out.json> --kernel "..." --command "..."
+      vector-ALU instructions per launch of one kernel from an SQ_INSTS_VALU counter run
+      (wave-level instructions; each is 64 lane operations).
   python -m paper_2510_01764_amd.profile_summary traffic <fetch dir> <write dir> <out.json>
       --calib-bytes N --kernel "step_fused_kernel<256, true, false, false>" --command-fetch "..." --command-write "..."
       HBM bytes per launch of one kernel from FETCH_SIZE and WRITE_SIZE counter runs, each
@@ -102,6 +105,23 @@ def traffic(fetch_dir, write_dir, out, calib_bytes, kernel, cmd_f, cmd_w):
     print(json.dumps(d, indent=1))
 
 
+def valu(d, out, kernel, command):
+    sys.path.insert(0, ROOT)
+    import bench
+    v = _counter_means(d, "SQ_INSTS_VALU")
+    insts, n = _pick(v, kernel)
+    res = {
+        "kernel": kernel,
+        "kernel_source_hash": bench.kernel_source_hash(),
+        "valu_insts_per_dispatch": insts, "dispatches": n,
+        "valu_lane_ops_per_launch": insts * 64,
+        "command": command,
+    }
+    with open(out, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -117,9 +137,16 @@ def main():
     t.add_argument("--kernel", required=True)
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
+    v = sub.add_parser("valu")
+    v.add_argument("dir")
+    v.add_argument("out")
+    v.add_argument("--kernel", required=True)
+    v.add_argument("--command", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
         stats(a.dir, a.out, a.command)
+    elif a.cmd == "valu":
+        valu(a.dir, a.out, a.kernel, a.command)
     else:
         traffic(a.fetch_dir, a.write_dir, a.out, a.calib_bytes, a.kernel, a.command_fetch, a.command_write)
 
