@@ -78,9 +78,9 @@ def cpu_baseline(spec, sample_envs: int, sample_steps: int):
     sub = spec.subset(list(range(sample_envs)), name="cpu-sample")
     orc = O.OracleBatch(sub)
     acts = spec.actions(0, sample_steps)[:, :sample_envs]
-    t0 = time.perf_counter()
+    t0, c0 = time.perf_counter(), time.process_time()
     _, _, used = orc.run_threaded(acts, cores)
-    dt = time.perf_counter() - t0
+    dt, cpu_s = time.perf_counter() - t0, time.process_time() - c0
     orc.close()
     model = ""
     try:
@@ -91,7 +91,7 @@ def cpu_baseline(spec, sample_envs: int, sample_steps: int):
     return {"value": sample_envs * sample_steps / dt, "unit": "env steps/s", "cores": int(used),
             "kind": "oracle", "cpu_model": model,
             "sample": f"first {sample_envs} envs of the workload x {sample_steps} steps, observations "
-                      f"materialised every step, {used} POSIX threads, {dt:.2f} s wall"}
+                      f"materialised every step, {used} POSIX threads, {dt:.2f} s wall, {cpu_s:.1f} s of CPU time"}
 
 
 def time_replays(torch, stream, graph, act_buf, act_pool, n, start):
@@ -152,8 +152,8 @@ def main():
     ap.add_argument("--envs", type=int, default=65536)
     ap.add_argument("--k", type=int, default=64, help="env steps per replay")
     ap.add_argument("--latency-steps", type=int, default=50)
-    ap.add_argument("--cpu-envs", type=int, default=16384)
-    ap.add_argument("--cpu-steps", type=int, default=96)
+    ap.add_argument("--cpu-envs", type=int, default=65536)
+    ap.add_argument("--cpu-steps", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-wrappers", action="store_true",
