@@ -4,9 +4,12 @@ steps per second as the number of parallel environments grows, one game,
 constant action).
 
     python -m paper_2510_01764_amd.env_sweep [--sizes 1024,4096,...] [--k 64]
+        [--workloads mixed,single-const,draw-heavy]
 
-Two workloads per size: the mixed-ROM recipe (16 generated programs, random
-actions) and a single generated program with one action held throughout.
+Workloads: the mixed-ROM recipe (16 generated programs, random actions), a
+single generated program with one action held throughout, and the draw-heavy
+recipe (64 generated programs with 40% DXYN of up to 15 rows near the screen
+edges, 20 instructions per frame, random actions).
 Each point is graph replays of K steps with observations written every step
 into one observation slot (so at small sizes a step's observations can stay
 in the on-package cache; the benchmark's K-slot buffer does not allow that).
@@ -22,6 +25,7 @@ def main():
     ap.add_argument("--sizes", default="1024,4096,16384,65536,262144,1048576")
     ap.add_argument("--k", type=int, default=64)
     ap.add_argument("--replays", type=int, default=6)
+    ap.add_argument("--workloads", default="mixed,single-const")
     args = ap.parse_args()
     import torch
     from . import octax as X
@@ -29,9 +33,10 @@ def main():
     dev = torch.device("cuda")
     K = args.k
     print(f"{'workload':13s} {'envs':>8s} {'ms per launch':>14s} {'M env steps/s':>14s}", flush=True)
-    for label in ("mixed", "single-const"):
+    config = {"mixed": "c3", "single-const": "c2", "draw-heavy": "c5"}
+    for label in args.workloads.split(","):
         for E in (int(x) for x in args.sizes.split(",")):
-            spec = W.make_config("c3" if label == "mixed" else "c2", num_envs=E)
+            spec = W.make_config(config[label], num_envs=E)
             act_np = spec.actions(0, K)
             if label == "single-const":
                 act_np[:] = 0
