@@ -1,7 +1,8 @@
 """Summaries of rocprofv3 output for the profiles/ folder.
 
   python -m paper_2510_01764_amd.profile_summary stats <rocprof dir> <out.txt> --command "..."
-      per-kernel call count and duration statistics (from --kernel-trace --stats)
+      per-kernel call count and duration statistics (from --kernel-trace --stats), with the
+      median dispatch duration from the kernel trace
   python -m paper_2510_01764_amd.profile_summary valu <pmc dir> <out.json> --kernel "..." --command "..."
       vector-ALU instructions per launch of one kernel from an SQ_INSTS_VALU counter run
       (wave-level instructions; each is 64 lane operations).
@@ -45,10 +46,27 @@ def stats(d, out, command):
                 return name[:i]
         return name
 
+    # per-dispatch durations from the kernel trace, for the median (the mean
+    # also holds the autotuner's and the warm-up's launches of the same kernel)
+    durations = defaultdict(list)
+    for f in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                durations[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+
+    def median_us(name):
+        v = sorted(durations.get(name, []))
+        if not v:
+            return float("nan")
+        m = len(v) // 2
+        return (v[m] if len(v) % 2 else (v[m - 1] + v[m]) / 2) / 1e3
+
     lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
-             f"{'kernel':<56} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_ms':>10} {'pct':>6}"]
+             f"{'kernel':<56} {'calls':>6} {'avg_us':>10} {'median_us':>10} {'min_us':>10} {'max_us':>10} "
+             f"{'total_ms':>10} {'pct':>6}"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
         lines.append(f"{short(r['Name'])[:56]:<56} {int(r['Calls']):>6} {float(r['AverageNs'])/1e3:>10.1f} "
+                     f"{median_us(r['Name']):>10.1f} "
                      f"{float(r['MinNs'])/1e3:>10.1f} {float(r['MaxNs'])/1e3:>10.1f} "
                      f"{float(r['TotalDurationNs'])/1e6:>10.2f} {float(r['Percentage']):>6.2f}")
     text = "\n".join(lines) + "\n"
