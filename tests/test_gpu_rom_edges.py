@@ -1,0 +1,71 @@
+"""Parity at the edges of the program space (Section 2: programs load at
+0x200 and the 4 KB address space wraps): ROMs of 0 to 3 bytes, of 3,583 and
+3,584 bytes (the last byte of memory), raw random bytes run as code, and a
+program whose fetches, sprite reads, BCD stores and bulk loads and stores
+cross the 0xFFF -> 0x000 boundary (the one the oracle's wrap tests pin).
+Both kernels against the oracle: every checked step's observations, rewards
+and done flags, and the full state.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from tests.parity_util import Pair
+from tests.test_oracle_wrap import WRAP_PROGRAM
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2510_01764_amd import octax
+    octax.library()
+    return torch
+
+
+def _edge_spec(num_envs, seed):
+    from paper_2510_01764_amd import workload as W
+    spec = W.make_config("c3", num_envs=num_envs)
+    rng = np.random.default_rng(seed)
+    rnd = lambda n: rng.integers(0, 256, size=n, dtype=np.uint8).tobytes()   # noqa: E731
+    full = 0x1000 - 0x200                               # 3,584 bytes: the program ends at 0xFFF
+    roms = [
+        b"",                                            # all zeros: no-ops through memory and the font
+        b"\x12",                                        # 0x1200 with the zero after it: jump to self
+        b"\x12\x00",
+        rnd(3),
+        rnd(full - 1),
+        rnd(full),
+        WRAP_PROGRAM + rnd(full - len(WRAP_PROGRAM)),   # the program, ROM up to 0xFFF
+        WRAP_PROGRAM,                                   # the program, memory after it zero
+        rnd(64), rnd(65), rnd(127), rnd(1000), rnd(2047), rnd(2048), rnd(3500), rnd(full),
+    ]
+    assert len(roms) == spec.num_roms and max(len(r) for r in roms) == full
+    horizon = W.geometric_horizons(rng, num_envs, 24.0)
+    return dataclasses.replace(spec, roms=roms, horizon=horizon, name="rom-edges")
+
+
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+def test_rom_sizes_and_address_wrap(kernel):
+    spec = _edge_spec(700, seed=31)
+    p = Pair(spec, kernel=kernel)
+    acts = spec.actions(0, 60)
+    for k in range(60):
+        p.step(acts[k], check_obs=(k % 6 == 5 or k < 3))
+        if k % 20 == 19:
+            p.check_state(f"rom edges {kernel} step {k}")
+    p.close()
+
+
+@pytest.mark.parametrize("ipw,lds", [(64, True), (256, False)])
+def test_rom_edges_fused_tunings(ipw, lds):
+    spec = _edge_spec(333, seed=32)
+    p = Pair(spec, kernel="fused", envs_per_block=ipw, rom_in_lds=lds)
+    acts = spec.actions(0, 40)
+    for k in range(40):
+        p.step(acts[k], check_obs=(k % 8 == 7))
+    p.check_state(f"rom edges fused {ipw}/{lds}")
+    p.close()
