@@ -140,3 +140,39 @@ def test_schip_with_every_wrapper_and_masked_reset():
     compare_schip(eng.get_schip_state(), orc.get_schip(), "schip wrappers masked reset")
     eng.close()
     orc.close()
+
+
+# 128x64 mode; a 16x16 sprite from 0xFF0 (rows 8..15 read 0x000..0x00F) drawn
+# at (120, 56) so that both the right and the bottom edge clip it; BCD, bulk
+# stores and loads across 0xFFF as in the CHIP-8 wrap program; flag
+# registers; scrolls; the instruction at 0xFFF is V3 << 8 | V4 = 0x1202.
+SCHIP_WRAP_PROGRAM = bytes.fromhex(
+    "00FF"  # 200 128x64 mode
+    "6A12" "6312" "6402" "6581" "6642" "6724" "60F0"
+    "6178"  # V1 = 120
+    "6238"  # V2 = 56
+    "AFF0"  # I = 0xFF0
+    "D120"  # 16x16 sprite
+    "AFFE" "F033" "AFFC" "F755" "AFFD" "F565"
+    "F775"  # V0..V7 to the flag registers
+    "7C01"
+    "00C1"  # scroll down 1
+    "00FB"  # scroll right 4
+    "3C40" "1FFF"
+    "00FE" "6C00" "00FF" "1202"
+)
+
+
+def test_schip_program_space_edges():
+    """ROMs of 0 to 3,584 bytes and random bytes as code on the SUPER-CHIP
+    platform, and a 128x64 program that reads and writes across 0xFFF."""
+    from tests.test_oracle_wrap import WRAP_PROGRAM
+    spec = _s1(640, seed=12, mean_horizon=24.0)
+    rng = np.random.default_rng(12)
+    rnd = lambda n: rng.integers(0, 256, size=n, dtype=np.uint8).tobytes()   # noqa: E731
+    full = 0x1000 - 0x200
+    roms = [b"", b"\x12", rnd(full), WRAP_PROGRAM + rnd(full - len(WRAP_PROGRAM)),
+            SCHIP_WRAP_PROGRAM, SCHIP_WRAP_PROGRAM + rnd(full - len(SCHIP_WRAP_PROGRAM)), rnd(full - 1), rnd(97)]
+    assert len(roms) == spec.num_roms
+    spec = dataclasses.replace(spec, roms=roms, name="schip-rom-edges")
+    run_rollouts(spec, "plain", K=12, launches=3)
