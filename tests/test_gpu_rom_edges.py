@@ -69,3 +69,28 @@ def test_rom_edges_fused_tunings(ipw, lds):
         p.step(acts[k], check_obs=(k % 8 == 7))
     p.check_state(f"rom edges fused {ipw}/{lds}")
     p.close()
+
+
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+def test_rom_edges_with_every_quirk_flag(kernel):
+    """The same ROMs with all seven quirk flags (pixel wrap and display wait
+    among them) and per-ROM score and termination descriptors."""
+    from paper_2510_01764_amd import workload as W
+    spec = W.with_profile(_edge_spec(500, seed=33), quirks=0x7F, seed=33)
+    p = Pair(spec, kernel=kernel)
+    acts = spec.actions(0, 40)
+    for k in range(40):
+        p.step(acts[k], check_obs=(k % 5 == 4))
+    p.check_state(f"rom edges with quirks {kernel}")
+    p.close()
+
+
+def test_rom_edges_fused_mixed_waves():
+    """Identity placement: the edge ROMs mixed within every wavefront."""
+    spec = _edge_spec(450, seed=34)
+    p = Pair(spec, kernel="fused", placement="identity")
+    acts = spec.actions(0, 40)
+    for k in range(40):
+        p.step(acts[k], check_obs=(k % 5 == 4))
+    p.check_state("rom edges fused identity")
+    p.close()
