@@ -114,3 +114,36 @@ def test_million_env_draw_heavy_digests_agree_across_kernels():
     assert np.array_equal(rew.cpu().numpy(), rew_f) and np.array_equal(done.cpu().numpy(), done_f)
     bad = np.nonzero(d_fused != d_plain)[0]
     assert bad.size == 0, f"digests differ at envs {bad[:8]}"
+
+
+def test_digest_on_a_superchip_engine():
+    """For a SUPER-CHIP engine the digest covers the CHIP-8 record of the
+    state: it equals FNV-1a over the octax_get_state bytes and over the
+    oracle's state in the same record."""
+    import dataclasses
+    import torch
+    from oracle import oracle as O
+    from paper_2510_01764_amd import octax as X
+    from paper_2510_01764_amd import workload as W
+    spec = W.make_config("s1", num_envs=500)
+    rng = np.random.default_rng(8)
+    spec = dataclasses.replace(spec, horizon=W.geometric_horizons(rng, spec.num_envs, 30.0))
+    eng = X.Engine(spec, kernel="plain")
+    orc = O.OracleBatch(spec)
+    K = 6
+    act = torch.zeros((K, spec.num_envs), dtype=torch.int32, device="cuda")
+    rew = torch.zeros((K, spec.num_envs), dtype=torch.float32, device="cuda")
+    done = torch.zeros((K, spec.num_envs), dtype=torch.uint8, device="cuda")
+    for rep in range(3):
+        an = spec.actions(rep * K, K)
+        act.copy_(torch.from_numpy(an))
+        eng.step_many(act, None, rew, done)
+        for k in range(K):
+            orc.step(an[k], want_obs=False)
+        got = _digest(eng)
+        raw = eng.get_state().view(np.uint8).reshape(spec.num_envs, -1)
+        assert np.array_equal(got, fnv1a64(raw)), rep
+        want = fnv1a64(oracle_env_state_bytes(orc.get_state()).view(np.uint8).reshape(spec.num_envs, -1))
+        assert np.array_equal(got, want), (rep, np.nonzero(got != want)[0][:8])
+    eng.close()
+    orc.close()
