@@ -87,3 +87,19 @@ def test_ambiguous_kernel_name_is_an_error(tmp_path):
     _counters(d, "SQ_INSTS_VALU", [(FUSED, 1.0), (FUSED.replace("true, false, false", "false, false, false"), 2.0)])
     with pytest.raises(SystemExit):
         PS.valu(d, str(tmp_path / "o.json"), "step_fused_kernel<256", "cmd")
+
+
+def test_bench_reads_counter_summaries_only_for_the_current_kernel_source(tmp_path, monkeypatch):
+    import bench
+    h = bench.kernel_source_hash()
+    assert len(h) == 16
+    t, v = tmp_path / "t.json", tmp_path / "v.json"
+    t.write_text(json.dumps({"kernel_source_hash": h, "hbm_bytes_per_launch": 123.0}))
+    v.write_text(json.dumps({"kernel_source_hash": h, "valu_lane_ops_per_launch": 456.0}))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(t))
+    monkeypatch.setattr(bench, "VALU_FILE", str(v))
+    assert bench.measured_traffic() == 123.0 and bench.measured_valu() == 456.0
+    # a summary of another source version, or an unreadable one, gives null
+    t.write_text(json.dumps({"kernel_source_hash": "0" * 16, "hbm_bytes_per_launch": 123.0}))
+    v.write_text("not json")
+    assert bench.measured_traffic() is None and bench.measured_valu() is None
