@@ -58,6 +58,19 @@ def measured_valu():
     return d.get("valu_lane_ops_per_launch")
 
 
+def measured_active_lanes():
+    """Mean fraction of the 64 lanes active per VALU instruction, from the
+    same summary under the same condition; else None."""
+    try:
+        with open(VALU_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("active_lane_fraction")
+
+
 def measured_traffic():
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the kernel source as it is now; else None."""
@@ -418,7 +431,8 @@ def main():
         # SQ_INSTS_VALU counter summary of the same kernel (null if stale)
         "valu": (None if valu_ops is None else {
             "achieved": valu_ops / (kernel_ms * 1e-3), "peak": VALU_PEAK_LANE_OPS, "unit": "lane ops/s",
-            "frac": valu_ops / (kernel_ms * 1e-3) / VALU_PEAK_LANE_OPS, "lane_ops_per_launch": valu_ops}),
+            "frac": valu_ops / (kernel_ms * 1e-3) / VALU_PEAK_LANE_OPS, "lane_ops_per_launch": valu_ops,
+            "active_lane_fraction": measured_active_lanes()}),
         "context": "paper: 350,000 env steps/s (Pong, constant action, RTX 3090) - other hardware and workload",
     }
     if serving is not None:

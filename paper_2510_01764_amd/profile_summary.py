@@ -6,6 +6,9 @@
   python -m paper_2510_01764_amd.profile_summary valu <pmc dir> <out.json> --kernel "..." --command "..."
       vector-ALU instructions per launch of one kernel from an SQ_INSTS_VALU counter run
       (wave-level instructions; each is 64 lane operations).
+  python -m paper_2510_01764_amd.profile_summary lanes <pmc dir> <valu.json> --kernel "..." --command "..."
+      adds to a valu summary the mean active lanes per VALU instruction, from an
+      SQ_THREAD_CYCLES_VALU / SQ_ACTIVE_INST_VALU counter run of the same kernel.
   python -m paper_2510_01764_amd.profile_summary traffic <fetch dir> <write dir> <out.json>
       --calib-bytes N --kernel "step_fused_kernel<256, true, false, false>" --command-fetch "..." --command-write "..."
       HBM bytes per launch of one kernel from FETCH_SIZE and WRITE_SIZE counter runs, each
@@ -140,6 +143,25 @@ def valu(d, out, kernel, command):
     print(json.dumps(res, indent=1))
 
 
+def lanes(d, out, kernel, command):
+    """Active lanes per VALU instruction = thread-cycles / instruction-cycles
+    (both counted per VALU instruction issue), into the existing summary."""
+    sys.path.insert(0, ROOT)
+    import bench
+    thr, n = _pick(_counter_means(d, "SQ_THREAD_CYCLES_VALU"), kernel)
+    ins, _ = _pick(_counter_means(d, "SQ_ACTIVE_INST_VALU"), kernel)
+    with open(out) as fh:
+        res = json.load(fh)
+    if res.get("kernel_source_hash") != bench.kernel_source_hash():
+        raise SystemExit(f"{out} was taken on another kernel source; take the VALU counters again first")
+    res.update({"thread_cycles_valu_per_dispatch": thr, "active_inst_valu_per_dispatch": ins,
+                "lane_dispatches": n, "valu_active_lanes": thr / ins, "active_lane_fraction": thr / ins / 64,
+                "command_lanes": command})
+    with open(out, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -160,11 +182,18 @@ def main():
     v.add_argument("out")
     v.add_argument("--kernel", required=True)
     v.add_argument("--command", required=True)
+    ln = sub.add_parser("lanes")
+    ln.add_argument("dir")
+    ln.add_argument("out")
+    ln.add_argument("--kernel", required=True)
+    ln.add_argument("--command", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
         stats(a.dir, a.out, a.command)
     elif a.cmd == "valu":
         valu(a.dir, a.out, a.kernel, a.command)
+    elif a.cmd == "lanes":
+        lanes(a.dir, a.out, a.kernel, a.command)
     else:
         traffic(a.fetch_dir, a.write_dir, a.out, a.calib_bytes, a.kernel, a.command_fetch, a.command_write)
 

@@ -95,11 +95,32 @@ def test_bench_reads_counter_summaries_only_for_the_current_kernel_source(tmp_pa
     assert len(h) == 16
     t, v = tmp_path / "t.json", tmp_path / "v.json"
     t.write_text(json.dumps({"kernel_source_hash": h, "hbm_bytes_per_launch": 123.0}))
-    v.write_text(json.dumps({"kernel_source_hash": h, "valu_lane_ops_per_launch": 456.0}))
+    v.write_text(json.dumps({"kernel_source_hash": h, "valu_lane_ops_per_launch": 456.0,
+                             "active_lane_fraction": 0.75}))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(t))
     monkeypatch.setattr(bench, "VALU_FILE", str(v))
     assert bench.measured_traffic() == 123.0 and bench.measured_valu() == 456.0
+    assert bench.measured_active_lanes() == 0.75
     # a summary of another source version, or an unreadable one, gives null
     t.write_text(json.dumps({"kernel_source_hash": "0" * 16, "hbm_bytes_per_launch": 123.0}))
     v.write_text("not json")
     assert bench.measured_traffic() is None and bench.measured_valu() is None
+    assert bench.measured_active_lanes() is None
+
+
+def test_lanes_adds_the_active_lane_fraction(tmp_path, monkeypatch):
+    import bench
+    d = str(tmp_path / "l")
+    os.makedirs(d)
+    _write(os.path.join(d, "l_counter_collection.csv"), ["Kernel_Name", "Counter_Name", "Counter_Value"],
+           [[FUSED, "SQ_THREAD_CYCLES_VALU", 4800.0], [FUSED, "SQ_ACTIVE_INST_VALU", 100.0],
+            [FUSED, "SQ_THREAD_CYCLES_VALU", 4800.0], [FUSED, "SQ_ACTIVE_INST_VALU", 100.0]])
+    out = tmp_path / "v.json"
+    out.write_text(json.dumps({"kernel_source_hash": bench.kernel_source_hash(), "valu_lane_ops_per_launch": 1.0}))
+    PS.lanes(d, str(out), "step_fused_kernel<256, true, false, false>", "cmd")
+    r = json.load(open(out))
+    assert r["valu_active_lanes"] == 48.0 and r["active_lane_fraction"] == 0.75
+    assert r["valu_lane_ops_per_launch"] == 1.0          # the VALU count is kept
+    out.write_text(json.dumps({"kernel_source_hash": "0" * 16}))
+    with pytest.raises(SystemExit):
+        PS.lanes(d, str(out), "step_fused_kernel<256, true, false, false>", "cmd")
