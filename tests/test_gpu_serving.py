@@ -78,13 +78,23 @@ def test_pool_admit_retire_and_info():
     pool.close()
 
 
-@pytest.mark.parametrize("depth,wrappers,profile", [(1, False, False), (2, False, False), (2, True, False),
-                                                   (2, False, True)])
-def test_groups_in_the_mix_match_groups_alone(depth, wrappers, profile):
+@pytest.mark.parametrize("depth,wrappers,profile,edges", [(1, False, False, False), (2, False, False, False),
+                                                         (2, True, False, False), (2, False, True, False),
+                                                         (2, False, False, True)])
+def test_groups_in_the_mix_match_groups_alone(depth, wrappers, profile, edges):
     from oracle import oracle as O
     from paper_2510_01764_amd import serving as S
     from paper_2510_01764_amd import workload as W
     spec = W.make_config("c4")
+    if edges:      # ROMs of 0..3,584 bytes, random bytes as code, the program that runs across 0xFFF
+        from tests.test_oracle_wrap import WRAP_PROGRAM
+        rng = np.random.default_rng(40)
+        rnd = lambda n: rng.integers(0, 256, size=n, dtype=np.uint8).tobytes()   # noqa: E731
+        full = 0x1000 - 0x200
+        roms = [b"", b"\x12", b"\x12\x00", rnd(3), rnd(full - 1), rnd(full),
+                WRAP_PROGRAM + rnd(full - len(WRAP_PROGRAM)), WRAP_PROGRAM]
+        roms += [rnd(int(n)) for n in rng.integers(0, full + 1, size=spec.num_roms - len(roms))]
+        spec = dataclasses.replace(spec, roms=roms)
     if wrappers:   # sticky actions, no-op reset and start-up sequences at every admission and reset
         spec = W.with_wrappers(spec, sticky=0.25, noop_max=6, startup_max=3, seed=2)
     if profile:    # every quirk flag and per-ROM game descriptors
