@@ -241,6 +241,8 @@ typedef struct {
     uint8_t *term2_reg;
     uint8_t *term2_value;
     int schip;                           /* 1: SUPER-CHIP machines */
+    uint32_t *pc_hist;                   /* [R][4096] executed instructions by PC, or NULL */
+    uint32_t *op_hist;                   /* [R][65536] executed instructions by word, or NULL */
     oracle_env *env;
 } oracle_batch;
 
@@ -595,12 +597,20 @@ void oracle_machine_tick(oracle_machine *m)
 /* Environment                                                          */
 /* ------------------------------------------------------------------ */
 
-/* One environment step's worth of emulation with `key` held (-1: none). */
-static void run_step_frames(const oracle_batch *b, oracle_machine *m, int key)
+/* One environment step's worth of emulation with `key` held (-1: none).
+ * With an execution profile attached, every instruction is counted by the
+ * env's ROM and its PC, and by its 16-bit word, before it runs. */
+static void run_step_frames(const oracle_batch *b, oracle_env *e, int key)
 {
+    oracle_machine *m = &e->m;
     for (int f = 0; f < b->frame_skip; f++) {
         for (int k = 0; k < b->instr_per_frame; k++) {
             int draws = (m->mem[m->pc] >> 4) == 0xD;
+            if (b->pc_hist) {
+                uint16_t op = (uint16_t)((m->mem[m->pc] << 8) | m->mem[(m->pc + 1) & 0xFFF]);
+                b->pc_hist[(size_t)e->rom * MEM_BYTES + m->pc]++;
+                b->op_hist[(size_t)e->rom * 65536 + op]++;
+            }
             oracle_machine_execute(m, key);
             if (draws && (m->quirks & QUIRK_DISPLAY_WAIT))
                 break;
@@ -662,14 +672,14 @@ static void env_reset(const oracle_batch *b, oracle_env *e)
     if (b->startup_len) {
         for (int i = 0; i < b->startup_len[e->rom]; i++) {
             int k = b->startup_keys[e->rom][i];
-            run_step_frames(b, &e->m, k < 16 ? k : -1);
+            run_step_frames(b, e, k < 16 ? k : -1);
         }
     }
     if (b->noop_max) {
         uint64_t u = oracle_splitmix64_next(&e->m.rng);
         uint64_t n = ((u >> 32) * ((uint64_t)b->noop_max + 1)) >> 32;
         for (uint64_t i = 0; i < n; i++)
-            run_step_frames(b, &e->m, -1);
+            run_step_frames(b, e, -1);
     }
     for (int k = 0; k < 3; k++)
         memcpy(e->hist[k], e->m.disp, sizeof e->m.disp);
@@ -723,7 +733,7 @@ static void env_step(const oracle_batch *b, oracle_env *e, int32_t action, uint8
         memcpy(sx->hist[2], sx->hd, sizeof sx->hd);
     }
 
-    run_step_frames(b, &e->m, key);
+    run_step_frames(b, e, key);
 
     memcpy(e->hist[0], e->hist[1], sizeof before);
     memcpy(e->hist[1], e->hist[2], sizeof before);
@@ -944,13 +954,22 @@ static void *run_shard(void *arg)
 int oracle_run_threaded(oracle_batch *b, int steps, const int32_t *action, uint8_t *obs,
                         float *reward, uint8_t *done, int threads)
 {
-    if (threads < 1)
-        threads = 1;
+    if (threads < 1 || b->pc_hist)
+        threads = 1;                  /* the execution profile's counters are not shared safely */
     if (threads > b->num_envs)
         threads = b->num_envs > 0 ? b->num_envs : 1;
     pthread_t *tid = calloc((size_t)threads, sizeof *tid);
+    unsigned char *started = calloc((size_t)threads, 1);
     oracle_shard *sh = calloc((size_t)threads, sizeof *sh);
     int used = 0;
+    if (!tid || !started || !sh) {    /* no memory for the bookkeeping: run every env here */
+        free(tid);
+        free(started);
+        free(sh);
+        oracle_shard all = {b, 0, b->num_envs, steps, action, obs, reward, done};
+        run_shard(&all);
+        return 1;
+    }
     for (int t = 0; t < threads; t++) {
         sh[t].b = b;
         sh[t].first = (int)((long)b->num_envs * t / threads);
@@ -961,14 +980,19 @@ int oracle_run_threaded(oracle_batch *b, int steps, const int32_t *action, uint8
         sh[t].reward = reward;
         sh[t].done = done;
     }
-    for (int t = 0; t < threads; t++)
-        if (pthread_create(&tid[t], NULL, run_shard, &sh[t]) == 0)
+    for (int t = 0; t < threads; t++) {
+        if (pthread_create(&tid[t], NULL, run_shard, &sh[t]) == 0) {
+            started[t] = 1;
             used++;
-        else
-            run_shard(&sh[t]);
+        } else {
+            run_shard(&sh[t]);        /* no thread: this shard runs here */
+        }
+    }
     for (int t = 0; t < threads; t++)
-        pthread_join(tid[t], NULL);
+        if (started[t])               /* join only the threads that were created */
+            pthread_join(tid[t], NULL);
     free(tid);
+    free(started);
     free(sh);
     return used > 0 ? threads : 1;
 }
@@ -1084,6 +1108,20 @@ int oracle_machine_set_schip(oracle_machine *m, const oracle_schip_view *v)
 
 /* Make every env of a batch a SUPER-CHIP machine (schip = 1) or a CHIP-8
  * one; applies from the next reset on, so callers reset after this. */
+/* Attach (or, with NULL, detach) an execution profile: pc_hist [R][4096]
+ * and op_hist [R][65536] counters owned by the caller, which every
+ * instruction run from then on increments (step, reset steps and start-up
+ * sequences alike).  The counters are plain, so a profiled batch runs its
+ * threaded rollouts on one thread. */
+int oracle_set_exec_profile(oracle_batch *b, uint32_t *pc_hist, uint32_t *op_hist)
+{
+    if ((pc_hist == NULL) != (op_hist == NULL))
+        return -1;
+    b->pc_hist = pc_hist;
+    b->op_hist = op_hist;
+    return 0;
+}
+
 int oracle_set_platform(oracle_batch *b, int schip)
 {
     for (int e = 0; e < b->num_envs; e++)

@@ -85,6 +85,8 @@ def lib():
         L.oracle_set_profile.restype = i32
         L.oracle_set_platform.argtypes = [P, i32]
         L.oracle_set_platform.restype = i32
+        L.oracle_set_exec_profile.argtypes = [P, P, P]
+        L.oracle_set_exec_profile.restype = i32
         L.oracle_get_schip.argtypes = [P, i32, i32, P]
         L.oracle_machine_set_platform.argtypes = [P, i32]
         L.oracle_machine_set_platform.restype = i32
@@ -281,6 +283,17 @@ class OracleBatch:
         done = np.zeros((K, self.E), dtype=np.uint8)
         used = lib().oracle_run_threaded(self._h, K, _p(a), _p(obs), _p(rew), _p(done), threads)
         return rew, done, used
+
+    def profile_execution(self):
+        """Count every instruction run from now on: returns (pc_hist [R][4096],
+        op_hist [R][65536]) uint32 arrays that the oracle keeps incrementing."""
+        R = len(self.spec.roms)
+        pc = np.zeros((R, 4096), dtype=np.uint32)
+        op = np.zeros((R, 65536), dtype=np.uint32)
+        self._keep["exec_profile"] = (pc, op)
+        if lib().oracle_set_exec_profile(self._h, _p(pc), _p(op)) != 0:
+            raise ValueError("oracle_set_exec_profile")
+        return pc, op
 
     def get_state(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
         count = self.E - first if count is None else count

@@ -72,9 +72,273 @@ def _enc(op: int) -> List[int]:
     return [(op >> 8) & 0xFF, op & 0xFF]
 
 
+# Stores (FX33 / FX55) of structured programs go to this scratch area, below
+# the program and above the SUPER-CHIP big font (0x0A0..0x13F).
+STORE_START = 0x140
+STORE_END = 0x200
+MAX_STORE = 16          # FX55 with X = F writes 16 bytes
+
+_CLS = {c: k for k, c in enumerate(CLASS_NAMES)}
+# Look-ahead of the quota draw: a class is drawn with probability proportional
+# to how far its count trails weight x (instructions so far + _LOOK).
+_LOOK = 8
+
+
+@dataclasses.dataclass
+class _Unit:
+    """A run of words that control flow only ever enters at its first word."""
+
+    words: List[int]
+    skip: bool = False                  # a conditional skip of the next unit
+    jump: Optional[int] = None          # forward jump by this many units
+    call: Optional[int] = None          # 2NNN to this subroutine
+    table: Optional[int] = None         # BNNN jump table, data register index
+    table_v0: Optional[int] = None      # the table's V0: a copy of VX (None) or this constant
+    terminator: bool = False
+
+
+@dataclasses.dataclass
+class Program:
+    """A generated program and where a SUPER-CHIP instruction may replace a word."""
+
+    rom: bytes
+    replaceable: np.ndarray    # bool per instruction slot: a single-word unit, not a region's end
+    code_slots: int            # instructions before the sprite-data tail
+
+
+def program_code_slots(n_instr: int) -> int:
+    """Instruction slots of a structured program before its sprite-data tail
+    (one slot in sixteen, at least eight, is sprite data)."""
+    return n_instr - max(8, n_instr // 16)
+
+
+def gen_program(seed: int, n_instr: int, mix: OpcodeMix = OpcodeMix(),
+                action_keys: Sequence[int] = KEYS_5) -> Program:
+    """Draw one structured CHIP-8 program of ``n_instr`` two-byte slots.
+
+    Layout, like the code of a real game: a main loop that ends with a jump
+    back to 0x200, then subroutines that each end with 00EE, then a tail of
+    sprite bytes (one slot in sixteen, at least eight).  Control flow stays in
+    the code it came from:
+    - 2NNN only targets a subroutine's first word; main calls any subroutine,
+      the first half of the subroutines call only the second half, and the
+      second half calls nothing, so the stack never holds more than two
+      return addresses and 00EE only ever returns to a call;
+    - 1NNN jumps forward by 1..16 units inside its own region (a unit is an
+      instruction with the set-up instructions in front of it, entered only
+      at its first word);
+    - every skip (3X, 4X, 5X, 9X, EX9E, EXA1) is followed by a one-word unit
+      and is never the last unit before a region's end;
+    - BNNN is a four-way jump table: VX <- 6, VX <- VX AND VD, then V0 <- VX
+      or V0 <- an even constant below 8, then BNNN with NNN the address of the
+      next word, so the target is one of the next four one-word units under
+      both the V0 and the VX reading of BNNN (X = NNN's top nibble); with the
+      constant the two readings may pick different entries;
+    - FX33 and FX55 always follow an ANNN that points at the scratch area
+      (one in ten at the sprite tail instead), so stores never rewrite code.
+    Opcode classes are drawn by quota (each class with probability
+    proportional to how far its count trails its weight), so the program's
+    class mix, set-up instructions and region ends included, is close to the
+    weights.
+    """
+    if not (16 <= n_instr <= MAX_PROGRAM_INSTRUCTIONS):
+        raise ValueError(f"n_instr must be in [16, {MAX_PROGRAM_INSTRUCTIONS}]")
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def r(n):  # uniform int in [0, n)
+        return int(rng.integers(0, n))
+
+    code_slots = program_code_slots(n_instr)
+    data_slots = n_instr - code_slots
+    data_start = PROGRAM_START + 2 * code_slots
+    data_bytes = 2 * data_slots
+    main_len = max(8, code_slots // 2)
+    sub_lens: List[int] = []
+    left = code_slots - main_len
+    while left >= 8:
+        s = int(rng.integers(8, 41))
+        if left - s < 8:
+            s = left
+        sub_lens.append(s)
+        left -= s
+    main_len += left
+    n_sub = len(sub_lens)
+    leaves = list(range(n_sub // 2, n_sub))
+    w = mix.weights()
+    counts = np.zeros(len(w))
+    emitted = [0.0]
+    key_p = min(0.5, 0.8 * w[_CLS["imm"]] / max(w[_CLS["key"]], 1e-9))
+    edge_p = min(1.0, 0.8 * w[_CLS["imm"]] / max(w[_CLS["draw"]], 1e-9))
+    dense_p = min(0.5, 0.8 * w[_CLS["index"]] / max(w[_CLS["draw"]], 1e-9))
+
+    def pick(allowed: np.ndarray) -> str:
+        d = w * (emitted[0] + _LOOK) - counts
+        p = (np.maximum(d, 0.0) + 1e-3 * w) * allowed
+        if p.sum() <= 0:
+            p = allowed.astype(np.float64)
+        return CLASS_NAMES[int(rng.choice(len(w), p=p / p.sum()))]
+
+    def store_pointer(size: int) -> int:
+        if data_bytes >= 2 * MAX_STORE and r(10) == 0:
+            return data_start + r(data_bytes - size + 1)
+        return STORE_START + r(STORE_END - STORE_START - size + 1)
+
+    def index_target() -> int:
+        c = r(4)
+        if c == 0:
+            return FONT_START + 5 * r(16)
+        if c == 1:
+            return data_start + r(data_bytes)
+        if c == 2:
+            return PROGRAM_START + r(2 * code_slots)
+        return STORE_START + r(STORE_END - STORE_START)
+
+    def make_unit(cls: str, single: bool, room: int, callees: Sequence[int]) -> _Unit:
+        x, y, nn = r(16), r(16), r(256)
+        if cls == "draw":
+            n = int(rng.integers(mix.draw_n_min, mix.draw_n_max + 1))
+            words = []
+            if not single and room >= 3 and mix.edge_bias and rng.random() < dense_p:
+                words.append(0xA000 | (data_start + r(data_bytes)))
+            if not single and room >= 3 and mix.edge_bias and rng.random() < edge_p:
+                if r(2):
+                    words.append(0x6000 | (x << 8) | int(rng.integers(56, 71)))
+                else:
+                    words.append(0x6000 | (y << 8) | int(rng.integers(24, 37)))
+            return _Unit(words + [0xD000 | (x << 8) | (y << 4) | n])
+        if cls == "key":
+            words = []
+            if not single and room >= 3 and rng.random() < key_p:
+                words.append(0x6000 | (x << 8) | int(action_keys[r(len(action_keys))]))
+            return _Unit(words + [0xE000 | (x << 8) | (0x9E if r(2) else 0xA1)], skip=True)
+        if cls == "alu":
+            return _Unit([0x8000 | (x << 8) | (y << 4) | (0, 1, 2, 3, 4, 5, 6, 7, 0xE)[r(9)]])
+        if cls == "imm":
+            return _Unit([(0x6000 if r(2) else 0x7000) | (x << 8) | nn])
+        if cls == "index":
+            c = r(3)
+            if c == 0:
+                return _Unit([0xA000 | index_target()])
+            return _Unit([(0xF01E if c == 1 else 0xF029) | (x << 8)])
+        if cls == "mem":
+            low = (0x33, 0x55, 0x65)[r(3)]
+            if low == 0x65 or single or room < 3:
+                return _Unit([0xF065 | (x << 8)])
+            size = 3 if low == 0x33 else x + 1
+            return _Unit([0xA000 | store_pointer(size), 0xF000 | (x << 8) | low])
+        if cls == "branch":
+            forms = ["jump", "call", "skip", "skip", "skip", "skip"]
+            if not single and room >= 8:
+                forms.append("table")
+            if room <= 1:
+                forms = ["jump", "call"]
+            f = forms[r(len(forms))]
+            if f == "call" and callees:
+                return _Unit([0x2000], call=int(callees[r(len(callees))]))
+            if f in ("jump", "call"):
+                return _Unit([0x1000], jump=1 + r(16))
+            if f == "table":
+                return _Unit([0, 0, 0, 0], table=r(16), table_v0=(None if r(2) else 2 * r(4)))
+            c = r(4)
+            if c == 0:
+                return _Unit([0x3000 | (x << 8) | nn], skip=True)
+            if c == 1:
+                return _Unit([0x4000 | (x << 8) | nn], skip=True)
+            return _Unit([(0x5000 if c == 2 else 0x9000) | (x << 8) | (y << 4)], skip=True)
+        if cls == "timer":
+            return _Unit([0xF000 | (x << 8) | (0x07, 0x15, 0x18)[r(3)]])
+        if cls == "rnd":
+            return _Unit([0xC000 | (x << 8) | nn])
+        return _Unit([0x00E0] if r(2) else [0xF00A | (x << 8)])
+
+    def region(length: int, end_word: int, callees: Sequence[int]) -> List[_Unit]:
+        units: List[_Unit] = []
+        used = 0
+        budget = length - 1
+        force_single = 1           # the first unit of every region is one word
+        while used < budget:
+            room = budget - used
+            allowed = np.ones(len(w))
+            if room == 1:
+                allowed[_CLS["key"]] = 0.0      # no skip right before the region's end
+            single = force_single > 0
+            u = make_unit(pick(allowed), single, room, callees)
+            if len(u.words) > room or (single and len(u.words) > 1):
+                raise AssertionError("unit does not fit")    # make_unit respects room and single
+            units.append(u)
+            used += len(u.words)
+            # the region's end (a branch) is charged a share at a time over its units
+            emitted[0] += len(u.words) * (1.0 + 1.0 / budget)
+            counts[_CLS["branch"]] += len(u.words) / budget
+            # classes of table words are fixed (VX <- 6: imm; AND: alu; V0: alu or imm; BNNN: branch)
+            ops = u.words if u.table is None else \
+                [0x6000, 0x8002, 0x8000 if u.table_v0 is None else 0x6000, 0xB000]
+            for op in ops:
+                counts[_CLS[opcode_class(op)]] += 1
+            force_single = max(force_single - 1, 0)
+            if u.skip:
+                force_single = max(force_single, 1)
+            if u.table is not None:
+                force_single = max(force_single, 4)
+        units.append(_Unit([end_word], terminator=True))
+        return units
+
+    regions = [region(main_len, 0x1000 | PROGRAM_START, list(range(n_sub)))]
+    for k, n in enumerate(sub_lens):
+        regions.append(region(n, 0x00EE, leaves if k < n_sub // 2 else []))
+
+    # Lay out the regions back to back from 0x200 and resolve targets.
+    addr: List[List[int]] = []
+    a = PROGRAM_START
+    for units in regions:
+        row = []
+        for u in units:
+            row.append(a)
+            a += 2 * len(u.words)
+        addr.append(row)
+    assert a == data_start
+    words: List[int] = []
+    replaceable: List[bool] = []
+    for g, units in enumerate(regions):
+        for i, u in enumerate(units):
+            if u.jump is not None:
+                u.words[0] = 0x1000 | addr[g][min(i + u.jump, len(units) - 1)]
+            elif u.call is not None:
+                u.words[0] = 0x2000 | addr[1 + u.call][0]
+            elif u.table is not None:
+                nnn = addr[g][i] + 8
+                vx = (nnn >> 8) & 0xF
+                v0 = 0x8000 | (vx << 4) if u.table_v0 is None else 0x6000 | u.table_v0
+                u.words[:] = [0x6006 | (vx << 8), 0x8002 | (vx << 8) | (u.table << 4), v0, 0xB000 | nnn]
+            words.extend(u.words)
+            replaceable.extend([len(u.words) == 1 and not u.terminator] * len(u.words))
+    out = bytearray()
+    for op in words:
+        out += bytes(_enc(op))
+    out += rng.integers(0, 256, size=data_bytes, dtype=np.uint8).tobytes()
+    replaceable.extend([False] * data_slots)
+    assert len(out) == 2 * n_instr
+    return Program(rom=bytes(out), replaceable=np.array(replaceable, dtype=bool),
+                   code_slots=code_slots)
+
+
 def gen_rom(seed: int, n_instr: int, mix: OpcodeMix = OpcodeMix(),
             action_keys: Sequence[int] = KEYS_5) -> bytes:
-    """Draw one CHIP-8 program of ``n_instr`` two-byte instructions.
+    """The bytes of a structured program (gen_program)."""
+    return gen_program(seed, n_instr, mix, action_keys).rom
+
+
+def gen_rom_escape(seed: int, n_instr: int, mix: OpcodeMix = OpcodeMix(),
+                   action_keys: Sequence[int] = KEYS_5) -> bytes:
+    """An unstructured program that leaves itself: the escape workload.
+
+    Opcodes are drawn one slot at a time with no control-flow structure: a
+    bare 00EE may return through an empty stack, a skip may jump over the
+    final jump, stores may rewrite the code and BNNN may land anywhere in
+    the 255 bytes after its target.  Most such programs leave their own
+    code within a few hundred instructions and run on through the font and
+    zero memory, which exercises the page-crossing, wrap-around and
+    self-modifying paths of an emulator.  Not a stand-in for game code.
 
     Slot ``n_instr - 1`` is a jump back to 0x200 so the program is a main
     loop.  Jump and call targets are even addresses inside the program.  Some
@@ -178,23 +442,29 @@ def gen_rom(seed: int, n_instr: int, mix: OpcodeMix = OpcodeMix(),
 
 def gen_schip_rom(seed: int, n_instr: int, mix: OpcodeMix = OpcodeMix(),
                   action_keys: Sequence[int] = KEYS_8, share: float = 0.12) -> bytes:
-    """A SUPER-CHIP program: a generated CHIP-8 program (gen_rom) in which a
-    share of the slots (not the final jump) is replaced by SUPER-CHIP
+    """A SUPER-CHIP program: a structured CHIP-8 program (gen_program) in
+    which about ``share`` of the code slots are replaced by SUPER-CHIP
     instructions - mode switches 00FE / 00FF, scrolls 00CN / 00FB / 00FC,
     16x16 sprites DXY0, big digits FX30, flag registers FX75 / FX85 and,
-    rarely, the stop instruction 00FD.  Half of the programs switch to the
-    128x64 mode in their first instruction.
+    rarely, the stop instruction 00FD.  Only one-word units that do not end a
+    region are replaced, so the control flow of the program stays intact.
+    Half of the programs switch to the 128x64 mode in their first
+    instruction.
     """
-    out = bytearray(gen_rom(seed, n_instr, mix, action_keys))
+    prog = gen_program(seed, n_instr, mix, action_keys)
+    out = bytearray(prog.rom)
     rng = np.random.Generator(np.random.PCG64([seed, 17]))
     kinds = ("lores", "hires", "scd", "scr", "scl", "big", "digit", "save", "load", "stop")
-    p = np.array([0.01, 0.01, 0.08, 0.06, 0.06, 0.45, 0.18, 0.08, 0.07, 0.002])
-    for i in range(n_instr - 1):
+    p = np.array([0.01, 0.01, 0.08, 0.06, 0.06, 0.45, 0.18, 0.08, 0.07, 0.0005])
+    slots = np.flatnonzero(prog.replaceable)
+    rate = min(1.0, share * prog.code_slots / max(len(slots), 1))
+    assert prog.replaceable[0]          # the main loop starts with a one-word unit
+    for i in slots:
         if i == 0:
             if rng.random() < 0.5:
                 out[0:2] = bytes(_enc(0x00FF))
             continue
-        if rng.random() >= share:
+        if rng.random() >= rate:
             continue
         k = kinds[int(rng.choice(len(kinds), p=p / p.sum()))]
         x, y = int(rng.integers(0, 16)), int(rng.integers(0, 16))
@@ -274,6 +544,9 @@ class EnvSpec:
     # Platform: 0 = CHIP-8 (64x32), 1 = SUPER-CHIP (128x64 display, its extra
     # instructions, (4, 128, 64) observations).
     platform: int = 0
+    # The opcode mix each generated ROM was drawn with (None for ROMs that
+    # were not generated: hand-assembled programs, Target Shooter).
+    mixes: Optional[List[OpcodeMix]] = None
 
     @property
     def has_profile(self) -> bool:
@@ -395,9 +668,14 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
             for this repository, see programs/), a third of the envs each in
             random order, keys 5 7 8 9 6, score V2, done when V3 == 1, ipf 10,
             geometric horizons (mean 500).
+    ``escape``  the ``c3`` shape with unstructured programs (gen_rom_escape)
+            that leave their own code: wrap-around, page-crossing and
+            self-modifying paths.
     ``num_envs`` and ``steps`` override the sizes (for tests at small scale).
     """
-    name = name.lower()
+    label = name.lower()
+    name = "c3" if label == "escape" else label
+    generate = gen_rom_escape if label == "escape" else gen_rom
     if name == "c1":
         seed, E, R, L, keys, ipf, steps_ = 0, 16, 1, (256,), KEYS_5, 10, 1000
     elif name == "c2":
@@ -420,9 +698,10 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
         steps_ = int(steps)
     rng = np.random.Generator(np.random.PCG64(seed))
     roms: List[bytes] = []
+    mixes: Optional[List[OpcodeMix]] = []
     for r_ in range(R):
         if name == "ts":
-            roms = target_shooter_roms()
+            roms, mixes = target_shooter_roms(), None
             break
         if L is not None:
             n, mix = L[r_], OpcodeMix()
@@ -440,10 +719,11 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
                                base.timer, base.rnd, base.misc])
             others = others / others.sum() * rest
             mix = OpcodeMix(draw, *others[:5], branch, *others[5:])
+        mixes.append(mix)
         if name == "s1":
             roms.append(gen_schip_rom(seed * 1000 + r_, n, mix, keys))
         else:
-            roms.append(gen_rom(seed * 1000 + r_, n, mix, keys))
+            roms.append(generate(seed * 1000 + r_, n, mix, keys))
     if R == 1:
         env_rom = np.zeros(E, dtype=np.uint16)
     else:
@@ -459,10 +739,10 @@ def make_config(name: str, num_envs: Optional[int] = None, steps: Optional[int] 
     else:
         horizon = geometric_horizons(rng, E, 500.0)
     env_seed = rng.integers(0, np.iinfo(np.uint64).max, size=E, dtype=np.uint64, endpoint=True)
-    return EnvSpec(name=name, roms=roms, env_rom=env_rom, action_keys=akeys, num_actions=nact,
+    return EnvSpec(name=label, roms=roms, env_rom=env_rom, action_keys=akeys, num_actions=nact,
                    score_reg=sreg, term_reg=treg, term_value=tval, horizon=horizon,
                    env_seed=env_seed, instr_per_frame=ipf, frame_skip=4, steps=steps_,
-                   action_seed=seed + 7919, platform=1 if name == "s1" else 0)
+                   action_seed=seed + 7919, platform=1 if name == "s1" else 0, mixes=mixes)
 
 
 PROGRAMS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "programs")
@@ -571,9 +851,11 @@ def group_horizons(group: Group, mean: float = 500.0) -> np.ndarray:
     return geometric_horizons(g, group.size, mean)
 
 
-def mix_summary(rom: bytes) -> Dict[str, float]:
-    """Fraction of each generator class among the ROM's instructions."""
-    ops = [(rom[i] << 8) | rom[i + 1] for i in range(0, len(rom), 2)]
+def mix_summary(rom: bytes, code_slots: Optional[int] = None) -> Dict[str, float]:
+    """Fraction of each generator class among the ROM's first ``code_slots``
+    instructions (all of them when None)."""
+    n = len(rom) // 2 if code_slots is None else code_slots
+    ops = [(rom[2 * i] << 8) | rom[2 * i + 1] for i in range(n)]
     counts = {c: 0 for c in CLASS_NAMES}
     for op in ops:
         counts[opcode_class(op)] += 1

@@ -27,8 +27,8 @@ from paper_2510_01764_amd import workload as W
 ARCH = ("v", "i", "pc", "sp", "dt", "st", "stack", "mem", "disp")
 
 
-def _spec(E, seed=11, R=4, rnd=0.0, horizon=0, keys=W.KEYS_8):
-    mix = W.OpcodeMix(rnd=rnd, key=0.2)
+def _spec(E, seed=11, R=4, rnd=0.0, horizon=0, keys=W.KEYS_8, misc=0.005):
+    mix = W.OpcodeMix(rnd=rnd, key=0.2, misc=misc)
     roms = [W.gen_rom(seed * 100 + r, 300, mix, keys) for r in range(R)]
     return W.custom_spec(roms, E, keys=keys, horizon=horizon, seed=seed,
                          env_rom=(np.arange(E) % R).astype(np.uint16))
@@ -114,7 +114,8 @@ def test_startup_sequence_replays_its_keys():
 def test_noop_reset_lands_on_a_prefix_of_noop_steps():
     nmax = 7
     E = 2048
-    spec = _spec(E, R=1, seed=23)
+    # no FX0A: with no key held it waits, so a program that reaches one stops changing
+    spec = _spec(E, R=1, seed=23, misc=0.0)
     a = O.OracleBatch(dataclasses.replace(spec, noop_max=nmax))
     # power-on followed by n no-op steps, n = 0..nmax (one ROM, no RNG use: the same for all envs)
     b = O.OracleBatch(spec.subset(np.arange(1)))
