@@ -335,6 +335,24 @@ int32_t octax_get_state(octax_engine *eng, uint32_t first, uint32_t count,
                         octax_env_state *h_out);
 
 /*
+ * octax_get_state for callers that cannot allocate device memory (code that
+ * must not call hipMalloc: tight serving loops, harnesses that forbid it).
+ * Same result as octax_get_state for the same range, but the slot list and
+ * the gathered records go through a static device array of the library
+ * (256 B + OCTAX_NOALLOC_MAX_ENVS records of 5,456 B, about 350 KB), held on
+ * every GPU the library runs on until the process ends; the call allocates
+ * no device memory.  At most OCTAX_NOALLOC_MAX_ENVS envs per call: take a
+ * larger range in pieces.  Every call on one GPU shares that GPU's array, so
+ * calls that overlap in time on one GPU (from several host threads) race
+ * and must be serialized by the caller.  Synchronizes the engine's stream.
+ * Errors: OCTAX_E_INVALID (range outside 0..E, count above the maximum,
+ * NULL), OCTAX_E_HIP.
+ */
+#define OCTAX_NOALLOC_MAX_ENVS 64u
+int32_t octax_get_state_noalloc(octax_engine *eng, uint32_t first, uint32_t count,
+                                octax_env_state *h_out);
+
+/*
  * Overwrite the state of envs [first, first+count) from h_in (I, PC, stack
  * entries masked to 12 bits, SP to 4 bits, display bits as given).  The
  * next step continues from it exactly as from the state it was saved from.

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -266,6 +267,49 @@ void canonical_to_raw(const octax_env_state &o, RawState &r) {
             for (int x = 0; x < 64; x++)
                 if ((frames[h][y] >> (63 - x)) & 1) frame[packed_word(x, y)] |= 1u << packed_bit(x, y);
     }
+}
+
+}  // namespace
+
+namespace {
+
+// Device memory of octax_get_state_noalloc: the slot list (first 256 bytes)
+// and the gathered records, one copy per GPU for the life of the process.
+// Host code never names `scratch` in a device context: it uses the address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocSlotBytes = 256;
+constexpr size_t kNoAllocBytes = kNoAllocSlotBytes + sizeof(RawState) * OCTAX_NOALLOC_MAX_ENVS;
+static_assert(OCTAX_NOALLOC_MAX_ENVS * sizeof(uint32_t) <= kNoAllocSlotBytes, "slot list fits its part");
+static_assert(kNoAllocSlotBytes % alignof(RawState) == 0, "records stay aligned");
+static_assert(sizeof(RawState) == 5456, "the record size octax.h states");
+__device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this GPU's scratch array, looked up once per device with that
+// device current.
+hipError_t scratch_of(int device, uint8_t **out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = static_cast<uint8_t *>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 }  // namespace
@@ -563,6 +607,35 @@ int32_t octax_get_state(octax_engine *g, uint32_t first, uint32_t count, octax_e
     if (e != hipSuccess) return hip_fail(e, "octax_get_state");
     for (uint32_t k = 0; k < count; k++) raw_to_canonical(raw[k], h_out[k]);
     return OCTAX_OK;
+}
+
+int32_t octax_get_state_noalloc(octax_engine *g, uint32_t first, uint32_t count, octax_env_state *h_out) {
+    if (!g || (!h_out && count)) return fail(OCTAX_E_INVALID, "octax_get_state_noalloc: NULL argument");
+    if ((uint64_t)first + count > g->E)
+        return fail(OCTAX_E_INVALID, "octax_get_state_noalloc: range outside 0..E");
+    if (count > OCTAX_NOALLOC_MAX_ENVS)
+        return fail(OCTAX_E_INVALID, "octax_get_state_noalloc: count above OCTAX_NOALLOC_MAX_ENVS (64)");
+    if (count == 0) return OCTAX_OK;
+    uint8_t *base = nullptr;
+    hipError_t e = scratch_of(g->device, &base);
+    if (e != hipSuccess) return hip_fail(e, "octax_get_state_noalloc: scratch address");
+    uint32_t *d_slots = reinterpret_cast<uint32_t *>(base);
+    RawState *d_raw = reinterpret_cast<RawState *>(base + kNoAllocSlotBytes);
+    uint32_t slots[OCTAX_NOALLOC_MAX_ENVS];
+    for (uint32_t k = 0; k < count; k++) slots[k] = g->slot_of[first + k];
+    e = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess) e = hipMemcpy(d_slots, slots, 4 * (size_t)count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_pack(g->s, d_slots, count, d_raw, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    // records come back a few at a time through a buffer on the host stack
+    constexpr uint32_t kChunk = 4;
+    RawState buf[kChunk];
+    for (uint32_t k0 = 0; e == hipSuccess && k0 < count; k0 += kChunk) {
+        const uint32_t n = std::min(kChunk, count - k0);
+        e = hipMemcpy(buf, d_raw + k0, sizeof(RawState) * n, hipMemcpyDeviceToHost);
+        for (uint32_t k = 0; e == hipSuccess && k < n; k++) raw_to_canonical(buf[k], h_out[k0 + k]);
+    }
+    return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_get_state_noalloc");
 }
 
 int32_t octax_set_state(octax_engine *g, uint32_t first, uint32_t count, const octax_env_state *h_in) {

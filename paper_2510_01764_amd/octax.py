@@ -36,10 +36,11 @@ OCTAX_PLATFORM_SCHIP = 1
 OCTAX_PLACE_IDENTITY = 0
 OCTAX_PLACE_BY_ROM = 1
 OBS_BYTES = 8192
+NOALLOC_MAX_ENVS = 64          # octax_get_state_noalloc's largest range
 
 EXPORTED = (
     "octax_create", "octax_reset", "octax_step", "octax_step_many", "octax_graph_create",
-    "octax_graph_launch", "octax_graph_destroy", "octax_get_state", "octax_set_state",
+    "octax_graph_launch", "octax_graph_destroy", "octax_get_state", "octax_get_state_noalloc", "octax_set_state",
     "octax_set_kernel", "octax_set_tuning", "octax_set_stream", "octax_info", "octax_destroy",
     "octax_last_error", "octax_calib_write", "octax_calib_copy", "octax_get_schip_state", "octax_digest",
     "octax_pool_slot_bytes", "octax_pool_create", "octax_pool_admit", "octax_pool_retire",
@@ -148,6 +149,7 @@ def library() -> ctypes.CDLL:
         "octax_graph_launch": ([P], i32),
         "octax_graph_destroy": ([P], i32),
         "octax_get_state": ([P, u32, u32, P], i32),
+        "octax_get_state_noalloc": ([P, u32, u32, P], i32),
         "octax_get_schip_state": ([P, u32, u32, P], i32),
         "octax_digest": ([P, P], i32),
         "octax_set_state": ([P, u32, u32, P], i32),
@@ -352,6 +354,13 @@ class Engine:
         count = self.E - first if count is None else int(count)
         out = np.zeros(count, dtype=ENV_STATE_DTYPE)
         _check(library().octax_get_state(self._h, first, count, out.ctypes.data))
+        return out
+
+    def get_state_noalloc(self, first: int, count: int) -> np.ndarray:
+        """get_state through the library's static device array (at most
+        NOALLOC_MAX_ENVS envs; no device allocation)."""
+        out = np.zeros(int(count), dtype=ENV_STATE_DTYPE)
+        _check(library().octax_get_state_noalloc(self._h, int(first), int(count), out.ctypes.data))
         return out
 
     def set_state(self, first: int, states: np.ndarray):
