@@ -7,7 +7,9 @@ geometric truncation horizons (mean 500), auto-reset.  One benchmark step is
 one replay of a captured HIP graph holding one fused launch of 64
 environment steps over all envs (64 x 65,536 env steps); actions for each
 replay are copied into the graph's action buffer from a pool already in HBM.
-The same inputs are then run through the plain one-env-per-lane kernel.
+The headline runs the envs in their own order, so that every wavefront holds
+a mix of ROMs; the same inputs are then run with the envs sorted by ROM, and
+through the plain one-env-per-lane kernel on both placements.
 
 Prints one JSON line on stdout.  Everything else goes to stderr.
 """
@@ -85,8 +87,12 @@ def measured_traffic():
 
 
 def cpu_baseline(spec, sample_envs: int, sample_steps: int):
-    """The CPU oracle on a bounded sample of the same workload."""
+    """The CPU oracle on a bounded sample of the same workload, and what the
+    workload's programs execute (the oracle's execution profile of every ROM
+    over 1,000 frames, two envs per ROM, the workload's own actions)."""
+    import numpy as np
     from oracle import oracle as O
+    from paper_2510_01764_amd import workload as W
     cores = min(16, len(os.sched_getaffinity(0)))
     sub = spec.subset(list(range(sample_envs)), name="cpu-sample")
     orc = O.OracleBatch(sub)
@@ -101,10 +107,32 @@ def cpu_baseline(spec, sample_envs: int, sample_steps: int):
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": sample_envs * sample_steps / dt, "unit": "env steps/s", "cores": int(used),
+    base = {"value": sample_envs * sample_steps / dt, "unit": "env steps/s", "cores": int(used),
             "kind": "oracle", "cpu_model": model,
             "sample": f"first {sample_envs} envs of the workload x {sample_steps} steps, observations "
                       f"materialised every step, {used} POSIX threads, {dt:.2f} s wall, {cpu_s:.1f} s of CPU time"}
+    # executed instruction classes, per ROM and over the workload
+    R = spec.num_roms
+    prof_spec = spec.subset(np.concatenate([np.flatnonzero(spec.env_rom == r)[:2] for r in range(R)]),
+                            name="exec-profile")
+    po = O.OracleBatch(prof_spec)
+    pc_hist, op_hist = po.profile_execution()
+    steps = 1000 // spec.frame_skip
+    pacts = spec.actions(0, steps)[:, np.concatenate([np.flatnonzero(spec.env_rom == r)[:2] for r in range(R)])]
+    for k in range(steps):
+        po.step(pacts[k], want_obs=False)
+    po.close()
+    cls = np.array([W.CLASS_NAMES.index(W.opcode_class(op)) for op in range(65536)])
+    per_rom = np.stack([np.bincount(cls, weights=op_hist[r].astype(np.float64), minlength=len(W.CLASS_NAMES))
+                        for r in range(R)])
+    total = per_rom.sum()
+    inside = sum(float(pc_hist[r, W.PROGRAM_START:W.PROGRAM_START + len(spec.roms[r])].sum()) for r in range(R))
+    draw = per_rom[:, W.CLASS_NAMES.index("draw")] / per_rom.sum(axis=1)
+    executed = {"classes": dict(zip(W.CLASS_NAMES, (per_rom.sum(axis=0) / total).round(4).tolist())),
+                "in_program_share": round(inside / float(pc_hist.sum()), 4),
+                "draw_share_by_rom": [round(float(x), 4) for x in draw],
+                "how": "oracle execution profile: every ROM, 2 envs each, 1,000 frames, the workload's actions"}
+    return base, executed
 
 
 def time_replays(torch, stream, graph, act_buf, act_pool, n, start):
@@ -157,6 +185,19 @@ def serving_run(args, step_lat_ms, log):
     }
 
 
+def step_latency(stamps_np, hz):
+    """Per-step latency (ms) from one launch's step clock: for each step, the
+    largest end minus the smallest start over the wave pairs that ran."""
+    import numpy as np
+    st, en = stamps_np[..., 0].astype(np.float64), stamps_np[..., 1].astype(np.float64)
+    ok = (stamps_np[..., 0] != 0) & (stamps_np[..., 1] != 0)
+    lat = []
+    for k in range(stamps_np.shape[0]):
+        if ok[k].any():
+            lat.append((en[k][ok[k]].max() - st[k][ok[k]].min()) / hz * 1e3)
+    return lat
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,11 +205,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--envs", type=int, default=65536)
     ap.add_argument("--k", type=int, default=64, help="env steps per replay")
-    ap.add_argument("--latency-steps", type=int, default=50)
+    ap.add_argument("--latency-replays", type=int, default=10,
+                    help="replays after the timed region whose step clocks give the step latency")
+    ap.add_argument("--latency-steps", type=int, default=50, help="octax_step launches for the K = 1 latency")
     ap.add_argument("--cpu-envs", type=int, default=65536)
     ap.add_argument("--cpu-steps", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-by-rom", action="store_true", help="skip the legs on ROM-sorted placement")
     ap.add_argument("--no-wrappers", action="store_true",
                     help="skip the leg with sticky actions, no-op reset and start-up sequences")
     ap.add_argument("--no-profile", action="store_true",
@@ -176,13 +220,23 @@ def main():
     ap.add_argument("--no-programs", action="store_true",
                     help="skip the leg on the Target Shooter programs")
     ap.add_argument("--no-schip", action="store_true", help="skip the SUPER-CHIP leg")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline leg (fused kernel, ROMs mixed in every wave): for profiler runs")
     ap.add_argument("--tune", choices=["auto", "default"], default="auto")
+    ap.add_argument("--sweep", default="",
+                    help="comma-separated env counts: also time the fused kernel at each (the paper's scaling "
+                         "experiment), mixed-ROM workload, one observation slot")
     ap.add_argument("--serving-groups", type=int, default=2000,
                     help="groups of the serving run (0 = skip it)")
     ap.add_argument("--serving-load", type=float, default=0.7,
                     help="offered load as a fraction of the pool's measured step capacity")
     ap.add_argument("--serving-slots", type=int, default=65536)
     args = ap.parse_args()
+    if args.headline_only:
+        args.no_cpu = args.no_plain = args.no_by_rom = args.no_wrappers = args.no_profile = True
+        args.no_programs = args.no_schip = True
+        args.serving_groups = 0
+        args.latency_steps = 0
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the environment step has no multi-GPU path); got --gpus {args.gpus}",
@@ -231,15 +285,18 @@ def main():
     del cbuf
     log(f"calibration: streaming write {write_gbs:.0f} GB/s")
 
-    # fused engine, tuned for this workload
+    # fused engine on identity placement (the ROMs mixed within every
+    # wavefront), tuned for this workload
     act.copy_(act_pool[0])
     tuning = (T.default_tuning() if args.tune == "default" else
-              T.tune(spec, K=K, stream=stream, log=log, buffers=(act, obs, rew, done), use_cache=False))
-    eng = X.Engine(spec, kernel="fused", envs_per_block=tuning["envs_per_block"],
+              T.tune(spec, K=K, stream=stream, log=log, buffers=(act, obs, rew, done), use_cache=False,
+                     placement="identity"))
+    eng = X.Engine(spec, kernel="fused", placement="identity", envs_per_block=tuning["envs_per_block"],
                    rom_in_lds=tuning["rom_in_lds"], stream=stream)
+    stamps = torch.zeros((K, (E + 63) // 64, 2), dtype=torch.int64, device=dev)
+    clock_hz = eng.set_step_clock(stamps, K)
     graph = eng.graph(act, obs, rew, done)
-    for ev in time_replays(torch, stream, graph, act, act_pool, args.warmup, 0):
-        pass
+    time_replays(torch, stream, graph, act, act_pool, args.warmup, 0)
     stream.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -250,45 +307,73 @@ def main():
     replay_ms = np.array([a.elapsed_time(b) for a, b in evs])
     value = E * K * args.steps / wall
     kernel_ms = float(replay_ms.mean())
+    # per-step latency inside the K-step launches, from the step clock of
+    # replays run after the timed region (each read back before the next)
+    lat_k = []
+    for i in range(args.latency_replays):
+        time_replays(torch, stream, graph, act, act_pool, 1, args.warmup + args.steps + i)
+        stream.synchronize()
+        lat_k += step_latency(stamps.cpu().numpy(), clock_hz)
+    lat_k = np.array(lat_k if lat_k else [float("nan")])
+    graph.close()
+    eng.set_step_clock(None, 0)
+    eng.status()
+    log(f"fused, identity placement: {value / 1e6:.1f} M env steps/s ({kernel_ms:.3f} ms per replay), "
+        f"step latency p50 {np.percentile(lat_k, 50):.3f} ms p99 {np.percentile(lat_k, 99):.3f} ms")
 
     # single-step latency: octax_step (one fused launch of K = 1) over all envs
-    a1 = act_pool[0, 0].contiguous()
-    obs1, rew1, done1 = obs[0], rew[0], done[0]
-    lat = []
-    for i in range(5 + args.latency_steps):
-        with torch.cuda.stream(stream):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            eng.step(a1, obs1, rew1, done1)
-            e1.record(stream)
-        stream.synchronize()
-        if i >= 5:
-            lat.append(e0.elapsed_time(e1))
-    lat = np.array(lat if lat else [float("nan")])
-    graph.close()
+    lat1 = []
+    if args.latency_steps > 0:
+        a1 = act_pool[0, 0].contiguous()
+        for i in range(5 + args.latency_steps):
+            with torch.cuda.stream(stream):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                eng.step(a1, obs[0], rew[0], done[0])
+                e1.record(stream)
+            stream.synchronize()
+            if i >= 5:
+                lat1.append(e0.elapsed_time(e1))
+        eng.status()
+    lat1 = np.array(lat1 if lat1 else [float("nan")])
     eng.close()
 
-    # plain kernel on identical inputs (fresh engine, same seeds and actions)
-    plain = None
-    if not args.no_plain:
-        engp = X.Engine(spec, kernel="plain", stream=stream)
-        gp = engp.graph(act, obs, rew, done)
-        time_replays(torch, stream, gp, act, act_pool, 1, 0)
+    def timed_leg(kernel, placement, n):
+        """Graph replays of the same workload on another kernel or placement."""
+        kw = {}
+        if kernel == "fused":
+            tn = (T.default_tuning() if args.tune == "default" else
+                  T.tune(spec, K=K, stream=stream, log=log, buffers=(act, obs, rew, done), use_cache=False,
+                         placement=placement))
+            kw = dict(envs_per_block=tn["envs_per_block"], rom_in_lds=tn["rom_in_lds"])
+        e2 = X.Engine(spec, kernel=kernel, placement=placement, stream=stream, **kw)
+        g2 = e2.graph(act, obs, rew, done)
+        time_replays(torch, stream, g2, act, act_pool, 1, 0)
         stream.synchronize()
         t0 = time.perf_counter()
-        pevs = time_replays(torch, stream, gp, act, act_pool, max(2, args.steps // 4), args.warmup)
+        time_replays(torch, stream, g2, act, act_pool, n, args.warmup)
         stream.synchronize()
-        pwall = time.perf_counter() - t0
-        n_p = max(2, args.steps // 4)
-        plain = {"value": E * K * n_p / pwall, "ms_per_step": pwall * 1e3 / n_p,
-                 "replays": n_p}
-        gp.close()
-        engp.close()
+        w2 = time.perf_counter() - t0
+        g2.close()
+        e2.status()
+        e2.close()
+        out = {"value": E * K * n / w2, "ms_per_step": w2 * 1e3 / n, "replays": n, "placement": placement}
+        out.update(kw)
+        log(f"{kernel}, {placement} placement: {out['value'] / 1e6:.1f} M env steps/s "
+            f"({out['ms_per_step']:.2f} ms per replay)")
+        return out
+
+    fused_by_rom = None if args.no_by_rom else timed_leg("fused", "by_rom", max(2, args.steps // 2))
+    plain = None
+    if not args.no_plain:
+        plain = {"identity": timed_leg("plain", "identity", max(2, args.steps // 4))}
+        if not args.no_by_rom:
+            plain["by_rom"] = timed_leg("plain", "by_rom", max(2, args.steps // 4))
 
     def variant_leg(vspec, pool=None):
         """Graph replays of the same launch shape under another spec; (env steps/s, ms per replay, replays)."""
         pool = act_pool if pool is None else pool
-        engv = X.Engine(vspec, kernel="fused", envs_per_block=tuning["envs_per_block"],
+        engv = X.Engine(vspec, kernel="fused", placement="identity", envs_per_block=tuning["envs_per_block"],
                         rom_in_lds=tuning["rom_in_lds"], stream=stream)
         gv = engv.graph(act, obs, rew, done)
         time_replays(torch, stream, gv, act, pool, 1, 0)
@@ -300,9 +385,10 @@ def main():
         vwall = time.perf_counter() - t0
         resets = float((done != 0).float().mean().item())
         gv.close()
+        engv.status()
         engv.close()
         return {"value": E * K * n_v / vwall, "ms_per_step": vwall * 1e3 / n_v, "replays": n_v,
-                "resets_per_env_step": resets}
+                "resets_per_env_step": resets, "placement": "identity"}
 
     # the same workload with the environment wrappers of Section 3.2 on
     wrappers = None
@@ -375,14 +461,50 @@ def main():
         gs.close()
         engs.close()
 
+    # the paper's scaling experiment: env steps/s against the number of envs
+    sweep = None
+    if args.sweep:
+        sweep = []
+        for Ew in (int(x) for x in args.sweep.split(",")):
+            wspec = W.make_config("c3", num_envs=Ew)
+            wact = torch.from_numpy(wspec.actions(0, K)).to(dev)
+            wobs = torch.empty((1, Ew, 4, 64, 32), dtype=torch.uint8, device=dev)
+            wrew = torch.empty((K, Ew), dtype=torch.float32, device=dev)
+            wdone = torch.empty((K, Ew), dtype=torch.uint8, device=dev)
+            ew = X.Engine(wspec, kernel="fused", placement="identity", stream=stream)
+            gw = ew.graph(wact, wobs, wrew, wdone)
+            with torch.cuda.stream(stream):
+                gw.launch()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                n_w = 6 if Ew <= 65536 else 3
+                for _ in range(n_w):
+                    gw.launch()
+                e1.record(stream)
+            stream.synchronize()
+            ms = e0.elapsed_time(e1) / n_w
+            gw.close()
+            ew.status()
+            ew.close()
+            sweep.append({"envs": Ew, "ms_per_launch": ms, "env_steps_per_s": Ew * K / ms * 1e3})
+            log(f"sweep: {Ew} envs {ms:.3f} ms per launch, {Ew * K / ms / 1e3:.1f} M env steps/s")
+            del wobs, wrew, wdone, wact
+            torch.cuda.empty_cache()
+
     serving = None
     if args.serving_groups > 0:
-        serving = serving_run(args, lat, log)
+        serving = serving_run(args, lat1, log)
 
     algo_per_launch = E * K * ALGO_BYTES_PER_ENV_STEP
     achieved = algo_per_launch / (kernel_ms * 1e-3) / 1e9
     traffic = measured_traffic()
     valu_ops = measured_valu()
+    cpu, executed = (None, None) if args.no_cpu else cpu_baseline(spec, min(args.cpu_envs, E), args.cpu_steps)
+    fop = None
+    if plain:
+        fop = {"identity": value / plain["identity"]["value"]}
+        if fused_by_rom and "by_rom" in plain:
+            fop["by_rom"] = fused_by_rom["value"] / plain["by_rom"]["value"]
     out = {
         "metric": "env steps/s @65,536 envs mixed-ROM (fused vs plain), p99 step latency",
         "value": value,
@@ -397,27 +519,34 @@ def main():
         "dtype": "u8",
         "data": "synthetic: seed-generated CHIP-8 ROMs and uniform random actions",
         "config": {
-            "workload": "mixed-ROM batching: 65,536 envs over 16 seed-generated ROMs, 64 env steps "
-                        "per graph replay, ipf 10, frame skip 4, 4x64x32 uint8 obs, geometric "
-                        "horizons mean 500, auto-reset",
+            "workload": "mixed-ROM batching: 65,536 envs over 16 seed-generated ROMs mixed within every "
+                        "wavefront, 64 env steps per graph replay, ipf 10, frame skip 4, 4x64x32 uint8 obs, "
+                        "geometric horizons mean 500, auto-reset",
             "envs": E, "roms": spec.num_roms, "env_steps_per_bench_step": E * K,
             "instr_per_frame": spec.instr_per_frame, "frame_skip": spec.frame_skip,
             "kernel": "fused", "envs_per_block": tuning["envs_per_block"],
-            "lanes_per_env": 1, "rom_in_lds": bool(tuning["rom_in_lds"]), "placement": "by_rom",
+            "lanes_per_env": 1, "rom_in_lds": bool(tuning["rom_in_lds"]), "placement": "identity",
+            "executed": executed,
         },
         "frames_per_s": 4 * value,
         "chip8_instr_per_s": value * spec.instr_per_frame * spec.frame_skip,
-        "p50_step_latency_ms": float(np.percentile(lat, 50)),
-        "p99_step_latency_ms": float(np.percentile(lat, 99)),
-        "step_latency_def": "octax_step on all 65,536 envs (one fused launch, K = 1), HIP events on the engine's stream",
+        "p50_step_latency_ms": float(np.percentile(lat_k, 50)),
+        "p99_step_latency_ms": float(np.percentile(lat_k, 99)),
+        "step_latency_def": f"per step of the timed {K}-step graph launches: the last wave pair's end of step k "
+                            f"(its last observation store issued) minus the first pair's start of step k, from "
+                            f"the device wall clock ({len(lat_k)} steps over {args.latency_replays} launches)",
+        "octax_step_latency_ms": {"p50": float(np.percentile(lat1, 50)), "p99": float(np.percentile(lat1, 99)),
+                                  "def": "octax_step on all envs (one fused launch of K = 1), HIP events"},
         "replay_ms_p50": float(np.percentile(replay_ms, 50)),
         "replay_ms_p99": float(np.percentile(replay_ms, 99)),
+        "fused_by_rom": fused_by_rom,
         "plain": plain,
-        "fused_over_plain": (value / plain["value"]) if plain else None,
+        "fused_over_plain": fop,
         "wrappers": wrappers,
         "profile": profile,
         "target_shooter": shooter,
         "schip": schip,
+        "sweep": sweep,
         "calib_write_GBs": write_gbs,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -437,8 +566,8 @@ def main():
     }
     if serving is not None:
         out["serving"] = serving
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(spec, min(args.cpu_envs, E), args.cpu_steps)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -385,9 +385,59 @@ int32_t octax_info(const octax_engine *eng, uint32_t *num_envs, uint64_t *device
 
 /*
  * Destroy an engine (synchronizes its stream, frees its device memory).
- * NULL is accepted.  Errors: OCTAX_E_HIP.
+ * NULL is accepted.  Errors: OCTAX_E_HIP; OCTAX_E_STATE as octax_status
+ * (the engine is destroyed all the same).
  */
 int32_t octax_destroy(octax_engine *eng);
+
+/*
+ * Completion check of the asynchronous calls.  In a fused launch each
+ * emulator wave and its observation-writer wave wait for each other once per
+ * step; every such wait is bounded (0.25 s plus 16 us per instruction slot of
+ * the longest step the config allows, on the device wall clock), so every
+ * launch ends.  A wait that gives up sets the engine's device error word:
+ * that launch's observations, rewards and done flags are not valid, and nor
+ * need the envs' state be (a writer wave that ran ahead may have staged the
+ * wrong keys and frame history): restore it with octax_set_state or
+ * octax_reset before going on.  octax_status
+ * synchronizes the engine's stream and returns OCTAX_E_STATE once if the
+ * word is set since the last check, clearing it; octax_get_state,
+ * octax_get_state_noalloc, octax_destroy and the pool's get_state and
+ * destroy report it the same way (get_state after filling h_out).  The
+ * fused kernel therefore takes configs with at most 1,048,576 instruction
+ * slots per step (instr_per_frame x frame_skip x (1 + longest start-up
+ * sequence + noop_max)); octax_create and octax_set_kernel reject longer
+ * ones for it (the plain kernel has no such wait and takes them).
+ * Errors: OCTAX_E_INVALID (NULL), OCTAX_E_STATE, OCTAX_E_HIP.
+ */
+int32_t octax_status(octax_engine *eng);
+
+/*
+ * Replace the derived wait bound of the fused kernel by `ticks` of the
+ * device wall clock (0 restores the derived bound).  A diagnostic hook: a
+ * tiny bound makes the waits give up, so the error path can be exercised
+ * without a long step.  Errors: OCTAX_E_INVALID (NULL), OCTAX_E_STATE
+ * (graphs of the engine exist: they hold the old bound).
+ */
+int32_t octax_set_wait_limit(octax_engine *eng, uint64_t ticks);
+
+/*
+ * Step clock of the fused kernel (measurement of the per-step latency inside
+ * a multi-step launch).  With d_stamps set, every fused launch records for
+ * each step k < steps and each wave pair w (w = 0 .. ceil(E / 64) - 1, the
+ * 64 consecutive slots of emulator wave w) two readings of the device wall
+ * clock: d_stamps[(k * ceil(E / 64) + w) * 2] when the emulator wave starts
+ * step k, and [... + 1] when the paired observation-writer wave has issued
+ * the last observation store of step k.  The latency of step k is then the
+ * largest end minus the smallest start over all pairs.  Pairs with no live
+ * env write nothing.  d_stamps is caller-owned device memory of
+ * steps * ceil(E / 64) * 2 uint64 that stays valid while launches run; NULL
+ * (or steps = 0) switches the clock off.  *h_clock_hz (if not NULL) receives
+ * the clock's rate.  Graphs keep the setting they were captured with.
+ * Errors: OCTAX_E_INVALID (NULL engine, or d_stamps NULL with steps > 0),
+ * OCTAX_E_STATE (graphs of the engine exist), OCTAX_E_HIP.
+ */
+int32_t octax_set_step_clock(octax_engine *eng, uint64_t *d_stamps, uint32_t steps, uint64_t *h_clock_hz);
 
 /*
  * Serving pool: continuous batching of environment groups (requests) that

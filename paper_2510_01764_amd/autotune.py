@@ -50,12 +50,13 @@ def _save_cache(d: Dict):
 
 
 def tune(spec, K: int = 64, stream=None, log: Callable = print, replays: int = 3,
-         buffers: Optional[tuple] = None, use_cache: bool = True) -> Dict:
-    """Time each candidate on `spec` (K env steps per graph replay) and return the fastest."""
+         buffers: Optional[tuple] = None, use_cache: bool = True, placement: str = "by_rom") -> Dict:
+    """Time each candidate on `spec` (K env steps per graph replay, envs placed
+    on slots by `placement`) and return the fastest."""
     import torch
     from . import octax as X
     dev = torch.device("cuda")
-    key = workload_key(spec, K, torch.cuda.get_device_name(dev))
+    key = workload_key(spec, K, torch.cuda.get_device_name(dev)) + f"|{placement}"
     cache = _load_cache() if use_cache else {}
     if key in cache:
         log(f"autotune: cached {cache[key]}")
@@ -70,7 +71,7 @@ def tune(spec, K: int = 64, stream=None, log: Callable = print, replays: int = 3
     else:
         act, obs, rew, done = (b[:Kt] for b in buffers)
     stream = stream or torch.cuda.current_stream(dev)
-    eng = X.Engine(spec, kernel="fused", stream=stream)
+    eng = X.Engine(spec, kernel="fused", placement=placement, stream=stream)
     results = []
     for ipw, lds in CANDIDATES:
         eng.set_tuning(ipw, lds)

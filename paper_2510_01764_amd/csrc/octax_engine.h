@@ -32,6 +32,12 @@ struct octax_engine {
     octax::RawState *d_raw = nullptr;
     uint32_t raw_capacity = 0;
     int graphs = 0;
+    uint64_t step_slots = 0;                          // longest step: ipf x frame_skip x (1 + reset steps)
+    uint64_t wait_ticks = 0;                          // fused pair wait bound (device wall-clock ticks)
+    uint64_t wait_override = 0;                       // octax_set_wait_limit (0: derived from the config)
+    uint32_t *d_err = nullptr;                        // device error word of the fused kernel
+    uint64_t *d_stamps = nullptr;                     // octax_set_step_clock (caller's buffer)
+    uint32_t stamp_steps = 0;
 
     template <class T>
     hipError_t alloc(T **p, size_t count) {
@@ -76,6 +82,18 @@ Wrap make_wrap(const uint8_t *d_table, const std::vector<uint8_t> &table, uint32
 // Fill table[2b], table[2b+1] with the two most frequent ROMs among the
 // (occupied) slots of block b (0xFFFFFFFF = none); blocks of envs_per_block.
 void block_rom_table(const octax_engine *g, std::vector<uint32_t> &table);
+
+// Largest step, in instruction slots, that the fused kernel accepts: its
+// paired waves wait for each other once per step, with a bound derived from
+// this (see fused_wait_ticks).
+constexpr uint64_t kFusedMaxStepSlots = 1ull << 20;
+// Wait bound of the fused kernel's paired waves for a step of `slots`
+// instruction slots: 0.25 s plus 16 us per slot (about ten times the slowest
+// slot measured), in ticks of the device wall clock (wall_khz kHz).
+uint64_t fused_wait_ticks(uint64_t slots, uint64_t wall_khz);
+// Report (and clear) the fused kernel's error word; `what` names the call.
+// Synchronizes the engine's stream.
+int32_t check_device_error(octax_engine *g, const char *what);
 
 // K fused or plain steps of every env of g on stream st.
 hipError_t launch_steps(octax_engine *g, uint32_t K, const int32_t *d_action, uint8_t *d_obs,

@@ -184,10 +184,30 @@ hipError_t octax::launch_steps(octax_engine *g, uint32_t K, const int32_t *d_act
     StepIO io{d_action, d_obs, d_reward, d_done, K, obs_slots ? obs_slots : 1, g->ipf, g->frame_skip};
     if (g->schip) return launch_step_schip(g->s, g->roms, io, st);
     if (g->kernel == OCTAX_KERNEL_FUSED) {
-        FusedCfg f{g->envs_per_block, g->rom_in_lds, g->d_block_roms};
+        FusedCfg f{g->envs_per_block, g->rom_in_lds, g->d_block_roms,
+                   g->wait_override ? g->wait_override : g->wait_ticks, g->d_err, g->d_stamps, g->stamp_steps};
         return launch_step_fused(g->s, g->roms, io, f, st);
     }
     return launch_step_plain(g->s, g->roms, io, st);
+}
+
+uint64_t octax::fused_wait_ticks(uint64_t slots, uint64_t wall_khz) {
+    const uint64_t us = 250000 + 16 * slots;
+    return us * wall_khz / 1000;
+}
+
+int32_t octax::check_device_error(octax_engine *g, const char *what) {
+    hipError_t e = hipStreamSynchronize(g->stream);
+    uint32_t word = 0;
+    if (e == hipSuccess) e = hipMemcpy(&word, g->d_err, 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && word) {
+        const uint32_t zero = 0;
+        e = hipMemcpy(g->d_err, &zero, 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            return fail(OCTAX_E_STATE, std::string(what) + ": a fused launch gave up waiting for a partner wave; "
+                                                           "the observations, rewards and done flags it wrote are not valid");
+    }
+    return e == hipSuccess ? OCTAX_OK : hip_fail(e, what);
 }
 
 namespace {
@@ -358,6 +378,12 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     const bool schip = cfg->platform == OCTAX_PLATFORM_SCHIP;
     if (schip && cfg->kernel != OCTAX_KERNEL_PLAIN)
         return fail(OCTAX_E_INVALID, "octax_create: SUPER-CHIP engines run on the plain kernel");
+    uint32_t max_startup = 0;
+    for (uint32_t r = 0; r < R; r++) max_startup = std::max<uint32_t>(max_startup, startup[17 * (size_t)r]);
+    const uint64_t step_slots = (uint64_t)cfg->instr_per_frame * cfg->frame_skip * (1 + max_startup + cfg->noop_max);
+    if (cfg->kernel == OCTAX_KERNEL_FUSED && step_slots > octax::kFusedMaxStepSlots)
+        return fail(OCTAX_E_INVALID, "octax_create: the fused kernel takes at most 1,048,576 instruction slots per "
+                                     "step (ipf x frame_skip x (1 + start-up steps + noop_max)); use the plain kernel");
 
     octax_engine *g = new (std::nothrow) octax_engine;
     if (!g) return fail(OCTAX_E_NOMEM, "octax_create: out of host memory");
@@ -372,6 +398,7 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     g->schip = schip ? 1 : 0;
     g->stream = static_cast<hipStream_t>(cfg->stream);
     (void)hipGetDevice(&g->device);
+    g->step_slots = step_slots;
 
     // Placement: slot -> env.
     g->env_of.resize(E);
@@ -465,6 +492,13 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     g->roms.schip = g->schip;
     g->roms.w = octax::make_wrap(g->d_startup, startup, cfg->sticky_q24, cfg->noop_max, g->ipf, g->frame_skip);
     TRY(upload_block_roms(g));
+    {
+        int wall_khz = 0;
+        TRY(hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, g->device));
+        g->wait_ticks = octax::fused_wait_ticks(step_slots, wall_khz > 0 ? (uint64_t)wall_khz : 100000u);
+    }
+    TRY(g->alloc(&g->d_err, 4));
+    TRY(hipMemset(g->d_err, 0, 16));
     TRY(launch_reset(g->s, g->roms, nullptr, true, g->stream));
     TRY(hipStreamSynchronize(g->stream));
 #undef TRY
@@ -474,10 +508,35 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
 
 int32_t octax_destroy(octax_engine *g) {
     if (!g) return OCTAX_OK;
-    hipError_t e = hipStreamSynchronize(g->stream);
+    const int32_t rc = check_device_error(g, "octax_destroy");
     g->free_all();
     delete g;
-    if (e != hipSuccess) return hip_fail(e, "octax_destroy");
+    return rc;
+}
+
+int32_t octax_status(octax_engine *g) {
+    if (!g) return fail(OCTAX_E_INVALID, "octax_status: engine is NULL");
+    return check_device_error(g, "octax_status");
+}
+
+int32_t octax_set_step_clock(octax_engine *g, uint64_t *d_stamps, uint32_t steps, uint64_t *h_clock_hz) {
+    if (!g || (steps && !d_stamps)) return fail(OCTAX_E_INVALID, "octax_set_step_clock: NULL argument");
+    if (g->graphs > 0) return fail(OCTAX_E_STATE, "octax_set_step_clock: destroy the engine's graphs first");
+    if (h_clock_hz) {
+        int khz = 0;
+        const hipError_t e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device);
+        if (e != hipSuccess) return hip_fail(e, "octax_set_step_clock");
+        *h_clock_hz = 1000ull * (uint64_t)khz;
+    }
+    g->d_stamps = steps ? d_stamps : nullptr;
+    g->stamp_steps = steps;
+    return OCTAX_OK;
+}
+
+int32_t octax_set_wait_limit(octax_engine *g, uint64_t ticks) {
+    if (!g) return fail(OCTAX_E_INVALID, "octax_set_wait_limit: engine is NULL");
+    if (g->graphs > 0) return fail(OCTAX_E_STATE, "octax_set_wait_limit: destroy the engine's graphs first");
+    g->wait_override = ticks;
     return OCTAX_OK;
 }
 
@@ -606,7 +665,7 @@ int32_t octax_get_state(octax_engine *g, uint32_t first, uint32_t count, octax_e
     if (e == hipSuccess) e = hipMemcpy(raw.data(), g->d_raw, sizeof(RawState) * (size_t)count, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "octax_get_state");
     for (uint32_t k = 0; k < count; k++) raw_to_canonical(raw[k], h_out[k]);
-    return OCTAX_OK;
+    return check_device_error(g, "octax_get_state");
 }
 
 int32_t octax_get_state_noalloc(octax_engine *g, uint32_t first, uint32_t count, octax_env_state *h_out) {
@@ -635,7 +694,8 @@ int32_t octax_get_state_noalloc(octax_engine *g, uint32_t first, uint32_t count,
         e = hipMemcpy(buf, d_raw + k0, sizeof(RawState) * n, hipMemcpyDeviceToHost);
         for (uint32_t k = 0; e == hipSuccess && k < n; k++) raw_to_canonical(buf[k], h_out[k0 + k]);
     }
-    return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_get_state_noalloc");
+    if (e != hipSuccess) return hip_fail(e, "octax_get_state_noalloc");
+    return check_device_error(g, "octax_get_state_noalloc");
 }
 
 int32_t octax_set_state(octax_engine *g, uint32_t first, uint32_t count, const octax_env_state *h_in) {
@@ -661,6 +721,8 @@ int32_t octax_set_kernel(octax_engine *g, uint32_t kernel) {
     if (!g || kernel > OCTAX_KERNEL_FUSED) return fail(OCTAX_E_INVALID, "octax_set_kernel: bad argument");
     if (g->schip && kernel != OCTAX_KERNEL_PLAIN)
         return fail(OCTAX_E_INVALID, "octax_set_kernel: SUPER-CHIP engines run on the plain kernel");
+    if (kernel == OCTAX_KERNEL_FUSED && g->step_slots > kFusedMaxStepSlots)
+        return fail(OCTAX_E_INVALID, "octax_set_kernel: the config's steps are too long for the fused kernel");
     g->kernel = kernel;
     return OCTAX_OK;
 }

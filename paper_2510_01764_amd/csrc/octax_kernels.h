@@ -25,6 +25,10 @@ struct FusedCfg {
     uint32_t envs_per_block;      // 64, 128 or 256
     uint32_t rom_in_lds;          // stage up to two ROM images per block in LDS
     const uint32_t *block_roms;   // [blocks][2] ROM ids to stage (0xFFFFFFFF = none)
+    uint64_t wait_ticks;          // longest wait of a wave for its partner, in device wall-clock ticks
+    uint32_t *err;                // device error word: bit 0 set when a wait gave up
+    uint64_t *stamps;             // [stamp_steps][ceil(E / 64)][2] step start / end clocks, or nullptr
+    uint32_t stamp_steps;
 };
 
 hipError_t launch_step_plain(const State &s, const Roms &r, const StepIO &io, hipStream_t st);

@@ -279,9 +279,9 @@ int32_t octax_pool_get_state(octax_pool *p, uint32_t first, uint32_t count, octa
 
 int32_t octax_pool_destroy(octax_pool *p) {
     if (!p) return OCTAX_OK;
-    hipError_t e = hipStreamSynchronize(p->eng->stream);
+    const int32_t rc = check_device_error(p->eng, "octax_pool_destroy");
     delete p;
-    return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_pool_destroy");
+    return rc;
 }
 
 }  // extern "C"

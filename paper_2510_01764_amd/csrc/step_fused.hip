@@ -115,11 +115,23 @@ struct FusedMem {
     // Pick the slot for page p, never slot `keep` (-1: none); the slot's old
     // tag is returned in `old`.
     __device__ __forceinline__ static uint32_t next_slot(uint32_t s) { return s + 1 == kSlots ? 0u : s + 1; }
+    // The slot to replace: in fill order from the replacement pointer, the
+    // first slot without modified data (a clean page costs no write-back and
+    // comes back cheaply), else the slot at the pointer; never `keep`.
     __device__ __forceinline__ uint32_t victim(int32_t keep, uint32_t &old) const {
         uint32_t s = vic;
         if ((int32_t)s == keep) s = next_slot(s);
-        old = tag(s);
-        return s;
+        uint32_t pick = s;
+        bool found = false;
+#pragma unroll
+        for (uint32_t i = 0; i < kSlots; i++) {
+            const uint32_t c = (vic + i) % kSlots;
+            const bool ok = !found && (int32_t)c != keep && !(tag(c) & 0x80);
+            pick = ok ? c : pick;
+            found = found || ok;
+        }
+        old = tag(pick);
+        return pick;
     }
     // Slots are replaced in fill order: the next victim follows the slot filled.
     __device__ __forceinline__ void set_tag(uint32_t s, uint32_t t) {
@@ -448,10 +460,23 @@ __device__ __forceinline__ void set_flag(uint32_t *f, uint32_t v) {
 __device__ __forceinline__ uint32_t get_flag(const uint32_t *f) {
     return __builtin_amdgcn_readfirstlane(__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
 }
-// Wait until the flag reaches v.  The partner wave raises it within a step;
-// the bound on the number of polls only guarantees that every wave ends.
-__device__ __forceinline__ void wait_flag(const uint32_t *f, uint32_t v) {
-    for (uint32_t n = 0; n < (1u << 22) && get_flag(f) < v; n++) __builtin_amdgcn_s_sleep(1);
+// Wait until the flag reaches v.  The partner wave raises it within a step.
+// The wait is bounded by `limit` ticks of the device wall clock, derived by
+// the host from the longest step the config allows, so that every wave ends
+// whatever happens; a wait that gives up sets bit 0 of the engine's error
+// word (one lane, a global atomic), which the host reports: the outputs of
+// that launch are not valid.
+__device__ __forceinline__ void wait_flag(const uint32_t *f, uint32_t v, uint64_t limit, uint32_t *err) {
+    if (get_flag(f) < v) {
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        while (get_flag(f) < v) {
+            if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+                if (__lane_id() == 0) __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
@@ -651,11 +676,21 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     }
     __syncthreads();
 
+    // Step clock (optional): wave pair gw records, on the device wall clock,
+    // when its emulator wave starts step k and when its writer wave has issued
+    // the last store of step k.
+    const uint32_t gw = wave_slot0 / 64, nwaves = (E + 63) / 64;
+    auto stamp = [&](uint32_t k, uint32_t which) {
+        if (cfg.stamps && k < cfg.stamp_steps && nj > 0 && lane64 == 0)
+            cfg.stamps[((size_t)k * nwaves + gw) * 2 + which] = __builtin_amdgcn_s_memrealtime();
+    };
+
     FusedMem<IPW> mem{sh, l, lidx, gimg, ram, dirty, tags};
     if (emu) {
         for (uint32_t k = 0; k < K; k++) {
             // the display of step k - 1 must have been copied before it changes
-            if (k > 0) wait_flag(&sh.taken[wave], k);
+            if (k > 0) wait_flag(&sh.taken[wave], k, cfg.wait_ticks, cfg.err);
+            stamp(k, 0);
             if (active) {
                 const uint32_t key = sticky_key(roms, c, sh.key[k & 1][l]);
                 run_frames<kProfile>(c, mem, key, io.ipf, io.frame_skip, quirks);
@@ -693,7 +728,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             // Copy the display, reward and done bits of step k once final,
             // stage the held key of step k + 2 in the key slot step k has
             // finished with, and let the emulator go on.
-            wait_flag(&sh.ready[wave], k + 1);
+            wait_flag(&sh.ready[wave], k + 1, cfg.wait_ticks, cfg.err);
             uint32_t hi[32], lo[32];
 #pragma unroll
             for (int r = 0; r < 32; r++) {
@@ -714,7 +749,10 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 io.done[(size_t)k * E + env] = (uint8_t)done;
             }
             head = done ? 0u : (head + 1) & 3;
-            if (!(io.obs || ring_step)) continue;
+            if (!(io.obs || ring_step)) {
+                stamp(k, 1);
+                continue;
+            }
             uint32_t pw[64];
             rows_to_cols(hi, lo);
             pack_frame(hi, lo, pw);
@@ -805,6 +843,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 }
                 wave_sync();
             }
+            stamp(k, 1);
         }
     }
     if (emu && active) mem.flush();

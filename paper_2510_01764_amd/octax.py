@@ -42,6 +42,7 @@ EXPORTED = (
     "octax_create", "octax_reset", "octax_step", "octax_step_many", "octax_graph_create",
     "octax_graph_launch", "octax_graph_destroy", "octax_get_state", "octax_get_state_noalloc", "octax_set_state",
     "octax_set_kernel", "octax_set_tuning", "octax_set_stream", "octax_info", "octax_destroy",
+    "octax_status", "octax_set_wait_limit", "octax_set_step_clock",
     "octax_last_error", "octax_calib_write", "octax_calib_copy", "octax_get_schip_state", "octax_digest",
     "octax_pool_slot_bytes", "octax_pool_create", "octax_pool_admit", "octax_pool_retire",
     "octax_pool_step", "octax_pool_info", "octax_pool_get_state", "octax_pool_destroy",
@@ -158,6 +159,9 @@ def library() -> ctypes.CDLL:
         "octax_set_stream": ([P, P], i32),
         "octax_info": ([P, ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_uint64)], i32),
         "octax_destroy": ([P], i32),
+        "octax_status": ([P], i32),
+        "octax_set_wait_limit": ([P, ctypes.c_uint64], i32),
+        "octax_set_step_clock": ([P, P, u32, ctypes.POINTER(ctypes.c_uint64)], i32),
         "octax_last_error": ([], ctypes.c_char_p),
         "octax_calib_write": ([P, ctypes.c_uint64, u32, u32, P], i32),
         "octax_calib_copy": ([P, P, ctypes.c_uint64, P], i32),
@@ -287,10 +291,32 @@ class Engine:
     def handle(self):
         return self._h
 
+    def status(self):
+        """Raise OctaxError (OCTAX_E_STATE) if a fused launch since the last
+        check gave up waiting for a partner wave (synchronizes)."""
+        _check(library().octax_status(self._h))
+
+    def set_step_clock(self, stamps, steps: int) -> int:
+        """Record per-step clocks of fused launches into a device int64 tensor
+        [steps, ceil(E / 64), 2] (None switches it off); returns the clock rate in Hz."""
+        hz = ctypes.c_uint64(0)
+        if stamps is None:
+            _check(library().octax_set_step_clock(self._h, None, 0, ctypes.byref(hz)))
+        else:
+            import torch
+            self._need(stamps, torch.int64, (int(steps), (self.E + 63) // 64, 2), "stamps")
+            _check(library().octax_set_step_clock(self._h, _ptr(stamps), int(steps), ctypes.byref(hz)))
+        return int(hz.value)
+
+    def set_wait_limit(self, ticks: int):
+        """Override the fused kernel's wait bound (device wall-clock ticks, 0 = derived)."""
+        _check(library().octax_set_wait_limit(self._h, int(ticks)))
+
     def close(self):
-        if getattr(self, "_h", None):
-            _check(library().octax_destroy(self._h))
+        h = getattr(self, "_h", None)
+        if h:
             self._h = None
+            _check(library().octax_destroy(h))
 
     def __del__(self):
         try:
@@ -504,9 +530,10 @@ class Pool:
         return out
 
     def close(self):
-        if getattr(self, "_h", None):
-            _check(library().octax_pool_destroy(self._h))
+        h = getattr(self, "_h", None)
+        if h:
             self._h = None
+            _check(library().octax_pool_destroy(h))
 
     def __del__(self):
         try:

@@ -243,3 +243,21 @@ def test_null_pool_calls_fail_cleanly():
     assert L.octax_pool_destroy(None) == X.OCTAX_OK
     assert L.octax_pool_create(None, None) == X.OCTAX_E_INVALID
     assert L.octax_pool_slot_bytes() == 5470
+
+
+def test_create_rejects_fused_steps_beyond_the_wait_bound_without_gpu():
+    """The fused kernel's paired waves wait for each other once per step with a
+    bound derived from the longest step; configs past 2^20 instruction slots per
+    step are refused for it (the plain kernel has no such wait)."""
+    L = X.library()
+    h = ctypes.c_void_p()
+    # 1000 x 64 x (1 + 20) = 1,344,000 slots: over the bound
+    c, keep = _cfg(kernel=X.OCTAX_KERNEL_FUSED, instr_per_frame=1000, frame_skip=64, noop_max=20)
+    assert L.octax_create(ctypes.byref(c), ctypes.byref(h)) == X.OCTAX_E_INVALID and not h.value
+    assert "fused kernel" in L.octax_last_error().decode()
+
+
+def test_status_and_wait_limit_reject_null_without_gpu():
+    L = X.library()
+    assert L.octax_status(None) == X.OCTAX_E_INVALID
+    assert L.octax_set_wait_limit(None, 5) == X.OCTAX_E_INVALID
