@@ -23,10 +23,11 @@ struct octax_engine {
     uint64_t device_bytes = 0;
     std::vector<void *> allocations;
     std::vector<uint32_t> env_of, slot_of, rom_of;   // host copies of the placement
+    std::vector<uint32_t> rom_len;                    // ROM bytes per ROM
     std::vector<uint8_t> occupied;                    // serving pool: host copy of State::occupied (empty: all)
     octax::State s{};
     octax::Roms roms{};
-    uint32_t *d_block_roms = nullptr;                 // [blocks][2] for the current tuning
+    uint32_t *d_block_roms = nullptr;                 // [blocks][kPoolRoms][2] page-pool table, current tuning
     uint8_t *d_startup = nullptr;                     // [R][17] start-up sequences (Wrap::startup)
     uint32_t *d_slot_scratch = nullptr;               // slot lists for get/set_state
     octax::RawState *d_raw = nullptr;
@@ -79,8 +80,10 @@ const char *check_profile(const octax_config *cfg, std::vector<uint32_t> &desc2)
 Wrap make_wrap(const uint8_t *d_table, const std::vector<uint8_t> &table, uint32_t sticky_q24,
                uint32_t noop_max, uint32_t ipf, uint32_t frame_skip);
 
-// Fill table[2b], table[2b+1] with the two most frequent ROMs among the
-// (occupied) slots of block b (0xFFFFFFFF = none); blocks of envs_per_block.
+// The fused kernel's page-pool table (octax_kernels.h) for blocks of
+// envs_per_block slots: per block, the ROMs of its (occupied) slots from the
+// most to the least frequent, each with as many program pages as the pool
+// still holds.
 void block_rom_table(const octax_engine *g, std::vector<uint32_t> &table);
 
 // Largest step, in instruction slots, that the fused kernel accepts: its

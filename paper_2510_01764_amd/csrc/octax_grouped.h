@@ -7,8 +7,8 @@
 // the union of all handlers behind a tree of divergent branches, each with
 // its exec-mask bookkeeping on the scalar unit.  Here the instructions are
 // grouped instead:
-//   * the fetch reads the instruction word and, in the same LDS round trip,
-//     the return address on top of the stack, for every lane;
+//   * the fetch reads the instruction word and the return address on top of
+//     the stack, for every lane;
 //   * the memory and display classes (DXYN, FX33/FX55, FX65, 00E0), the
 //     stack write of 2NNN and the random byte of CXNN are blocks that run
 //     only for the lanes that need them and are skipped when no lane of the
@@ -18,7 +18,8 @@
 //     and ST - is computed for all lanes with selects, in one pass, without
 //     branches.
 // The memory policy supplies fetch(pc, sp, ret) (instruction word at pc and
-// ret = stack[(sp - 1) & 15]) besides the operations listed in octax_core.h.
+// ret = stack[(sp - 1) & 15]) and stack_popped(sp) (called after a return
+// with the new SP) besides the operations listed in octax_core.h.
 #pragma once
 
 #include "octax_core.h"
@@ -122,6 +123,7 @@ __device__ __forceinline__ bool exec_grouped(Core &c, Mem &mem, uint32_t key, ui
     const uint32_t seq = pick(wait_key, c.pc, pick(skip, (pc2 + 2) & 0xFFF, pc2));
     c.pc = pick((h == 0x1) | (h == 0x2), nnn, pick(h == 0xB, (nnn + v0) & 0xFFF, pick(ret_op, ret, seq)));
     c.sp = pick(h == 0x2, (c.sp + 1) & 15, pick(ret_op, (c.sp - 1) & 15, c.sp));
+    if (ret_op) mem.stack_popped(c.sp);
     const uint32_t I = c.I;
     const uint32_t iF = pick(nn == 0x1E, (I + vx) & 0xFFF,
                              pick(nn == 0x29, kFont + 5 * kx,

@@ -135,7 +135,8 @@ octax::Wrap octax::make_wrap(const uint8_t *d_table, const std::vector<uint8_t> 
 void octax::block_rom_table(const octax_engine *g, std::vector<uint32_t> &table) {
     const uint32_t ipw = g->envs_per_block;
     const uint32_t blocks = (g->E + ipw - 1) / ipw;
-    table.assign(2 * (size_t)blocks, 0xFFFFFFFFu);
+    const uint32_t capacity = fused_pool_pages(ipw) - kPoolFixedPages;
+    table.assign(2 * (size_t)kPoolRoms * blocks, kPoolEnd);
     std::vector<uint32_t> count(g->R, 0);
     std::vector<uint32_t> seen;
     for (uint32_t b = 0; b < blocks; b++) {
@@ -146,17 +147,20 @@ void octax::block_rom_table(const octax_engine *g, std::vector<uint32_t> &table)
             const uint32_t r = g->rom_of[sl];
             if (count[r]++ == 0) seen.push_back(r);
         }
-        uint32_t best0 = 0xFFFFFFFFu, best1 = 0xFFFFFFFFu, c0 = 0, c1 = 0;
-        for (uint32_t r : seen) {
-            if (count[r] > c0 || (count[r] == c0 && r < best0)) {
-                best1 = best0; c1 = c0; best0 = r; c0 = count[r];
-            } else if (count[r] > c1 || (count[r] == c1 && r < best1)) {
-                best1 = r; c1 = count[r];
-            }
+        std::sort(seen.begin(), seen.end(), [&](uint32_t a, uint32_t c) {
+            return count[a] != count[c] ? count[a] > count[c] : a < c;
+        });
+        uint32_t used = 0;
+        uint32_t *row = table.data() + 2 * (size_t)kPoolRoms * b;
+        for (uint32_t k = 0; k < seen.size() && k < kPoolRoms; k++) {
+            const uint32_t r = seen[k];
+            const uint32_t pages = (g->rom_len[r] + 63) / 64;
+            const uint32_t staged = std::min(pages, capacity - used);
+            row[2 * k] = r;
+            row[2 * k + 1] = staged | (pages << 8) | ((kPoolFixedPages + used) << 16);
+            used += staged;
         }
         for (uint32_t r : seen) count[r] = 0;
-        table[2 * (size_t)b] = best0;
-        table[2 * (size_t)b + 1] = best1;
     }
 }
 
@@ -399,6 +403,7 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     g->stream = static_cast<hipStream_t>(cfg->stream);
     (void)hipGetDevice(&g->device);
     g->step_slots = step_slots;
+    g->rom_len.assign(cfg->h_rom_len, cfg->h_rom_len + R);
 
     // Placement: slot -> env.
     g->env_of.resize(E);

@@ -20,11 +20,46 @@ struct StepIO {
     uint32_t frame_skip;
 };
 
+// LDS layout of the fused kernel, shared with the host so that both agree on
+// the size of a block's page pool.  A block of IPW envs (2 * IPW threads)
+// owns IPW / 256 of a CU's 160 KB:
+//   * the displays: IPW x kFbStride u64 (32 rows + 1 pad row per env);
+//   * written-page cache slots: IPW x (64 x slots + 8) bytes;
+//   * the writers' staging: (IPW / 64) waves x kStageEnvs x kStageStride u32;
+//   * reward, done, two held-key slots per env and two step counters per wave;
+//   * the page pool: everything left, in 64-byte pages.
+constexpr uint32_t kFbStride = 33;
+constexpr uint32_t kStageEnvs = 4;
+constexpr uint32_t kStageStride = 68;
+constexpr uint32_t fused_cache_slots(uint32_t ipw) { return ipw == 64 ? 2 : 3; }
+constexpr uint32_t fused_lds_bytes(uint32_t ipw) { return 163840u / (256u / ipw); }
+constexpr uint32_t fused_fixed_lds(uint32_t ipw) {
+    return ipw * kFbStride * 8 + ipw * (64 * fused_cache_slots(ipw) + 8) + (ipw / 64) * kStageEnvs * kStageStride * 4 +
+           ipw * (4 + 1 + 2) + 2 * 4 * (ipw / 64);
+}
+constexpr uint32_t fused_pool_pages(uint32_t ipw) { return (fused_lds_bytes(ipw) - fused_fixed_lds(ipw)) / 64; }
+
+// The page pool of a fused block holds power-on memory pages read from LDS
+// instead of HBM: pool page 0 is a page of zeros (every page past a ROM's
+// last byte and below 0x200 outside the font), pool pages 1 and 2 hold
+// memory pages 1 and 2 (the font at 0x050..0x09F, the same in every image),
+// and from pool page kPoolFixedPages on, the program pages (from 0x200) of
+// the block's most frequent ROMs, back to back.  The host describes them in
+// a table of kPoolRoms entries per block, two u32 each:
+//   [0] ROM id, kPoolEnd after the last entry (first entry kPoolEnd: the
+//       block holds no env);
+//   [1] staged pages | program pages << 8 | first pool page << 16
+//       (program pages = ceil(ROM bytes / 64); the last ROM staged may have
+//       fewer staged pages than program pages when the pool is full).
+constexpr uint32_t kPoolRoms = 32;
+constexpr uint32_t kPoolFixedPages = 3;
+constexpr uint32_t kPoolEnd = 0xFFFFFFFFu;
+
 // Fused-kernel tuning.
 struct FusedCfg {
     uint32_t envs_per_block;      // 64, 128 or 256
-    uint32_t rom_in_lds;          // stage up to two ROM images per block in LDS
-    const uint32_t *block_roms;   // [blocks][2] ROM ids to stage (0xFFFFFFFF = none)
+    uint32_t rom_in_lds;          // stage the block's ROM program pages in its LDS page pool
+    const uint32_t *block_roms;   // [blocks][kPoolRoms][2] page-pool table (see above)
     uint64_t wait_ticks;          // longest wait of a wave for its partner, in device wall-clock ticks
     uint32_t *err;                // device error word: bit 0 set when a wait gave up
     uint64_t *stamps;             // [stamp_steps][ceil(E / 64)][2] step start / end clocks, or nullptr

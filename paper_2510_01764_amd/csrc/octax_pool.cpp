@@ -41,7 +41,7 @@ struct octax_pool {
     uint32_t *h_rom_stage = nullptr;            // pinned [capacity]
     uint32_t *h_hor_stage = nullptr;            // pinned [capacity]
     uint64_t *h_seed_stage = nullptr;           // pinned [capacity]
-    uint32_t *h_table = nullptr;                // pinned [2 * blocks]
+    uint32_t *h_table = nullptr;                // pinned [blocks][kPoolRoms][2]
     size_t table_len = 0;
     hipEvent_t table_done = nullptr;            // the last table upload has been read
     hipEvent_t stage_done = nullptr;            // the last admission's copies have been read
@@ -162,7 +162,7 @@ int32_t octax_pool_create(const octax_pool_config *cfg, octax_pool **out) {
     if (e == hipSuccess) e = g->alloc(&p->d_mask, cap);
     if (e == hipSuccess) e = hipMemsetAsync(p->d_occupied, 0, cap, g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(p->d_mask, 0, cap, g->stream);
-    p->table_len = 2 * (size_t)((cap + g->envs_per_block - 1) / g->envs_per_block);
+    p->table_len = 2 * (size_t)kPoolRoms * ((cap + g->envs_per_block - 1) / g->envs_per_block);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&p->h_rom_stage), 4 * (size_t)cap, 0);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&p->h_hor_stage), 4 * (size_t)cap, 0);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&p->h_seed_stage), 8 * (size_t)cap, 0);

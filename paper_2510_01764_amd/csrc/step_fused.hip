@@ -33,46 +33,47 @@ typedef __attribute__((address_space(3))) uint64_t lds_u64;
 typedef __attribute__((address_space(1))) uint8_t glb_u8;
 typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
 
-constexpr uint32_t kNoRom = 0xFFFFFFFFu;
 constexpr int kPrologueEnvs = 16;  // envs whose ring frames one prologue round loads
-constexpr int kStageStride = 68;   // u32 per staged env (64 + 4 pad, 16-byte aligned)
-// Written-page cache slots per env, as many as the block's LDS share allows
-// beside the two staged ROM images: four at 256 envs per block, three at
-// 128, two at 64.
-template <int IPW>
-constexpr int cache_slots() { return IPW == 64 ? 2 : IPW == 128 ? 3 : 4; }
-// Envs staged per round of the writers' cooperative pass (eight: room for the
-// fourth cache slot at 256 envs per block, and few registers for the frames
-// of one round).
-constexpr uint32_t kStageEnvs = 8;
-// bytes per env: the slots + 8 pad bytes (spreads lanes over banks)
-template <int IPW>
-constexpr int cache_stride() { return 64 * cache_slots<IPW>() + 8; }
 
-// LDS of one block.  The display of lane l is fb[l][0..31], one padded
-// 33-row stride per lane, so a lane's rows are contiguous (sprite rows are
-// addressed with immediate offsets) and lanes reading the same row index
-// spread over the banks.  At every block size the block uses at most
-// IPW / 256 of the CU's 160 KB, so 256 envs per CU stay resident.
-constexpr int kFbStride = 33;
-
+// LDS of one block (sizes in octax_kernels.h).  The display of lane l is
+// fb[l][0..31], one padded 33-row stride per lane, so a lane's rows are
+// contiguous (sprite rows are addressed with immediate offsets) and lanes
+// reading the same row index spread over the banks.  The page pool and the
+// cache slots are read up to 14 bytes before and one byte past a page (see
+// FusedMem), so neither is first or last.  At every block size the block
+// uses at most IPW / 256 of the CU's 160 KB, so 256 envs per CU stay
+// resident.
 template <int IPW>
 struct Shared {
+    static constexpr uint32_t kSlots = fused_cache_slots(IPW);
+    static constexpr uint32_t kCacheStride = 64 * kSlots + 8;   // + 8 pad bytes: lanes spread over banks
+    static constexpr uint32_t kPoolPages = fused_pool_pages(IPW);
     uint64_t fb[IPW][kFbStride];
-    uint8_t cache[IPW][cache_stride<IPW>()];
+    uint8_t pool[kPoolPages][64];
+    uint8_t cache[IPW][kCacheStride];
     uint32_t stage[IPW / 64][kStageEnvs][kStageStride];
-    uint8_t img[2][kMem];     // not last: a read one byte past a page stays inside the block's LDS
-    uint32_t stack[IPW][9];
     float rew[IPW];           // reward and done bits of the step just emulated, for the writer waves
     uint8_t done[IPW];
     uint8_t key[2][IPW];      // held key of step k (slot k & 1), staged by the writer waves
     uint32_t ready[IPW / 64]; // steps emulated by emulator wave w
     uint32_t taken[IPW / 64]; // displays taken by writer wave w
 };
+template <int IPW>
+constexpr bool layout_ok() {
+    return sizeof(Shared<IPW>) <= fused_lds_bytes(IPW) &&
+           offsetof(Shared<IPW>, pool) >= 16 && offsetof(Shared<IPW>, cache) >= offsetof(Shared<IPW>, pool) + 16 &&
+           offsetof(Shared<IPW>, stage) >= offsetof(Shared<IPW>, cache) + 16 &&
+           sizeof(Shared<IPW>) >= offsetof(Shared<IPW>, stage) + 16 &&
+           Shared<IPW>::kPoolPages > kPoolFixedPages;
+}
+static_assert(layout_ok<64>() && layout_ok<128>() && layout_ok<256>(),
+              "LDS layout: within the block's share, page pool and cache slots neither first nor last");
 
 // Memory of one env in the fused kernel.
-//   * pages not written since the reset read from the power-on image: the
-//     LDS copy when the block staged this ROM, else HBM;
+//   * pages not written since the reset read from the power-on image: from
+//     the block's page pool when it holds the page (always for the pages below
+//     0x200 and past the ROM's last byte; for program pages, when the block
+//     staged them), else through a cache slot filled from the image in HBM;
 //   * written pages are kept in two to four LDS cache slots per env,
 //     write-back: a write fills a slot (from the image for a clean page, from
 //     the env's memory in HBM for a written one) and marks it modified; HBM
@@ -87,17 +88,24 @@ struct Shared {
 // So the emulator waves touch HBM only on cache misses and resets: under the
 // observation stores of the writer waves every global access of a wave waits
 // behind them.
+//   * the call stack is held in registers: 16 return addresses two to a
+//     word, and the top entry stack[(SP - 1) & 15] apart, kept current on
+//     every call and return, which is what the instruction cycle reads.
 template <int IPW>
 struct FusedMem {
     Shared<IPW> &sh;
     uint32_t lane;
-    int32_t lidx;            // staged image index or -1
+    uint32_t pool_rom;       // pool byte offset of the env's program page 8 (0x200)
+    uint32_t staged;         // program pages of the env's ROM held in the pool
+    uint32_t rom_pages;      // program pages of the env's ROM (beyond: zero pages)
     const glb_u8 *gimg;      // power-on image in HBM
     glb_u8 *ram;             // env memory in HBM
     uint64_t dirty;
     uint32_t tags;           // slot i at bits 8i..8i+7: page | valid << 6 | modified << 7
+    uint32_t stk[8];         // stack entry i in the 16-bit half i & 1 of stk[i >> 1]
+    uint32_t top;            // stack[(SP - 1) & 15]
     uint32_t vic = 0;        // slot replaced next
-    static constexpr uint32_t kSlots = cache_slots<IPW>();
+    static constexpr uint32_t kSlots = Shared<IPW>::kSlots;
 
     __device__ __forceinline__ lds_u8 *slot_ptr(uint32_t s) const {
         return (lds_u8 *)&sh.cache[lane][0] + 64 * s;
@@ -177,13 +185,25 @@ struct FusedMem {
         set_tag(s, p | 0x40);
         return s;
     }
+    // Pool byte offset of clean page p, with in_pool false when the pool does
+    // not hold it (a program page of a ROM the block did not stage).
+    __device__ __forceinline__ uint32_t pool_off(uint32_t p, bool &in_pool) const {
+        const uint32_t q = p - 8;                  // program page index (wraps below 0x200)
+        const bool low = p < 8, font = (p == 1) | (p == 2);
+        const bool prog = !low & (q < staged);
+        const bool beyond = !low & (q >= rom_pages);
+        in_pool = low | prog | beyond;
+        return prog ? pool_rom + 64 * q : (font ? 64 * p : 0u);
+    }
     __device__ __forceinline__ uint32_t fill_from_image(uint32_t p, int32_t keep) {
         uint32_t old;
         const uint32_t s = victim(keep, old);
         uint4 *slot = reinterpret_cast<uint4 *>(&sh.cache[lane][64 * s]);
         if (old & 0x80) write_back(old, slot[0], slot[1], slot[2], slot[3]);
-        const uint4 *src = lidx >= 0 ? reinterpret_cast<const uint4 *>(&sh.img[lidx & 1][p * 64]) : nullptr;
-        if (lidx >= 0) {
+        bool in_pool;
+        const uint32_t off = pool_off(p, in_pool);
+        if (in_pool) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(&sh.pool[0][0] + off);
             slot[0] = src[0];
             slot[1] = src[1];
             slot[2] = src[2];
@@ -212,24 +232,26 @@ struct FusedMem {
     }
     // Slow path of the selects below: make page p readable from LDS.  A
     // written page that is not cached is filled from the env's memory in HBM,
-    // a clean page of a ROM the block has not staged from the power-on image
-    // in HBM; slot `keep` is not reused.  Returns the page's slot, or -1 for a
-    // page of the staged image.
+    // a clean page that the pool does not hold from the power-on image in
+    // HBM; slot `keep` is not reused.  Returns the page's slot, or -1 for a
+    // page of the pool.
     __device__ __forceinline__ int32_t make_resident(uint32_t p, int32_t keep) {
         int32_t s = find(p);
+        bool in_pool;
+        (void)pool_off(p, in_pool);
         if (s < 0 && is_dirty(p)) s = (int32_t)fill_from_ram(p, keep);
-        else if (s < 0 && lidx < 0) s = (int32_t)fill_from_image(p, keep);
+        else if (s < 0 && !in_pool) s = (int32_t)fill_from_image(p, keep);
         return s;
     }
     // LDS address of byte a, computed with selects only: the cache slot of
-    // its page, else the staged image for a clean page.  `slow` is raised
-    // when neither holds (the address is then some other byte of the block's
+    // its page, else the pool for a clean page.  `slow` is raised when
+    // neither holds (the address is then some other byte of the block's
     // LDS).
     __device__ __forceinline__ const lds_u8 *lds_byte(uint32_t a, bool &slow) const {
         return lds_page_sel(a >> 6, slow) + (a & 63);
     }
-    // Instruction word at pc and, in the same LDS round trip, the return
-    // address stack[(sp - 1) & 15].  Both code bytes are read from pc's page;
+    // Instruction word at pc, and the return address stack[(sp - 1) & 15]
+    // (the register copy of the top).  Both code bytes are read from pc's page;
     // lanes whose pc is the last byte of a page, or whose page is not in LDS,
     // take the slow path afterwards.
     __device__ __forceinline__ uint32_t fetch(uint32_t pc, uint32_t sp, uint32_t &ret) {
@@ -237,7 +259,7 @@ struct FusedMem {
         bool slow = (pc & 63) == 63;
         const lds_u8 *b0 = lds_byte(pc, slow);
         uint32_t op = ((uint32_t)b0[0] << 8) | b0[1];
-        ret = stack_get((sp - 1) & 15);
+        ret = top;
         if (slow) {
             make_resident(a1 >> 6, make_resident(pc >> 6, -1));
             bool no = false;
@@ -316,8 +338,10 @@ struct FusedMem {
     // LDS base of page p, computed with selects only (see lds_byte).
     __device__ __forceinline__ lds_u8 *lds_page_sel(uint32_t p, bool &slow) const {
         const int32_t s = find(p);
-        slow = slow | ((s < 0) & (is_dirty(p) | (lidx < 0)));
-        return s >= 0 ? slot_ptr((uint32_t)s) : (lds_u8 *)&sh.img[lidx & 1][0] + 64 * p;
+        bool in_pool;
+        const uint32_t off = pool_off(p, in_pool);
+        slow = slow | ((s < 0) & (is_dirty(p) | !in_pool));
+        return s >= 0 ? slot_ptr((uint32_t)s) : (lds_u8 *)&sh.pool[0][0] + off;
     }
     // Window rows [W0, W0 + NR): one batch of LDS reads, then the XOR and the
     // row writes.  Window row w is display row b + w (at fbw[w]) and sprite
@@ -415,12 +439,32 @@ struct FusedMem {
 #pragma unroll
         for (int y = 0; y < 32; y++) fb[y] = 0;
     }
-    // Stack entry i is the i-th 16-bit half of the env's stack words.
+    // Stack entry i (0..15), picked out of the registers with masks (a
+    // select between array elements would be folded into an indexed load,
+    // which puts the whole structure in scratch memory).
     __device__ __forceinline__ uint32_t stack_get(uint32_t i) const {
-        return ((const lds_u16 *)&sh.stack[lane][0])[i];
+        uint32_t w = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < 8; j++) w |= stk[j] & (0u - (uint32_t)((i >> 1) == j));
+        return __builtin_amdgcn_ubfe(w, (i & 1) * 16, 16);
     }
+    // A call stores its return address at entry i = SP, which becomes the top.
     __device__ __forceinline__ void stack_set(uint32_t i, uint32_t v) {
-        ((lds_u16 *)&sh.stack[lane][0])[i] = (uint16_t)v;
+        const uint32_t sh16 = (i & 1) * 16;
+        const uint32_t m = 0xFFFFu << sh16, nv = (v & 0xFFFF) << sh16;
+#pragma unroll
+        for (uint32_t j = 0; j < 8; j++) {
+            const uint32_t mj = m & (0u - (uint32_t)((i >> 1) == j));
+            stk[j] = (stk[j] & ~mj) | (nv & mj);
+        }
+        top = v & 0xFFFF;
+    }
+    // After a return SP is sp: the new top is stack[(sp - 1) & 15].
+    __device__ __forceinline__ void stack_popped(uint32_t sp) { top = stack_get((sp - 1) & 15); }
+    __device__ __forceinline__ void stack_clear() {
+#pragma unroll
+        for (uint32_t j = 0; j < 8; j++) stk[j] = 0;
+        top = 0;
     }
     // Restore the written pages from the image (automatic reset).
     __device__ __forceinline__ void restore_pages() {
@@ -429,8 +473,10 @@ struct FusedMem {
             const uint32_t p = __builtin_ctzll(d);
             d &= d - 1;
             uint4 *dst = reinterpret_cast<uint4 *>((uint8_t *)ram + p * 64);
-            if (lidx >= 0) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(&sh.img[lidx][p * 64]);
+            bool in_pool;
+            const uint32_t off = pool_off(p, in_pool);
+            if (in_pool) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(&sh.pool[0][0] + off);
 #pragma unroll
                 for (int q = 0; q < 4; q++) dst[q] = src[q];
             } else {
@@ -541,30 +587,32 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     const uint32_t K = io.K;
     const bool active = slot_live(s, slot);
     // A block with no env (free range of a serving pool) has nothing to do:
-    // the host marks it in the block's ROM table (no ROM to stage).
-    if (cfg.block_roms[blockIdx.x * 2] == kNoRom) return;
+    // the host marks it in the block's pool table (no ROM listed).
+    const uint32_t *ptab = cfg.block_roms + (size_t)blockIdx.x * kPoolRoms * 2;
+    if (ptab[0] == kPoolEnd) return;
     const uint32_t live = active ? 1u : 0u;
     const uint64_t live_bits = __builtin_amdgcn_ballot_w64(active);   // live slots of this wave
     const uint32_t wave_slot0 = blockIdx.x * IPW + wave_base;
     const uint32_t nj = (E > wave_slot0) ? min(64u, E - wave_slot0) : 0u;   // slots of this wave
 
-    // Stage the block's ROM images (all threads).
-    uint32_t brom0 = kNoRom, brom1 = kNoRom;
-    if (cfg.rom_in_lds) {
-        brom0 = cfg.block_roms[blockIdx.x * 2 + 0];
-        brom1 = cfg.block_roms[blockIdx.x * 2 + 1];
-        for (uint32_t q = tid; q < 2 * kMem / 16; q += 2 * IPW) {
-            const uint32_t which = q / (kMem / 16);
-            const uint32_t rid = which ? brom1 : brom0;
-            if (rid != kNoRom) {
-                reinterpret_cast<uint4 *>(sh.img[which])[q % (kMem / 16)] =
-                    reinterpret_cast<const uint4 *>(roms.image + (size_t)rid * kMem)[q % (kMem / 16)];
-            }
+    // Fill the block's page pool (all threads): the zero page, memory pages 1
+    // and 2 (the font; the same in every image, taken from the first listed
+    // ROM's) and, with ROM staging on, the program pages the table lists.
+    {
+        uint4 *pool4 = reinterpret_cast<uint4 *>(&sh.pool[0][0]);
+        const uint4 *img0 = reinterpret_cast<const uint4 *>(roms.image + (size_t)ptab[0] * kMem);
+        for (uint32_t q = tid; q < 12; q += 2 * IPW) pool4[q] = q < 4 ? make_uint4(0, 0, 0, 0) : img0[q];
+        for (uint32_t j = 0; cfg.rom_in_lds && j < kPoolRoms && ptab[2 * j] != kPoolEnd; j++) {
+            const uint32_t info = ptab[2 * j + 1];
+            const uint32_t n16 = (info & 0xFF) * 4, first16 = (info >> 16) * 4;
+            const uint4 *src = reinterpret_cast<const uint4 *>(roms.image + (size_t)ptab[2 * j] * kMem + kProgram);
+            for (uint32_t q = tid; q < n16; q += 2 * IPW) pool4[first16 + q] = src[q];
         }
     }
 
     Core c;
     uint32_t head = 0, env = 0, rom = 0, desc = 0, desc2 = kDesc2Default, t = 0, hor = 0, tags = 0;
+    uint4 stack_in[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
     const uint32_t quirks = kProfile ? roms.quirks : 0u;   // 0: the base profile
     int32_t prev = 0;
     uint64_t dirty = 0;
@@ -626,11 +674,21 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             sh.fb[l][2 * q + 1] = (uint64_t)v.z | ((uint64_t)v.w << 32);
         }
         const uint4 *st4 = reinterpret_cast<const uint4 *>(s.stack + (size_t)slot * 8);
-        const uint4 a0 = st4[0], a1 = st4[1];
-        sh.stack[l][0] = a0.x; sh.stack[l][1] = a0.y; sh.stack[l][2] = a0.z; sh.stack[l][3] = a0.w;
-        sh.stack[l][4] = a1.x; sh.stack[l][5] = a1.y; sh.stack[l][6] = a1.z; sh.stack[l][7] = a1.w;
+        stack_in[0] = st4[0];
+        stack_in[1] = st4[1];
     }
-    const int32_t lidx = (rom == brom0) ? 0 : (rom == brom1) ? 1 : -1;
+    // This env's ROM in the pool table: its staged and program pages, and
+    // where they start.  A ROM the table does not list has no staged page,
+    // and all its program pages read through the cache slots.
+    uint32_t staged = 0, rom_pages = 56, pool_rom = 0;
+    for (uint32_t j = 0; j < kPoolRoms && ptab[2 * j] != kPoolEnd; j++) {
+        const uint32_t info = ptab[2 * j + 1];
+        if (ptab[2 * j] == rom) {
+            staged = cfg.rom_in_lds ? (info & 0xFF) : 0u;
+            rom_pages = (info >> 8) & 0xFF;
+            pool_rom = 64 * (info >> 16);
+        }
+    }
     const glb_u8 *gimg = (const glb_u8 *)(roms.image + (size_t)rom * kMem);
     glb_u8 *ram = (glb_u8 *)(s.ram + (size_t)slot * kMem);
     const size_t obs_step = (size_t)E * kObsBytes;
@@ -685,7 +743,10 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             cfg.stamps[((size_t)k * nwaves + gw) * 2 + which] = __builtin_amdgcn_s_memrealtime();
     };
 
-    FusedMem<IPW> mem{sh, l, lidx, gimg, ram, dirty, tags};
+    FusedMem<IPW> mem{sh, l, pool_rom, staged, rom_pages, gimg, ram, dirty, tags,
+                      {stack_in[0].x, stack_in[0].y, stack_in[0].z, stack_in[0].w,
+                       stack_in[1].x, stack_in[1].y, stack_in[1].z, stack_in[1].w}, 0u};
+    mem.top = mem.stack_get((c.sp - 1) & 15);
     if (emu) {
         for (uint32_t k = 0; k < K; k++) {
             // the display of step k - 1 must have been copied before it changes
@@ -707,7 +768,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                     mem.restore_pages();
                     reset_core(c);
                     mem.clear();
-                    for (int q = 0; q < 8; q++) sh.stack[l][q] = 0;
+                    mem.stack_clear();
                     if (kResetSteps) {
                         run_reset_steps(roms, rom, c, [&](uint32_t rkey) {
                             run_frames<kProfile>(c, mem, rkey, io.ipf, io.frame_skip, quirks);
@@ -766,6 +827,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             // belongs to and keep the last four frames of the launch in the
             // env's ring.
             constexpr uint32_t kStage = kStageEnvs;
+            static_assert(kStage == 4 || kStage == 8, "rounds of four or eight envs");
             for (uint32_t r0 = 0; r0 < nj; r0 += kStage) {
                 if (active && lane64 - r0 < kStage) {
                     uint4 *stg = reinterpret_cast<uint4 *>(sh.stage[wave][lane64 - r0]);
@@ -862,8 +924,8 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             fb4[q] = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
         }
         uint4 *st4 = reinterpret_cast<uint4 *>(s.stack + (size_t)slot * 8);
-        st4[0] = make_uint4(sh.stack[l][0], sh.stack[l][1], sh.stack[l][2], sh.stack[l][3]);
-        st4[1] = make_uint4(sh.stack[l][4], sh.stack[l][5], sh.stack[l][6], sh.stack[l][7]);
+        st4[0] = make_uint4(mem.stk[0], mem.stk[1], mem.stk[2], mem.stk[3]);
+        st4[1] = make_uint4(mem.stk[4], mem.stk[5], mem.stk[6], mem.stk[7]);
     }
 }
 
