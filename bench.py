@@ -73,6 +73,39 @@ def measured_active_lanes():
     return d.get("active_lane_fraction")
 
 
+COUNTER_FILES = {
+    "fused": (os.path.join(ROOT, "profiles", "step_fused_c3_counters.json"), KERNEL_SOURCES),
+    "plain": (os.path.join(ROOT, "profiles", "step_plain_c3_counters.json"),
+              ["step_plain.hip", "octax_core.h", "octax_device.h", "octax_kernels.h", "octax_plain_mem.h"]),
+}
+
+
+def measured_counters(which):
+    """LDS, VALU and active-lane figures of one kernel from its committed
+    counter summary, if taken on the kernel source as it is now; else None."""
+    path, sources = COUNTER_FILES[which]
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(ROOT, "paper_2510_01764_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if d.get("kernel_source_hash") != h.hexdigest()[:16]:
+        return None
+    c, dv = d["per_dispatch"], d["derived"]
+    return {"kernel": d["kernel"],
+            "lds_insts_per_wave": dv.get("lds_per_wave"),
+            "lds_bank_conflict_cycles_per_lds_active_cycle": dv.get("lds_bank_conflict_per_active_cycle"),
+            "lds_wait_cycles_per_dispatch": c.get("SQ_WAIT_INST_LDS"),
+            "valu_insts_per_wave": dv.get("valu_per_wave"),
+            "salu_insts_per_wave": dv.get("salu_per_wave"),
+            "active_lane_fraction": dv.get("active_lane_fraction"),
+            "source": os.path.relpath(path, ROOT)}
+
+
 def measured_traffic():
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the kernel source as it is now; else None."""
@@ -562,6 +595,9 @@ def main():
             "achieved": valu_ops / (kernel_ms * 1e-3), "peak": VALU_PEAK_LANE_OPS, "unit": "lane ops/s",
             "frac": valu_ops / (kernel_ms * 1e-3) / VALU_PEAK_LANE_OPS, "lane_ops_per_launch": valu_ops,
             "active_lane_fraction": measured_active_lanes()}),
+        # LDS instructions and bank conflicts, VALU issue and active lanes of the
+        # fused and plain kernels, from the committed counter summaries (null if stale)
+        "counters": {"fused": measured_counters("fused"), "plain": measured_counters("plain")},
         "context": "paper: 350,000 env steps/s (Pong, constant action, RTX 3090) - other hardware and workload",
     }
     if serving is not None:

@@ -9,6 +9,10 @@
   python -m paper_2510_01764_amd.profile_summary lanes <pmc dir> <valu.json> --kernel "..." --command "..."
       adds to a valu summary the mean active lanes per VALU instruction, from an
       SQ_THREAD_CYCLES_VALU / SQ_ACTIVE_INST_VALU counter run of the same kernel.
+  python -m paper_2510_01764_amd.profile_summary counters <out.json> --kernel "..." --sources a.hip,b.h
+      --pass <pmc dir> "<command>" [--pass ...]
+      every counter of the runs averaged per dispatch of one kernel, with instructions per wave,
+      active lanes per VALU instruction and LDS bank-conflict cycles per LDS-active cycle.
   python -m paper_2510_01764_amd.profile_summary traffic <fetch dir> <write dir> <out.json>
       --calib-bytes N --kernel "step_fused_kernel<256, true, false, false>" --command-fetch "..." --command-write "..."
       HBM bytes per launch of one kernel from FETCH_SIZE and WRITE_SIZE counter runs, each
@@ -162,6 +166,54 @@ def lanes(d, out, kernel, command):
     print(json.dumps(res, indent=1))
 
 
+def source_hash(files):
+    """The same digest as bench.kernel_source_hash, over the named csrc files."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2510_01764_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counters(out, kernel, sources, passes):
+    """Every counter of the given counter-run directories, averaged per
+    dispatch of one kernel, with the ratios the roofline discussion uses:
+    instructions of each kind per wave, the mean active lanes per VALU
+    instruction, LDS bank-conflict cycles per LDS-active cycle.  `passes` is
+    a list of (directory, command) pairs."""
+    res = {"kernel": kernel, "kernel_source_hash": source_hash(sources), "sources": sources,
+           "per_dispatch": {}, "dispatches": {}, "commands": []}
+    for d, cmd in passes:
+        res["commands"].append(cmd)
+        names = set()
+        for f in _find(d, "*counter_collection.csv"):
+            with open(f) as fh:
+                names |= {r["Counter_Name"] for r in csv.DictReader(fh)}
+        for n in sorted(names):
+            mean, cnt = _pick(_counter_means(d, n), kernel)
+            res["per_dispatch"][n] = mean
+            res["dispatches"][n] = cnt
+    c = res["per_dispatch"]
+    waves = c.get("SQ_WAVES")
+    derived = {}
+    if waves:
+        for n in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_SMEM", "SQ_INSTS_VMEM_RD",
+                  "SQ_INSTS_VMEM_WR"):
+            if n in c:
+                derived[n.replace("SQ_INSTS_", "").lower() + "_per_wave"] = c[n] / waves
+    if "SQ_THREAD_CYCLES_VALU" in c and c.get("SQ_ACTIVE_INST_VALU"):
+        derived["active_lane_fraction"] = c["SQ_THREAD_CYCLES_VALU"] / c["SQ_ACTIVE_INST_VALU"] / 64
+    if c.get("SQ_LDS_IDX_ACTIVE"):
+        derived["lds_bank_conflict_per_active_cycle"] = c.get("SQ_LDS_BANK_CONFLICT", 0.0) / c["SQ_LDS_IDX_ACTIVE"]
+    if c.get("SQ_INSTS_VALU"):
+        derived["valu_lane_ops_per_launch"] = c["SQ_INSTS_VALU"] * 64
+    res["derived"] = derived
+    with open(out, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -187,8 +239,15 @@ def main():
     ln.add_argument("out")
     ln.add_argument("--kernel", required=True)
     ln.add_argument("--command", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("out")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--sources", required=True, help="comma-separated csrc files the kernel is built from")
+    c.add_argument("--pass", dest="passes", action="append", nargs=2, metavar=("DIR", "COMMAND"), required=True)
     a = ap.parse_args()
-    if a.cmd == "stats":
+    if a.cmd == "counters":
+        counters(a.out, a.kernel, a.sources.split(","), [tuple(x) for x in a.passes])
+    elif a.cmd == "stats":
         stats(a.dir, a.out, a.command)
     elif a.cmd == "valu":
         valu(a.dir, a.out, a.kernel, a.command)
