@@ -446,11 +446,12 @@ int32_t octax_set_step_clock(octax_engine *eng, uint64_t *d_stamps, uint32_t ste
  *
  * A pool holds `capacity` env slots, fixed at creation from a device-memory
  * budget (pool_bytes / octax_pool_slot_bytes()).  octax_pool_admit places a
- * group of `count` envs of one ROM in a free contiguous range of slots
- * (first fit) and resets them to the power-on state of that ROM (Section 3.2,
- * ROM loading and initialization); with no free range large enough it
+ * group of `count` envs of one ROM in the `count` lowest-numbered free slots,
+ * contiguous or not, and resets them to the power-on state of that ROM
+ * (Section 3.2, ROM loading and initialization); with fewer free slots it
  * returns OCTAX_E_NOMEM and changes nothing, so the caller keeps the request
- * queued.  octax_pool_step runs K environment steps (the semantics of
+ * queued (admission is by memory only: free slots never fragment).
+ * octax_pool_step runs K environment steps (the semantics of
  * octax_step_many) of every occupied slot; free slots are neither read nor
  * written.  octax_pool_retire frees a group's slots.  A group's results do
  * not depend on its slots or on the other groups in the pool: each env's
@@ -506,19 +507,20 @@ int32_t octax_pool_create(const octax_pool_config *cfg, octax_pool **out);
 
 /*
  * Admit a group: count envs of ROM `rom`, env k with RNG seed h_env_seed[k]
- * and truncation horizon h_horizon[k] (0 = none).  On success *first_slot is
- * the first of its count contiguous slots.  Errors: OCTAX_E_INVALID (rom >= R,
- * count == 0 or > capacity, NULL), OCTAX_E_NOMEM (no free range of count
- * slots: nothing changed), OCTAX_E_HIP.
+ * and truncation horizon h_horizon[k] (0 = none).  On success h_slots[k]
+ * (caller-owned, count entries) is env k's slot, in ascending order, and
+ * *group the group's id for octax_pool_retire.  Errors: OCTAX_E_INVALID
+ * (rom >= R, count == 0 or > capacity, NULL), OCTAX_E_NOMEM (fewer than
+ * count free slots: nothing changed), OCTAX_E_HIP.
  */
 int32_t octax_pool_admit(octax_pool *p, uint32_t rom, uint32_t count, const uint64_t *h_env_seed,
-                         const uint32_t *h_horizon, uint32_t *first_slot);
+                         const uint32_t *h_horizon, uint32_t *h_slots, uint32_t *group);
 
 /*
- * Free the group that starts at first_slot.  Steps already enqueued still
- * see it.  Errors: OCTAX_E_INVALID (no group starts there).
+ * Free the slots of a group.  Steps already enqueued still see it.
+ * Errors: OCTAX_E_INVALID (no such group).
  */
-int32_t octax_pool_retire(octax_pool *p, uint32_t first_slot);
+int32_t octax_pool_retire(octax_pool *p, uint32_t group);
 
 /* K environment steps of every occupied slot (buffers as described above).
  * Errors: OCTAX_E_INVALID (K == 0, NULL action/reward/done, obs_slots == 0
@@ -526,14 +528,15 @@ int32_t octax_pool_retire(octax_pool *p, uint32_t first_slot);
 int32_t octax_pool_step(octax_pool *p, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
                         uint32_t obs_slots, float *d_reward, uint8_t *d_done);
 
-/* Capacity, free slots, largest free range and number of groups. */
+/* Capacity, free slots, the largest group admissible now (equal to the free
+ * slots: any free slots take a group) and number of groups. */
 int32_t octax_pool_info(const octax_pool *p, uint32_t *capacity, uint32_t *free_slots,
                         uint32_t *largest_free, uint32_t *groups);
 
-/* Architectural state of slots [first, first + count) (synchronizes).  The
- * observation history is that of the env in the slot.  Errors as
- * octax_get_state. */
-int32_t octax_pool_get_state(octax_pool *p, uint32_t first, uint32_t count, octax_env_state *h_out);
+/* Architectural state of the envs in slots h_slots[0..count) into
+ * h_out[0..count) (synchronizes).  The observation history is that of the
+ * env in the slot.  Errors as octax_get_state. */
+int32_t octax_pool_get_state(octax_pool *p, const uint32_t *h_slots, uint32_t count, octax_env_state *h_out);
 
 /* Destroy a pool (synchronizes its stream).  NULL is accepted. */
 int32_t octax_pool_destroy(octax_pool *p);

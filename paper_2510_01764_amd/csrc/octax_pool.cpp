@@ -1,16 +1,19 @@
 // Serving pool of liboctax (declared in include/octax.h): environment groups
-// admitted into contiguous slot ranges of one resident engine and stepped
-// together, one fused launch per tick, while groups arrive and leave.
+// admitted into free slots of one resident engine and stepped together, one
+// fused launch per tick, while groups arrive and leave.
 //
 // The pool is an engine of `capacity` slots with identity placement and the
 // fused kernel.  Membership lives in the device table State::occupied; the
-// step kernel skips free slots and whole blocks with no occupied slot.
-// Admission writes the group's ROM id, horizons and RNG seeds into its slots
-// (copied from pinned staging indexed by slot; an admission first waits for
-// the copies of the previous one, so staging is never rewritten while a copy
-// from it may be pending) and resets the slots to the ROM's power-on image.
-// The table of ROM images each workgroup stages in LDS is recomputed on the
-// host when membership changes and uploaded before the next step.
+// step kernel skips free slots and whole blocks with no occupied slot.  A
+// group takes the lowest-numbered free slots, contiguous or not, so any group
+// fits as long as enough slots are free (no fragmentation).  Admission writes
+// the group's ROM id, horizons and RNG seeds into its slots (copied, one run
+// of consecutive slots at a time, from pinned staging indexed by slot; an
+// admission first waits for the copies of the previous one, so staging is
+// never rewritten while a copy from it may be pending) and resets the slots
+// to the ROM's power-on image.  The page-pool table of the workgroups is
+// recomputed on the host when membership changes and uploaded before the
+// next step.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -34,8 +37,10 @@ constexpr uint64_t kSlotBytes = 16 + 4 + 4 + 32 + 4 + 4 + 8 + 8 + 256 + 1024 + 4
 struct octax_pool {
     octax_engine *eng = nullptr;
     uint32_t capacity = 0;
-    std::map<uint32_t, uint32_t> free_ranges;   // first slot -> length; disjoint, coalesced
-    std::map<uint32_t, uint32_t> groups;        // first slot -> length
+    std::vector<uint64_t> free_bits;            // bit s of word s / 64: slot s is free
+    uint32_t free_count = 0;
+    std::map<uint32_t, std::vector<uint32_t>> groups;   // group id -> its slots, ascending
+    uint32_t next_group = 0;
     uint8_t *d_occupied = nullptr;              // [capacity]
     uint8_t *d_mask = nullptr;                  // [capacity], zero outside an admission
     uint32_t *h_rom_stage = nullptr;            // pinned [capacity]
@@ -59,20 +64,14 @@ struct octax_pool {
 
 namespace {
 
-void release_range(octax_pool *p, uint32_t first, uint32_t len) {
-    auto next = p->free_ranges.lower_bound(first);
-    if (next != p->free_ranges.end() && first + len == next->first) {
-        len += next->second;
-        next = p->free_ranges.erase(next);
+// Runs of consecutive slots of an ascending slot list: (first, length).
+std::vector<std::pair<uint32_t, uint32_t>> runs_of(const std::vector<uint32_t> &slots) {
+    std::vector<std::pair<uint32_t, uint32_t>> out;
+    for (uint32_t s : slots) {
+        if (!out.empty() && out.back().first + out.back().second == s) out.back().second++;
+        else out.emplace_back(s, 1u);
     }
-    if (next != p->free_ranges.begin()) {
-        auto prev = std::prev(next);
-        if (prev->first + prev->second == first) {
-            prev->second += len;
-            return;
-        }
-    }
-    p->free_ranges.emplace(first, len);
+    return out;
 }
 
 hipError_t upload_table(octax_pool *p) {
@@ -178,68 +177,90 @@ int32_t octax_pool_create(const octax_pool_config *cfg, octax_pool **out) {
                                         : hip_fail(e, "octax_pool_create");
     }
     g->s.occupied = p->d_occupied;
-    p->free_ranges.emplace(0u, cap);
+    p->free_bits.assign((cap + 63) / 64, ~0ull);
+    if (cap % 64) p->free_bits.back() = (1ull << (cap % 64)) - 1;
+    p->free_count = cap;
     *out = p;
     return OCTAX_OK;
 }
 
 int32_t octax_pool_admit(octax_pool *p, uint32_t rom, uint32_t count, const uint64_t *h_env_seed,
-                         const uint32_t *h_horizon, uint32_t *first_slot) {
-    if (!p || !h_env_seed || !h_horizon || !first_slot)
+                         const uint32_t *h_horizon, uint32_t *h_slots, uint32_t *group) {
+    if (!p || !h_env_seed || !h_horizon || !h_slots || !group)
         return fail(OCTAX_E_INVALID, "octax_pool_admit: NULL argument");
     octax_engine *g = p->eng;
     if (rom >= g->R) return fail(OCTAX_E_INVALID, "octax_pool_admit: rom >= num_roms");
     if (count == 0 || count > p->capacity) return fail(OCTAX_E_INVALID, "octax_pool_admit: count out of range");
-    auto it = p->free_ranges.begin();
-    while (it != p->free_ranges.end() && it->second < count) ++it;
-    if (it == p->free_ranges.end()) return fail(OCTAX_E_NOMEM, "octax_pool_admit: no free range of that many slots");
-    const uint32_t first = it->first, len = it->second;
+    if (count > p->free_count) return fail(OCTAX_E_NOMEM, "octax_pool_admit: fewer free slots than the group's envs");
+    // the lowest-numbered free slots
+    std::vector<uint32_t> slots;
+    slots.reserve(count);
+    for (uint32_t w = 0; w < p->free_bits.size() && slots.size() < count; w++) {
+        uint64_t bits = p->free_bits[w];
+        while (bits && slots.size() < count) {
+            slots.push_back(64 * w + (uint32_t)__builtin_ctzll(bits));
+            bits &= bits - 1;
+        }
+    }
+    const auto runs = runs_of(slots);
 
     hipError_t e = hipEventSynchronize(p->stage_done);
     if (e != hipSuccess) return hip_fail(e, "octax_pool_admit");
     for (uint32_t k = 0; k < count; k++) {
-        p->h_rom_stage[first + k] = rom;
-        p->h_hor_stage[first + k] = h_horizon[k];
-        p->h_seed_stage[first + k] = h_env_seed[k];
+        p->h_rom_stage[slots[k]] = rom;
+        p->h_hor_stage[slots[k]] = h_horizon[k];
+        p->h_seed_stage[slots[k]] = h_env_seed[k];
     }
     hipStream_t st = g->stream;
     uint32_t *rom_of = const_cast<uint32_t *>(g->s.rom_of);
     uint32_t *hor = const_cast<uint32_t *>(g->s.horizon);
-    e = hipMemcpyAsync(rom_of + first, p->h_rom_stage + first, 4 * (size_t)count, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(hor + first, p->h_hor_stage + first, 4 * (size_t)count, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(g->s.rng + first, p->h_seed_stage + first, 8 * (size_t)count, hipMemcpyHostToDevice, st);
+    for (const auto &r : runs) {
+        const uint32_t a = r.first, n = r.second;
+        if (e == hipSuccess) e = hipMemcpyAsync(rom_of + a, p->h_rom_stage + a, 4 * (size_t)n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hor + a, p->h_hor_stage + a, 4 * (size_t)n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(g->s.rng + a, p->h_seed_stage + a, 8 * (size_t)n, hipMemcpyHostToDevice, st);
+    }
     if (e == hipSuccess) e = hipEventRecord(p->stage_done, st);
-    if (e == hipSuccess) e = hipMemsetAsync(p->d_mask + first, 1, count, st);
-    if (e == hipSuccess) e = launch_reset_range(g->s, g->roms, p->d_mask, true, first, count, st);
-    if (e == hipSuccess) e = hipMemsetAsync(p->d_mask + first, 0, count, st);
-    if (e == hipSuccess) e = hipMemsetAsync(p->d_occupied + first, 1, count, st);
+    for (const auto &r : runs)
+        if (e == hipSuccess) e = hipMemsetAsync(p->d_mask + r.first, 1, r.second, st);
+    // one reset over the span of the group's slots: slots of other groups in it have a zero mask
+    const uint32_t lo = slots.front(), span = slots.back() - lo + 1;
+    if (e == hipSuccess) e = launch_reset_range(g->s, g->roms, p->d_mask, true, lo, span, st);
+    for (const auto &r : runs) {
+        if (e == hipSuccess) e = hipMemsetAsync(p->d_mask + r.first, 0, r.second, st);
+        if (e == hipSuccess) e = hipMemsetAsync(p->d_occupied + r.first, 1, r.second, st);
+    }
     if (e != hipSuccess) return hip_fail(e, "octax_pool_admit");
 
-    p->free_ranges.erase(it);
-    if (len > count) p->free_ranges.emplace(first + count, len - count);
-    p->groups.emplace(first, count);
-    for (uint32_t k = 0; k < count; k++) {
-        g->rom_of[first + k] = rom;
-        g->occupied[first + k] = 1;
+    for (uint32_t s : slots) {
+        p->free_bits[s / 64] &= ~(1ull << (s % 64));
+        g->rom_of[s] = rom;
+        g->occupied[s] = 1;
     }
+    p->free_count -= count;
+    const uint32_t id = p->next_group++;
+    std::copy(slots.begin(), slots.end(), h_slots);
+    p->groups.emplace(id, std::move(slots));
     p->table_dirty = true;
-    *first_slot = first;
+    *group = id;
     return OCTAX_OK;
 }
 
-int32_t octax_pool_retire(octax_pool *p, uint32_t first_slot) {
+int32_t octax_pool_retire(octax_pool *p, uint32_t group) {
     if (!p) return fail(OCTAX_E_INVALID, "octax_pool_retire: pool is NULL");
-    auto it = p->groups.find(first_slot);
-    if (it == p->groups.end()) return fail(OCTAX_E_INVALID, "octax_pool_retire: no group starts at that slot");
-    const uint32_t len = it->second;
+    auto it = p->groups.find(group);
+    if (it == p->groups.end()) return fail(OCTAX_E_INVALID, "octax_pool_retire: no such group");
     octax_engine *g = p->eng;
-    hipError_t e = hipMemsetAsync(p->d_occupied + first_slot, 0, len, g->stream);
+    hipError_t e = hipSuccess;
+    for (const auto &r : runs_of(it->second))
+        if (e == hipSuccess) e = hipMemsetAsync(p->d_occupied + r.first, 0, r.second, g->stream);
     if (e != hipSuccess) return hip_fail(e, "octax_pool_retire");
+    for (uint32_t s : it->second) {
+        p->free_bits[s / 64] |= 1ull << (s % 64);
+        g->occupied[s] = 0;
+    }
+    p->free_count += (uint32_t)it->second.size();
     p->groups.erase(it);
-    for (uint32_t k = 0; k < len; k++) g->occupied[first_slot + k] = 0;
-    release_range(p, first_slot, len);
     p->table_dirty = true;
     return OCTAX_OK;
 }
@@ -260,21 +281,24 @@ int32_t octax_pool_step(octax_pool *p, uint32_t K, const int32_t *d_action, uint
 int32_t octax_pool_info(const octax_pool *p, uint32_t *capacity, uint32_t *free_slots,
                         uint32_t *largest_free, uint32_t *groups) {
     if (!p) return fail(OCTAX_E_INVALID, "octax_pool_info: pool is NULL");
-    uint32_t total = 0, largest = 0;
-    for (const auto &r : p->free_ranges) {
-        total += r.second;
-        largest = std::max(largest, r.second);
-    }
     if (capacity) *capacity = p->capacity;
-    if (free_slots) *free_slots = total;
-    if (largest_free) *largest_free = largest;
+    if (free_slots) *free_slots = p->free_count;
+    if (largest_free) *largest_free = p->free_count;   // any free slots take a group
     if (groups) *groups = (uint32_t)p->groups.size();
     return OCTAX_OK;
 }
 
-int32_t octax_pool_get_state(octax_pool *p, uint32_t first, uint32_t count, octax_env_state *h_out) {
-    if (!p) return fail(OCTAX_E_INVALID, "octax_pool_get_state: pool is NULL");
-    return octax_get_state(p->eng, first, count, h_out);
+int32_t octax_pool_get_state(octax_pool *p, const uint32_t *h_slots, uint32_t count, octax_env_state *h_out) {
+    if (!p || (count && (!h_slots || !h_out))) return fail(OCTAX_E_INVALID, "octax_pool_get_state: NULL argument");
+    // runs of consecutive slots, each one octax_get_state call (env = slot in a pool)
+    for (uint32_t k = 0; k < count;) {
+        uint32_t n = 1;
+        while (k + n < count && h_slots[k + n] == h_slots[k] + n) n++;
+        const int32_t rc = octax_get_state(p->eng, h_slots[k], n, h_out + k);
+        if (rc != OCTAX_OK) return rc;
+        k += n;
+    }
+    return OCTAX_OK;
 }
 
 int32_t octax_pool_destroy(octax_pool *p) {

@@ -55,6 +55,8 @@ struct Shared {
     float rew[IPW];           // reward and done bits of the step just emulated, for the writer waves
     uint8_t done[IPW];
     uint8_t key[2][IPW];      // held key of step k (slot k & 1), staged by the writer waves
+    uint8_t lready[IPW];      // per-lane progress (variants with reset steps): steps published, mod 256
+    uint8_t ltaken[IPW];      // displays taken, mod 256
     uint32_t ready[IPW / 64]; // steps emulated by emulator wave w
     uint32_t taken[IPW / 64]; // displays taken by writer wave w
 };
@@ -268,6 +270,29 @@ struct FusedMem {
         touch(pc >> 6);
         return op;
     }
+    // Sixteen bytes of a run of memory that lies on page q0 from byte `off`
+    // on and goes on at page q1 (both LDS page bases; off may be below 0 or
+    // the run may end before q1 is reached: those bytes are unspecified).
+    // The five aligned dwords covering the run are read, dword w of the run's
+    // page space from q0 while w < 16 and from q1 after (page ends are dword
+    // boundaries, and every page base in LDS is dword aligned), and shifted
+    // into place with v_alignbyte.  Byte k of the run lands at bits 8k.  The
+    // dwords read outside the two pages lie inside the block's LDS (neither
+    // the pool nor the slots is first or last in it).
+    __device__ __forceinline__ u32x4 window16(const lds_u8 *q0, const lds_u8 *q1, int32_t off) const {
+        const int32_t w0 = off >> 2;
+        uint32_t d[5];
+#pragma unroll
+        for (int i = 0; i < 5; i++) {
+            const int32_t w = w0 + i;
+            d[i] = *(const lds_u32 *)((w < 16 ? q0 : q1 - 64) + 4 * w);
+        }
+        const uint32_t sb = (uint32_t)off & 3;
+        u32x4 v;
+#pragma unroll
+        for (int i = 0; i < 4; i++) v[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sb);
+        return v;
+    }
     // count (1..16) bytes from address a on (12-bit wrap), on at most two
     // pages; byte k lands at bits 8k of the vector.  Bytes past count are
     // left unspecified: the caller masks them.
@@ -284,25 +309,13 @@ struct FusedMem {
         }
         touch(p0);
         touch(p1);
-        // byte k is at s0[k] while k < rb, else at s1[k]; groups of four bytes
-        // are read only when a byte of the group is wanted
-        const lds_u8 *s0 = q0 + off, *s1 = q1 + off - 64;
-        const uint32_t rb = 64 - off;
-        u32x4 v = {0, 0, 0, 0};
-#pragma unroll
-        for (int g = 0; g < 4; g++) {
-            if ((uint32_t)(4 * g) < count) {
-                uint32_t w = 0;
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int k = 4 * g + q;
-                    w |= (uint32_t)((uint32_t)k < rb ? s0 : s1)[k] << (8 * q);
-                }
-                v[g] = w;
-            }
-        }
-        return v;
+        return window16(q0, q1, (int32_t)off);
     }
+    // count (1..16) bytes from address a on (12-bit wrap), byte k of `bytes`
+    // to a + k: both pages are made resident in cache slots, then the five
+    // aligned dwords covering the run are read and written back with the
+    // run's bytes merged in under a byte mask (dwords the run does not reach
+    // are written back unchanged).
     __device__ __forceinline__ void store_bytes(uint32_t a, uint32_t count, u32x4 bytes) {
         const uint32_t p0 = a >> 6, p1 = ((a + count - 1) & 0xFFF) >> 6;
         touch(p0);
@@ -314,23 +327,27 @@ struct FusedMem {
             s1 = find(p1);
             if (s1 < 0) s1 = (int32_t)(is_dirty(p1) ? fill_from_ram(p1, s0) : fill_from_image(p1, s0));
         }
-        // byte k goes to c0[k] while k < rb, else to c1[k]; in a group of four
-        // that some lane writes, bytes past count go to the pad bytes after
-        // the env's slots
         const uint32_t off = a & 63;
-        const uint32_t rb = 64 - off;
-        lds_u8 *c0 = slot_ptr((uint32_t)s0) + off, *c1 = slot_ptr((uint32_t)s1) + off - 64;
-        lds_u8 *pad = (lds_u8 *)&sh.cache[lane][64 * kSlots];
+        lds_u8 *c0 = slot_ptr((uint32_t)s0), *c1 = slot_ptr((uint32_t)s1);
+        const uint32_t w0 = off >> 2, sb = off & 3;
+        // the data and its byte mask, one dword before and after: window dword
+        // i is dwords i and i + 1 of these shifted right by 4 - sb bytes
+        const u32x4 m = byte_mask(count);
+        const uint32_t x[6] = {0u, bytes[0], bytes[1], bytes[2], bytes[3], 0u};
+        const uint32_t mk[6] = {0u, m[0], m[1], m[2], m[3], 0u};
+        lds_u32 *ptr[5];
+        uint32_t old[5];
 #pragma unroll
-        for (int g = 0; g < 4; g++) {
-            if ((uint32_t)(4 * g) < count) {
+        for (int i = 0; i < 5; i++) {
+            const uint32_t w = w0 + i;
+            ptr[i] = (lds_u32 *)((w < 16 ? c0 : c1 - 64) + 4 * w);
+            old[i] = *ptr[i];
+        }
 #pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int k = 4 * g + q;
-                    lds_u8 *base = (uint32_t)k < count ? ((uint32_t)k < rb ? c0 : c1) : pad + (k & 7) - k;
-                    base[k] = (uint8_t)byte_of(bytes, k);
-                }
-            }
+        for (int i = 0; i < 5; i++) {
+            const uint32_t val = sb ? __builtin_amdgcn_alignbyte(x[i + 1], x[i], 4 - sb) : x[i + 1];
+            const uint32_t msk = sb ? __builtin_amdgcn_alignbyte(mk[i + 1], mk[i], 4 - sb) : mk[i + 1];
+            *ptr[i] = (old[i] & ~msk) | (val & msk);
         }
         tags |= (0x80u << (8 * s0)) | (0x80u << (8 * s1));
         dirty |= (1ull << p0) | (1ull << p1);
@@ -344,40 +361,39 @@ struct FusedMem {
         return s >= 0 ? slot_ptr((uint32_t)s) : (lds_u8 *)&sh.pool[0][0] + off;
     }
     // Window rows [W0, W0 + NR): one batch of LDS reads, then the XOR and the
-    // row writes.  Window row w is display row b + w (at fbw[w]) and sprite
-    // row w - sh0 (at s0w[w] while w < rbw, else at s1w[w]).  Bit w of vm
-    // marks the sprite's rows; the other rows get an empty mask and are
+    // row writes.  Window row w is display row b + w (at fbw[w]); its sprite
+    // byte is byte w of `spr` (the sixteen memory bytes from I - sh0).  Bit w
+    // of vm marks the sprite's rows; the other rows get an empty mask and are
     // written back unchanged.
     template <int W0, int NR>
-    __device__ __forceinline__ uint64_t draw_rows(lds_u64 *fbw, uint32_t x0, uint32_t vm,
-                                                  const lds_u8 *s0w, const lds_u8 *s1w, uint32_t rbw) {
-        uint32_t spr[NR];
+    __device__ __forceinline__ uint64_t draw_rows(lds_u64 *fbw, uint32_t x0, uint32_t vm, const u32x4 &spr) {
         uint64_t row[NR];
 #pragma unroll
-        for (int r = 0; r < NR; r++) {
-            spr[r] = ((uint32_t)(W0 + r) < rbw ? s0w : s1w)[W0 + r];
-            row[r] = fbw[W0 + r];
-        }
+        for (int r = 0; r < NR; r++) row[r] = fbw[W0 + r];
         uint64_t hit = 0;
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            const uint32_t sb = spr[r] * __builtin_amdgcn_ubfe(vm, W0 + r, 1);
+            const int w = W0 + r;
+            const uint32_t sb = __builtin_amdgcn_ubfe(spr[w >> 2], 8 * (w & 3), 8) * __builtin_amdgcn_ubfe(vm, w, 1);
             const uint64_t m = ((uint64_t)sb << 56) >> x0;
             hit |= row[r] & m;
-            fbw[W0 + r] = row[r] ^ m;
+            fbw[w] = row[r] ^ m;
         }
         return hit;
     }
     // DXYN at (x0, y0) = (VX & 63, VY & 31): rows below the screen are
     // clipped, pixels past x = 63 fall off the shifted mask.  Sprite bytes
     // are at I + r (12-bit wrap), on at most two pages.  Rows are taken in a
-    // window of 15 display rows from b = min(y0, 17), which lies inside the
-    // env's 32 rows, so every window row can be written back without a
-    // per-row condition.  Sprite rows are read from at most 14 bytes before
-    // or after the sprite (inside the block's LDS) when they are not used.
+    // window of display rows that lies inside the env's 32 rows, so every
+    // window row can be written back without a per-row condition: 15 rows
+    // from b = min(y0, 17) when some drawing lane of the wave has N > 8, else
+    // 8 rows from b = min(y0, 24).  The window's sprite bytes are the sixteen
+    // memory bytes from I - sh0 (sh0 = y0 - b rows above the sprite), read as
+    // five dwords; the bytes outside the sprite are masked.
     __device__ __forceinline__ uint32_t draw(uint32_t x0, uint32_t y0, uint32_t I, uint32_t n) {
         const uint32_t cnt = min(n, 32 - y0);
-        const uint32_t b = min(y0, 17u);
+        const bool longw = __builtin_amdgcn_ballot_w64(n > 8) != 0;   // among the drawing lanes
+        const uint32_t b = min(y0, longw ? 17u : 24u);
         const uint32_t sh0 = y0 - b;                    // window rows above the sprite
         const uint32_t vm = ((1u << cnt) - 1) << sh0;   // window rows of the sprite
         lds_u64 *fbw = (lds_u64 *)&sh.fb[lane][0] + b;
@@ -393,14 +409,11 @@ struct FusedMem {
         }
         touch(p0);
         touch(p1);
-        // sprite row r = w - sh0 is at I + r: on the first page while r < 64 - off
-        const lds_u8 *s0w = q0 + off - sh0;
-        const lds_u8 *s1w = q1 + off - 64 - sh0;
-        const uint32_t rbw = 64 - off + sh0;
+        const u32x4 spr = window16(q0, q1, (int32_t)off - (int32_t)sh0);
         uint64_t hit = 0;
-        if (vm & 0x000Fu) hit |= draw_rows<0, 4>(fbw, x0, vm, s0w, s1w, rbw);
-        if (vm & 0x00F0u) hit |= draw_rows<4, 4>(fbw, x0, vm, s0w, s1w, rbw);
-        if (vm & 0x7F00u) hit |= draw_rows<8, 7>(fbw, x0, vm, s0w, s1w, rbw);
+        if (vm & 0x000Fu) hit |= draw_rows<0, 4>(fbw, x0, vm, spr);
+        if (vm & 0x00F0u) hit |= draw_rows<4, 4>(fbw, x0, vm, spr);
+        if (longw && (vm & 0x7F00u)) hit |= draw_rows<8, 7>(fbw, x0, vm, spr);
         return hit != 0;
     }
     // DXYN with the pixel-wrap quirk: all n rows are drawn, row y0 + r at
@@ -524,6 +537,34 @@ __device__ __forceinline__ void wait_flag(const uint32_t *f, uint32_t v, uint64_
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Per-lane step counters (variants with reset steps): a byte per env, counting
+// modulo 256; a partner is never more than one step ahead, so a difference
+// of zero or one is all they ever hold.
+__device__ __forceinline__ void set_lane_flag(uint8_t *f, uint32_t v) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __hip_atomic_store(f, (uint8_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t get_lane_flag(const uint8_t *f) {
+    return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// Bounded wait of a per-lane loop in which no lane can go on: true while it
+// may go on waiting (after a short sleep); false once `limit` ticks have
+// passed since the wait began, after setting bit 0 of the error word.
+__device__ __forceinline__ bool keep_waiting(bool &waiting, uint64_t &since, uint64_t limit, uint32_t *err) {
+    const uint64_t now = __builtin_amdgcn_s_memrealtime();
+    if (!waiting) {
+        waiting = true;
+        since = now;
+    }
+    if (now - since > limit) {
+        if (__lane_id() == 0) __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        waiting = false;
+        return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    return true;
 }
 
 // One environment step of emulation with `key` held: frame_skip frames of
@@ -732,6 +773,10 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
         sh.ready[tid] = 0;
         sh.taken[tid] = 0;
     }
+    if (tid < IPW) {
+        sh.lready[tid] = 0;
+        sh.ltaken[tid] = 0;
+    }
     __syncthreads();
 
     // Step clock (optional): wave pair gw records, on the device wall clock,
@@ -747,7 +792,214 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                       {stack_in[0].x, stack_in[0].y, stack_in[0].z, stack_in[0].w,
                        stack_in[1].x, stack_in[1].y, stack_in[1].z, stack_in[1].w}, 0u};
     mem.top = mem.stack_get((c.sp - 1) & 15);
-    if (emu) {
+    if constexpr (kResetSteps) {
+        // Per-lane progress (variants whose resets run emulation steps).  A
+        // reset here runs a ROM's start-up sequence and up to noop_max no-op
+        // steps before the step can return its observation; in lockstep the
+        // whole wave would wait for that lane.  Instead every lane keeps its
+        // own step counter and reset phase, and the wave runs step-sized slots
+        // (frame_skip frames of ipf instructions) for all lanes that can go on:
+        //   * emulator lane l publishes step k (display final, reward and done
+        //     in LDS) by raising lready[l] to k + 1, and runs the slot of step
+        //     k + 1 once ltaken[l] says that display has been copied; slots of
+        //     a reset's steps need no such wait (step k's display is not
+        //     published before the reset ends), and a slot starts when no
+        //     lane is left waiting;
+        //   * writer lane l copies its env's display whenever a new step is
+        //     published, and the wave stores the frames of all lanes that had
+        //     one, four envs per round, each into the observations of its own
+        //     steps.
+        if (emu) {
+            uint32_t k = 0;          // the step this lane emulates next
+            uint32_t phase = 0;      // 0: a step; 1: start-up steps of a reset; 2: its no-op steps
+            uint32_t si = 0, left = 0;
+            float pend_rew = 0.f;
+            uint32_t pend_done = 0;
+            const uint8_t *su = roms.w.startup ? roms.w.startup + (size_t)rom * 17 : nullptr;
+            const uint32_t n_startup = su ? su[0] : 0u;
+            bool waiting = false;
+            uint64_t since = 0;
+            while (true) {
+                const bool want = active && k < K;
+                if (!__builtin_amdgcn_ballot_w64(want)) break;
+                // A slot starts once no lane waits for its display to be
+                // copied: the lanes of a reset then run their reset steps in
+                // the same slots as the other lanes' steps, instead of in
+                // slots of their own while those lanes wait.
+                bool run = want && (phase != 0 || k == 0 || ((get_lane_flag(&sh.ltaken[l]) - k) & 0xFF) == 0);
+                if (__builtin_amdgcn_ballot_w64(want && !run)) {
+                    if (keep_waiting(waiting, since, cfg.wait_ticks, cfg.err)) continue;
+                    run = want;      // gave up (reported): go on regardless
+                } else {
+                    waiting = false;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+                // a step whose display is final this slot is published at the
+                // slot's end by all its lanes at once, so the writer takes the
+                // slot's frames in one pass
+                bool pub = false;
+                float pub_rew = 0.f;
+                uint32_t pub_done = 0;
+                if (run) {
+                    uint32_t key = kKeyNone;
+                    if (phase == 0) key = sticky_key(roms, c, sh.key[k & 1][l]);
+                    else if (phase == 1) key = su[1 + si];
+                    run_frames<kProfile>(c, mem, key, io.ipf, io.frame_skip, quirks);
+                    if (phase == 0) {
+                        const int32_t score = score_of(c.r, desc, desc2);
+                        const float reward = (float)(score - prev);
+                        const uint32_t term = terminated_of(c.r, desc, desc2);
+                        t += 1;
+                        const uint32_t trunc = (hor != 0) && (t >= hor);
+                        const uint32_t done = term | (trunc << 1);
+                        if (done) {
+                            // Automatic reset (Section 3.4); the RNG stream continues.
+                            mem.restore_pages();
+                            reset_core(c);
+                            mem.clear();
+                            mem.stack_clear();
+                            phase = 1;
+                            si = 0;
+                            pend_rew = reward;
+                            pend_done = done;
+                        } else {
+                            prev = score;
+                            head = (head + 1) & 3;
+                            pub = true;
+                            pub_rew = reward;
+                            pub_done = done;
+                        }
+                    } else if (phase == 1) {
+                        si += 1;
+                    } else {
+                        left -= 1;
+                    }
+                    // the start-up sequence done, draw the no-op steps; those done, the reset ends
+                    if (phase == 1 && si >= n_startup) {
+                        phase = 2;
+                        left = 0;
+                        if (roms.w.noop_max) {
+                            const uint64_t u = splitmix_next(c.rng);
+                            left = (uint32_t)(((u >> 32) * ((uint64_t)roms.w.noop_max + 1)) >> 32);
+                        }
+                    }
+                    if (phase == 2 && left == 0) {
+                        c.pkey = kKeyNone;
+                        head = 0;
+                        t = 0;
+                        prev = score_of(c.r, desc, desc2);   // the score after the reset's steps
+                        phase = 0;
+                        pub = true;
+                        pub_rew = pend_rew;
+                        pub_done = pend_done;
+                    }
+                }
+                if (pub) {
+                    sh.rew[l] = pub_rew;
+                    sh.done[l] = (uint8_t)pub_done;
+                }
+                if (pub) {
+                    set_lane_flag(&sh.lready[l], k + 1);
+                    k += 1;
+                }
+            }
+        } else {
+            uint32_t kw = 0;         // steps whose display this lane has taken
+            bool waiting = false;
+            uint64_t since = 0;
+            while (true) {
+                const bool want = active && kw < K;
+                if (!__builtin_amdgcn_ballot_w64(want)) break;
+                bool have = want && ((get_lane_flag(&sh.lready[l]) - kw) & 0xFF) != 0;
+                if (!__builtin_amdgcn_ballot_w64(have)) {
+                    if (keep_waiting(waiting, since, cfg.wait_ticks, cfg.err)) continue;
+                    have = want;     // gave up (reported): take the displays as they are
+                } else {
+                    waiting = false;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+                uint32_t hi[32], lo[32];
+#pragma unroll
+                for (int r = 0; r < 32; r++) {
+                    const uint64_t row = sh.fb[l][31 - r];
+                    hi[r] = (uint32_t)(row >> 32);
+                    lo[r] = (uint32_t)row;
+                }
+                uint32_t done = 0;
+                if (have) {
+                    done = sh.done[l];
+                    const float wrew = sh.rew[l];
+                    if (kw + 2 < K) {
+                        if (((kw + 2) & 63) == 0) load_keys(kw + 2);
+                        sh.key[kw & 1][l] = (uint8_t)key_of_step(kw + 2);
+                    }
+                    set_lane_flag(&sh.ltaken[l], kw + 1);
+                    io.reward[(size_t)kw * E + env] = wrew;
+                    io.done[(size_t)kw * E + env] = (uint8_t)done;
+                    head = done ? 0u : (head + 1) & 3;
+                }
+                uint32_t pw[64];
+                rows_to_cols(hi, lo);
+                pack_frame(hi, lo, pw);
+                // the lanes with a new frame, four per round (rank: place among them)
+                const uint64_t hmask = __builtin_amdgcn_ballot_w64(have);
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(hmask >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)hmask, 0u));
+                uint64_t rem = hmask;
+                for (uint32_t r0 = 0; rem; r0 += kStageEnvs) {
+                    if (have && rank - r0 < kStageEnvs) {
+                        uint4 *stg = reinterpret_cast<uint4 *>(sh.stage[wave][rank - r0]);
+#pragma unroll
+                        for (int q = 0; q < 16; q++)
+                            stg[q] = make_uint4(pw[4 * q], pw[4 * q + 1], pw[4 * q + 2], pw[4 * q + 3]);
+                    }
+                    wave_sync();
+#pragma unroll
+                    for (uint32_t jj = 0; jj < kStageEnvs; jj++) {
+                        if (!rem) break;
+                        const uint32_t j = (uint32_t)__builtin_ctzll(rem);
+                        rem &= rem - 1;
+                        const uint32_t w = sh.stage[wave][jj][lane64];
+                        const uint32_t kj = __builtin_amdgcn_readlane(kw, j);
+                        const uint32_t je = __builtin_amdgcn_readlane(env, j);
+                        const uint32_t jdone = __builtin_amdgcn_readlane(done, j);
+                        if (io.obs) {
+                            const u32x4 x0 = spread16(w), x1 = spread16(w >> 16);
+                            // frame 3 - d of observation kj + d
+#pragma unroll
+                            for (uint32_t d = 0; d < 4; d++) {
+                                if (kj + d < K) {
+                                    uint8_t *o = obs_of(kj + d, je) + (3 - d) * 2048;
+                                    store_obs(o + 16 * lane64, x0);
+                                    store_obs(o + 1024 + 16 * lane64, x1);
+                                }
+                            }
+                            if (jdone) {
+                                // the frames before the reset belong to the old episode
+#pragma unroll
+                                for (uint32_t d = 0; d < 3; d++)
+#pragma unroll
+                                    for (uint32_t f = 0; f < 3 - d; f++)
+                                        if (kj + d < K) store_frame(obs_of(kj + d, je) + f * 2048, lane64, w);
+                            }
+                        }
+                        if (kj + 4 >= K) {
+                            const uint32_t jh = __builtin_amdgcn_readlane(head, j);
+                            uint32_t *ring = s.cols + (size_t)(wave_slot0 + j) * 256 + lane64;
+                            ring[jh * 64] = w;
+                            if (jdone) {
+                                ring[((jh + 1) & 3) * 64] = w;
+                                ring[((jh + 2) & 3) * 64] = w;
+                                ring[((jh + 3) & 3) * 64] = w;
+                            }
+                        }
+                    }
+                    wave_sync();
+                }
+                kw += have ? 1u : 0u;
+            }
+        }
+    } else if (emu) {
         for (uint32_t k = 0; k < K; k++) {
             // the display of step k - 1 must have been copied before it changes
             if (k > 0) wait_flag(&sh.taken[wave], k, cfg.wait_ticks, cfg.err);

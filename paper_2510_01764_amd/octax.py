@@ -167,11 +167,11 @@ def library() -> ctypes.CDLL:
         "octax_calib_copy": ([P, P, ctypes.c_uint64, P], i32),
         "octax_pool_slot_bytes": ([], ctypes.c_uint64),
         "octax_pool_create": ([ctypes.POINTER(octax_pool_config), ctypes.POINTER(P)], i32),
-        "octax_pool_admit": ([P, u32, u32, P, P, ctypes.POINTER(u32)], i32),
+        "octax_pool_admit": ([P, u32, u32, P, P, P, ctypes.POINTER(u32)], i32),
         "octax_pool_retire": ([P, u32], i32),
         "octax_pool_step": ([P, u32, P, P, u32, P, P], i32),
         "octax_pool_info": ([P] + [ctypes.POINTER(u32)] * 4, i32),
-        "octax_pool_get_state": ([P, u32, u32, P], i32),
+        "octax_pool_get_state": ([P, P, u32, P], i32),
         "octax_pool_destroy": ([P], i32),
     }
     for name, (args, res) in sig.items():
@@ -496,22 +496,24 @@ class Pool:
     def slot_bytes() -> int:
         return int(library().octax_pool_slot_bytes())
 
-    def admit(self, rom: int, env_seed: np.ndarray, horizon: np.ndarray) -> Optional[int]:
-        """First slot of the admitted group, or None when no free range fits it."""
+    def admit(self, rom: int, env_seed: np.ndarray, horizon: np.ndarray):
+        """(group id, slots of its envs as uint32 [count]) of the admitted
+        group, or None when fewer slots are free."""
         seeds = np.ascontiguousarray(env_seed, dtype=np.uint64)
         hor = np.ascontiguousarray(horizon, dtype=np.uint32)
         if seeds.shape != hor.shape or seeds.ndim != 1:
             raise ValueError("env_seed and horizon must be 1-D of the same length")
-        first = ctypes.c_uint32()
+        slots = np.zeros(len(seeds), dtype=np.uint32)
+        group = ctypes.c_uint32()
         code = library().octax_pool_admit(self._h, int(rom), len(seeds), seeds.ctypes.data,
-                                          hor.ctypes.data, ctypes.byref(first))
+                                          hor.ctypes.data, slots.ctypes.data, ctypes.byref(group))
         if code == OCTAX_E_NOMEM:
             return None
         _check(code)
-        return int(first.value)
+        return int(group.value), slots
 
-    def retire(self, first_slot: int):
-        _check(library().octax_pool_retire(self._h, int(first_slot)))
+    def retire(self, group: int):
+        _check(library().octax_pool_retire(self._h, int(group)))
 
     def step(self, action, obs, reward, done):
         K = int(action.shape[0])
@@ -524,9 +526,10 @@ class Pool:
         _check(library().octax_pool_info(self._h, *[ctypes.byref(x) for x in v]))
         return dict(zip(("capacity", "free", "largest_free", "groups"), (int(x.value) for x in v)))
 
-    def get_state(self, first: int, count: int) -> np.ndarray:
-        out = np.zeros(int(count), dtype=ENV_STATE_DTYPE)
-        _check(library().octax_pool_get_state(self._h, int(first), int(count), out.ctypes.data))
+    def get_state(self, slots) -> np.ndarray:
+        sl = np.ascontiguousarray(slots, dtype=np.uint32)
+        out = np.zeros(len(sl), dtype=ENV_STATE_DTYPE)
+        _check(library().octax_pool_get_state(self._h, sl.ctypes.data, len(sl), out.ctypes.data))
         return out
 
     def close(self):

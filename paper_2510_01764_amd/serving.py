@@ -2,10 +2,11 @@
 
 Requests are groups of envs of one ROM that run a fixed number of steps
 (Section 3.2's functional reset/step environment, many of them at once).
-They arrive over time.  Each arrival waits in a FIFO queue until a free
-range of pool slots can hold it; admission is by memory (the pool has a
-fixed device budget) and is first fit in arrival order, with later groups
-allowed to fill a range the head of the queue does not fit in.  Every tick
+They arrive over time.  Each arrival waits in a FIFO queue until enough pool
+slots are free to hold it; admission is by memory (the pool has a fixed
+device budget; a group takes any free slots, so the pool never fragments),
+in arrival order, with later groups allowed to start while a larger one at
+the head of the queue does not fit yet.  Every tick
 enqueues one step of every resident group as one launch over the pool, so
 the work of groups that arrived at different times runs together on the
 device.  A group leaves the pool after its last step.
@@ -31,7 +32,8 @@ from . import workload as W
 class GroupRun:
     group: W.Group
     num_actions: int
-    first: int = -1            # first slot while resident
+    pool_id: int = -1          # the pool's id of the group while resident
+    slots: Optional[np.ndarray] = None   # its envs' slots while resident
     t0: int = -1               # tick of the group's first step
     step: int = 0              # steps run (set when the group leaves)
     t_arrival: float = 0.0
@@ -79,8 +81,8 @@ class PoolBackend:
     def admit(self, rom, seeds, horizons):
         return self.pool.admit(rom, seeds, horizons)
 
-    def retire(self, first):
-        self.pool.retire(first)
+    def retire(self, pool_id):
+        self.pool.retire(pool_id)
 
     def schedule(self) -> np.ndarray:
         """Host action schedule [rows, capacity] (pinned)."""
@@ -109,12 +111,12 @@ class PoolBackend:
     def finish(self):
         self.stream.synchronize()
 
-    def obs_of(self, first: int, count: int) -> np.ndarray:
+    def obs_of(self, slots: np.ndarray) -> np.ndarray:
         self.stream.synchronize()
-        return self.obs[0, first:first + count].cpu().numpy()
+        return self.obs[0].cpu().numpy()[slots]
 
-    def state_of(self, first: int, count: int) -> np.ndarray:
-        return self.pool.get_state(first, count)
+    def state_of(self, slots: np.ndarray) -> np.ndarray:
+        return self.pool.get_state(slots)
 
     def close(self):
         self.stream.synchronize()
@@ -132,7 +134,7 @@ def _weighted_percentile(values: np.ndarray, weights: np.ndarray, q: float) -> f
     return float(values[o][np.searchsorted(cw, q / 100.0 * cw[-1])])
 
 
-def serve(spec, groups: List[W.Group], backend, *, record: bool = False,
+def serve(spec, groups: List[W.Group], backend, *, record=False,
           clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
           log: Optional[Callable[[str], None]] = None) -> Dict:
     """Run the request loop over `groups` (arrival times in seconds from the start).
@@ -141,10 +143,11 @@ def serve(spec, groups: List[W.Group], backend, *, record: bool = False,
     group admitted before tick T0 takes step k in tick T0 + k, and its
     actions are written into the ring a window of steps ahead, so a tick
     costs the host O(1) work besides admissions, window refills and
-    retirements.  With ``record`` every step's rewards and dones, each
-    group's last observation and its final architectural state are kept
-    (the ticks in flight are drained before a finishing group's slots are
-    read).  Returns per-group runs and latency figures.
+    retirements.  With ``record`` (True for every group, or a set of group
+    ids) every step's rewards and dones, the last observation and the final
+    architectural state of the recorded groups are kept (the ticks in flight
+    are drained before a finishing recorded group's slots are read).
+    Returns per-group runs and latency figures.
     """
     depth = backend.depth
     R = backend.rows
@@ -168,26 +171,28 @@ def serve(spec, groups: List[W.Group], backend, *, record: bool = False,
     changed = True
     t0 = clock()
 
+    def recorded(r: GroupRun) -> bool:
+        return record is True or (bool(record) and r.group.gid in record)
+
     def write_window(r: GroupRun, t_start: int):
         g = r.group
         k0 = t_start - r.t0
         n = min(WINDOW, g.steps - k0)
         rows = (t_start + np.arange(n)) % R
-        sched[rows, r.first:r.first + g.size] = W.group_actions(g, k0, n, r.num_actions)
+        sched[np.ix_(rows, r.slots)] = W.group_actions(g, k0, n, r.num_actions)
         if k0 + n < g.steps:
             refill_at[t_start + n].append(r)
 
     def collect():
-        ticket, tick, members, t_launch = inflight.popleft()
+        ticket, tick, n_groups, members, t_launch = inflight.popleft()
         rew, done, dev_ms = backend.wait(ticket)
         tick_lat.append(clock() - t0 - t_launch)
-        tick_groups.append(len(members) if record else members)
+        tick_groups.append(n_groups)
         tick_ms.append(dev_ms)
-        if record:
-            for r in members:
-                k = tick - r.t0
-                r.rewards[k] = rew[r.first:r.first + r.group.size]
-                r.dones[k] = done[r.first:r.first + r.group.size]
+        for r in members:
+            k = tick - r.t0
+            r.rewards[k] = rew[r.slots]
+            r.dones[k] = done[r.slots]
 
     while nxt < len(order) or queue or resident or inflight:
         now = clock() - t0
@@ -200,21 +205,21 @@ def serve(spec, groups: List[W.Group], backend, *, record: bool = False,
             queue.append(r)
             fresh.append(r)
             nxt += 1
-        # admission: arrival order, first fit; a group that does not fit lets
-        # later ones try.  Queued groups are retried only after a retirement.
+        # admission: arrival order; a group that does not fit lets later ones
+        # try.  Queued groups are retried only after a retirement.
         for r in (list(queue) if changed else fresh):
             g = r.group
-            first = backend.admit(g.rom, r.seeds, r.horizons)
-            if first is None:
+            adm = backend.admit(g.rom, r.seeds, r.horizons)
+            if adm is None:
                 continue
-            r.first = first
+            r.pool_id, r.slots = adm
             r.t0 = T
             r.t_admit = clock() - t0
-            if record:
+            if recorded(r):
                 r.rewards = np.zeros((g.steps, g.size), dtype=np.float32)
                 r.dones = np.zeros((g.steps, g.size), dtype=np.uint8)
             queue.remove(r)
-            resident[first] = r
+            resident[r.pool_id] = r
             resident_envs += g.size
             write_window(r, T)
             finish_at[T + g.steps - 1].append(r)
@@ -226,19 +231,20 @@ def serve(spec, groups: List[W.Group], backend, *, record: bool = False,
                 write_window(r, T)
             t_launch = clock() - t0
             ticket = backend.launch(T % R)
-            inflight.append((ticket, T, list(resident.values()) if record else len(resident), t_launch))
+            members = [r for r in resident.values() if recorded(r)] if record else []
+            inflight.append((ticket, T, len(resident), members, t_launch))
             busy_env_steps += resident_envs
             finished = finish_at.pop(T, ())
-            if finished and record:
+            if any(recorded(r) for r in finished):
                 while inflight:
                     collect()
             for r in finished:
-                resident.pop(r.first)
+                resident.pop(r.pool_id)
                 resident_envs -= r.group.size
-                if record:
-                    r.final_obs = backend.obs_of(r.first, r.group.size)
-                    r.final_state = backend.state_of(r.first, r.group.size)
-                backend.retire(r.first)
+                if recorded(r):
+                    r.final_obs = backend.obs_of(r.slots)
+                    r.final_state = backend.state_of(r.slots)
+                backend.retire(r.pool_id)
                 r.step = r.group.steps
                 r.t_done = clock() - t0
                 changed = True

@@ -234,12 +234,13 @@ def test_pool_create_rejects_bad_config_without_gpu(field, value):
 
 def test_null_pool_calls_fail_cleanly():
     L = X.library()
-    first = ctypes.c_uint32()
-    assert L.octax_pool_admit(None, 0, 1, None, None, ctypes.byref(first)) == X.OCTAX_E_INVALID
+    group = ctypes.c_uint32()
+    slots = (ctypes.c_uint32 * 1)()
+    assert L.octax_pool_admit(None, 0, 1, None, None, slots, ctypes.byref(group)) == X.OCTAX_E_INVALID
     assert L.octax_pool_retire(None, 0) == X.OCTAX_E_INVALID
     assert L.octax_pool_step(None, 1, None, None, 1, None, None) == X.OCTAX_E_INVALID
     assert L.octax_pool_info(None, None, None, None, None) == X.OCTAX_E_INVALID
-    assert L.octax_pool_get_state(None, 0, 1, None) == X.OCTAX_E_INVALID
+    assert L.octax_pool_get_state(None, None, 1, None) == X.OCTAX_E_INVALID
     assert L.octax_pool_destroy(None) == X.OCTAX_OK
     assert L.octax_pool_create(None, None) == X.OCTAX_E_INVALID
     assert L.octax_pool_slot_bytes() == 5470

@@ -53,28 +53,34 @@ def test_pool_admit_retire_and_info():
     a = pool.admit(0, z, h)
     b = pool.admit(1, z, h)
     c = pool.admit(2, z, h)
-    assert (a, b, c) == (0, 100, 200)
+    assert [list(x[1]) for x in (a, b, c)] == [list(range(0, 100)), list(range(100, 200)), list(range(200, 300))]
     assert pool.admit(3, z[:1], h[:1]) is None          # full: nothing changes
-    pool.retire(100)
+    pool.retire(b[0])
     assert pool.info() == {"capacity": 300, "free": 100, "largest_free": 100, "groups": 2}
-    assert pool.admit(4, z[:60], h[:60]) == 100
-    pool.retire(0)
-    pool.retire(100)
-    assert pool.info()["largest_free"] == 200           # freed ranges coalesce
+    d = pool.admit(4, z[:60], h[:60])
+    assert list(d[1]) == list(range(100, 160))
+    pool.retire(a[0])
+    # free: 0..99 and 160..199; a group of 120 takes the lowest free slots, in two runs
+    e = pool.admit(5, np.zeros(120, dtype=np.uint64), np.zeros(120, dtype=np.uint32))
+    assert list(e[1]) == list(range(0, 100)) + list(range(160, 180))
+    assert pool.info()["free"] == 20
     with pytest.raises(X.OctaxError):
-        pool.retire(5)                                   # no group starts there
+        pool.retire(9999)                                # no such group
     with pytest.raises(X.OctaxError):
         pool.admit(32, z[:1], h[:1])                     # no such ROM
-    # a step with one resident group touches only its slots
+    # a step touches only occupied slots: the free slots 180..199 keep their values
     act = torch.zeros((1, 300), dtype=torch.int32, device="cuda")
     rew = torch.full((1, 300), 7.0, dtype=torch.float32, device="cuda")
     done = torch.full((1, 300), 9, dtype=torch.uint8, device="cuda")
     pool.step(act, None, rew, done)
     torch.cuda.synchronize()
     r = rew.cpu().numpy()[0]
-    d = done.cpu().numpy()[0]
-    assert (r[:200] == 7.0).all() and (d[:200] == 9).all()
-    assert (d[200:] != 9).all()
+    d_ = done.cpu().numpy()[0]
+    assert (r[180:200] == 7.0).all() and (d_[180:200] == 9).all()
+    assert (d_[:180] != 9).all() and (d_[200:] != 9).all()
+    # the state of a group on scattered slots reads back in its envs' order
+    st = pool.get_state(e[1])
+    assert len(st) == 120 and (st["t"] == 1).all()
     pool.close()
 
 
@@ -124,3 +130,30 @@ def test_groups_in_the_mix_match_groups_alone(depth, wrappers, profile, edges):
         assert np.array_equal(r.final_obs, oo)
         compare_states(r.final_state, orc.get_state(), f"group {g.gid} vs oracle")
         orc.close()
+
+
+def test_full_size_serving_sampled_groups_match_alone():
+    """The serving workload at full size: 2,000 groups over 32 ROMs, sizes
+    log-uniform in 1..4,096, 200-2,000 steps, Poisson arrivals, on a pool of
+    65,536 slots.  Eight groups spread over the sizes are recorded in the mix
+    and replayed alone; all their rewards, done flags, last observations and
+    final states agree."""
+    from paper_2510_01764_amd import octax as X
+    from paper_2510_01764_amd import serving as S
+    from paper_2510_01764_amd import workload as W
+    spec = W.make_config("c4")
+    groups = W.serving_groups(2000, rate=180.0, seed=3)
+    by_size = sorted(groups, key=lambda g: g.size)
+    sample = {by_size[int(q * (len(by_size) - 1))].gid for q in (0.0, 0.2, 0.4, 0.6, 0.8, 0.9, 0.97, 1.0)}
+    be = S.PoolBackend(spec, pool_bytes=65536 * X.Pool.slot_bytes(), depth=2)
+    out = S.serve(spec, groups, be, record=sample)
+    be.close()
+    runs = {r.group.gid: r for r in out["runs"]}
+    for gid in sorted(sample):
+        r = runs[gid]
+        g = r.group
+        rew, done, obs, state = _alone(spec, g)
+        assert np.array_equal(r.rewards, rew), f"group {gid} ({g.size} envs): rewards differ"
+        assert np.array_equal(r.dones, done), f"group {gid}: done flags differ"
+        assert np.array_equal(r.final_obs, obs), f"group {gid}: last observation differs"
+        compare_gpu_states(r.final_state, state, f"group {gid} in the pool vs alone")

@@ -1,9 +1,10 @@
 """Host logic of the serving loop, on the CPU with a stand-in backend.
 
-The stand-in keeps the pool's contract (first-fit contiguous slot ranges of a
-fixed capacity, admission refused when no range fits, one result vector per
-tick indexed by slot) and reports, as each slot's reward, the tick number and
-the slot, so the tests can check which group stepped where and when.
+The stand-in keeps the pool's contract (a group takes the lowest-numbered
+free slots of a fixed capacity, admission refused when too few are free, one
+result vector per tick indexed by slot) and reports, as each slot's reward,
+the tick number and the slot, so the tests can check which group stepped
+where and when.
 """
 import numpy as np
 import pytest
@@ -18,8 +19,8 @@ class FakeBackend:
         self.depth = depth
         self.rows = rows
         self.sched = np.zeros((rows, capacity), dtype=np.int32)
-        self.free = [(0, capacity)]        # sorted (first, length)
         self.groups = {}
+        self.next_id = 0
         self.occupied = np.zeros(capacity, dtype=np.int32)
         self.ticks = []                     # per tick: copy of the occupied map
         self.n = 0
@@ -27,31 +28,19 @@ class FakeBackend:
         self.max_used = 0
 
     def admit(self, rom, seeds, horizons):
-        count = len(seeds)
-        for i, (f, ln) in enumerate(self.free):
-            if ln >= count:
-                self.free[i] = (f + count, ln - count)
-                if self.free[i][1] == 0:
-                    del self.free[i]
-                self.groups[f] = count
-                assert not self.occupied[f:f + count].any()
-                self.occupied[f:f + count] = 1
-                self.max_used = max(self.max_used, int(self.occupied.sum()))
-                return f
-        return None
+        free = np.flatnonzero(self.occupied == 0)
+        if len(free) < len(seeds):
+            return None
+        slots = free[:len(seeds)].astype(np.uint32)
+        self.occupied[slots] = 1
+        self.max_used = max(self.max_used, int(self.occupied.sum()))
+        gid = self.next_id
+        self.next_id += 1
+        self.groups[gid] = slots
+        return gid, slots
 
-    def retire(self, first):
-        count = self.groups.pop(first)
-        self.occupied[first:first + count] = 0
-        self.free.append((first, count))
-        self.free.sort()
-        merged = []
-        for f, ln in self.free:
-            if merged and merged[-1][0] + merged[-1][1] == f:
-                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
-            else:
-                merged.append((f, ln))
-        self.free = merged
+    def retire(self, gid):
+        self.occupied[self.groups.pop(gid)] = 0
 
     def schedule(self):
         return self.sched
@@ -70,11 +59,11 @@ class FakeBackend:
     def finish(self):
         pass
 
-    def obs_of(self, first, count):
-        return np.zeros((count, 4, 64, 32), dtype=np.uint8)
+    def obs_of(self, slots):
+        return np.zeros((len(slots), 4, 64, 32), dtype=np.uint8)
 
-    def state_of(self, first, count):
-        return np.zeros(count)
+    def state_of(self, slots):
+        return np.zeros(len(slots))
 
 
 class FakeClock:
@@ -113,12 +102,12 @@ def test_every_group_runs_exactly_its_steps_in_its_own_slots(depth):
         ticks = (r.rewards[:, 0] // 1000).astype(int)
         slots = (r.rewards % 1000).astype(int)
         assert np.all(np.diff(ticks) == 1), "a resident group steps in every tick"
-        assert np.all(slots == r.first + np.arange(g.size)[None, :])
+        assert np.all(slots == r.slots[None, :].astype(int))
         # the actions sent in those ticks are the group's own stream
         for k in sorted({0, 63, 64, 65, g.steps // 2, g.steps - 1}):
             if k >= g.steps:
                 continue
-            sent = be.acts[ticks[k]][r.first:r.first + g.size]
+            sent = be.acts[ticks[k]][r.slots]
             assert np.array_equal(sent, W.group_actions(g, k, 1, int(spec.num_actions[g.rom]))[0])
     assert be.max_used <= be.capacity
     assert not be.groups, "every group was retired"
@@ -165,3 +154,35 @@ def test_group_generators_are_slot_independent_and_windowed():
     assert np.array_equal(W.group_env_seeds(g), W.group_env_seeds(g))
     h = W.group_horizons(g)
     assert h.dtype == np.uint32 and (h >= 1).all()
+
+
+def test_a_group_takes_free_slots_wherever_they_are():
+    """Free slots never fragment: a group larger than any run of free slots is
+    admitted as soon as enough slots are free in total."""
+    spec = W.make_config("c4")
+    gs = [W.Group(0, 0.0, 1, 300, 40, 5), W.Group(1, 0.0, 2, 300, 10, 6), W.Group(2, 0.0, 3, 100, 40, 7),
+          W.Group(3, 0.002, 4, 350, 10, 8)]
+    be = FakeBackend(capacity=750, depth=2)
+    clk = FakeClock()
+    out = S.serve(spec, gs, be, record={3}, clock=clk, sleep=clk.sleep)
+    r0, r1, r2, r3 = out["runs"]
+    # group 3 (350 envs) fits once group 1 (300) leaves: slots 300..599 and 700..749
+    assert r1.t_done <= r3.t_admit < r0.t_done
+    assert len(np.flatnonzero(np.diff(r3.slots.astype(int)) != 1)) == 1      # two runs of slots
+    assert r3.rewards is not None and r0.rewards is None   # only the sampled group is recorded
+    assert be.max_used <= 750
+
+
+def test_recorded_sample_sees_its_own_slots():
+    spec = W.make_config("c4")
+    groups = _groups(30, rate=400.0, steps=(5, 90))
+    be = FakeBackend(capacity=500, depth=2)
+    clk = FakeClock()
+    sample = {g.gid for g in groups[::7]}
+    out = S.serve(spec, groups, be, record=sample, clock=clk, sleep=clk.sleep)
+    for r in out["runs"]:
+        if r.group.gid in sample:
+            slots = (r.rewards % 1000).astype(int)
+            assert np.all(slots == r.slots[None, :].astype(int))
+        else:
+            assert r.rewards is None
