@@ -54,7 +54,6 @@ struct Shared {
     uint32_t stage[IPW / 64][kStageEnvs][kStageStride];
     float rew[IPW];           // reward and done bits of the step just emulated, for the writer waves
     uint8_t done[IPW];
-    uint8_t key[2][IPW];      // held key of step k (slot k & 1), staged by the writer waves
     uint8_t lready[IPW];      // per-lane progress (variants with reset steps): steps published, mod 256
     uint8_t ltaken[IPW];      // displays taken, mod 256
     uint32_t ready[IPW / 64]; // steps emulated by emulator wave w
@@ -592,6 +591,20 @@ __device__ __forceinline__ void store_frame(uint8_t *frame, uint32_t lane64, uin
     store16(frame + 1024 + 16 * lane64, w >> 16);
 }
 
+// Lane l's share of two consecutive expanded frames, one 4 KB piece of an
+// observation: bytes [16l, 16l+16) and [1024+16l, ...) of each frame.
+__device__ __forceinline__ void store_pair(uint8_t *o, uint32_t lane64, u32x4 a0, u32x4 a1, u32x4 b0, u32x4 b1) {
+    store_obs(o + 16 * lane64, a0);
+    store_obs(o + 1024 + 16 * lane64, a1);
+    store_obs(o + 2048 + 16 * lane64, b0);
+    store_obs(o + 3072 + 16 * lane64, b1);
+}
+
+// Envs per round of the writers' cooperative pass: the staging area of a
+// wave holds kStageEnvs packed frames, the frames of steps k - 1 and k of
+// each env of the round.
+constexpr uint32_t kPairEnvs = kStageEnvs / 2;
+
 // Wave roles.  A block runs IPW envs with 2 * IPW threads: waves
 // 0 .. IPW/64 - 1 emulate (one env per lane, thread l is env l) and waves
 // IPW/64 .. 2 * IPW/64 - 1 write observations (thread IPW + l serves env l).
@@ -675,10 +688,9 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
         const uint32_t word = (ua & 8) ? ((ua & 4) ? keys.w : keys.z) : ((ua & 4) ? keys.y : keys.x);
         return (ua < nact) ? (__builtin_amdgcn_ubfe(word, (ua & 3) * 8, 8) & 15) : kKeyNone;
     };
-    // Writers keep the held keys of 64 consecutive steps in registers, one
-    // byte each, loaded 64 steps at a time: on CDNA a wave's loads complete
-    // in order with its stores, so each load batch waits for every
-    // observation store issued before it, once per 64 steps.
+    // Emulator lanes keep the held keys of 64 consecutive steps in
+    // registers, one byte each, loaded 64 steps at a time (the loads of a
+    // batch go out together: one round trip per 64 steps).
     u32x16 kp = {};
     auto load_keys = [&](uint32_t k0) {
 #pragma unroll
@@ -687,7 +699,8 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
 #pragma unroll
             for (int b = 0; b < 4; b++) {
                 const uint32_t kk = k0 + 4 * w + b;
-                const int32_t a = kk < K ? io.action[(size_t)kk * E + env] : -1;
+                const int32_t *row = io.action + (size_t)kk * E;   // wave-uniform row base
+                const int32_t a = kk < K ? row[env] : -1;
                 word |= held_key(a) << (8 * b);
             }
             kp[w] = word;
@@ -696,12 +709,8 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     auto key_of_step = [&](uint32_t kk) -> uint32_t {
         return __builtin_amdgcn_ubfe(kp[(kk >> 2) & 15], (kk & 3) * 8, 8);
     };
-    if (!emu && active) {
-        load_keys(0);
-        sh.key[0][l] = (uint8_t)key_of_step(0);
-        sh.key[1][l] = (uint8_t)key_of_step(1);
-    }
     if (emu && active) {
+        load_keys(0);
         load_core(s, slot, c, head);
         t = s.t[slot];
         hor = s.horizon[slot];
@@ -737,10 +746,26 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
         return io.obs + (size_t)(kk % io.obs_slots) * obs_step + (size_t)e * kObsBytes;
     };
 
-    // Writers, prologue: the three frames before this launch go into the
-    // observations of steps 0..2 (frame f of step k is the frame of step
+    // Writers, prologue: the three frames before this launch fill the lower
+    // halves of observations 0 and 1 (frame f of step k is the frame of step
     // k - 3 + f).  All loads of a chunk of envs are issued before its stores.
+    // Each writer lane also loads its own env's packed frame of step -1, the
+    // first of the pair that step 0 stores.
+    uint32_t pa[64], pb[64];   // packed frames of the current and the previous step
+#pragma unroll
+    for (int q = 0; q < 64; q++) pb[q] = 0;
     if (!emu && io.obs) {
+        if (active) {
+            const uint4 *r4 = reinterpret_cast<const uint4 *>(s.cols + (size_t)slot * 256 + head * 64);
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const uint4 v = r4[q];
+                pb[4 * q] = v.x;
+                pb[4 * q + 1] = v.y;
+                pb[4 * q + 2] = v.z;
+                pb[4 * q + 3] = v.w;
+            }
+        }
         for (uint32_t j0 = 0; j0 < nj; j0 += kPrologueEnvs) {
             uint32_t w[kPrologueEnvs][3];
 #pragma unroll
@@ -758,14 +783,11 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 if (j >= nj) break;
                 if (!__builtin_amdgcn_readlane(live, j)) continue;
                 const uint32_t je = __builtin_amdgcn_readlane(env, j);
-#pragma unroll
-                for (int back = 0; back < 3; back++) {          // frame of step -1 - back
-#pragma unroll
-                    for (int kk = 0; kk < 3 - back; kk++) {      // lands in step kk as frame 2 - back - kk
-                        if ((uint32_t)kk < K)
-                            store_frame(obs_of(kk, je) + (2 - back - kk) * 2048, lane64, w[jj][back]);
-                    }
-                }
+                const u32x4 m1a = spread16(w[jj][0]), m1b = spread16(w[jj][0] >> 16);
+                const u32x4 m2a = spread16(w[jj][1]), m2b = spread16(w[jj][1] >> 16);
+                const u32x4 m3a = spread16(w[jj][2]), m3b = spread16(w[jj][2] >> 16);
+                store_pair(obs_of(0, je), lane64, m3a, m3b, m2a, m2b);                 // steps -3, -2
+                if (K > 1) store_pair(obs_of(1, je), lane64, m2a, m2b, m1a, m1b);      // steps -2, -1
             }
         }
     }
@@ -792,6 +814,26 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                       {stack_in[0].x, stack_in[0].y, stack_in[0].z, stack_in[0].w,
                        stack_in[1].x, stack_in[1].y, stack_in[1].z, stack_in[1].w}, 0u};
     mem.top = mem.stack_get((c.sp - 1) & 15);
+    // End of an emulator wave: the state goes back to HBM once per launch.
+    // (Called at the end of each emulator loop, so that none of the
+    // emulator's registers stay live in the writer waves' loops.)
+    auto emu_epilogue = [&]() {
+        if (!active) return;
+        mem.flush();
+        store_core(s, slot, c, head);
+        s.t[slot] = t;
+        s.prev[slot] = prev;
+        s.dirty[slot] = mem.dirty;
+        uint4 *fb4 = reinterpret_cast<uint4 *>(s.fb + (size_t)slot * 32);
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const uint64_t a = sh.fb[l][2 * q], b = sh.fb[l][2 * q + 1];
+            fb4[q] = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+        }
+        uint4 *st4 = reinterpret_cast<uint4 *>(s.stack + (size_t)slot * 8);
+        st4[0] = make_uint4(mem.stk[0], mem.stk[1], mem.stk[2], mem.stk[3]);
+        st4[1] = make_uint4(mem.stk[4], mem.stk[5], mem.stk[6], mem.stk[7]);
+    };
     if constexpr (kResetSteps) {
         // Per-lane progress (variants whose resets run emulation steps).  A
         // reset here runs a ROM's start-up sequence and up to noop_max no-op
@@ -813,6 +855,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             uint32_t k = 0;          // the step this lane emulates next
             uint32_t phase = 0;      // 0: a step; 1: start-up steps of a reset; 2: its no-op steps
             uint32_t si = 0, left = 0;
+            uint32_t kblock = 0;     // first step of the loaded key batch
             float pend_rew = 0.f;
             uint32_t pend_done = 0;
             const uint8_t *su = roms.w.startup ? roms.w.startup + (size_t)rom * 17 : nullptr;
@@ -842,7 +885,13 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 uint32_t pub_done = 0;
                 if (run) {
                     uint32_t key = kKeyNone;
-                    if (phase == 0) key = sticky_key(roms, c, sh.key[k & 1][l]);
+                    if (phase == 0) {
+                        if ((k & 63) == 0 && k != kblock) {
+                            load_keys(k);
+                            kblock = k;
+                        }
+                        key = sticky_key(roms, c, key_of_step(k));
+                    }
                     else if (phase == 1) key = su[1 + si];
                     run_frames<kProfile>(c, mem, key, io.ipf, io.frame_skip, quirks);
                     if (phase == 0) {
@@ -903,6 +952,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                     k += 1;
                 }
             }
+            emu_epilogue();
         } else {
             uint32_t kw = 0;         // steps whose display this lane has taken
             bool waiting = false;
@@ -929,73 +979,69 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 if (have) {
                     done = sh.done[l];
                     const float wrew = sh.rew[l];
-                    if (kw + 2 < K) {
-                        if (((kw + 2) & 63) == 0) load_keys(kw + 2);
-                        sh.key[kw & 1][l] = (uint8_t)key_of_step(kw + 2);
-                    }
                     set_lane_flag(&sh.ltaken[l], kw + 1);
                     io.reward[(size_t)kw * E + env] = wrew;
                     io.done[(size_t)kw * E + env] = (uint8_t)done;
                     head = done ? 0u : (head + 1) & 3;
                 }
-                uint32_t pw[64];
                 rows_to_cols(hi, lo);
-                pack_frame(hi, lo, pw);
-                // the lanes with a new frame, four per round (rank: place among them)
+                pack_frame(hi, lo, pa);
+                // the lanes with a new frame, two per round (rank: place among
+                // them); each stages its frames of steps kw - 1 and kw and
+                // goes out as in the lockstep pass, into its own steps'
+                // observations
                 const uint64_t hmask = __builtin_amdgcn_ballot_w64(have);
                 const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(hmask >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)hmask, 0u));
                 uint64_t rem = hmask;
-                for (uint32_t r0 = 0; rem; r0 += kStageEnvs) {
-                    if (have && rank - r0 < kStageEnvs) {
-                        uint4 *stg = reinterpret_cast<uint4 *>(sh.stage[wave][rank - r0]);
+                for (uint32_t r0 = 0; rem; r0 += kPairEnvs) {
+                    if (have && rank - r0 < kPairEnvs) {
+                        uint4 *stp = reinterpret_cast<uint4 *>(sh.stage[wave][2 * (rank - r0)]);
+                        uint4 *stc = reinterpret_cast<uint4 *>(sh.stage[wave][2 * (rank - r0) + 1]);
 #pragma unroll
-                        for (int q = 0; q < 16; q++)
-                            stg[q] = make_uint4(pw[4 * q], pw[4 * q + 1], pw[4 * q + 2], pw[4 * q + 3]);
+                        for (int q = 0; q < 16; q++) {
+                            stp[q] = make_uint4(pb[4 * q], pb[4 * q + 1], pb[4 * q + 2], pb[4 * q + 3]);
+                            stc[q] = make_uint4(pa[4 * q], pa[4 * q + 1], pa[4 * q + 2], pa[4 * q + 3]);
+                        }
                     }
                     wave_sync();
 #pragma unroll
-                    for (uint32_t jj = 0; jj < kStageEnvs; jj++) {
+                    for (uint32_t jj = 0; jj < kPairEnvs; jj++) {
                         if (!rem) break;
                         const uint32_t j = (uint32_t)__builtin_ctzll(rem);
                         rem &= rem - 1;
-                        const uint32_t w = sh.stage[wave][jj][lane64];
                         const uint32_t kj = __builtin_amdgcn_readlane(kw, j);
                         const uint32_t je = __builtin_amdgcn_readlane(env, j);
                         const uint32_t jdone = __builtin_amdgcn_readlane(done, j);
+                        const uint32_t cw = sh.stage[wave][2 * jj + 1][lane64];
+                        // the frames before a reset belong to the old episode
+                        const uint32_t pv = jdone ? cw : sh.stage[wave][2 * jj][lane64];
                         if (io.obs) {
-                            const u32x4 x0 = spread16(w), x1 = spread16(w >> 16);
-                            // frame 3 - d of observation kj + d
-#pragma unroll
-                            for (uint32_t d = 0; d < 4; d++) {
-                                if (kj + d < K) {
-                                    uint8_t *o = obs_of(kj + d, je) + (3 - d) * 2048;
-                                    store_obs(o + 16 * lane64, x0);
-                                    store_obs(o + 1024 + 16 * lane64, x1);
-                                }
-                            }
+                            const u32x4 p0 = spread16(pv), p1 = spread16(pv >> 16);
+                            const u32x4 c0 = spread16(cw), c1 = spread16(cw >> 16);
+                            store_pair(obs_of(kj, je) + 4096, lane64, p0, p1, c0, c1);
+                            if (kj + 2 < K) store_pair(obs_of(kj + 2, je), lane64, p0, p1, c0, c1);
                             if (jdone) {
-                                // the frames before the reset belong to the old episode
-#pragma unroll
-                                for (uint32_t d = 0; d < 3; d++)
-#pragma unroll
-                                    for (uint32_t f = 0; f < 3 - d; f++)
-                                        if (kj + d < K) store_frame(obs_of(kj + d, je) + f * 2048, lane64, w);
+                                store_pair(obs_of(kj, je), lane64, c0, c1, c0, c1);
+                                if (kj + 1 < K) store_pair(obs_of(kj + 1, je), lane64, c0, c1, c0, c1);
                             }
                         }
                         if (kj + 4 >= K) {
                             const uint32_t jh = __builtin_amdgcn_readlane(head, j);
                             uint32_t *ring = s.cols + (size_t)(wave_slot0 + j) * 256 + lane64;
-                            ring[jh * 64] = w;
+                            ring[jh * 64] = cw;
                             if (jdone) {
-                                ring[((jh + 1) & 3) * 64] = w;
-                                ring[((jh + 2) & 3) * 64] = w;
-                                ring[((jh + 3) & 3) * 64] = w;
+                                ring[((jh + 1) & 3) * 64] = cw;
+                                ring[((jh + 2) & 3) * 64] = cw;
+                                ring[((jh + 3) & 3) * 64] = cw;
                             }
                         }
                     }
                     wave_sync();
                 }
+                // this lane's frame of its step kw is the first of its next pair
+#pragma unroll
+                for (int q = 0; q < 64; q++) pb[q] = have ? pa[q] : pb[q];
                 kw += have ? 1u : 0u;
             }
         }
@@ -1005,7 +1051,8 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             if (k > 0) wait_flag(&sh.taken[wave], k, cfg.wait_ticks, cfg.err);
             stamp(k, 0);
             if (active) {
-                const uint32_t key = sticky_key(roms, c, sh.key[k & 1][l]);
+                if (k > 0 && (k & 63) == 0) load_keys(k);
+                const uint32_t key = sticky_key(roms, c, key_of_step(k));
                 run_frames<kProfile>(c, mem, key, io.ipf, io.frame_skip, quirks);
                 const int32_t score = score_of(c.r, desc, desc2);
                 const float reward = (float)(score - prev);
@@ -1036,11 +1083,15 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             }
             set_flag(&sh.ready[wave], k + 1);
         }
+        emu_epilogue();
     } else {
-        for (uint32_t k = 0; k < K; k++) {
-            // Copy the display, reward and done bits of step k once final,
-            // stage the held key of step k + 2 in the key slot step k has
-            // finished with, and let the emulator go on.
+        // Each step k stores two 4 KB pieces per env: frames k - 1 and k are
+        // the upper half of observation k and the lower half of observation
+        // k + 2.  The packed frame of step k - 1 stays in registers; the two
+        // arrays trade roles from one step to the next.
+        auto wstep = [&](uint32_t k, uint32_t (&pw)[64], const uint32_t (&pp)[64]) __attribute__((always_inline)) {
+            // Copy the display, reward and done bits of step k once final
+            // and let the emulator go on.
             wait_flag(&sh.ready[wave], k + 1, cfg.wait_ticks, cfg.err);
             uint32_t hi[32], lo[32];
 #pragma unroll
@@ -1051,10 +1102,6 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             }
             const uint32_t done = active ? sh.done[l] : 0u;
             const float wrew = sh.rew[l];
-            if (active && k + 2 < K) {
-                if (((k + 2) & 63) == 0) load_keys(k + 2);
-                sh.key[k & 1][l] = (uint8_t)key_of_step(k + 2);
-            }
             set_flag(&sh.taken[wave], k + 1);
             const bool ring_step = k + 4 >= K;
             if (active) {
@@ -1064,120 +1111,97 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             head = done ? 0u : (head + 1) & 3;
             if (!(io.obs || ring_step)) {
                 stamp(k, 1);
-                continue;
+                return;
             }
-            uint32_t pw[64];
             rows_to_cols(hi, lo);
             pack_frame(hi, lo, pw);
-            // frame 3 - d of observation k + d, at env 0
-            uint8_t *obs_slot[4];
+            // observations k (upper half), k + 2 (lower half) and, after a
+            // reset, k and k + 1 (lower half), at env 0
+            uint8_t *const o_k = io.obs ? obs_of(k, 0) : nullptr;
+            uint8_t *const o_k1 = io.obs ? obs_of(k + 1, 0) : nullptr;
+            uint8_t *const o_k2 = io.obs ? obs_of(k + 2, 0) : nullptr;
+            // Cooperative pass, two envs per round: stage their packed
+            // frames of steps k - 1 and k, then each lane expands its 16 + 16
+            // pixels of the four frames into bytes and the round's pieces go
+            // out, observation k before observation k + 2.  The env's
+            // observation base is wave-uniform, so a store is one scalar add
+            // and the store itself.
+            for (uint32_t r0 = 0; r0 < nj; r0 += kPairEnvs) {
+                if (active && lane64 - r0 < kPairEnvs) {
+                    uint4 *stp = reinterpret_cast<uint4 *>(sh.stage[wave][2 * (lane64 - r0)]);
+                    uint4 *stc = reinterpret_cast<uint4 *>(sh.stage[wave][2 * (lane64 - r0) + 1]);
 #pragma unroll
-            for (uint32_t d = 0; d < 4; d++)
-                obs_slot[d] = io.obs ? obs_of(k + d, 0) + (3 - d) * 2048 : nullptr;
-            // Cooperative pass, a few envs per round: stage their packed frames,
-            // then for each env store its frame into every observation it
-            // belongs to and keep the last four frames of the launch in the
-            // env's ring.
-            constexpr uint32_t kStage = kStageEnvs;
-            static_assert(kStage == 4 || kStage == 8, "rounds of four or eight envs");
-            for (uint32_t r0 = 0; r0 < nj; r0 += kStage) {
-                if (active && lane64 - r0 < kStage) {
-                    uint4 *stg = reinterpret_cast<uint4 *>(sh.stage[wave][lane64 - r0]);
-#pragma unroll
-                    for (int q = 0; q < 16; q++)
-                        stg[q] = make_uint4(pw[4 * q], pw[4 * q + 1], pw[4 * q + 2], pw[4 * q + 3]);
+                    for (int q = 0; q < 16; q++) {
+                        stp[q] = make_uint4(pp[4 * q], pp[4 * q + 1], pp[4 * q + 2], pp[4 * q + 3]);
+                        stc[q] = make_uint4(pw[4 * q], pw[4 * q + 1], pw[4 * q + 2], pw[4 * q + 3]);
+                    }
                 }
                 wave_sync();
-                const uint32_t r1 = min(r0 + kStage, nj);
-                if (io.obs) {
-                    // Each lane expands its 16 + 16 pixels of every staged
-                    // frame into bytes once, then the round's frames go into
-                    // observation k + d of every env of the round before
-                    // observation k + d + 1 (2 KB pieces 8 KB apart in one
-                    // region at a time).  The env's observation base is
-                    // wave-uniform, so a store is one scalar add and the
-                    // store itself.
-                    u32x4 x0[kStage], x1[kStage];
-                    uint64_t eo[kStage];   // observation offset of env r0 + jj
+                const uint32_t n = __builtin_amdgcn_readfirstlane(min(r0 + kPairEnvs, nj) - r0);
+                // slots of the round that hold a live env (wave-uniform)
+                const uint32_t rmask = (uint32_t)(live_bits >> r0) & ((1u << n) - 1);
+                uint32_t cw[kPairEnvs], pv[kPairEnvs], jdone[kPairEnvs];
 #pragma unroll
-                    for (uint32_t jj = 0; jj < kStage; jj++) {
-                        const uint32_t w = sh.stage[wave][jj][lane64];
-                        x0[jj] = spread16(w);
-                        x1[jj] = spread16(w >> 16);
+                for (uint32_t jj = 0; jj < kPairEnvs; jj++) {
+                    cw[jj] = sh.stage[wave][2 * jj + 1][lane64];
+                    jdone[jj] = __builtin_amdgcn_readlane(done, r0 + jj);
+                    // the frames before a reset belong to the old episode:
+                    // the stack restarts with the display after the reset
+                    pv[jj] = jdone[jj] ? cw[jj] : sh.stage[wave][2 * jj][lane64];
+                }
+                if (io.obs) {
+                    u32x4 xp0[kPairEnvs], xp1[kPairEnvs], xc0[kPairEnvs], xc1[kPairEnvs];
+                    uint64_t eo[kPairEnvs];   // observation offset of env r0 + jj
+#pragma unroll
+                    for (uint32_t jj = 0; jj < kPairEnvs; jj++) {
+                        xp0[jj] = spread16(pv[jj]);
+                        xp1[jj] = spread16(pv[jj] >> 16);
+                        xc0[jj] = spread16(cw[jj]);
+                        xc1[jj] = spread16(cw[jj] >> 16);
                         eo[jj] = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(env, r0 + jj) * kObsBytes;
                     }
-                    // slots of the round that hold a live env (wave-uniform)
-                    const uint32_t rmask = (uint32_t)(live_bits >> r0) &
-                                           (__builtin_amdgcn_readfirstlane(r1 - r0) >= kStage
-                                                ? (1u << kStage) - 1
-                                                : (1u << __builtin_amdgcn_readfirstlane(r1 - r0)) - 1);
-                    const bool full = rmask == (1u << kStage) - 1;
 #pragma unroll
-                    for (uint32_t d = 0; d < 4; d++) {
-                        if (k + d >= K) break;
+                    for (uint32_t jj = 0; jj < kPairEnvs; jj++)
+                        if ((rmask >> jj) & 1) store_pair(o_k + eo[jj] + 4096, lane64, xp0[jj], xp1[jj], xc0[jj], xc1[jj]);
+                    if (k + 2 < K) {
 #pragma unroll
-                        for (uint32_t jj = 0; jj < kStage; jj++) {
-                            if (full || ((rmask >> jj) & 1)) {
-                                uint8_t *o = obs_slot[d] + eo[jj];
-                                store_obs(o + 16 * lane64, x0[jj]);
-                                store_obs(o + 1024 + 16 * lane64, x1[jj]);
-                            }
+                        for (uint32_t jj = 0; jj < kPairEnvs; jj++)
+                            if ((rmask >> jj) & 1) store_pair(o_k2 + eo[jj], lane64, xp0[jj], xp1[jj], xc0[jj], xc1[jj]);
+                    }
+#pragma unroll
+                    for (uint32_t jj = 0; jj < kPairEnvs; jj++) {
+                        if (((rmask >> jj) & 1) && jdone[jj]) {
+                            store_pair(o_k + eo[jj], lane64, xc0[jj], xc1[jj], xc0[jj], xc1[jj]);
+                            if (k + 1 < K) store_pair(o_k1 + eo[jj], lane64, xc0[jj], xc1[jj], xc0[jj], xc1[jj]);
                         }
                     }
                 }
-                for (uint32_t j = r0; j < r1; j++) {
-                    if (!__builtin_amdgcn_readlane(live, j)) continue;
-                    const uint32_t w = sh.stage[wave][j - r0][lane64];
-                    const uint32_t jdone = __builtin_amdgcn_readlane(done, j);
-                    if (io.obs) {
-                        const uint32_t je = __builtin_amdgcn_readlane(env, j);
-                        if (jdone) {
-                            // the frames before the reset belong to the old episode:
-                            // the stack restarts with the display after the reset
+                // the last four frames of the launch stay in the ring; a
+                // reset fills the three slots before the new head with the
+                // display after the reset
+                if (ring_step) {
 #pragma unroll
-                            for (uint32_t d = 0; d < 3; d++)
-#pragma unroll
-                                for (uint32_t f = 0; f < 3 - d; f++)
-                                    if (k + d < K) store_frame(obs_of(k + d, je) + f * 2048, lane64, w);
-                        }
-                    }
-                    // the last four frames of the launch stay in the ring; a
-                    // reset fills the three slots before the new head with
-                    // the display after the reset
-                    if (ring_step) {
-                        const uint32_t jh = __builtin_amdgcn_readlane(head, j);
-                        uint32_t *ring = s.cols + (size_t)(wave_slot0 + j) * 256 + lane64;
-                        ring[jh * 64] = w;
-                        if (jdone) {
-                            ring[((jh + 1) & 3) * 64] = w;
-                            ring[((jh + 2) & 3) * 64] = w;
-                            ring[((jh + 3) & 3) * 64] = w;
+                    for (uint32_t jj = 0; jj < kPairEnvs; jj++) {
+                        if (!((rmask >> jj) & 1)) continue;
+                        const uint32_t jh = __builtin_amdgcn_readlane(head, r0 + jj);
+                        uint32_t *ring = s.cols + (size_t)(wave_slot0 + r0 + jj) * 256 + lane64;
+                        ring[jh * 64] = cw[jj];
+                        if (jdone[jj]) {
+                            ring[((jh + 1) & 3) * 64] = cw[jj];
+                            ring[((jh + 2) & 3) * 64] = cw[jj];
+                            ring[((jh + 3) & 3) * 64] = cw[jj];
                         }
                     }
                 }
                 wave_sync();
             }
             stamp(k, 1);
-        }
-    }
-    if (emu && active) mem.flush();
-    dirty = mem.dirty;
-    tags = mem.tags;
-
-    if (emu && active) {
-        store_core(s, slot, c, head);
-        s.t[slot] = t;
-        s.prev[slot] = prev;
-        s.dirty[slot] = dirty;
-        uint4 *fb4 = reinterpret_cast<uint4 *>(s.fb + (size_t)slot * 32);
+        };
+        for (uint32_t k = 0; k < K; k++) {
+            wstep(k, pa, pb);
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const uint64_t a = sh.fb[l][2 * q], b = sh.fb[l][2 * q + 1];
-            fb4[q] = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+            for (int q = 0; q < 64; q++) pb[q] = pa[q];
         }
-        uint4 *st4 = reinterpret_cast<uint4 *>(s.stack + (size_t)slot * 8);
-        st4[0] = make_uint4(mem.stk[0], mem.stk[1], mem.stk[2], mem.stk[3]);
-        st4[1] = make_uint4(mem.stk[4], mem.stk[5], mem.stk[6], mem.stk[7]);
     }
 }
 
