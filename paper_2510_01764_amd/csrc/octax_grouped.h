@@ -19,7 +19,11 @@
 //     branches.
 // The memory policy supplies fetch(pc, sp, ret) (instruction word at pc and
 // ret = stack[(sp - 1) & 15]) and stack_popped(sp) (called after a return
-// with the new SP) besides the operations listed in octax_core.h.
+// with the new SP) besides the operations listed in octax_core.h.  A policy
+// with kOneAccess also supplies access(), one call that performs the memory
+// access of DXYN, FX33, FX55 or FX65 for every lane that has one (all four
+// read at most sixteen bytes around I), used unless the pixel-wrap quirk is
+// on.
 #pragma once
 
 #include "octax_core.h"
@@ -62,18 +66,42 @@ __device__ __forceinline__ bool exec_grouped(Core &c, Mem &mem, uint32_t key, ui
     const bool isF = h == 0xF;
 
     // ---- memory, display, stack and random classes (read the old I and V) ----
-    if (h == 0xD) set_vf(c.r, mem.draw(vx & 63, vy & 31, c.I, n, (quirks & kQuirkPixelWrap) != 0));
-    if (isF & ((nn == 0x33) | (nn == 0x55))) {
-        // FX33: three BCD digits of VX; FX55: V0..VX (in memory order in the register vector)
-        const bool bcd = nn == 0x33;
-        const uint32_t digits = (vx / 100) | (((vx / 10) % 10) << 8) | ((vx % 10) << 16);
-        const u32x4 bytes = bcd ? u32x4{digits, 0, 0, 0} : c.r.w;
-        mem.store_bytes(c.I, bcd ? 3u : x + 1, bytes);
+    // FX33 stores three BCD digits of VX, FX55 V0..VX (in memory order in the
+    // register vector), FX65 loads V0..VX.
+    const bool st = isF & ((nn == 0x33) | (nn == 0x55));
+    const bool ld = isF & (nn == 0x65);
+    const bool bcd = nn == 0x33;
+    bool separate = true;
+    if constexpr (Mem::kOneAccess) {
+        if (!(quirks & kQuirkPixelWrap)) {
+            // one memory access per lane for DXYN, FX33, FX55 and FX65
+            separate = false;
+            const bool longw = __builtin_amdgcn_ballot_w64((h == 0xD) & (n > 8)) != 0;   // among the drawing lanes
+            if ((h == 0xD) | st | ld) {
+                const uint32_t digits = (vx / 100) | (((vx / 10) % 10) << 8) | ((vx % 10) << 16);
+                u32x4 data = bcd ? u32x4{digits, 0, 0, 0} : c.r.w;
+                const uint32_t count = (h == 0xD) ? n : (bcd ? 3u : x + 1);
+                const uint32_t hit = mem.access(h == 0xD, st, c.I, count, vx & 63, vy & 31, longw, data);
+                if (h == 0xD) set_vf(c.r, hit);
+                if (ld) {
+                    const u32x4 m = byte_mask(x + 1);
+                    c.r.w = (c.r.w & ~m) | (data & m);
+                }
+            }
+        }
     }
-    if (isF & (nn == 0x65)) {
-        const u32x4 b = mem.load_bytes(c.I, x + 1);
-        const u32x4 m = byte_mask(x + 1);
-        c.r.w = (c.r.w & ~m) | (b & m);
+    if (separate) {
+        if (h == 0xD) set_vf(c.r, mem.draw(vx & 63, vy & 31, c.I, n, (quirks & kQuirkPixelWrap) != 0));
+        if (st) {
+            const uint32_t digits = (vx / 100) | (((vx / 10) % 10) << 8) | ((vx % 10) << 16);
+            const u32x4 bytes = bcd ? u32x4{digits, 0, 0, 0} : c.r.w;
+            mem.store_bytes(c.I, bcd ? 3u : x + 1, bytes);
+        }
+        if (ld) {
+            const u32x4 b = mem.load_bytes(c.I, x + 1);
+            const u32x4 m = byte_mask(x + 1);
+            c.r.w = (c.r.w & ~m) | (b & m);
+        }
     }
     if (op == 0x00E0) mem.clear();
     if (h == 0x2) mem.stack_set(c.sp, pc2);

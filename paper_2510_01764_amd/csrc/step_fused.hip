@@ -107,6 +107,7 @@ struct FusedMem {
     uint32_t top;            // stack[(SP - 1) & 15]
     uint32_t vic = 0;        // slot replaced next
     static constexpr uint32_t kSlots = Shared<IPW>::kSlots;
+    static constexpr bool kOneAccess = true;   // access() serves DXYN, FX33, FX55 and FX65
 
     __device__ __forceinline__ lds_u8 *slot_ptr(uint32_t s) const {
         return (lds_u8 *)&sh.cache[lane][0] + 64 * s;
@@ -350,6 +351,89 @@ struct FusedMem {
         }
         tags |= (0x80u << (8 * s0)) | (0x80u << (8 * s1));
         dirty |= (1ull << p0) | (1ull << p1);
+    }
+    // Page p readable from LDS for a read, or held in a cache slot for a
+    // store (slow path): filled from the env's memory in HBM when written, else
+    // from the power-on image (the pool or HBM); slot `keep` is not reused.
+    // Returns the page's slot, or -1 for a page read from the pool.
+    __device__ __forceinline__ int32_t ensure(uint32_t p, int32_t keep, bool st) {
+        int32_t s = find(p);
+        bool in_pool;
+        (void)pool_off(p, in_pool);
+        if (s < 0 && is_dirty(p)) s = (int32_t)fill_from_ram(p, keep);
+        else if (s < 0 && (st || !in_pool)) s = (int32_t)fill_from_image(p, keep);
+        return s;
+    }
+    // The memory access of one instruction, for the lanes that have one:
+    // DXYN (dr: the sprite's rows drawn, the collision flag returned), FX65
+    // (count bytes at I returned in `data`) or FX33 / FX55 (st: count bytes
+    // of `data` stored at I).  Each reads at most sixteen bytes around I on
+    // at most two pages, so one page lookup, one slow path and one read of
+    // five aligned dwords serve all three; a store merges its bytes into the
+    // dwords read and writes them back.  A DXYN's dwords cover a window of
+    // display rows as in draw() (window row w: byte w of the run from I - sh0).
+    __device__ __forceinline__ uint32_t access(bool dr, bool st, uint32_t I, uint32_t count, uint32_t x0,
+                                               uint32_t y0, bool longw, u32x4 &data) {
+        const uint32_t cnt = dr ? min(count, 32 - y0) : count;
+        const uint32_t b = min(y0, longw ? 17u : 24u);
+        const uint32_t sh0 = dr ? y0 - b : 0u;          // window rows above the sprite
+        const uint32_t p0 = I >> 6, p1 = ((I + max(cnt, 1u) - 1) & 0xFFF) >> 6;
+        touch(p0);
+        touch(p1);
+        int32_t s0 = find(p0), s1 = find(p1);
+        bool in0, in1;
+        const uint32_t o0 = pool_off(p0, in0), o1 = pool_off(p1, in1);
+        // readable: cached, or clean and in the pool; a store needs the slot
+        const bool ok = ((s0 >= 0) | (!st & !is_dirty(p0) & in0)) & ((s1 >= 0) | (!st & !is_dirty(p1) & in1));
+        lds_u8 *pool = (lds_u8 *)&sh.pool[0][0];
+        lds_u8 *q0 = s0 >= 0 ? slot_ptr((uint32_t)s0) : pool + o0;
+        lds_u8 *q1 = s1 >= 0 ? slot_ptr((uint32_t)s1) : pool + o1;
+        if (!ok) {
+            s0 = ensure(p0, -1, st);
+            s1 = ensure(p1, s0, st);
+            q0 = s0 >= 0 ? slot_ptr((uint32_t)s0) : pool + o0;
+            q1 = s1 >= 0 ? slot_ptr((uint32_t)s1) : pool + o1;
+        }
+        const int32_t off = (int32_t)(I & 63) - (int32_t)sh0;
+        const int32_t w0 = off >> 2;
+        const uint32_t sb = (uint32_t)off & 3;
+        lds_u32 *ptr[5];
+        uint32_t d[5];
+#pragma unroll
+        for (int i = 0; i < 5; i++) {
+            const int32_t w = w0 + i;
+            ptr[i] = (lds_u32 *)((w < 16 ? q0 : q1 - 64) + 4 * w);
+            d[i] = *ptr[i];
+        }
+        u32x4 v;
+#pragma unroll
+        for (int i = 0; i < 4; i++) v[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sb);
+        uint64_t hit = 0;
+        if (st) {
+            // the data and its byte mask, one dword before and after: dword i
+            // of the window is dwords i and i + 1 of these shifted right by
+            // 4 - sb bytes
+            const u32x4 m = byte_mask(count);
+            const uint32_t x[6] = {0u, data[0], data[1], data[2], data[3], 0u};
+            const uint32_t mk[6] = {0u, m[0], m[1], m[2], m[3], 0u};
+#pragma unroll
+            for (int i = 0; i < 5; i++) {
+                const uint32_t val = sb ? __builtin_amdgcn_alignbyte(x[i + 1], x[i], 4 - sb) : x[i + 1];
+                const uint32_t msk = sb ? __builtin_amdgcn_alignbyte(mk[i + 1], mk[i], 4 - sb) : mk[i + 1];
+                *ptr[i] = (d[i] & ~msk) | (val & msk);
+            }
+            tags |= (0x80u << (8 * (uint32_t)s0)) | (0x80u << (8 * (uint32_t)s1));
+            dirty |= (1ull << p0) | (1ull << p1);
+        } else if (dr) {
+            const uint32_t vm = ((1u << cnt) - 1) << sh0;   // window rows of the sprite
+            lds_u64 *fbw = (lds_u64 *)&sh.fb[lane][0] + b;
+            if (vm & 0x000Fu) hit |= draw_rows<0, 4>(fbw, x0, vm, v);
+            if (vm & 0x00F0u) hit |= draw_rows<4, 4>(fbw, x0, vm, v);
+            if (longw && (vm & 0x7F00u)) hit |= draw_rows<8, 7>(fbw, x0, vm, v);
+        } else {
+            data = v;
+        }
+        return hit != 0;
     }
     // LDS base of page p, computed with selects only (see lds_byte).
     __device__ __forceinline__ lds_u8 *lds_page_sel(uint32_t p, bool &slow) const {
@@ -605,6 +689,19 @@ __device__ __forceinline__ void store_pair(uint8_t *o, uint32_t lane64, u32x4 a0
 // each env of the round.
 constexpr uint32_t kPairEnvs = kStageEnvs / 2;
 
+// The range of slots a block serves.  The hardware deals the blocks of a
+// launch to the eight XCDs in turn (block b to XCD b % 8); the mapping gives
+// each XCD one contiguous run of slot ranges, so the CUs of an XCD write
+// neighbouring observations (on MI355X the observation stores run about a
+// fifth faster than with consecutive ranges spread over the XCDs).  Any
+// grid size maps one to one.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+    constexpr uint32_t kXcds = 8;
+    const uint32_t x = b % kXcds, i = b / kXcds;
+    const uint32_t per = nb / kXcds, rem = nb % kXcds;
+    return x * per + min(x, rem) + i;
+}
+
 // Wave roles.  A block runs IPW envs with 2 * IPW threads: waves
 // 0 .. IPW/64 - 1 emulate (one env per lane, thread l is env l) and waves
 // IPW/64 .. 2 * IPW/64 - 1 write observations (thread IPW + l serves env l).
@@ -636,17 +733,18 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     const uint32_t lane64 = l & 63;
     const uint32_t wave = l >> 6;
     const uint32_t wave_base = l & ~63u;
-    const uint32_t slot = blockIdx.x * IPW + l;
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);   // slot range of this block
+    const uint32_t slot = blk * IPW + l;
     const uint32_t E = s.num;
     const uint32_t K = io.K;
     const bool active = slot_live(s, slot);
     // A block with no env (free range of a serving pool) has nothing to do:
     // the host marks it in the block's pool table (no ROM listed).
-    const uint32_t *ptab = cfg.block_roms + (size_t)blockIdx.x * kPoolRoms * 2;
+    const uint32_t *ptab = cfg.block_roms + (size_t)blk * kPoolRoms * 2;
     if (ptab[0] == kPoolEnd) return;
     const uint32_t live = active ? 1u : 0u;
     const uint64_t live_bits = __builtin_amdgcn_ballot_w64(active);   // live slots of this wave
-    const uint32_t wave_slot0 = blockIdx.x * IPW + wave_base;
+    const uint32_t wave_slot0 = blk * IPW + wave_base;
     const uint32_t nj = (E > wave_slot0) ? min(64u, E - wave_slot0) : 0u;   // slots of this wave
 
     // Fill the block's page pool (all threads): the zero page, memory pages 1

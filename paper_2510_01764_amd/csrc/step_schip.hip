@@ -71,6 +71,7 @@ struct SchipMem : PlainMem {
     }
     // The top of the stack is read from memory at every fetch: nothing to update.
     __device__ __forceinline__ void stack_popped(uint32_t) const {}
+    static constexpr bool kOneAccess = false;   // separate draw, load and store calls
     __device__ __forceinline__ u32x4 load_bytes(uint32_t a, uint32_t count) const {
         u32x4 v = {0, 0, 0, 0};
 #pragma unroll
