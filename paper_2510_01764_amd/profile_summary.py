@@ -99,7 +99,7 @@ def _pick(means, needle):
     return means[hits[0]]
 
 
-def traffic(fetch_dir, write_dir, out, calib_bytes, kernel, cmd_f, cmd_w):
+def traffic(fetch_dir, write_dir, out, calib_bytes, kernel, cmd_f, cmd_w, sources=None):
     sys.path.insert(0, ROOT)
     import bench
     f = _counter_means(fetch_dir, "FETCH_SIZE")
@@ -114,7 +114,8 @@ def traffic(fetch_dir, write_dir, out, calib_bytes, kernel, cmd_f, cmd_w):
     write_b = kw * 1024.0 * scale_w
     d = {
         "kernel": kernel,
-        "kernel_source_hash": bench.kernel_source_hash(),
+        "kernel_source_hash": source_hash(sources) if sources else bench.kernel_source_hash(),
+        **({"sources": sources} if sources else {}),
         "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw,
         "dispatches": [nf, nw],
         "calib_copy_bytes": calib_bytes,
@@ -229,6 +230,8 @@ def main():
     t.add_argument("--kernel", required=True)
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
+    t.add_argument("--sources", default=None,
+                   help="comma-separated csrc files the kernel is built from (default: the fused kernel's)")
     v = sub.add_parser("valu")
     v.add_argument("dir")
     v.add_argument("out")
@@ -254,7 +257,8 @@ def main():
     elif a.cmd == "lanes":
         lanes(a.dir, a.out, a.kernel, a.command)
     else:
-        traffic(a.fetch_dir, a.write_dir, a.out, a.calib_bytes, a.kernel, a.command_fetch, a.command_write)
+        traffic(a.fetch_dir, a.write_dir, a.out, a.calib_bytes, a.kernel, a.command_fetch, a.command_write,
+                a.sources.split(",") if a.sources else None)
 
 
 if __name__ == "__main__":
