@@ -280,7 +280,9 @@ def main():
     ap.add_argument("--tune", choices=["auto", "default"], default="auto")
     ap.add_argument("--sweep", default="",
                     help="comma-separated env counts: also time the fused kernel at each (the paper's scaling "
-                         "experiment), mixed-ROM workload, one observation slot")
+                         "experiment), one observation slot")
+    ap.add_argument("--sweep-workloads", default="mixed",
+                    help="comma-separated workloads of the sweep: mixed, single-const, draw-heavy")
     ap.add_argument("--serving-groups", type=int, default=2000,
                     help="groups of the serving run (0 = skip it)")
     ap.add_argument("--serving-loads", type=lambda t: [float(x) for x in t.split(",")], default=[0.4, 0.7, 0.9],
@@ -517,34 +519,43 @@ def main():
         engs.close()
 
     # the paper's scaling experiment: env steps/s against the number of envs
+    # (mixed: the benchmark recipe; single-const: one generated program with
+    # one action held throughout, the shape of the paper's own measurement;
+    # draw-heavy: 64 programs, 40 % DXYN of up to 15 rows, 20 instructions
+    # per frame)
     sweep = None
     if args.sweep:
         sweep = []
-        for Ew in (int(x) for x in args.sweep.split(",")):
-            wspec = W.make_config("c3", num_envs=Ew)
-            wact = torch.from_numpy(wspec.actions(0, K)).to(dev)
-            wobs = torch.empty((1, Ew, 4, 64, 32), dtype=torch.uint8, device=dev)
-            wrew = torch.empty((K, Ew), dtype=torch.float32, device=dev)
-            wdone = torch.empty((K, Ew), dtype=torch.uint8, device=dev)
-            ew = X.Engine(wspec, kernel="fused", placement="identity", stream=stream)
-            gw = ew.graph(wact, wobs, wrew, wdone)
-            with torch.cuda.stream(stream):
-                gw.launch()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                n_w = 6 if Ew <= 65536 else 3
-                for _ in range(n_w):
+        sweep_cfg = {"mixed": "c3", "single-const": "c2", "draw-heavy": "c5"}
+        for label in args.sweep_workloads.split(","):
+            for Ew in (int(x) for x in args.sweep.split(",")):
+                wspec = W.make_config(sweep_cfg[label], num_envs=Ew)
+                wact_np = wspec.actions(0, K)
+                if label == "single-const":
+                    wact_np[:] = 0
+                wact = torch.from_numpy(wact_np).to(dev)
+                wobs = torch.empty((1, Ew, 4, 64, 32), dtype=torch.uint8, device=dev)
+                wrew = torch.empty((K, Ew), dtype=torch.float32, device=dev)
+                wdone = torch.empty((K, Ew), dtype=torch.uint8, device=dev)
+                ew = X.Engine(wspec, kernel="fused", placement="identity", stream=stream)
+                gw = ew.graph(wact, wobs, wrew, wdone)
+                with torch.cuda.stream(stream):
                     gw.launch()
-                e1.record(stream)
-            stream.synchronize()
-            ms = e0.elapsed_time(e1) / n_w
-            gw.close()
-            ew.status()
-            ew.close()
-            sweep.append({"envs": Ew, "ms_per_launch": ms, "env_steps_per_s": Ew * K / ms * 1e3})
-            log(f"sweep: {Ew} envs {ms:.3f} ms per launch, {Ew * K / ms / 1e3:.1f} M env steps/s")
-            del wobs, wrew, wdone, wact
-            torch.cuda.empty_cache()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    n_w = 6 if Ew <= 65536 else 3
+                    for _ in range(n_w):
+                        gw.launch()
+                    e1.record(stream)
+                stream.synchronize()
+                ms = e0.elapsed_time(e1) / n_w
+                gw.close()
+                ew.status()
+                ew.close()
+                sweep.append({"workload": label, "envs": Ew, "ms_per_launch": ms, "env_steps_per_s": Ew * K / ms * 1e3})
+                log(f"sweep: {label} {Ew} envs {ms:.3f} ms per launch, {Ew * K / ms / 1e3:.1f} M env steps/s")
+                del wobs, wrew, wdone, wact
+                torch.cuda.empty_cache()
 
     serving = None
     if args.serving_groups > 0:
