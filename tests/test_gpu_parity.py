@@ -341,13 +341,16 @@ def test_single_rom_at_scale_full_run():
 
 def test_draw_heavy_full_size_sampled():
     """1,048,576 envs over 64 draw-heavy ROMs (40% DXYN, N up to 15 near the edges,
-    20 instructions per frame) in graph replays of K = 8; a sample of envs is
-    replayed on the oracle step by step (envs are independent)."""
+    20 instructions per frame) for the workload's full 1,000 steps, in graph
+    replays of K = 50; a sample of 207 envs is replayed on the oracle step by
+    step (envs are independent): every step's rewards and done flags, the last
+    observation of every replay and the final state."""
     import torch
     from oracle import oracle as O
     from paper_2510_01764_amd import octax as X
     spec = _spec("c5")
-    E, K = spec.num_envs, 8
+    E, K, S = spec.num_envs, 50, spec.steps
+    assert S % K == 0
     dev = torch.device("cuda")
     eng = X.Engine(spec, kernel="fused")
     act = torch.zeros((K, E), dtype=torch.int32, device=dev)
@@ -358,7 +361,8 @@ def test_draw_heavy_full_size_sampled():
     sample = np.random.default_rng(11).choice(E, size=200, replace=False)
     sample = np.concatenate([sample, [0, 1, 255, 256, E // 2, E - 2, E - 1]])
     orc = O.OracleBatch(spec.subset(sample))
-    for rep in range(2):
+    resets = 0
+    for rep in range(S // K):
         an = spec.actions(rep * K, K)
         act.copy_(torch.from_numpy(an))
         g.launch()
@@ -368,7 +372,9 @@ def test_draw_heavy_full_size_sampled():
         for k in range(K):
             oo, orw, od = orc.step(an[k][sample], want_obs=(k == K - 1))
             assert np.array_equal(r_np[k], orw) and np.array_equal(d_np[k], od), (rep, k)
+        resets += int((d_np != 0).sum())
         assert np.array_equal(obs[0, sample].cpu().numpy(), oo), rep
+    assert resets > 100, "episodes end and restart during the run"
     got = np.concatenate([eng.get_state(int(e), 1) for e in sample])
     compare_states(got, orc.get_state(), "c5 full-size sample")
     g.close()
