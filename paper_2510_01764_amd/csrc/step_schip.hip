@@ -45,10 +45,6 @@ __device__ __forceinline__ uint32_t double_bits(uint32_t b) {
     return x | (x << 1);
 }
 
-__device__ __forceinline__ u128 rotr128(u128 v, uint32_t s) {
-    return s ? (v >> s) | (v << (128 - s)) : v;
-}
-
 struct SchipMem : PlainMem {
     uint64_t *hd;      // [64][2] display rows
     const uint8_t *img;    // the ROM's power-on image
@@ -57,13 +53,34 @@ struct SchipMem : PlainMem {
 
     // Memory reads: a page not written since the reset equals the ROM's
     // power-on image, which all envs of the ROM share (it stays in cache);
-    // written pages come from the env's own memory.
-    __device__ __forceinline__ uint32_t rd(uint32_t a) const {
-        a &= 0xFFF;
-        const uint8_t *base = ((dirty >> (a >> 6)) & 1) ? ram : img;   // one load either way
-        return base[a];
+    // written pages come from the env's own memory.  Reads are aligned dwords
+    // (which never straddle a page) through global-memory pointers: a byte at
+    // a time, the scattered reads of 64 lanes are bound by the memory
+    // system's request rate.
+    __device__ __forceinline__ uint32_t rd4(uint32_t a) const {
+        typedef __attribute__((address_space(1))) const uint32_t glb_u32;
+        a &= 0xFFC;
+        const glb_u32 *base = (const glb_u32 *)(((dirty >> (a >> 6)) & 1) ? ram : img);
+        return base[a >> 2];
     }
-    __device__ __forceinline__ uint32_t fetch(uint32_t pc) const { return (rd(pc) << 8) | rd(pc + 1); }
+    // Bytes a .. a + 4*NW - 1 (12-bit wrap) as NW words, byte k at bits
+    // 8 (k % 4) of word k / 4: NW + 1 aligned dwords shifted into place.
+    template <int NW>
+    __device__ __forceinline__ void run(uint32_t a, uint32_t (&w)[NW]) const {
+        uint32_t d[NW + 1];
+#pragma unroll
+        for (int i = 0; i <= NW; i++) d[i] = rd4((a & ~3u) + 4 * i);
+#pragma unroll
+        for (int i = 0; i < NW; i++) w[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], a & 3);
+    }
+    // The instruction word at pc: one dword, and the next one only when pc is
+    // its last byte.
+    __device__ __forceinline__ uint32_t fetch(uint32_t pc) const {
+        const uint32_t d0 = rd4(pc);
+        const uint32_t d1 = (pc & 3) == 3 ? rd4(pc + 1) : 0u;
+        const uint32_t w = __builtin_amdgcn_alignbyte(d1, d0, pc & 3);
+        return ((w & 0xFF) << 8) | ((w >> 8) & 0xFF);
+    }
     // The grouped cycle's fetch: the word at pc and the top of the stack.
     __device__ __forceinline__ uint32_t fetch(uint32_t pc, uint32_t sp, uint32_t &ret) const {
         ret = stack_get((sp - 1) & 15);
@@ -72,12 +89,12 @@ struct SchipMem : PlainMem {
     // The top of the stack is read from memory at every fetch: nothing to update.
     __device__ __forceinline__ void stack_popped(uint32_t) const {}
     static constexpr bool kOneAccess = false;   // separate draw, load and store calls
+    // count (1..16) bytes from a; bytes past count are unspecified (the
+    // caller masks them).
     __device__ __forceinline__ u32x4 load_bytes(uint32_t a, uint32_t count) const {
-        u32x4 v = {0, 0, 0, 0};
-#pragma unroll
-        for (int k = 0; k < 16; k++)
-            if ((uint32_t)k < count) or_byte(v, k, rd(a + k));
-        return v;
+        uint32_t w[4];
+        run<4>(a, w);
+        return u32x4{w[0], w[1], w[2], w[3]};
     }
 
     // Row y as a 128-bit word, pixel x at bit 127 - x.
@@ -90,11 +107,20 @@ struct SchipMem : PlainMem {
     }
     __device__ __forceinline__ uint32_t scale() const { return hires ? 1u : 2u; }
 
-    // DXYN / DXY0 with the raw register values (see the header).  Memory
-    // bytes may alias the display for the compiler, so the loads are batched
-    // by hand: all sprite bytes first, then the display rows of four sprite
-    // rows at a time before any of their stores (the rows of one draw are
-    // distinct, so this order changes no result).
+    // DXYN / DXY0 with the raw register values (see the header).  A sprite
+    // row is at most 32 display pixels wide (16 pixels, doubled in the 64x32
+    // mode), so it lands in two neighbouring 32-pixel words of the 128-pixel
+    // row: word q = X / 32 shifted right by X % 32 and word q + 1 (mod 4 with
+    // wrap, dropped past the right edge without) the rest.  The words and
+    // shifts are the same for every row of the draw, so each display row
+    // costs two 32-bit shifts and two 32-bit read-XOR-writes.  In memory a
+    // row is two u64, pixels 0..63 then 64..127 with pixel x at bit
+    // 63 - (x mod 64), so pixel word q is dword q ^ 1 of the row.  The loads
+    // are batched by hand (memory bytes may alias the display for the
+    // compiler): all sprite bytes first, in one round of dword loads, then
+    // the two words of every sprite row's display rows before any of their
+    // stores (the rows of one draw are distinct, so this order changes no
+    // result).
     template <bool wrap>
     __device__ __forceinline__ uint32_t draw_s(uint32_t vx, uint32_t vy, uint32_t I, uint32_t n) {
         const uint32_t sc = scale();
@@ -102,68 +128,76 @@ struct SchipMem : PlainMem {
         const uint32_t x0 = vx & (W - 1), y0 = vy & (H - 1);
         const bool big = n == 0;
         const uint32_t h = big ? 16 : n;
-        const uint32_t pw = 16 * sc;   // physical width of a 16-pixel sprite row
         const uint32_t X = x0 * sc;
         // sprite rows drawn: all h when wrapping, else those above the bottom edge
         const uint32_t rows = wrap ? h : min(h, H - y0);
-        u128 hit = 0;
+        uint32_t sw[8];   // 32 bytes from I: a 16x16 sprite, two per row, high byte first; else one per row
+        run<8>(I, sw);
+        const uint32_t q = X >> 5, sh = X & 31;
+        const bool spill = sh != 0 && (wrap || q < 3);
+        const uint32_t d0 = q ^ 1, d1 = ((q + 1) & 3) ^ 1;
+        uint32_t *disp = reinterpret_cast<uint32_t *>(hd);
+        uint32_t hit = 0;
 #pragma unroll
-        for (int r0 = 0; r0 < 16; r0 += 4) {
-            if ((uint32_t)r0 >= rows) continue;   // (fully unrolled: the arrays stay in registers)
-            // this chunk's sprite bytes, then its display rows, then the stores
-            uint32_t bits[4];
-            u128 cur[4][2];
-            uint32_t y[4];
+        for (int r0 = 0; r0 < 16; r0 += 16) {
+            uint32_t lo[16], hi[16], y[16], o0[16][2], o1[16][2];
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const uint32_t r = r0 + i;
-                bits[i] = r < rows ? (big ? (rd(I + 2 * r) << 8) | rd(I + 2 * r + 1) : rd(I + r) << 8) : 0u;
+            for (int i = 0; i < 16; i++) {
+                const int r = r0 + i;
+                const uint32_t b0 = big ? __builtin_amdgcn_ubfe(sw[r >> 1], 16 * (r & 1), 8)
+                                        : __builtin_amdgcn_ubfe(sw[r >> 2], 8 * (r & 3), 8);
+                const uint32_t b1 = big ? __builtin_amdgcn_ubfe(sw[r >> 1], 16 * (r & 1) + 8, 8) : 0u;
+                const uint32_t bits = (uint32_t)r < rows ? (b0 << 8) | b1 : 0u;   // pixel 0 at bit 15
+                const uint32_t B = sc == 2 ? double_bits(bits) : bits << 16;       // pixel 0 at bit 31
+                lo[i] = B >> sh;
+                hi[i] = spill ? B << (32 - sh) : 0u;
                 uint32_t py = y0 + r;
                 py = py >= H ? py - H : py;
                 y[i] = py * sc;
 #pragma unroll
-                for (int d = 0; d < 2; d++)
-                    cur[i][d] = (r < rows && (uint32_t)d < sc) ? row(y[i] + d) : (u128)0;
+                for (int d = 0; d < 2; d++) {
+                    const bool on = (uint32_t)r < rows && (uint32_t)d < sc;
+                    o0[i][d] = on ? disp[4 * (y[i] + d) + d0] : 0u;
+                    o1[i][d] = on ? disp[4 * (y[i] + d) + d1] : 0u;
+                }
             }
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
+            for (int i = 0; i < 16; i++) {
                 if ((uint32_t)(r0 + i) >= rows) continue;
-                const uint32_t b = sc == 2 ? double_bits(bits[i]) : bits[i];
-                const u128 P = (u128)b << (128 - pw);
-                const u128 m = wrap ? rotr128(P, X) : (P >> X);
 #pragma unroll
                 for (int d = 0; d < 2; d++) {
                     if ((uint32_t)d < sc) {
-                        hit |= cur[i][d] & m;
-                        set_row(y[i] + d, cur[i][d] ^ m);
+                        hit |= (o0[i][d] & lo[i]) | (o1[i][d] & hi[i]);
+                        disp[4 * (y[i] + d) + d0] = o0[i][d] ^ lo[i];
+                        disp[4 * (y[i] + d) + d1] = o1[i][d] ^ hi[i];
                     }
                 }
             }
         }
         return hit != 0;
     }
-    // Scrolls by physical pixels, eight rows at a time: a chunk's loads come
+    // Scrolls by physical pixels, sixteen rows at a time: a chunk's loads come
     // before its stores, and scrolling down goes bottom-up, so no row is read
     // after it was written.
     __device__ __forceinline__ void scroll_down(uint32_t s) {
-        for (int y0 = 56; y0 >= 0; y0 -= 8) {
-            u128 v[8];
+        for (int y0 = 48; y0 >= 0; y0 -= 16) {
+            u128 v[16];
 #pragma unroll
-            for (int j = 0; j < 8; j++) {
+            for (int j = 0; j < 16; j++) {
                 const uint32_t y = (uint32_t)(y0 + j);
                 v[j] = y >= s ? row(y - s) : (u128)0;
             }
 #pragma unroll
-            for (int j = 0; j < 8; j++) set_row((uint32_t)(y0 + j), v[j]);
+            for (int j = 0; j < 16; j++) set_row((uint32_t)(y0 + j), v[j]);
         }
     }
     __device__ __forceinline__ void scroll_side(uint32_t s, bool right) {
-        for (uint32_t y0 = 0; y0 < 64; y0 += 8) {
-            u128 v[8];
+        for (uint32_t y0 = 0; y0 < 64; y0 += 16) {
+            u128 v[16];
 #pragma unroll
-            for (int j = 0; j < 8; j++) v[j] = row(y0 + j);
+            for (int j = 0; j < 16; j++) v[j] = row(y0 + j);
 #pragma unroll
-            for (int j = 0; j < 8; j++) set_row(y0 + j, right ? v[j] >> s : v[j] << s);
+            for (int j = 0; j < 16; j++) set_row(y0 + j, right ? v[j] >> s : v[j] << s);
         }
     }
     // The CHIP-8 entry points of the instruction cycle; DXYN and 00E0 never
