@@ -390,30 +390,42 @@ __device__ __forceinline__ void schip_emulate(const State &s, const Roms &roms, 
 }
 
 // Observations of one env (a 64-thread block): its ring (5 KB) staged in
-// LDS, then for each frame each thread writes the 32 bytes of four half
-// columns (column x, rows 32h .. 32h + 31 for unit u = 2x + h), so every
-// store instruction of the block covers 2 KB of observation contiguously.
+// LDS; then 32 threads transpose one 32x32 bit block each (frame f, rows
+// 32h .. 32h + 31, pixels 32w .. 32w + 31; Hacker's Delight, 2nd ed., section
+// 7-3) into packed columns in LDS; then every thread expands 16 pixels of a
+// column into bytes per store, so each store instruction writes 1 KB of the
+// env's observation contiguously.
 __device__ __forceinline__ void schip_observe_env(const State &s, uint8_t *obs, uint32_t slot, uint32_t head,
                                                   uint32_t t) {
     __shared__ uint64_t ring[kRingSlots * 128];
+    __shared__ uint32_t cols[4][128][2];   // [frame][column x][h]: bit y = pixel (x, 32h + y)
     const uint32_t tid = threadIdx.x;
     const uint64_t *src = s.hring + (size_t)slot * kRingSlots * 128;
 #pragma unroll
     for (uint32_t q = 0; q < kRingSlots * 2; q++) ring[tid + 64 * q] = src[tid + 64 * q];
     __syncthreads();
-    uint8_t *o = obs + (size_t)s.env_of[slot] * kSchipObsBytes;
-#pragma unroll
-    for (uint32_t f = 0; f < 4; f++) {
+    if (tid < 32) {
+        const uint32_t f = tid >> 3, h = (tid >> 2) & 1, w = tid & 3;
         const uint64_t *rows = ring + frame_slot(head, t, f) * 128;
+        // a[r]: pixels 32w .. 32w + 31 of row 32h + 31 - r, pixel 32w + c at
+        // bit 31 - c (the high or low half of the row's u64)
+        uint32_t a[32];
 #pragma unroll
-        for (uint32_t u = 0; u < 4; u++) {
-            const uint32_t unit = tid + 64 * u, x = unit >> 1, h = unit & 1;
-            const uint32_t sh = 63 - (x & 63), half = x >> 6;
-            uint32_t col = 0;
-#pragma unroll
-            for (int r = 0; r < 32; r++) col |= (uint32_t)((rows[2 * (32 * h + r) + half] >> sh) & 1) << r;
-            store_column(o + f * 8192 + x * 64 + 32 * h, col);
+        for (int r = 0; r < 32; r++) {
+            const uint64_t v = rows[2 * (32 * h + 31 - r) + (w >> 1)];
+            a[r] = (w & 1) ? (uint32_t)v : (uint32_t)(v >> 32);
         }
+        transpose32(a);   // a[c] = column 32w + c, bit y = row 32h + y
+#pragma unroll
+        for (int c = 0; c < 32; c++) cols[f][32 * w + c][h] = a[c];
+    }
+    __syncthreads();
+    uint8_t *o = obs + (size_t)s.env_of[slot] * kSchipObsBytes;
+#pragma unroll 8
+    for (uint32_t q = 0; q < kSchipObsBytes / 1024; q++) {
+        const uint32_t off = q * 1024 + 16 * tid;   // byte of the observation: [frame][x][y]
+        const uint32_t f = off >> 13, x = (off >> 6) & 127, y0 = off & 63;
+        store_obs(o + off, spread16(cols[f][x][y0 >> 5] >> (y0 & 31)));
     }
 }
 
