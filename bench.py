@@ -194,7 +194,8 @@ def serving_run(args, log):
     from paper_2510_01764_amd import workload as W
     from paper_2510_01764_amd import octax as X
     spec = W.make_config("c4")
-    be = S.PoolBackend(spec, args.serving_slots * X.Pool.slot_bytes(), depth=2)
+    K = args.serving_steps_per_tick
+    be = S.PoolBackend(spec, args.serving_slots * X.Pool.slot_bytes(), depth=2, steps_per_tick=K)
     # sustained rate: groups of the workload's sizes that fill the pool at
     # once, all running 400 steps (the loop's steady state at full occupancy)
     burst, used = [], 0
@@ -204,7 +205,7 @@ def serving_run(args, log):
             used += g.size
     cal = S.serve(spec, burst, be)
     capacity = cal["env_steps_per_s"]
-    log(f"serving: sustained {capacity / 1e6:.1f} M env steps/s with the pool kept full")
+    log(f"serving: sustained {capacity / 1e6:.1f} M env steps/s with the pool kept full, {K} steps per tick")
     probe = W.serving_groups(args.serving_groups, 1.0, seed=3)
     mean_work = float(np.mean([g.size * g.steps for g in probe]))
     loads = {}
@@ -232,10 +233,13 @@ def serving_run(args, log):
         "workload": f"{args.serving_groups} groups per load over 32 ROMs, sizes log-uniform 1..4096, "
                     f"200-2000 steps, Poisson arrivals at the given fractions of the sustained rate",
         "pool_slots": args.serving_slots,
+        "steps_per_tick": K,
         "sustained_env_steps_per_s": capacity,
         "sustained_def": "groups filling the pool admitted at once, 400 steps each: env steps over wall time",
         "loads": loads,
-        "step_latency_def": "per group step: host time from enqueueing the tick to its rewards and done flags on the host",
+        "step_latency_def": "per group step: host time from enqueueing the tick that runs it to its rewards and done "
+                            "flags on the host (a tick runs steps_per_tick steps of every resident group; a group "
+                            "stops at its last step inside a tick)",
         "admission": "any free slots (the lowest-numbered), by memory, in arrival order",
     }
 
@@ -288,6 +292,8 @@ def main():
     ap.add_argument("--serving-loads", type=lambda t: [float(x) for x in t.split(",")], default=[0.4, 0.7, 0.9],
                     help="offered loads as fractions of the pool's measured sustained rate")
     ap.add_argument("--serving-slots", type=int, default=65536)
+    ap.add_argument("--serving-steps-per-tick", type=int, default=8,
+                    help="env steps per serving tick (1..255)")
     args = ap.parse_args()
     if args.headline_only:
         args.no_cpu = args.no_plain = args.no_by_rom = args.no_wrappers = args.no_profile = True

@@ -528,6 +528,18 @@ int32_t octax_pool_retire(octax_pool *p, uint32_t group);
 int32_t octax_pool_step(octax_pool *p, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
                         uint32_t obs_slots, float *d_reward, uint8_t *d_done);
 
+/* As octax_pool_step, with a step budget per slot: d_budget uint8 [capacity]
+ * (device), slot s runs min(K, d_budget[s]) steps of this call and stops
+ * there, its state, frame history and RNG stream exactly those after that
+ * many steps, so that a group whose last step falls inside a call of K steps
+ * ends on it.  Outputs of a slot for steps at or past its budget are
+ * unspecified.  NULL d_budget: every slot runs K steps.  The
+ * budget array is read when the launch runs (stream order).
+ * Errors: those of octax_pool_step, and OCTAX_E_INVALID for K > 255 with a
+ * budget array. */
+int32_t octax_pool_step_budget(octax_pool *p, uint32_t K, const uint8_t *d_budget, const int32_t *d_action,
+                               uint8_t *d_obs, uint32_t obs_slots, float *d_reward, uint8_t *d_done);
+
 /* Capacity, free slots, the largest group admissible now (equal to the free
  * slots: any free slots take a group) and number of groups. */
 int32_t octax_pool_info(const octax_pool *p, uint32_t *capacity, uint32_t *free_slots,

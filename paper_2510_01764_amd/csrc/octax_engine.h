@@ -100,6 +100,7 @@ int32_t check_device_error(octax_engine *g, const char *what);
 
 // K fused or plain steps of every env of g on stream st.
 hipError_t launch_steps(octax_engine *g, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
-                        uint32_t obs_slots, float *d_reward, uint8_t *d_done, hipStream_t st);
+                        uint32_t obs_slots, float *d_reward, uint8_t *d_done, hipStream_t st,
+                        const uint8_t *d_budget = nullptr);
 
 }  // namespace octax

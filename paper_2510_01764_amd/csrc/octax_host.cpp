@@ -184,12 +184,14 @@ hipError_t upload_block_roms(octax_engine *g) {
 }  // namespace
 
 hipError_t octax::launch_steps(octax_engine *g, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
-                               uint32_t obs_slots, float *d_reward, uint8_t *d_done, hipStream_t st) {
+                               uint32_t obs_slots, float *d_reward, uint8_t *d_done, hipStream_t st,
+                               const uint8_t *d_budget) {
     StepIO io{d_action, d_obs, d_reward, d_done, K, obs_slots ? obs_slots : 1, g->ipf, g->frame_skip};
     if (g->schip) return launch_step_schip(g->s, g->roms, io, st);
     if (g->kernel == OCTAX_KERNEL_FUSED) {
         FusedCfg f{g->envs_per_block, g->rom_in_lds, g->d_block_roms,
-                   g->wait_override ? g->wait_override : g->wait_ticks, g->d_err, g->d_stamps, g->stamp_steps};
+                   g->wait_override ? g->wait_override : g->wait_ticks, g->d_err, g->d_stamps, g->stamp_steps,
+                   d_budget};
         return launch_step_fused(g->s, g->roms, io, f, st);
     }
     return launch_step_plain(g->s, g->roms, io, st);

@@ -26,7 +26,7 @@ struct StepIO {
 //   * the displays: IPW x kFbStride u64 (32 rows + 1 pad row per env);
 //   * written-page cache slots: IPW x (64 x slots + 8) bytes;
 //   * the writers' staging: (IPW / 64) waves x kStageEnvs x kStageStride u32;
-//   * reward, done and two step counters per env, and
+//   * reward, done, a step budget and two step counters per env, and
 //     two step counters per wave;
 //   * the page pool: everything left, in 64-byte pages.
 constexpr uint32_t kFbStride = 33;
@@ -36,7 +36,7 @@ constexpr uint32_t fused_cache_slots(uint32_t ipw) { return ipw == 64 ? 2 : 3; }
 constexpr uint32_t fused_lds_bytes(uint32_t ipw) { return 163840u / (256u / ipw); }
 constexpr uint32_t fused_fixed_lds(uint32_t ipw) {
     return ipw * kFbStride * 8 + ipw * (64 * fused_cache_slots(ipw) + 8) + (ipw / 64) * kStageEnvs * kStageStride * 4 +
-           ipw * (4 + 1 + 2) + 2 * 4 * (ipw / 64);
+           ipw * (4 + 1 + 1 + 2) + 2 * 4 * (ipw / 64);
 }
 constexpr uint32_t fused_pool_pages(uint32_t ipw) { return (fused_lds_bytes(ipw) - fused_fixed_lds(ipw)) / 64; }
 
@@ -65,6 +65,7 @@ struct FusedCfg {
     uint32_t *err;                // device error word: bit 0 set when a wait gave up
     uint64_t *stamps;             // [stamp_steps][ceil(E / 64)][2] step start / end clocks, or nullptr
     uint32_t stamp_steps;
+    const uint8_t *budget;        // [slots] steps of the launch per slot (at most K), or nullptr: K for all
 };
 
 hipError_t launch_step_plain(const State &s, const Roms &r, const StepIO &io, hipStream_t st);

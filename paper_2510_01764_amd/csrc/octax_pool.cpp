@@ -265,17 +265,23 @@ int32_t octax_pool_retire(octax_pool *p, uint32_t group) {
     return OCTAX_OK;
 }
 
-int32_t octax_pool_step(octax_pool *p, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
-                        uint32_t obs_slots, float *d_reward, uint8_t *d_done) {
+int32_t octax_pool_step_budget(octax_pool *p, uint32_t K, const uint8_t *d_budget, const int32_t *d_action,
+                               uint8_t *d_obs, uint32_t obs_slots, float *d_reward, uint8_t *d_done) {
     if (!p || !d_action || !d_reward || !d_done)
         return fail(OCTAX_E_INVALID, "octax_pool_step: NULL pool, action, reward or done");
     if (K == 0) return fail(OCTAX_E_INVALID, "octax_pool_step: K == 0");
+    if (d_budget && K > 255) return fail(OCTAX_E_INVALID, "octax_pool_step_budget: K > 255 with step budgets");
     if (d_obs && obs_slots == 0) return fail(OCTAX_E_INVALID, "octax_pool_step: obs_slots == 0");
     octax_engine *g = p->eng;
     hipError_t e = hipSuccess;
     if (p->table_dirty) e = upload_table(p);
-    if (e == hipSuccess) e = launch_steps(g, K, d_action, d_obs, obs_slots, d_reward, d_done, g->stream);
+    if (e == hipSuccess) e = launch_steps(g, K, d_action, d_obs, obs_slots, d_reward, d_done, g->stream, d_budget);
     return e == hipSuccess ? OCTAX_OK : hip_fail(e, "octax_pool_step");
+}
+
+int32_t octax_pool_step(octax_pool *p, uint32_t K, const int32_t *d_action, uint8_t *d_obs,
+                        uint32_t obs_slots, float *d_reward, uint8_t *d_done) {
+    return octax_pool_step_budget(p, K, nullptr, d_action, d_obs, obs_slots, d_reward, d_done);
 }
 
 int32_t octax_pool_info(const octax_pool *p, uint32_t *capacity, uint32_t *free_slots,

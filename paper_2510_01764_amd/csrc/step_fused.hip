@@ -54,6 +54,7 @@ struct Shared {
     uint32_t stage[IPW / 64][kStageEnvs][kStageStride];
     float rew[IPW];           // reward and done bits of the step just emulated, for the writer waves
     uint8_t done[IPW];
+    uint8_t budget[IPW];      // steps of the launch per env when the launch has step budgets
     uint8_t lready[IPW];      // per-lane progress (variants with reset steps): steps published, mod 256
     uint8_t ltaken[IPW];      // displays taken, mod 256
     uint32_t ready[IPW / 64]; // steps emulated by emulator wave w
@@ -151,7 +152,7 @@ struct FusedMem {
     // An access to written page p: when p sits in the slot due for
     // replacement, the replacement pointer moves on to the next slot.
     __device__ __forceinline__ void touch(uint32_t p) {
-        const bool at_vic = is_dirty(p) & ((tag(vic) & 0x7F) == (p | 0x40));
+        const bool at_vic = (int)is_dirty(p) & (int)((tag(vic) & 0x7F) == (p | 0x40));
         vic = at_vic ? next_slot(vic) : vic;
     }
     // Write a modified slot's page back to HBM (16 bytes a piece, from
@@ -384,7 +385,8 @@ struct FusedMem {
         bool in0, in1;
         const uint32_t o0 = pool_off(p0, in0), o1 = pool_off(p1, in1);
         // readable: cached, or clean and in the pool; a store needs the slot
-        const bool ok = ((s0 >= 0) | (!st & !is_dirty(p0) & in0)) & ((s1 >= 0) | (!st & !is_dirty(p1) & in1));
+        const bool ok = ((int)(s0 >= 0) | ((int)!st & (int)!is_dirty(p0) & (int)in0)) &
+                        ((int)(s1 >= 0) | ((int)!st & (int)!is_dirty(p1) & (int)in1));
         lds_u8 *pool = (lds_u8 *)&sh.pool[0][0];
         lds_u8 *q0 = s0 >= 0 ? slot_ptr((uint32_t)s0) : pool + o0;
         lds_u8 *q1 = s1 >= 0 ? slot_ptr((uint32_t)s1) : pool + o1;
@@ -669,12 +671,6 @@ __device__ __forceinline__ void run_frames(Core &c, Mem &mem, uint32_t key, uint
     }
 }
 
-// Lane l's share of one packed frame: bytes [16l, 16l+16) and [1024+16l, ...).
-__device__ __forceinline__ void store_frame(uint8_t *frame, uint32_t lane64, uint32_t w) {
-    store16(frame + 16 * lane64, w & 0xFFFF);
-    store16(frame + 1024 + 16 * lane64, w >> 16);
-}
-
 // Lane l's share of two consecutive expanded frames, one 4 KB piece of an
 // observation: bytes [16l, 16l+16) and [1024+16l, ...) of each frame.
 __device__ __forceinline__ void store_pair(uint8_t *o, uint32_t lane64, u32x4 a0, u32x4 a1, u32x4 b0, u32x4 b1) {
@@ -738,12 +734,14 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     const uint32_t E = s.num;
     const uint32_t K = io.K;
     const bool active = slot_live(s, slot);
+    // steps this launch runs for the slot: K, or the slot's budget (at most
+    // K; a serving pool's group stops at its last step inside a launch)
+    const uint32_t steps = (cfg.budget && active) ? min(K, (uint32_t)cfg.budget[slot]) : K;
     // A block with no env (free range of a serving pool) has nothing to do:
     // the host marks it in the block's pool table (no ROM listed).
     const uint32_t *ptab = cfg.block_roms + (size_t)blk * kPoolRoms * 2;
     if (ptab[0] == kPoolEnd) return;
     const uint32_t live = active ? 1u : 0u;
-    const uint64_t live_bits = __builtin_amdgcn_ballot_w64(active);   // live slots of this wave
     const uint32_t wave_slot0 = blk * IPW + wave_base;
     const uint32_t nj = (E > wave_slot0) ? min(64u, E - wave_slot0) : 0u;   // slots of this wave
 
@@ -847,23 +845,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     // Writers, prologue: the three frames before this launch fill the lower
     // halves of observations 0 and 1 (frame f of step k is the frame of step
     // k - 3 + f).  All loads of a chunk of envs are issued before its stores.
-    // Each writer lane also loads its own env's packed frame of step -1, the
-    // first of the pair that step 0 stores.
-    uint32_t pa[64], pb[64];   // packed frames of the current and the previous step
-#pragma unroll
-    for (int q = 0; q < 64; q++) pb[q] = 0;
     if (!emu && io.obs) {
-        if (active) {
-            const uint4 *r4 = reinterpret_cast<const uint4 *>(s.cols + (size_t)slot * 256 + head * 64);
-#pragma unroll
-            for (int q = 0; q < 16; q++) {
-                const uint4 v = r4[q];
-                pb[4 * q] = v.x;
-                pb[4 * q + 1] = v.y;
-                pb[4 * q + 2] = v.z;
-                pb[4 * q + 3] = v.w;
-            }
-        }
         for (uint32_t j0 = 0; j0 < nj; j0 += kPrologueEnvs) {
             uint32_t w[kPrologueEnvs][3];
 #pragma unroll
@@ -885,7 +867,8 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 const u32x4 m2a = spread16(w[jj][1]), m2b = spread16(w[jj][1] >> 16);
                 const u32x4 m3a = spread16(w[jj][2]), m3b = spread16(w[jj][2] >> 16);
                 store_pair(obs_of(0, je), lane64, m3a, m3b, m2a, m2b);                 // steps -3, -2
-                if (K > 1) store_pair(obs_of(1, je), lane64, m2a, m2b, m1a, m1b);      // steps -2, -1
+                if (__builtin_amdgcn_readlane(steps, j) > 1)
+                    store_pair(obs_of(1, je), lane64, m2a, m2b, m1a, m1b);               // steps -2, -1
             }
         }
     }
@@ -896,6 +879,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
     if (tid < IPW) {
         sh.lready[tid] = 0;
         sh.ltaken[tid] = 0;
+        sh.budget[tid] = (uint8_t)min(steps, 255u);
     }
     __syncthreads();
 
@@ -932,6 +916,23 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
         st4[0] = make_uint4(mem.stk[0], mem.stk[1], mem.stk[2], mem.stk[3]);
         st4[1] = make_uint4(mem.stk[4], mem.stk[5], mem.stk[6], mem.stk[7]);
     };
+    // Writer lanes: their env's packed frame of step -1 (the first of the pair
+    // that step 0 stores), from the env's frame ring.
+    auto load_prev = [&](uint32_t (&pb)[64]) {
+#pragma unroll
+        for (int q = 0; q < 64; q++) pb[q] = 0;
+        if (active && io.obs) {
+            const uint4 *r4 = reinterpret_cast<const uint4 *>(s.cols + (size_t)slot * 256 + head * 64);
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const uint4 v = r4[q];
+                pb[4 * q] = v.x;
+                pb[4 * q + 1] = v.y;
+                pb[4 * q + 2] = v.z;
+                pb[4 * q + 3] = v.w;
+            }
+        }
+    };
     if constexpr (kResetSteps) {
         // Per-lane progress (variants whose resets run emulation steps).  A
         // reset here runs a ROM's start-up sequence and up to noop_max no-op
@@ -961,7 +962,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             bool waiting = false;
             uint64_t since = 0;
             while (true) {
-                const bool want = active && k < K;
+                const bool want = active && k < steps;
                 if (!__builtin_amdgcn_ballot_w64(want)) break;
                 // A slot starts once no lane waits for its display to be
                 // copied: the lanes of a reset then run their reset steps in
@@ -1052,11 +1053,13 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             }
             emu_epilogue();
         } else {
+            uint32_t pa[64], pb[64];   // packed frames of the current and the previous step
+            load_prev(pb);
             uint32_t kw = 0;         // steps whose display this lane has taken
             bool waiting = false;
             uint64_t since = 0;
             while (true) {
-                const bool want = active && kw < K;
+                const bool want = active && kw < steps;
                 if (!__builtin_amdgcn_ballot_w64(want)) break;
                 bool have = want && ((get_lane_flag(&sh.lready[l]) - kw) & 0xFF) != 0;
                 if (!__builtin_amdgcn_ballot_w64(have)) {
@@ -1118,13 +1121,17 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                             const u32x4 p0 = spread16(pv), p1 = spread16(pv >> 16);
                             const u32x4 c0 = spread16(cw), c1 = spread16(cw >> 16);
                             store_pair(obs_of(kj, je) + 4096, lane64, p0, p1, c0, c1);
-                            if (kj + 2 < K) store_pair(obs_of(kj + 2, je), lane64, p0, p1, c0, c1);
+                            // (observations past the env's last step of the launch are not
+                            // written: with fewer observation slots than steps they would
+                            // overwrite the slot of one that is)
+                            const uint32_t sj = __builtin_amdgcn_readlane(steps, j);
+                            if (kj + 2 < sj) store_pair(obs_of(kj + 2, je), lane64, p0, p1, c0, c1);
                             if (jdone) {
                                 store_pair(obs_of(kj, je), lane64, c0, c1, c0, c1);
-                                if (kj + 1 < K) store_pair(obs_of(kj + 1, je), lane64, c0, c1, c0, c1);
+                                if (kj + 1 < sj) store_pair(obs_of(kj + 1, je), lane64, c0, c1, c0, c1);
                             }
                         }
-                        if (kj + 4 >= K) {
+                        if (kj + 4 >= __builtin_amdgcn_readlane(steps, j)) {
                             const uint32_t jh = __builtin_amdgcn_readlane(head, j);
                             uint32_t *ring = s.cols + (size_t)(wave_slot0 + j) * 256 + lane64;
                             ring[jh * 64] = cw;
@@ -1148,8 +1155,10 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             // the display of step k - 1 must have been copied before it changes
             if (k > 0) wait_flag(&sh.taken[wave], k, cfg.wait_ticks, cfg.err);
             stamp(k, 0);
-            if (active) {
-                if (k > 0 && (k & 63) == 0) load_keys(k);
+            if (k > 0 && (k & 63) == 0 && active) load_keys(k);
+            // (the step count of a budgeted launch is read from LDS, so that it
+            // does not hold a register through the emulator loop)
+            if (active && (!cfg.budget || k < sh.budget[l])) {
                 const uint32_t key = sticky_key(roms, c, key_of_step(k));
                 run_frames<kProfile>(c, mem, key, io.ipf, io.frame_skip, quirks);
                 const int32_t score = score_of(c.r, desc, desc2);
@@ -1187,6 +1196,8 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
         // the upper half of observation k and the lower half of observation
         // k + 2.  The packed frame of step k - 1 stays in registers; the two
         // arrays trade roles from one step to the next.
+        uint32_t pa[64], pb[64];   // packed frames of the current and the previous step
+        load_prev(pb);
         auto wstep = [&](uint32_t k, uint32_t (&pw)[64], const uint32_t (&pp)[64]) __attribute__((always_inline)) {
             // Copy the display, reward and done bits of step k once final
             // and let the emulator go on.
@@ -1198,15 +1209,24 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 hi[r] = (uint32_t)(row >> 32);
                 lo[r] = (uint32_t)row;
             }
-            const uint32_t done = active ? sh.done[l] : 0u;
+            const bool ran = active && k < steps;   // this lane's env ran step k
+            const uint32_t done = ran ? sh.done[l] : 0u;
             const float wrew = sh.rew[l];
             set_flag(&sh.taken[wave], k + 1);
-            const bool ring_step = k + 4 >= K;
-            if (active) {
+            // the last four frames of each env's steps go into its ring; the
+            // observations past an env's last step of the launch are not
+            // written (with fewer observation slots than steps they would
+            // overwrite the slot of one that is)
+            const uint64_t ring_bits = __builtin_amdgcn_ballot_w64(ran && k + 4 >= steps);
+            const uint64_t k1_bits = __builtin_amdgcn_ballot_w64(ran && k + 1 < steps);
+            const uint64_t k2_bits = __builtin_amdgcn_ballot_w64(ran && k + 2 < steps);
+            const bool ring_step = ring_bits != 0;
+            if (ran) {
                 io.reward[(size_t)k * E + env] = wrew;
                 io.done[(size_t)k * E + env] = (uint8_t)done;
+                head = done ? 0u : (head + 1) & 3;
             }
-            head = done ? 0u : (head + 1) & 3;
+            const uint64_t ran_bits = __builtin_amdgcn_ballot_w64(ran);
             if (!(io.obs || ring_step)) {
                 stamp(k, 1);
                 return;
@@ -1237,7 +1257,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 wave_sync();
                 const uint32_t n = __builtin_amdgcn_readfirstlane(min(r0 + kPairEnvs, nj) - r0);
                 // slots of the round that hold a live env (wave-uniform)
-                const uint32_t rmask = (uint32_t)(live_bits >> r0) & ((1u << n) - 1);
+                const uint32_t rmask = (uint32_t)(ran_bits >> r0) & ((1u << n) - 1);
                 uint32_t cw[kPairEnvs], pv[kPairEnvs], jdone[kPairEnvs];
 #pragma unroll
                 for (uint32_t jj = 0; jj < kPairEnvs; jj++) {
@@ -1248,29 +1268,18 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                     pv[jj] = jdone[jj] ? cw[jj] : sh.stage[wave][2 * jj][lane64];
                 }
                 if (io.obs) {
-                    u32x4 xp0[kPairEnvs], xp1[kPairEnvs], xc0[kPairEnvs], xc1[kPairEnvs];
-                    uint64_t eo[kPairEnvs];   // observation offset of env r0 + jj
+                    // env by env: its four expanded frame halves, then its pieces
 #pragma unroll
                     for (uint32_t jj = 0; jj < kPairEnvs; jj++) {
-                        xp0[jj] = spread16(pv[jj]);
-                        xp1[jj] = spread16(pv[jj] >> 16);
-                        xc0[jj] = spread16(cw[jj]);
-                        xc1[jj] = spread16(cw[jj] >> 16);
-                        eo[jj] = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(env, r0 + jj) * kObsBytes;
-                    }
-#pragma unroll
-                    for (uint32_t jj = 0; jj < kPairEnvs; jj++)
-                        if ((rmask >> jj) & 1) store_pair(o_k + eo[jj] + 4096, lane64, xp0[jj], xp1[jj], xc0[jj], xc1[jj]);
-                    if (k + 2 < K) {
-#pragma unroll
-                        for (uint32_t jj = 0; jj < kPairEnvs; jj++)
-                            if ((rmask >> jj) & 1) store_pair(o_k2 + eo[jj], lane64, xp0[jj], xp1[jj], xc0[jj], xc1[jj]);
-                    }
-#pragma unroll
-                    for (uint32_t jj = 0; jj < kPairEnvs; jj++) {
-                        if (((rmask >> jj) & 1) && jdone[jj]) {
-                            store_pair(o_k + eo[jj], lane64, xc0[jj], xc1[jj], xc0[jj], xc1[jj]);
-                            if (k + 1 < K) store_pair(o_k1 + eo[jj], lane64, xc0[jj], xc1[jj], xc0[jj], xc1[jj]);
+                        if (!((rmask >> jj) & 1)) continue;
+                        const uint64_t eo = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(env, r0 + jj) * kObsBytes;
+                        const u32x4 p0 = spread16(pv[jj]), p1 = spread16(pv[jj] >> 16);
+                        const u32x4 c0 = spread16(cw[jj]), c1 = spread16(cw[jj] >> 16);
+                        store_pair(o_k + eo + 4096, lane64, p0, p1, c0, c1);
+                        if ((k2_bits >> (r0 + jj)) & 1) store_pair(o_k2 + eo, lane64, p0, p1, c0, c1);
+                        if (jdone[jj]) {
+                            store_pair(o_k + eo, lane64, c0, c1, c0, c1);
+                            if ((k1_bits >> (r0 + jj)) & 1) store_pair(o_k1 + eo, lane64, c0, c1, c0, c1);
                         }
                     }
                 }
@@ -1280,7 +1289,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                 if (ring_step) {
 #pragma unroll
                     for (uint32_t jj = 0; jj < kPairEnvs; jj++) {
-                        if (!((rmask >> jj) & 1)) continue;
+                        if (!((ring_bits >> (r0 + jj)) & 1)) continue;
                         const uint32_t jh = __builtin_amdgcn_readlane(head, r0 + jj);
                         uint32_t *ring = s.cols + (size_t)(wave_slot0 + r0 + jj) * 256 + lane64;
                         ring[jh * 64] = cw[jj];

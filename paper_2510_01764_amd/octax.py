@@ -45,7 +45,7 @@ EXPORTED = (
     "octax_status", "octax_set_wait_limit", "octax_set_step_clock",
     "octax_last_error", "octax_calib_write", "octax_calib_copy", "octax_get_schip_state", "octax_digest",
     "octax_pool_slot_bytes", "octax_pool_create", "octax_pool_admit", "octax_pool_retire",
-    "octax_pool_step", "octax_pool_info", "octax_pool_get_state", "octax_pool_destroy",
+    "octax_pool_step", "octax_pool_step_budget", "octax_pool_info", "octax_pool_get_state", "octax_pool_destroy",
 )
 
 
@@ -170,6 +170,7 @@ def library() -> ctypes.CDLL:
         "octax_pool_admit": ([P, u32, u32, P, P, P, ctypes.POINTER(u32)], i32),
         "octax_pool_retire": ([P, u32], i32),
         "octax_pool_step": ([P, u32, P, P, u32, P, P], i32),
+        "octax_pool_step_budget": ([P, u32, P, P, P, u32, P, P], i32),
         "octax_pool_info": ([P] + [ctypes.POINTER(u32)] * 4, i32),
         "octax_pool_get_state": ([P, P, u32, P], i32),
         "octax_pool_destroy": ([P], i32),
@@ -515,11 +516,20 @@ class Pool:
     def retire(self, group: int):
         _check(library().octax_pool_retire(self._h, int(group)))
 
-    def step(self, action, obs, reward, done):
+    def step(self, action, obs, reward, done, budget=None):
+        """K = action.shape[0] steps of every occupied slot; with budget (a
+        device uint8 tensor [capacity]) slot s runs min(K, budget[s]) of them."""
         K = int(action.shape[0])
         slots = 0 if obs is None else int(obs.shape[0])
-        _check(library().octax_pool_step(self._h, K, _ptr(action), _ptr(obs), slots,
-                                         _ptr(reward), _ptr(done)))
+        if budget is None:
+            _check(library().octax_pool_step(self._h, K, _ptr(action), _ptr(obs), slots,
+                                             _ptr(reward), _ptr(done)))
+            return
+        import torch
+        if budget.dtype != torch.uint8 or tuple(budget.shape) != (self.capacity,) or not budget.is_contiguous():
+            raise ValueError(f"budget must be a contiguous uint8 tensor of shape ({self.capacity},)")
+        _check(library().octax_pool_step_budget(self._h, K, _ptr(budget), _ptr(action), _ptr(obs), slots,
+                                                _ptr(reward), _ptr(done)))
 
     def info(self) -> dict:
         v = [ctypes.c_uint32() for _ in range(4)]

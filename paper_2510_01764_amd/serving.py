@@ -7,9 +7,11 @@ slots are free to hold it; admission is by memory (the pool has a fixed
 device budget; a group takes any free slots, so the pool never fragments),
 in arrival order, with later groups allowed to start while a larger one at
 the head of the queue does not fit yet.  Every tick
-enqueues one step of every resident group as one launch over the pool, so
-the work of groups that arrived at different times runs together on the
-device.  A group leaves the pool after its last step.
+enqueues K steps (steps_per_tick) of every resident group as one launch
+over the pool, so the work of groups that arrived at different times runs
+together on the device; a group whose last step falls inside a tick stops
+there (a per-slot step budget of the launch).  A group leaves the pool after
+its last step.
 
 All emulation runs in liboctax (``octax.Pool``); this module only decides
 which group goes where and when, builds the per-slot action vector of each
@@ -45,32 +47,43 @@ class GroupRun:
     final_state: Optional[np.ndarray] = None
     seeds: Optional[np.ndarray] = None     # per-env RNG seeds and horizons, drawn on arrival
     horizons: Optional[np.ndarray] = None
+    runs: Optional[list] = None            # runs of consecutive slots while resident
 
 
 class PoolBackend:
-    """liboctax pool on the current GPU, with `depth` ticks in flight.
+    """liboctax pool on the current GPU, with `depth` ticks of `steps_per_tick`
+    steps in flight.
 
-    Actions are taken from a pinned host schedule of `rows` tick rows (a
-    ring indexed by tick number); each tick copies its row to the device.
+    Actions are taken from a pinned host schedule of `rows` rows, one per
+    global step (a ring indexed by step number; tick T runs steps T*K ..
+    T*K + K - 1); each tick copies its K rows and the slots' step budgets to
+    the device.
     """
 
     def __init__(self, spec, pool_bytes: int, depth: int = 2, with_obs: bool = True,
-                 envs_per_block: int = 256, rows: int = 128):
+                 envs_per_block: int = 256, rows: int = 128, steps_per_tick: int = 1):
         import torch
         from . import octax as X
         self.torch = torch
         dev = torch.device("cuda")
+        K = self.K = int(steps_per_tick)
+        if not 1 <= K <= 255:
+            raise ValueError("steps_per_tick must be in 1..255")
+        rows = max(rows, WINDOW + (depth + 1) * K)
+        rows = -(-rows // K) * K
         self.stream = torch.cuda.Stream(device=dev)
         self.pool = X.Pool(spec, pool_bytes, envs_per_block=envs_per_block, stream=self.stream)
         cap = self.capacity = self.pool.capacity
         self.depth = depth
         self.rows = rows
         self.h_sched = torch.zeros((rows, cap), dtype=torch.int32).pin_memory()
-        self.act = [torch.zeros((1, cap), dtype=torch.int32, device=dev) for _ in range(depth)]
-        self.rew = [torch.zeros((1, cap), dtype=torch.float32, device=dev) for _ in range(depth)]
-        self.done = [torch.zeros((1, cap), dtype=torch.uint8, device=dev) for _ in range(depth)]
-        self.h_rew = [torch.zeros((1, cap), dtype=torch.float32).pin_memory() for _ in range(depth)]
-        self.h_done = [torch.zeros((1, cap), dtype=torch.uint8).pin_memory() for _ in range(depth)]
+        self.act = [torch.zeros((K, cap), dtype=torch.int32, device=dev) for _ in range(depth)]
+        self.rew = [torch.zeros((K, cap), dtype=torch.float32, device=dev) for _ in range(depth)]
+        self.done = [torch.zeros((K, cap), dtype=torch.uint8, device=dev) for _ in range(depth)]
+        self.h_rew = [torch.zeros((K, cap), dtype=torch.float32).pin_memory() for _ in range(depth)]
+        self.h_done = [torch.zeros((K, cap), dtype=torch.uint8).pin_memory() for _ in range(depth)]
+        self.h_budget = [torch.zeros(cap, dtype=torch.uint8).pin_memory() for _ in range(depth)]
+        self.budget = [torch.zeros(cap, dtype=torch.uint8, device=dev) for _ in range(depth)]
         self.obs = (torch.zeros((1, cap, 4, 64, 32), dtype=torch.uint8, device=dev)
                     if with_obs else None)
         self.ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -85,16 +98,23 @@ class PoolBackend:
         self.pool.retire(pool_id)
 
     def schedule(self) -> np.ndarray:
-        """Host action schedule [rows, capacity] (pinned)."""
+        """Host action schedule [rows, capacity] (pinned), one row per global step."""
         return self.h_sched.numpy()
 
-    def launch(self, row: int) -> int:
+    def launch(self, tick: int, budget: Optional[np.ndarray]) -> int:
+        """Tick `tick`: K steps of every resident slot, slot s stopping after
+        budget[s] of them (None: all K)."""
         d = self.n % self.depth
         torch = self.torch
+        r0 = (tick * self.K) % self.rows
         with torch.cuda.stream(self.stream):
-            self.act[d][0].copy_(self.h_sched[row], non_blocking=True)
+            self.act[d].copy_(self.h_sched[r0:r0 + self.K], non_blocking=True)
+            if budget is not None:
+                self.h_budget[d].numpy()[:] = budget
+                self.budget[d].copy_(self.h_budget[d], non_blocking=True)
             self.ev[d][0].record(self.stream)
-            self.pool.step(self.act[d], self.obs, self.rew[d], self.done[d])
+            self.pool.step(self.act[d], self.obs, self.rew[d], self.done[d],
+                           budget=self.budget[d] if budget is not None else None)
             self.ev[d][1].record(self.stream)
             self.h_rew[d].copy_(self.rew[d], non_blocking=True)
             self.h_done[d].copy_(self.done[d], non_blocking=True)
@@ -103,9 +123,10 @@ class PoolBackend:
         return self.n - 1
 
     def wait(self, ticket: int):
+        """Rewards and done flags [K][capacity] of a tick, and its device time (ms)."""
         d = ticket % self.depth
         self.ready[d].synchronize()
-        return (self.h_rew[d].numpy()[0], self.h_done[d].numpy()[0],
+        return (self.h_rew[d].numpy(), self.h_done[d].numpy(),
                 self.ev[d][0].elapsed_time(self.ev[d][1]))
 
     def finish(self):
@@ -139,34 +160,38 @@ def serve(spec, groups: List[W.Group], backend, *, record=False,
           log: Optional[Callable[[str], None]] = None) -> Dict:
     """Run the request loop over `groups` (arrival times in seconds from the start).
 
-    Tick T reads its actions from row T of the backend's schedule ring; a
-    group admitted before tick T0 takes step k in tick T0 + k, and its
-    actions are written into the ring a window of steps ahead, so a tick
-    costs the host O(1) work besides admissions, window refills and
-    retirements.  With ``record`` (True for every group, or a set of group
-    ids) every step's rewards and dones, the last observation and the final
-    architectural state of the recorded groups are kept (the ticks in flight
-    are drained before a finishing recorded group's slots are read).
-    Returns per-group runs and latency figures.
+    Tick T runs global steps T*K .. T*K + K - 1 (K = backend.K) and reads its
+    actions from those rows of the backend's schedule ring; a group admitted
+    before tick T0 takes its step k at global step T0*K + k, and its actions
+    are written into the ring a window of steps ahead, so a tick costs the
+    host O(1) work besides admissions, window refills, retirements and the
+    groups that stop inside it.  With ``record`` (True for every group, or a
+    set of group ids) every step's rewards and dones, the last observation
+    and the final architectural state of the recorded groups are kept (the
+    ticks in flight are drained before a finishing recorded group's slots are
+    read).  Returns per-group runs and latency figures.
     """
     depth = backend.depth
+    K = getattr(backend, "K", 1)
     R = backend.rows
-    if R < WINDOW + depth + 1:
-        raise ValueError("the schedule ring must hold a window plus the ticks in flight")
+    if R % K or R < WINDOW + (depth + 1) * K:
+        raise ValueError("the schedule ring must be a multiple of K rows holding a window plus the ticks in flight")
     sched = backend.schedule()
+    cap = backend.capacity
     runs = [GroupRun(g, int(spec.num_actions[g.rom])) for g in groups]
     order = sorted(range(len(runs)), key=lambda i: runs[i].group.arrival)
     queue: List[GroupRun] = []
     resident: Dict[int, GroupRun] = {}
     inflight: collections.deque = collections.deque()
-    refill_at: Dict[int, List[GroupRun]] = collections.defaultdict(list)
+    refill_at: Dict[int, List] = collections.defaultdict(list)
     finish_at: Dict[int, List[GroupRun]] = collections.defaultdict(list)
+    short_at: Dict[int, List[GroupRun]] = collections.defaultdict(list)   # groups that stop inside tick T
+    budget = np.full(cap, K, dtype=np.uint8)
     tick_lat: List[float] = []
     tick_groups: List[int] = []
     tick_ms: List[float] = []
     nxt = 0
     T = 0
-    resident_envs = 0
     busy_env_steps = 0
     changed = True
     t0 = clock()
@@ -174,14 +199,21 @@ def serve(spec, groups: List[W.Group], backend, *, record=False,
     def recorded(r: GroupRun) -> bool:
         return record is True or (bool(record) and r.group.gid in record)
 
-    def write_window(r: GroupRun, t_start: int):
+    def write_window(r: GroupRun, k0: int):
+        """Actions of the group's steps k0 .. k0 + WINDOW - 1 into the ring,
+        one block copy per run of consecutive slots and of ring rows."""
         g = r.group
-        k0 = t_start - r.t0
         n = min(WINDOW, g.steps - k0)
-        rows = (t_start + np.arange(n)) % R
-        sched[np.ix_(rows, r.slots)] = W.group_actions(g, k0, n, r.num_actions)
+        acts = W.group_actions(g, k0, n, r.num_actions)
+        row0 = (r.t0 * K + k0) % R
+        parts = [(row0, 0, min(n, R - row0))]
+        if parts[0][2] < n:
+            parts.append((0, parts[0][2], n - parts[0][2]))
+        for s0, i0, m in r.runs:
+            for q0, a0, c in parts:
+                sched[q0:q0 + c, s0:s0 + m] = acts[a0:a0 + c, i0:i0 + m]
         if k0 + n < g.steps:
-            refill_at[t_start + n].append(r)
+            refill_at[r.t0 + (k0 + n) // K].append((r, k0 + n))
 
     def collect():
         ticket, tick, n_groups, members, t_launch = inflight.popleft()
@@ -190,9 +222,10 @@ def serve(spec, groups: List[W.Group], backend, *, record=False,
         tick_groups.append(n_groups)
         tick_ms.append(dev_ms)
         for r in members:
-            k = tick - r.t0
-            r.rewards[k] = rew[r.slots]
-            r.dones[k] = done[r.slots]
+            k0 = (tick - r.t0) * K
+            n = min(K, r.group.steps - k0)
+            r.rewards[k0:k0 + n] = rew[:n, r.slots]
+            r.dones[k0:k0 + n] = done[:n, r.slots]
 
     while nxt < len(order) or queue or resident or inflight:
         now = clock() - t0
@@ -213,6 +246,11 @@ def serve(spec, groups: List[W.Group], backend, *, record=False,
             if adm is None:
                 continue
             r.pool_id, r.slots = adm
+            # runs of consecutive slots: (first slot, first env, length)
+            brk = np.flatnonzero(np.diff(r.slots.astype(np.int64)) != 1) + 1
+            starts = np.concatenate([[0], brk])
+            ends = np.concatenate([brk, [len(r.slots)]])
+            r.runs = [(int(r.slots[a]), int(a), int(b - a)) for a, b in zip(starts, ends)]
             r.t0 = T
             r.t_admit = clock() - t0
             if recorded(r):
@@ -220,27 +258,34 @@ def serve(spec, groups: List[W.Group], backend, *, record=False,
                 r.dones = np.zeros((g.steps, g.size), dtype=np.uint8)
             queue.remove(r)
             resident[r.pool_id] = r
-            resident_envs += g.size
-            write_window(r, T)
-            finish_at[T + g.steps - 1].append(r)
+            write_window(r, 0)
+            last = T + (g.steps - 1) // K
+            finish_at[last].append(r)
+            if g.steps % K:
+                short_at[last].append(r)
         changed = False
         if resident:
             if len(inflight) >= depth:
                 collect()
-            for r in refill_at.pop(T, ()):
-                write_window(r, T)
+            for r, k0 in refill_at.pop(T, ()):
+                write_window(r, k0)
+            # slots that stop inside this tick run only their remaining steps
+            short = short_at.pop(T, ())
+            for r in short:
+                budget[r.slots] = r.group.steps % K
             t_launch = clock() - t0
-            ticket = backend.launch(T % R)
+            ticket = backend.launch(T, budget if K > 1 else None)
+            for r in short:
+                budget[r.slots] = K
             members = [r for r in resident.values() if recorded(r)] if record else []
             inflight.append((ticket, T, len(resident), members, t_launch))
-            busy_env_steps += resident_envs
+            busy_env_steps += sum(r.group.size * min(K, r.group.steps - (T - r.t0) * K) for r in resident.values())
             finished = finish_at.pop(T, ())
             if any(recorded(r) for r in finished):
                 while inflight:
                     collect()
             for r in finished:
                 resident.pop(r.pool_id)
-                resident_envs -= r.group.size
                 if recorded(r):
                     r.final_obs = backend.obs_of(r.slots)
                     r.final_state = backend.state_of(r.slots)
@@ -267,12 +312,13 @@ def serve(spec, groups: List[W.Group], backend, *, record=False,
     p99 = _weighted_percentile(lat, wts, 99)
     if log:
         log(f"serving: {len(runs)} groups, {total} env steps in {t_end:.2f} s, "
-            f"{len(tick_ms)} ticks, p50/p99 step latency {p50:.3f}/{p99:.3f} ms")
+            f"{len(tick_ms)} ticks of {K} steps, p50/p99 tick latency {p50:.3f}/{p99:.3f} ms")
     return {
         "runs": runs,
         "wall_s": t_end,
         "env_steps": total,
         "env_steps_per_s": total / t_end if t_end > 0 else float("nan"),
+        "steps_per_tick": K,
         "ticks": len(tick_ms),
         "tick_ms_mean": float(np.mean(tick_ms)) if tick_ms else float("nan"),
         "busy_env_steps_per_s": (busy_env_steps / (np.sum(tick_ms) * 1e-3)) if tick_ms else float("nan"),

@@ -839,7 +839,7 @@ def group_actions(group: Group, step0: int, count: int, num_actions: int) -> np.
     while s < step0 + count:
         c = s // ACTION_CHUNK
         g = np.random.Generator(np.random.PCG64([group.seed, 3, c]))
-        chunk = (g.integers(0, 1 << 30, size=(ACTION_CHUNK, group.size)) % num_actions).astype(np.int32)
+        chunk = g.integers(0, num_actions, size=(ACTION_CHUNK, group.size), dtype=np.int32)
         lo, hi = s - c * ACTION_CHUNK, min(step0 + count - c * ACTION_CHUNK, ACTION_CHUNK)
         out[s - step0:s - step0 + hi - lo] = chunk[lo:hi]
         s += hi - lo

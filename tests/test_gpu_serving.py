@@ -84,10 +84,14 @@ def test_pool_admit_retire_and_info():
     pool.close()
 
 
-@pytest.mark.parametrize("depth,wrappers,profile,edges", [(1, False, False, False), (2, False, False, False),
-                                                         (2, True, False, False), (2, False, True, False),
-                                                         (2, False, False, True)])
-def test_groups_in_the_mix_match_groups_alone(depth, wrappers, profile, edges):
+@pytest.mark.parametrize("depth,wrappers,profile,edges,K", [(1, False, False, False, 1), (2, False, False, False, 1),
+                                                           (2, True, False, False, 1), (2, False, True, False, 1),
+                                                           (2, False, False, True, 1), (2, False, False, False, 4),
+                                                           (2, True, False, False, 3), (1, False, True, False, 5)])
+def test_groups_in_the_mix_match_groups_alone(depth, wrappers, profile, edges, K):
+    """Ticks of K steps: a group whose last step falls inside a tick stops
+    there (per-slot step budget), with the per-lane reset variant (wrappers)
+    and the quirk variant too."""
     from oracle import oracle as O
     from paper_2510_01764_amd import serving as S
     from paper_2510_01764_amd import workload as W
@@ -107,7 +111,7 @@ def test_groups_in_the_mix_match_groups_alone(depth, wrappers, profile, edges):
         spec = W.with_profile(spec, quirks=0x7F, seed=3)
     groups = W.serving_groups(18, rate=3000.0, seed=21, n_roms=32, max_size=400,
                               min_steps=20, max_steps=70)
-    be = S.PoolBackend(spec, pool_bytes=700 * 5470, depth=depth)
+    be = S.PoolBackend(spec, pool_bytes=700 * 5470, depth=depth, steps_per_tick=K)
     out = S.serve(spec, groups, be, record=True)
     be.close()
     runs = out["runs"]
@@ -135,9 +139,9 @@ def test_groups_in_the_mix_match_groups_alone(depth, wrappers, profile, edges):
 def test_full_size_serving_sampled_groups_match_alone():
     """The serving workload at full size: 2,000 groups over 32 ROMs, sizes
     log-uniform in 1..4,096, 200-2,000 steps, Poisson arrivals, on a pool of
-    65,536 slots.  Eight groups spread over the sizes are recorded in the mix
-    and replayed alone; all their rewards, done flags, last observations and
-    final states agree."""
+    65,536 slots in ticks of 8 steps.  Eight groups spread over the sizes are
+    recorded in the mix and replayed alone; all their rewards, done flags,
+    last observations and final states agree."""
     from paper_2510_01764_amd import octax as X
     from paper_2510_01764_amd import serving as S
     from paper_2510_01764_amd import workload as W
@@ -145,7 +149,7 @@ def test_full_size_serving_sampled_groups_match_alone():
     groups = W.serving_groups(2000, rate=180.0, seed=3)
     by_size = sorted(groups, key=lambda g: g.size)
     sample = {by_size[int(q * (len(by_size) - 1))].gid for q in (0.0, 0.2, 0.4, 0.6, 0.8, 0.9, 0.97, 1.0)}
-    be = S.PoolBackend(spec, pool_bytes=65536 * X.Pool.slot_bytes(), depth=2)
+    be = S.PoolBackend(spec, pool_bytes=65536 * X.Pool.slot_bytes(), depth=2, steps_per_tick=8)
     out = S.serve(spec, groups, be, record=sample)
     be.close()
     runs = {r.group.gid: r for r in out["runs"]}
@@ -157,3 +161,49 @@ def test_full_size_serving_sampled_groups_match_alone():
         assert np.array_equal(r.dones, done), f"group {gid}: done flags differ"
         assert np.array_equal(r.final_obs, obs), f"group {gid}: last observation differs"
         compare_gpu_states(r.final_state, state, f"group {gid} in the pool vs alone")
+
+
+def test_pool_step_budget_stops_each_slot_after_its_steps():
+    """octax_pool_step_budget: slots with budgets 0..K (and beyond K, clipped)
+    run exactly that many steps: their rewards and done flags for those steps
+    and their states afterwards equal an engine of the same envs stepped that
+    many steps alone."""
+    import dataclasses
+    import torch
+    from paper_2510_01764_amd import octax as X
+    from paper_2510_01764_amd import workload as W
+    spec = W.make_config("c4")
+    K, n, rom = 6, 96, 3
+    pool = X.Pool(spec, pool_bytes=n * X.Pool.slot_bytes())
+    rng = np.random.default_rng(4)
+    seeds = rng.integers(0, 2**63, size=n, dtype=np.uint64)
+    hor = rng.integers(1, 12, size=n).astype(np.uint32)   # resets inside the launch
+    _, slots = pool.admit(rom, seeds, hor)
+    assert list(slots) == list(range(n))
+    budget = (np.arange(n) % (K + 1)).astype(np.uint8)
+    budget[::13] = 200
+    steps = np.minimum(budget.astype(int), K)
+    act = torch.from_numpy(rng.integers(0, 8, size=(K, n)).astype(np.int32)).cuda()
+    rew = torch.zeros((K, n), dtype=torch.float32, device="cuda")
+    done = torch.zeros((K, n), dtype=torch.uint8, device="cuda")
+    pool.step(act, None, rew, done, budget=torch.from_numpy(budget).cuda())
+    torch.cuda.synchronize()
+    r_p, d_p = rew.cpu().numpy(), done.cpu().numpy()
+    st_p = pool.get_state(slots)
+    alone = dataclasses.replace(spec, env_rom=np.full(n, rom, dtype=np.uint16), horizon=hor, env_seed=seeds)
+    resets = 0
+    for b in range(K + 1):
+        envs = np.flatnonzero(steps == b)
+        eng = X.Engine(alone, kernel="fused")
+        if b:
+            r = torch.zeros((b, n), dtype=torch.float32, device="cuda")
+            d = torch.zeros((b, n), dtype=torch.uint8, device="cuda")
+            eng.step_many(act[:b].contiguous(), None, r, d)
+            torch.cuda.synchronize()
+            assert np.array_equal(r_p[:b, envs], r.cpu().numpy()[:, envs]), b
+            assert np.array_equal(d_p[:b, envs], d.cpu().numpy()[:, envs]), b
+            resets += int((d.cpu().numpy()[:, envs] != 0).sum())
+        compare_gpu_states(st_p[envs], eng.get_state()[envs], f"budget {b} vs {b} steps alone")
+        eng.close()
+    assert resets > 0, "resets happen inside the launch"
+    pool.close()

@@ -1,10 +1,11 @@
 """Host logic of the serving loop, on the CPU with a stand-in backend.
 
 The stand-in keeps the pool's contract (a group takes the lowest-numbered
-free slots of a fixed capacity, admission refused when too few are free, one
-result vector per tick indexed by slot) and reports, as each slot's reward,
-the tick number and the slot, so the tests can check which group stepped
-where and when.
+free slots of a fixed capacity, admission refused when too few are free;
+each tick runs K steps, slot s stopping after budget[s] of them, with one
+result row per step indexed by slot) and reports, as each slot's reward,
+the global step number and the slot, so the tests can check which group
+stepped where and when.
 """
 import numpy as np
 import pytest
@@ -14,17 +15,20 @@ from paper_2510_01764_amd import workload as W
 
 
 class FakeBackend:
-    def __init__(self, capacity, depth=2, rows=128):
+    def __init__(self, capacity, depth=2, rows=128, steps_per_tick=1):
         self.capacity = capacity
         self.depth = depth
-        self.rows = rows
-        self.sched = np.zeros((rows, capacity), dtype=np.int32)
+        self.K = steps_per_tick
+        self.rows = max(rows, S.WINDOW + (depth + 1) * self.K)
+        self.rows = -(-self.rows // self.K) * self.K
+        self.sched = np.zeros((self.rows, capacity), dtype=np.int32)
         self.groups = {}
         self.next_id = 0
         self.occupied = np.zeros(capacity, dtype=np.int32)
-        self.ticks = []                     # per tick: copy of the occupied map
+        self.ticks = []                     # per tick: (tick number, occupied map, budgets)
         self.n = 0
-        self.acts = []
+        self.acts = {}                      # global step -> action row sent
+        self.steps_run = np.zeros(capacity, dtype=np.int64)   # steps each slot ran while occupied
         self.max_used = 0
 
     def admit(self, rom, seeds, horizons):
@@ -33,6 +37,7 @@ class FakeBackend:
             return None
         slots = free[:len(seeds)].astype(np.uint32)
         self.occupied[slots] = 1
+        self.steps_run[slots] = 0
         self.max_used = max(self.max_used, int(self.occupied.sum()))
         gid = self.next_id
         self.next_id += 1
@@ -45,15 +50,20 @@ class FakeBackend:
     def schedule(self):
         return self.sched
 
-    def launch(self, row):
-        self.ticks.append(self.occupied.copy())
-        self.acts.append(self.sched[row].copy())
+    def launch(self, tick, budget):
+        b = np.full(self.capacity, self.K) if budget is None else budget.astype(np.int64).copy()
+        self.ticks.append((tick, self.occupied.copy(), b))
+        for i in range(self.K):
+            self.acts[tick * self.K + i] = self.sched[(tick * self.K + i) % self.rows].copy()
+        self.steps_run += np.where(self.occupied != 0, np.minimum(b, self.K), 0)
         self.n += 1
         return self.n - 1
 
     def wait(self, ticket):
-        rew = (ticket * 1000 + np.arange(self.capacity)).astype(np.float32)   # exact below 2^24
-        done = (self.ticks[ticket] != 0).astype(np.uint8)
+        tick, occ, b = self.ticks[ticket]
+        steps = tick * self.K + np.arange(self.K)
+        rew = (steps[:, None] * 1000 + np.arange(self.capacity)[None, :]).astype(np.float32)   # exact below 2^24
+        done = ((occ[None, :] != 0) & (np.arange(self.K)[:, None] < b[None, :])).astype(np.uint8)
         return rew, done, 0.1
 
     def finish(self):
@@ -63,7 +73,7 @@ class FakeBackend:
         return np.zeros((len(slots), 4, 64, 32), dtype=np.uint8)
 
     def state_of(self, slots):
-        return np.zeros(len(slots))
+        return self.steps_run[slots].copy()
 
 
 class FakeClock:
@@ -86,11 +96,11 @@ def _groups(n, rate, max_size=300, steps=(5, 30), seed=11):
     return gs
 
 
-@pytest.mark.parametrize("depth", [1, 2, 3])
-def test_every_group_runs_exactly_its_steps_in_its_own_slots(depth):
+@pytest.mark.parametrize("depth,K", [(1, 1), (2, 1), (3, 1), (2, 4), (1, 5), (3, 8)])
+def test_every_group_runs_exactly_its_steps_in_its_own_slots(depth, K):
     spec = W.make_config("c4")
     groups = _groups(40, rate=400.0, steps=(5, 150))
-    be = FakeBackend(capacity=700, depth=depth)
+    be = FakeBackend(capacity=700, depth=depth, steps_per_tick=K)
     clk = FakeClock()
     out = S.serve(spec, groups, be, record=True, clock=clk, sleep=clk.sleep)
     runs = out["runs"]
@@ -98,16 +108,20 @@ def test_every_group_runs_exactly_its_steps_in_its_own_slots(depth):
     for r in runs:
         g = r.group
         assert r.t_admit >= r.t_arrival and r.t_done > r.t_admit
-        # recorded rewards identify (tick, slot): consecutive ticks, the group's own slots
-        ticks = (r.rewards[:, 0] // 1000).astype(int)
+        # recorded rewards identify (global step, slot): consecutive steps, the group's own slots
+        steps = (r.rewards[:, 0] // 1000).astype(int)
         slots = (r.rewards % 1000).astype(int)
-        assert np.all(np.diff(ticks) == 1), "a resident group steps in every tick"
+        assert np.all(np.diff(steps) == 1), "a resident group steps in every step of every tick"
+        assert steps[0] % K == 0, "a group starts at a tick boundary"
         assert np.all(slots == r.slots[None, :].astype(int))
-        # the actions sent in those ticks are the group's own stream
+        assert r.dones.all(), "every recorded step of the group ran"
+        # the group's slots ran exactly its steps (the budget stops it inside its last tick)
+        assert np.all(r.final_state == g.steps)
+        # the actions sent in those steps are the group's own stream
         for k in sorted({0, 63, 64, 65, g.steps // 2, g.steps - 1}):
             if k >= g.steps:
                 continue
-            sent = be.acts[ticks[k]][r.slots]
+            sent = be.acts[steps[k]][r.slots]
             assert np.array_equal(sent, W.group_actions(g, k, 1, int(spec.num_actions[g.rom]))[0])
     assert be.max_used <= be.capacity
     assert not be.groups, "every group was retired"
@@ -144,6 +158,11 @@ def test_idle_pool_sleeps_until_next_arrival():
     out = S.serve(spec, gs, be, clock=clk, sleep=clk.sleep)
     assert out["runs"][1].t_admit >= 5.0
     assert be.n == 6
+    # with ticks of two steps a group of three steps takes two ticks
+    be2 = FakeBackend(capacity=64, steps_per_tick=2)
+    clk2 = FakeClock()
+    S.serve(spec, gs, be2, clock=clk2, sleep=clk2.sleep)
+    assert be2.n == 4
 
 
 def test_group_generators_are_slot_independent_and_windowed():
