@@ -271,6 +271,11 @@ struct FusedMem {
         touch(pc >> 6);
         return op;
     }
+    // The instruction word alone (the switch cycle of exec_one).
+    __device__ __forceinline__ uint32_t fetch(uint32_t pc) {
+        uint32_t ret;
+        return fetch(pc, 0u, ret);
+    }
     // Sixteen bytes of a run of memory that lies on page q0 from byte `off`
     // on and goes on at page q1 (both LDS page bases; off may be below 0 or
     // the run may end before q1 is reached: those bytes are unspecified).
@@ -655,15 +660,27 @@ __device__ __forceinline__ bool keep_waiting(bool &waiting, uint64_t &since, uin
 // One environment step of emulation with `key` held: frame_skip frames of
 // ipf instructions, each followed by a timer tick.  With the display-wait
 // quirk (kProfile variants only) a lane's DXYN ends its frame: the lane sits
-// out the frame's remaining instruction slots.
-template <bool kProfile, class Mem>
+// out the frame's remaining instruction slots.  With kSparse (the per-lane
+// variants), an instruction slot run by at most kSparseLanes lanes takes the
+// switch of exec_one instead of the grouped cycle: with few lanes left (the
+// envs still in their reset steps at the end of a launch) the wave then runs
+// only the handlers those lanes need, instead of the grouped cycle's selects
+// for every class.  Both are the same instruction set (octax_core.h).
+constexpr uint32_t kSparseLanes = 4;
+template <bool kProfile, bool kSparse, class Mem>
 __device__ __forceinline__ void run_frames(Core &c, Mem &mem, uint32_t key, uint32_t ipf, uint32_t fs,
                                            uint32_t quirks) {
     for (uint32_t f = 0; f < fs; f++) {
         bool run = true;
         for (uint32_t i = 0; i < ipf; i++) {
             if (!kProfile || run) {
-                const bool drew = exec_grouped(c, mem, key, quirks);
+                bool drew;
+                if (kSparse && __builtin_popcountll(__builtin_amdgcn_ballot_w64(true)) <= kSparseLanes) {
+                    drew = exec_one(c, mem, key, quirks);
+                    mem.top = mem.stack_get((c.sp - 1) & 15);   // the register copy of the top entry
+                } else {
+                    drew = exec_grouped(c, mem, key, quirks);
+                }
                 run = !(drew && (quirks & kQuirkDisplayWait));
             }
         }
@@ -992,7 +1009,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                         key = sticky_key(roms, c, key_of_step(k));
                     }
                     else if (phase == 1) key = su[1 + si];
-                    run_frames<kProfile>(c, mem, key, io.ipf, io.frame_skip, quirks);
+                    run_frames<kProfile, true>(c, mem, key, io.ipf, io.frame_skip, quirks);
                     if (phase == 0) {
                         const int32_t score = score_of(c.r, desc, desc2);
                         const float reward = (float)(score - prev);
@@ -1160,7 +1177,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
             // does not hold a register through the emulator loop)
             if (active && (!cfg.budget || k < sh.budget[l])) {
                 const uint32_t key = sticky_key(roms, c, key_of_step(k));
-                run_frames<kProfile>(c, mem, key, io.ipf, io.frame_skip, quirks);
+                run_frames<kProfile, false>(c, mem, key, io.ipf, io.frame_skip, quirks);
                 const int32_t score = score_of(c.r, desc, desc2);
                 const float reward = (float)(score - prev);
                 const uint32_t term = terminated_of(c.r, desc, desc2);
@@ -1177,7 +1194,7 @@ __global__ __launch_bounds__(2 * IPW) void step_fused_kernel(State s, Roms roms,
                     mem.stack_clear();
                     if (kResetSteps) {
                         run_reset_steps(roms, rom, c, [&](uint32_t rkey) {
-                            run_frames<kProfile>(c, mem, rkey, io.ipf, io.frame_skip, quirks);
+                            run_frames<kProfile, false>(c, mem, rkey, io.ipf, io.frame_skip, quirks);
                         });
                     }
                     head = 0;
