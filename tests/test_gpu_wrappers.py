@@ -98,3 +98,18 @@ def test_wrappers_masked_reset():
         compare_states(eng.get_state(), orc.get_state(), f"masked reset {kernel}")
         eng.close()
         orc.close()
+
+
+@pytest.mark.parametrize("chains", [1, 2, 5])
+def test_wrappers_lone_reset_chains(chains):
+    """One block whose envs never truncate except `chains` of them with a
+    horizon of one step: each of those resets at every step and runs up to 30
+    no-op steps and its start-up sequence, so its lane goes on alone (or with
+    one other lane of its wave, for chains = 5) for hundreds of slots after
+    the rest of its wave has finished the launch."""
+    spec = _wrapped(256, sticky=0.25, noop_max=30, seed=5, mean_horizon=1000.0)
+    horizon = np.zeros(256, dtype=np.uint32)          # 0: no truncation
+    horizon[[3, 77, 130, 200, 255][:chains]] = 1
+    spec = dataclasses.replace(spec, horizon=horizon)
+    resets = _run(spec, "fused", K=16, launches=2)
+    assert resets >= 2 * 16 * chains
