@@ -48,6 +48,7 @@ class GroupRun:
     seeds: Optional[np.ndarray] = None     # per-env RNG seeds and horizons, drawn on arrival
     horizons: Optional[np.ndarray] = None
     runs: Optional[list] = None            # runs of consecutive slots while resident
+    stream: Optional[np.random.PCG64] = None   # its action stream, drawn one window after another
 
 
 class PoolBackend:
@@ -204,11 +205,15 @@ def serve(spec, groups: List[W.Group], backend, *, record=False,
         one block copy per run of consecutive slots and of ring rows."""
         g = r.group
         n = min(WINDOW, g.steps - k0)
-        acts = W.group_actions(g, k0, n, r.num_actions)
         row0 = (r.t0 * K + k0) % R
         parts = [(row0, 0, min(n, R - row0))]
         if parts[0][2] < n:
             parts.append((0, parts[0][2], n - parts[0][2]))
+        # windows are the group's action chunks in order (WINDOW ==
+        # ACTION_CHUNK), drawn from one stream per group
+        if r.stream is None:
+            r.stream = W.action_stream(g)
+        acts = W.actions_from_words(W.group_action_words(g, k0 // WINDOW, r.stream), r.num_actions)
         for s0, i0, m in r.runs:
             for q0, a0, c in parts:
                 sched[q0:q0 + c, s0:s0 + m] = acts[a0:a0 + c, i0:i0 + m]

@@ -828,20 +828,42 @@ def group_env_seeds(group: Group) -> np.ndarray:
 ACTION_CHUNK = 64
 
 
-def group_actions(group: Group, step0: int, count: int, num_actions: int) -> np.ndarray:
-    """Actions of a serving group for steps [step0, step0+count) as int32 [count, size].
+def action_stream(group: Group) -> np.random.PCG64:
+    """The random stream of a serving group's actions: PCG64 seeded [seed, 3]."""
+    return np.random.PCG64([group.seed, 3])
 
-    Steps are drawn in chunks of ``ACTION_CHUNK`` from one stream per chunk,
-    uniform over the ROM's key actions, so any window is cheap to produce.
-    """
+
+def group_action_words(group: Group, c: int, stream: Optional[np.random.PCG64] = None) -> np.ndarray:
+    """The random words of a serving group's action chunk c (steps
+    [c * ACTION_CHUNK, (c + 1) * ACTION_CHUNK)) as uint16 [ACTION_CHUNK, size]:
+    64-bit outputs c * n .. (c + 1) * n - 1 of its action stream
+    (n = ACTION_CHUNK * size / 4), in step-major order.  `stream`, if given,
+    must stand at output c * n (a stream drawn chunk after chunk does)."""
+    n = ACTION_CHUNK * group.size // 4
+    if stream is None:
+        stream = action_stream(group)
+        stream.advance(c * n)
+    return stream.random_raw(n).view(np.uint16).reshape(ACTION_CHUNK, group.size)
+
+
+def actions_from_words(u: np.ndarray, num_actions: int) -> np.ndarray:
+    """(u * num_actions) >> 16 as int32: uniform over the ROM's key actions up
+    to a bias below num_actions / 2^16."""
+    t = np.multiply(u, num_actions, dtype=np.int32)
+    t >>= 16
+    return t
+
+
+def group_actions(group: Group, step0: int, count: int, num_actions: int) -> np.ndarray:
+    """Actions of a serving group for steps [step0, step0+count) as int32 [count, size],
+    drawn a chunk of ``ACTION_CHUNK`` steps at a time from one stream per chunk
+    (group_action_words, actions_from_words), so any window is cheap to produce."""
     out = np.empty((count, group.size), dtype=np.int32)
     s = step0
     while s < step0 + count:
         c = s // ACTION_CHUNK
-        g = np.random.Generator(np.random.PCG64([group.seed, 3, c]))
-        chunk = g.integers(0, num_actions, size=(ACTION_CHUNK, group.size), dtype=np.int32)
         lo, hi = s - c * ACTION_CHUNK, min(step0 + count - c * ACTION_CHUNK, ACTION_CHUNK)
-        out[s - step0:s - step0 + hi - lo] = chunk[lo:hi]
+        out[s - step0:s - step0 + hi - lo] = actions_from_words(group_action_words(group, c)[lo:hi], num_actions)
         s += hi - lo
     return out
 
