@@ -195,7 +195,7 @@ def serving_run(args, log):
     from paper_2510_01764_amd import octax as X
     spec = W.make_config("c4")
     K = args.serving_steps_per_tick
-    be = S.PoolBackend(spec, args.serving_slots * X.Pool.slot_bytes(), depth=2, steps_per_tick=K)
+    be = S.PoolBackend(spec, args.serving_slots * X.Pool.slot_bytes(), depth=args.serving_depth, steps_per_tick=K)
     # sustained rate: groups of the workload's sizes that fill the pool at
     # once, all running 400 steps (the loop's steady state at full occupancy)
     burst, used = [], 0
@@ -205,7 +205,8 @@ def serving_run(args, log):
             used += g.size
     cal = S.serve(spec, burst, be)
     capacity = cal["env_steps_per_s"]
-    log(f"serving: sustained {capacity / 1e6:.1f} M env steps/s with the pool kept full, {K} steps per tick")
+    log(f"serving: sustained {capacity / 1e6:.1f} M env steps/s with the pool kept full, {K} steps per tick, "
+        f"{args.serving_depth} ticks in flight")
     probe = W.serving_groups(args.serving_groups, 1.0, seed=3)
     mean_work = float(np.mean([g.size * g.steps for g in probe]))
     loads = {}
@@ -234,6 +235,7 @@ def serving_run(args, log):
                     f"200-2000 steps, Poisson arrivals at the given fractions of the sustained rate",
         "pool_slots": args.serving_slots,
         "steps_per_tick": K,
+        "ticks_in_flight": args.serving_depth,
         "sustained_env_steps_per_s": capacity,
         "sustained_def": "groups filling the pool admitted at once, 400 steps each: env steps over wall time",
         "loads": loads,
@@ -292,9 +294,13 @@ def main():
     ap.add_argument("--serving-loads", type=lambda t: [float(x) for x in t.split(",")], default=[0.4, 0.7, 0.9],
                     help="offered loads as fractions of the pool's measured sustained rate")
     ap.add_argument("--serving-slots", type=int, default=65536)
+    ap.add_argument("--serving-depth", type=int, default=2,
+                    help="serving ticks in flight (more overlap of the host loop with the device, longer tick latency)")
     ap.add_argument("--serving-steps-per-tick", type=int, default=8,
                     help="env steps per serving tick (1..255)")
     args = ap.parse_args()
+    if args.serving_depth < 1:
+        ap.error("--serving-depth must be at least 1")
     if args.headline_only:
         args.no_cpu = args.no_plain = args.no_by_rom = args.no_wrappers = args.no_profile = True
         args.no_programs = args.no_schip = True
