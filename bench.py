@@ -297,7 +297,7 @@ def main():
     ap.add_argument("--serving-depth", type=int, default=2,
                     help="serving ticks in flight (more overlap of the host loop with the device, longer tick latency)")
     ap.add_argument("--serving-steps-per-tick", type=int, default=8,
-                    help="env steps per serving tick (1..255)")
+                    help="env steps per serving tick (1..64, one action window)")
     args = ap.parse_args()
     if args.serving_depth < 1:
         ap.error("--serving-depth must be at least 1")

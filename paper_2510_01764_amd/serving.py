@@ -175,6 +175,8 @@ def serve(spec, groups: List[W.Group], backend, *, record=False,
     depth = backend.depth
     K = getattr(backend, "K", 1)
     R = backend.rows
+    if K > WINDOW:
+        raise ValueError(f"at most {WINDOW} steps per tick (one action window per group and tick)")
     if R % K or R < WINDOW + (depth + 1) * K:
         raise ValueError("the schedule ring must be a multiple of K rows holding a window plus the ticks in flight")
     sched = backend.schedule()

@@ -205,3 +205,12 @@ def test_recorded_sample_sees_its_own_slots():
             assert np.all(slots == r.slots[None, :].astype(int))
         else:
             assert r.rewards is None
+
+
+def test_ticks_longer_than_an_action_window_are_rejected():
+    # a tick reads one window of each group's actions; a longer tick would
+    # run steps whose actions were never written
+    spec = W.make_config("c4")
+    be = FakeBackend(capacity=64, depth=2, steps_per_tick=S.WINDOW + 1)
+    with pytest.raises(ValueError):
+        S.serve(spec, [W.Group(0, 0.0, 1, 8, 10, 5)], be)
