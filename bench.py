@@ -439,10 +439,10 @@ def main():
         if not args.no_by_rom:
             plain["by_rom"] = timed_leg("plain", "by_rom", max(2, args.steps // 4))
 
-    def variant_leg(vspec, pool=None):
+    def variant_leg(vspec, pool=None, placement="identity"):
         """Graph replays of the same launch shape under another spec; (env steps/s, ms per replay, replays)."""
         pool = act_pool if pool is None else pool
-        engv = X.Engine(vspec, kernel="fused", placement="identity", envs_per_block=tuning["envs_per_block"],
+        engv = X.Engine(vspec, kernel="fused", placement=placement, envs_per_block=tuning["envs_per_block"],
                         rom_in_lds=tuning["rom_in_lds"], stream=stream)
         gv = engv.graph(act, obs, rew, done)
         time_replays(torch, stream, gv, act, pool, 1, 0)
@@ -457,16 +457,22 @@ def main():
         engv.status()
         engv.close()
         return {"value": E * K * n_v / vwall, "ms_per_step": vwall * 1e3 / n_v, "replays": n_v,
-                "resets_per_env_step": resets, "placement": "identity"}
+                "resets_per_env_step": resets, "placement": placement}
 
     # the same workload with the environment wrappers of Section 3.2 on
     wrappers = None
     if not args.no_wrappers:
         wspec = W.with_wrappers(spec, sticky=0.25, noop_max=30, startup_max=3, seed=1)
-        wrappers = variant_leg(wspec)
+        # envs spread over the wavefronts by horizon, so that the envs that
+        # reset most often run their reset steps in different wavefronts; the
+        # identity placement beside it
+        wrappers = variant_leg(wspec, placement="by_horizon")
+        ident = variant_leg(wspec)
         wrappers.update({"sticky_prob": 0.25, "noop_max": 30,
-                         "startup_steps": [int(x) for x in wspec.startup_len]})
-        log(f"wrappers: {wrappers['value'] / 1e6:.1f} M env steps/s ({wrappers['ms_per_step']:.2f} ms per replay)")
+                         "startup_steps": [int(x) for x in wspec.startup_len],
+                         "identity": {"value": ident["value"], "ms_per_step": ident["ms_per_step"]}})
+        log(f"wrappers: {wrappers['value'] / 1e6:.1f} M env steps/s ({wrappers['ms_per_step']:.2f} ms per replay; "
+            f"identity placement {ident['value'] / 1e6:.1f} M)")
 
     # ... and with the quirk flags and per-ROM game descriptors (Section 3.3).
     # Display wait stays off: it cuts the instructions run per frame, so the

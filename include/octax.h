@@ -116,8 +116,12 @@ enum octax_platform {
 
 /* Placement of envs in the engine's state slots. */
 enum octax_placement {
-    OCTAX_PLACE_IDENTITY = 0, /* slot = env index */
-    OCTAX_PLACE_BY_ROM = 1    /* slots sorted by ROM id (stable), so workgroups share ROMs */
+    OCTAX_PLACE_IDENTITY = 0,  /* slot = env index */
+    OCTAX_PLACE_BY_ROM = 1,    /* slots sorted by ROM id (stable), so workgroups share ROMs */
+    OCTAX_PLACE_BY_HORIZON = 2 /* envs in order of truncation horizon (shortest first, 0 = none last,
+                                  stable), dealt round-robin over the wavefronts of 64 slots: the envs
+                                  that reset most often, whose resets run the start-up and no-op steps
+                                  of Section 3.2, land in different wavefronts */
 };
 
 typedef struct octax_config {

@@ -356,7 +356,7 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
         return fail(OCTAX_E_INVALID, "octax_create: instr_per_frame out of range");
     if (cfg->frame_skip == 0 || cfg->frame_skip > 64) return fail(OCTAX_E_INVALID, "octax_create: frame_skip out of range");
     if (cfg->kernel > OCTAX_KERNEL_FUSED) return fail(OCTAX_E_INVALID, "octax_create: unknown kernel");
-    if (cfg->placement > OCTAX_PLACE_BY_ROM) return fail(OCTAX_E_INVALID, "octax_create: unknown placement");
+    if (cfg->placement > OCTAX_PLACE_BY_HORIZON) return fail(OCTAX_E_INVALID, "octax_create: unknown placement");
     if (cfg->lanes_per_env > 1) return fail(OCTAX_E_INVALID, "octax_create: lanes_per_env must be 0 or 1");
     const uint32_t ipw = cfg->envs_per_block ? cfg->envs_per_block : 256;
     if (ipw != 64 && ipw != 128 && ipw != 256) return fail(OCTAX_E_INVALID, "octax_create: envs_per_block must be 64, 128 or 256");
@@ -413,6 +413,22 @@ int32_t octax_create(const octax_config *cfg, octax_engine **out) {
     if (g->placement == OCTAX_PLACE_BY_ROM)
         std::stable_sort(g->env_of.begin(), g->env_of.end(),
                          [&](uint32_t a, uint32_t b) { return cfg->h_env_rom[a] < cfg->h_env_rom[b]; });
+    if (g->placement == OCTAX_PLACE_BY_HORIZON) {
+        // envs by horizon (0: none, after every finite one), then the i-th of
+        // them into the i-th slot of the order lane 0 of every wavefront,
+        // lane 1 of every wavefront, ... (slots past E skipped)
+        std::vector<uint32_t> by_h(E);
+        for (uint32_t e = 0; e < E; e++) by_h[e] = e;
+        auto key = [&](uint32_t e) { return cfg->h_horizon[e] ? (uint64_t)cfg->h_horizon[e] : (uint64_t)1 << 32; };
+        std::stable_sort(by_h.begin(), by_h.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
+        const uint32_t waves = (E + 63) / 64;
+        uint32_t i = 0;
+        for (uint32_t lane = 0; lane < 64; lane++)
+            for (uint32_t w = 0; w < waves; w++) {
+                const uint32_t sl = w * 64 + lane;
+                if (sl < E) g->env_of[sl] = by_h[i++];
+            }
+    }
     g->slot_of.resize(E);
     g->rom_of.resize(E);
     std::vector<uint32_t> horizon(E);

@@ -35,6 +35,7 @@ OCTAX_PLATFORM_CHIP8 = 0
 OCTAX_PLATFORM_SCHIP = 1
 OCTAX_PLACE_IDENTITY = 0
 OCTAX_PLACE_BY_ROM = 1
+OCTAX_PLACE_BY_HORIZON = 2
 OBS_BYTES = 8192
 NOALLOC_MAX_ENVS = 64          # octax_get_state_noalloc's largest range
 
@@ -262,7 +263,8 @@ class Engine:
         cfg.frame_skip = int(spec.frame_skip)
         cfg.quirks = OCTAX_QUIRKS_V1
         cfg.kernel = {"plain": OCTAX_KERNEL_PLAIN, "fused": OCTAX_KERNEL_FUSED}[kernel]
-        cfg.placement = {"identity": OCTAX_PLACE_IDENTITY, "by_rom": OCTAX_PLACE_BY_ROM}[placement]
+        cfg.placement = {"identity": OCTAX_PLACE_IDENTITY, "by_rom": OCTAX_PLACE_BY_ROM,
+                         "by_horizon": OCTAX_PLACE_BY_HORIZON}[placement]
         cfg.envs_per_block = int(envs_per_block)
         cfg.lanes_per_env = 1
         cfg.rom_in_lds = 1 if rom_in_lds else 0

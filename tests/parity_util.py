@@ -84,7 +84,7 @@ def compare_schip(gpu_sx, oracle_sx, where=""):
     assert np.array_equal(schip_pixels(gpu_sx["hist"]), oracle_sx["hist"]), f"{where}: frame history differs"
 
 
-def run_rollouts(spec, kernel, K, launches, envs_per_block=256, graph=False):
+def run_rollouts(spec, kernel, K, launches, envs_per_block=256, graph=False, placement=None):
     """K-step launches (or graph replays) of the engine beside the oracle:
     rewards, done flags and observations compared at every step, the full
     architectural state after every launch.  Returns the number of resets."""
@@ -93,7 +93,7 @@ def run_rollouts(spec, kernel, K, launches, envs_per_block=256, graph=False):
     from paper_2510_01764_amd import octax as X
     E = spec.num_envs
     dev = torch.device("cuda")
-    eng = X.Engine(spec, kernel=kernel, envs_per_block=envs_per_block)
+    eng = X.Engine(spec, kernel=kernel, envs_per_block=envs_per_block, placement=placement)
     orc = O.OracleBatch(spec)
     compare_states(eng.get_state(), orc.get_state(), f"{kernel} after create")
     act = torch.zeros((K, E), dtype=torch.int32, device=dev)

@@ -43,7 +43,8 @@ def test_c1_every_step_full_state(kernel):
 
 
 @pytest.mark.parametrize("kernel,placement", [("plain", "identity"), ("fused", "by_rom"),
-                                              ("fused", "identity"), ("plain", "by_rom")])
+                                              ("fused", "identity"), ("plain", "by_rom"),
+                                              ("fused", "by_horizon"), ("plain", "by_horizon")])
 def test_mixed_roms_small(kernel, placement):
     """Sixteen ROMs mixed within every wavefront, ragged env count, geometric horizons."""
     spec = _spec("c3", num_envs=1000)

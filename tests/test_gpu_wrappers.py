@@ -113,3 +113,10 @@ def test_wrappers_lone_reset_chains(chains):
     spec = dataclasses.replace(spec, horizon=horizon)
     resets = _run(spec, "fused", K=16, launches=2)
     assert resets >= 2 * 16 * chains
+
+
+def test_wrappers_by_horizon_placement():
+    """Envs dealt over the wavefronts in order of horizon (a ragged last
+    wavefront of 40 envs): every env's outputs and state as with the oracle."""
+    spec = _wrapped(1000, sticky=0.25, noop_max=12, seed=8, mean_horizon=12.0)
+    _run(spec, "fused", K=16, launches=2, placement="by_horizon")
