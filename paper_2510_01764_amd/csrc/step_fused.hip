@@ -676,8 +676,10 @@ __device__ __forceinline__ void run_frames(Core &c, Mem &mem, uint32_t key, uint
             if (!kProfile || run) {
                 bool drew;
                 if (kSparse && __builtin_popcountll(__builtin_amdgcn_ballot_w64(true)) <= kSparseLanes) {
+                    const uint32_t sp0 = c.sp;
                     drew = exec_one(c, mem, key, quirks);
-                    mem.top = mem.stack_get((c.sp - 1) & 15);   // the register copy of the top entry
+                    // a call sets the register copy of the top entry itself, a return pops it
+                    if (c.sp == ((sp0 - 1) & 15)) mem.stack_popped(c.sp);
                 } else {
                     drew = exec_grouped(c, mem, key, quirks);
                 }
