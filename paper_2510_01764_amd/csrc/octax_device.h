@@ -125,16 +125,15 @@ __device__ __forceinline__ uint64_t splitmix_next(uint64_t &s) {
 }
 __device__ __forceinline__ uint32_t rnd_byte(uint64_t &s) { return (uint32_t)(splitmix_next(s) >> 56); }
 
-// 16-byte observation store.  Plain stores: on MI355X they stream to HBM
-// faster than stores with the nontemporal hint (measured with the
-// calibration kernels); OCTAX_OBS_NONTEMPORAL selects the hinted form.
+// 16-byte observation store, with the nontemporal hint.  A kernel that only
+// streams writes is faster without it on MI355X (the calibration kernels),
+// but the step kernels read state, memory pages and displays while their
+// observations stream out, and the hinted stores leave that data in the
+// caches: measured, the fused step is 1.5-4 % faster with the hint and the
+// SUPER-CHIP step 8 %.
 __device__ __forceinline__ void store_stream(void *dst, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
     u32x4 v = {a, b, c, d};
-#ifdef OCTAX_OBS_NONTEMPORAL
     __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(dst));
-#else
-    *reinterpret_cast<u32x4 *>(dst) = v;
-#endif
 }
 
 // ---------------------------------------------------------------------------
