@@ -125,15 +125,13 @@ __device__ __forceinline__ uint64_t splitmix_next(uint64_t &s) {
 }
 __device__ __forceinline__ uint32_t rnd_byte(uint64_t &s) { return (uint32_t)(splitmix_next(s) >> 56); }
 
-// 16-byte observation store, with the nontemporal hint.  A kernel that only
-// streams writes is faster without it on MI355X (the calibration kernels),
-// but the step kernels read state, memory pages and displays while their
-// observations stream out, and the hinted stores leave that data in the
-// caches: measured, the fused step is 1.5-4 % faster with the hint and the
-// SUPER-CHIP step 8 %.
+// 16-byte observation store of one thread (the plain kernel and reset, each
+// thread writing its own env's observation): plain stores, which on MI355X
+// stream to HBM faster than hinted ones here (28 against 94 M env steps/s for
+// the plain kernel, measured).
 __device__ __forceinline__ void store_stream(void *dst, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
     u32x4 v = {a, b, c, d};
-    __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(dst));
+    *reinterpret_cast<u32x4 *>(dst) = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -203,9 +201,15 @@ __device__ __forceinline__ u32x4 spread16(uint32_t bits) {
     return u32x4{spread4(bits, 0), spread4(bits, 4), spread4(bits, 8), spread4(bits, 12)};
 }
 
-// 16 observation bytes at dst (16-byte aligned).
+// 16 observation bytes at dst (16-byte aligned), for stores in which a
+// wavefront covers 1 KB of contiguous observation (the fused and SUPER-CHIP
+// step kernels).  They carry the nontemporal hint: a kernel that only streams
+// writes is faster without it (the calibration kernels), but these kernels
+// read state, memory pages and displays while their observations stream out,
+// and the hinted stores leave that data in the caches; measured, the fused
+// step is 1.5-4 % faster with the hint and the SUPER-CHIP step 8 %.
 __device__ __forceinline__ void store_obs(uint8_t *dst, u32x4 v) {
-    store_stream(dst, v.x, v.y, v.z, v.w);
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(dst));
 }
 
 }  // namespace octax
