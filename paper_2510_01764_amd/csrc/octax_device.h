@@ -202,13 +202,18 @@ __device__ __forceinline__ u32x4 spread16(uint32_t bits) {
 }
 
 // 16 observation bytes at dst (16-byte aligned), for stores in which a
-// wavefront covers 1 KB of contiguous observation (the fused and SUPER-CHIP
-// step kernels).  They carry the nontemporal hint: a kernel that only streams
-// writes is faster without it (the calibration kernels), but these kernels
-// read state, memory pages and displays while their observations stream out,
-// and the hinted stores leave that data in the caches; measured, the fused
-// step is 1.5-4 % faster with the hint and the SUPER-CHIP step 8 %.
+// wavefront covers 1 KB of contiguous observation: plain stores for the fused
+// kernel (the hint measured no faster there, and slower where the stores
+// alone set the time), ...
 __device__ __forceinline__ void store_obs(uint8_t *dst, u32x4 v) {
+    *reinterpret_cast<u32x4 *>(dst) = v;
+}
+// ... and stores with the nontemporal hint for the SUPER-CHIP step, whose
+// emulation reads displays, memory pages and state from HBM while its
+// observations stream out: the hinted stores leave that data in the caches
+// (8 % more env steps/s at 65,536 envs, measured against plain stores on the
+// same device).
+__device__ __forceinline__ void store_obs_nt(uint8_t *dst, u32x4 v) {
     __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(dst));
 }
 

@@ -425,7 +425,7 @@ __device__ __forceinline__ void schip_observe_env(const State &s, uint8_t *obs, 
     for (uint32_t q = 0; q < kSchipObsBytes / 1024; q++) {
         const uint32_t off = q * 1024 + 16 * tid;   // byte of the observation: [frame][x][y]
         const uint32_t f = off >> 13, x = (off >> 6) & 127, y0 = off & 63;
-        store_obs(o + off, spread16(cols[f][x][y0 >> 5] >> (y0 & 31)));
+        store_obs_nt(o + off, spread16(cols[f][x][y0 >> 5] >> (y0 & 31)));
     }
 }
 
