@@ -33,10 +33,12 @@ struct State {
     uint32_t *cols;      // [E][4][64] frame ring of packed frames (see pack_frame), slot = misc head
     uint8_t *ram;        // [E][4096]
     // SUPER-CHIP engines only (null otherwise):
-    uint64_t *hfb;       // [E][64][2] 128x64 display: row y = hfb[2y] (x 0..63) and hfb[2y+1]
-                         //            (x 64..127), bit 63 - (x mod 64) = pixel (x, y)
-    uint64_t *hring;     // [E][5][128] frame ring of displays in the same row form
-    uint32_t *sx;        // [E][4] word 0: 1 = 128x64 mode; words 1, 2: flag registers 0..7, one byte each;
+    uint64_t *hfb;       // [E][64][2] 128x64 display: row y = hfb[2p] (x 0..63) and hfb[2p+1]
+                         //            (x 64..127), p = (y + row offset) & 63, bit 63 - (x mod 64) =
+                         //            pixel (x, y)
+    uint64_t *hring;     // [E][5][128] frame ring of displays in the same row form, p = y
+    uint32_t *sx;        // [E][4] word 0: 1 = 128x64 mode | row offset of hfb << 8; words 1, 2: flag
+                         //        registers 0..7, one byte each;
                          //        word 3: ring slot of the display and per-step observation info
     const uint32_t *rom_of;   // [E] ROM id
     const uint32_t *horizon;  // [E]

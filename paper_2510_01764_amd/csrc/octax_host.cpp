@@ -592,7 +592,17 @@ int32_t octax_get_schip_state(octax_engine *g, uint32_t first, uint32_t count, o
         if (e == hipSuccess) e = hipMemcpy(o.fb, g->s.hfb + 128 * (size_t)slot, 1024, hipMemcpyDeviceToHost);
         if (e == hipSuccess) e = hipMemcpy(ring.data(), g->s.hring + 640 * (size_t)slot, 5120, hipMemcpyDeviceToHost);
         if (e != hipSuccess) break;
-        o.hires = sx[0];
+        o.hires = sx[0] & 1;
+        // the device keeps display row y in row (y + offset) & 63, the offset in bits 8..13 of sx word 0
+        const uint32_t roff = (sx[0] >> 8) & 63;
+        if (roff) {
+            uint64_t rows[64][2];
+            std::memcpy(rows, o.fb, sizeof rows);
+            for (uint32_t y = 0; y < 64; y++) {
+                o.fb[y][0] = rows[(y + roff) & 63][0];
+                o.fb[y][1] = rows[(y + roff) & 63][1];
+            }
+        }
         std::memcpy(o.rpl, &sx[1], 8);
         o.reserved = 0;
         // five ring slots, the display in slot head; frames from before the

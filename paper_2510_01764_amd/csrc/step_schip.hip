@@ -46,9 +46,10 @@ __device__ __forceinline__ uint32_t double_bits(uint32_t b) {
 }
 
 struct SchipMem : PlainMem {
-    uint64_t *hd;      // [64][2] display rows
+    uint64_t *hd;      // [64][2] display rows, row y of the display in physical row (y + roff) & 63
     const uint8_t *img;    // the ROM's power-on image
     uint32_t hires;
+    uint32_t roff;     // row offset of the display (a scroll down moves it instead of the rows)
     uint32_t rpl0, rpl1;   // flag registers 0..3 and 4..7, byte k = register k
 
     // Memory reads: a page not written since the reset equals the ROM's
@@ -97,7 +98,7 @@ struct SchipMem : PlainMem {
         return u32x4{w[0], w[1], w[2], w[3]};
     }
 
-    // Row y as a 128-bit word, pixel x at bit 127 - x.
+    // Physical row p as a 128-bit word, pixel x at bit 127 - x.
     __device__ __forceinline__ u128 row(uint32_t y) const {
         return ((u128)hd[2 * y] << 64) | hd[2 * y + 1];
     }
@@ -153,12 +154,13 @@ struct SchipMem : PlainMem {
                 hi[i] = spill ? B << (32 - sh) : 0u;
                 uint32_t py = y0 + r;
                 py = py >= H ? py - H : py;
-                y[i] = py * sc;
+                y[i] = py * sc + roff;   // physical row of the sprite row (its first, in the 64x32 mode)
 #pragma unroll
                 for (int d = 0; d < 2; d++) {
                     const bool on = (uint32_t)r < rows && (uint32_t)d < sc;
-                    o0[i][d] = on ? disp[4 * (y[i] + d) + d0] : 0u;
-                    o1[i][d] = on ? disp[4 * (y[i] + d) + d1] : 0u;
+                    const uint32_t p = (y[i] + d) & 63;
+                    o0[i][d] = on ? disp[4 * p + d0] : 0u;
+                    o1[i][d] = on ? disp[4 * p + d1] : 0u;
                 }
             }
 #pragma unroll
@@ -167,29 +169,24 @@ struct SchipMem : PlainMem {
 #pragma unroll
                 for (int d = 0; d < 2; d++) {
                     if ((uint32_t)d < sc) {
+                        const uint32_t p = (y[i] + d) & 63;
                         hit |= (o0[i][d] & lo[i]) | (o1[i][d] & hi[i]);
-                        disp[4 * (y[i] + d) + d0] = o0[i][d] ^ lo[i];
-                        disp[4 * (y[i] + d) + d1] = o1[i][d] ^ hi[i];
+                        disp[4 * p + d0] = o0[i][d] ^ lo[i];
+                        disp[4 * p + d1] = o1[i][d] ^ hi[i];
                     }
                 }
             }
         }
         return hit != 0;
     }
-    // Scrolls by physical pixels, sixteen rows at a time: a chunk's loads come
-    // before its stores, and scrolling down goes bottom-up, so no row is read
-    // after it was written.
+    // Scrolls by physical pixels.  Down by s rows: display row y - s becomes
+    // row y by moving the row offset back by s, and the s rows that come in
+    // at the top (the physical rows of those that left at the bottom) are
+    // cleared.  Sideways: every row shifted, sixteen rows at a time, a
+    // chunk's loads before its stores.
     __device__ __forceinline__ void scroll_down(uint32_t s) {
-        for (int y0 = 48; y0 >= 0; y0 -= 16) {
-            u128 v[16];
-#pragma unroll
-            for (int j = 0; j < 16; j++) {
-                const uint32_t y = (uint32_t)(y0 + j);
-                v[j] = y >= s ? row(y - s) : (u128)0;
-            }
-#pragma unroll
-            for (int j = 0; j < 16; j++) set_row((uint32_t)(y0 + j), v[j]);
-        }
+        roff = (roff - s) & 63;
+        for (uint32_t j = 0; j < s; j++) set_row((roff + j) & 63, (u128)0);
     }
     __device__ __forceinline__ void scroll_side(uint32_t s, bool right) {
         for (uint32_t y0 = 0; y0 < 64; y0 += 16) {
@@ -207,6 +204,7 @@ struct SchipMem : PlainMem {
     }
     __device__ __forceinline__ void clear() {
         for (uint32_t q = 0; q < 128; q++) hd[q] = 0;
+        roff = 0;
     }
 };
 
@@ -296,19 +294,24 @@ __device__ __forceinline__ SchipMem schip_mem(const State &s, uint32_t slot, con
     mem.dirty = s.dirty[slot];
     mem.hd = s.hfb + (size_t)slot * 128;
     mem.img = img;
-    mem.hires = sx[0];
+    mem.hires = sx[0] & 1;             // sx word 0: mode | row offset << 8
+    mem.roff = (sx[0] >> 8) & 63;
     mem.rpl0 = sx[1];
     mem.rpl1 = sx[2];
     return mem;
 }
 
-// Copy the display into ring slot `head`: eight loads, then their stores.
-__device__ __forceinline__ void ring_put(const State &s, uint32_t slot, uint32_t head, const uint64_t *hd) {
+// Copy the display into ring slot `head`, rows in display order (physical
+// row (y + roff) & 63 into ring row y): eight loads, then their stores.
+__device__ __forceinline__ void ring_put(const State &s, uint32_t slot, uint32_t head, const uint64_t *hd,
+                                         uint32_t roff) {
     uint4 *ring = reinterpret_cast<uint4 *>(s.hring + ((size_t)slot * kRingSlots + head) * 128);
     const uint4 *disp = reinterpret_cast<const uint4 *>(hd);
-    for (int w = 0; w < 64; w += 8) {
-        const uint4 a0 = disp[w], a1 = disp[w + 1], a2 = disp[w + 2], a3 = disp[w + 3];
-        const uint4 a4 = disp[w + 4], a5 = disp[w + 5], a6 = disp[w + 6], a7 = disp[w + 7];
+    for (uint32_t w = 0; w < 64; w += 8) {
+        const uint4 a0 = disp[(w + roff) & 63], a1 = disp[(w + 1 + roff) & 63];
+        const uint4 a2 = disp[(w + 2 + roff) & 63], a3 = disp[(w + 3 + roff) & 63];
+        const uint4 a4 = disp[(w + 4 + roff) & 63], a5 = disp[(w + 5 + roff) & 63];
+        const uint4 a6 = disp[(w + 6 + roff) & 63], a7 = disp[(w + 7 + roff) & 63];
         uint4 *dst = ring + w;
         dst[0] = a0; dst[1] = a1; dst[2] = a2; dst[3] = a3;
         dst[4] = a4; dst[5] = a5; dst[6] = a6; dst[7] = a7;
@@ -376,7 +379,7 @@ __device__ __forceinline__ void schip_emulate(const State &s, const Roms &roms, 
     // reset step and the three after it read the reset display for the
     // frames from before the reset (frame_slot), so a reset writes one slot.
     const uint32_t head = (ring_head(w3) + 1) % kRingSlots;
-    ring_put(s, slot, head, mem.hd);
+    ring_put(s, slot, head, mem.hd, mem.roff);
     const uint32_t sh = 8 * (k & 1);
     const uint32_t info = head | (min(t, 3u) << 3);
     sx[3] = (w3 & ~(0xFFu << sh) & ~(7u << 16)) | (info << sh) | (head << 16);
@@ -384,7 +387,7 @@ __device__ __forceinline__ void schip_emulate(const State &s, const Roms &roms, 
     s.t[slot] = t;
     s.prev[slot] = prev;
     s.dirty[slot] = mem.dirty;
-    sx[0] = mem.hires;
+    sx[0] = mem.hires | (mem.roff << 8);
     sx[1] = mem.rpl0;
     sx[2] = mem.rpl1;
 }
@@ -482,12 +485,12 @@ __global__ __launch_bounds__(64) void schip_reset_steps_kernel(State s, Roms rom
     run_reset_steps(roms, rom, c, [&](uint32_t rk) {
         schip_env_step(c, mem, rk, roms.w.ipf, roms.w.frame_skip, roms.quirks);
     });
-    ring_put(s, slot, 0, mem.hd);
+    ring_put(s, slot, 0, mem.hd, mem.roff);
     store_core(s, slot, c, 0);
     s.prev[slot] = score_of(c.r, desc, desc2);
     s.dirty[slot] = mem.dirty;
     uint32_t *sx = s.sx + (size_t)slot * 4;
-    sx[0] = mem.hires;
+    sx[0] = mem.hires | (mem.roff << 8);
     sx[1] = mem.rpl0;
     sx[2] = mem.rpl1;
 }
